@@ -1,0 +1,368 @@
+"""Pins for the CPU oracle: it is checked against things other than itself --
+brute-force enumeration, closed forms, published test vectors, exact
+identities and invariances that the mathematics fixes.  CPU only."""
+import itertools
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1903_04395_amd import inputs as I
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+M64 = 1 << 64
+
+
+# --------------------------------------------------------------- brute force
+
+def _adj_sets(g):
+    return [set(g.col_idx[g.row_ptr[v]:g.row_ptr[v + 1]].tolist()) for v in range(g.n)]
+
+
+def _bfs_order(t, edges, root):
+    adj = [[] for _ in range(t)]
+    for u, v in edges:
+        adj[u].append(v)
+        adj[v].append(u)
+    order, parent, seen = [root], {root: -1}, {root}
+    i = 0
+    while i < len(order):
+        u = order[i]
+        i += 1
+        for w in adj[u]:
+            if w not in seen:
+                seen.add(w)
+                parent[w] = u
+                order.append(w)
+    return order, parent
+
+
+def brute_maps(g, t, edges, root, col=None):
+    """Enumerate homomorphisms phi: T -> G (tree edges to graph edges).
+    Returns a Counter keyed by (phi(root), frozenset of colours) over colourful
+    maps if `col` is given, else the number of injective maps."""
+    from collections import Counter
+    adj = _adj_sets(g)
+    order, parent = _bfs_order(t, edges, root)
+    res = Counter()
+    injective = 0
+    phi = {}
+
+    def rec(i):
+        nonlocal injective
+        if i == len(order):
+            img = [phi[u] for u in range(t)]
+            if col is None:
+                if len(set(img)) == t:
+                    injective += 1
+            else:
+                cs = [int(col[x]) for x in img]
+                if len(set(cs)) == t:
+                    res[(phi[root], frozenset(cs))] += 1
+            return
+        u = order[i]
+        cands = range(g.n) if parent[u] < 0 else adj[phi[parent[u]]]
+        for x in cands:
+            phi[u] = x
+            rec(i + 1)
+        del phi[u]
+
+    rec(0)
+    return injective if col is None else res
+
+
+def colex_rank(colours):
+    """Position of a colour set among all sets of its size in colex order,
+    i.e. numeric order of the bitmasks -- computed without Eq. 1."""
+    mask = sum(1 << c for c in colours)
+    h = len(colours)
+    return sum(1 for m in range(mask) if bin(m).count("1") == h)
+
+
+def plans_for(t, edges):
+    out = []
+    for root in range(t):
+        for order in ("given", "small", "large"):
+            out.append(O.root_plan(t, edges, root, order))
+    return out
+
+
+# --------------------------------------------------------------- colouring rule
+
+def test_splitmix64_published_vectors():
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "splitmix64_seed0.txt")) if l.strip() and not l.startswith("#")]
+    assert rows
+    for idx, hx in rows:
+        assert O.splitmix64(0, int(idx)) == int(hx, 16)
+
+
+def test_color_rule_multiply_high_and_uniform():
+    k = 7
+    for v in range(50):
+        x = O.splitmix64(12345, (3 << 40) + v)
+        assert O.color(12345, 3, v, k) == (x * k) >> 64
+    col = O.colors(99, 0, 70000, k)
+    hist = np.bincount(col, minlength=k)
+    exp = col.size / k
+    chi2 = float(((hist - exp) ** 2 / exp).sum())
+    assert chi2 < 30.0   # 6 dof: p ~ 4e-5
+
+
+# --------------------------------------------------------------- Eq. 1
+
+def test_eq1_worked_example():
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "eq1_k5_h2.txt")) if l.strip() and not l.startswith("#")]
+    assert len(rows) == 10
+    for c1, c2, idx in rows:
+        assert O.rank((1 << int(c1)) | (1 << int(c2))) == int(idx)
+
+
+@pytest.mark.parametrize("k", [1, 2, 5, 10, 12, 16])
+def test_eq1_is_colex_bijection(k):
+    """Eq. 1 maps the size-h subsets of [k] onto [0, binom(k,h)) in colex
+    (= numeric bitmask) order -- the combinatorial number system."""
+    by_h = {}
+    for m in range(1 << k):
+        by_h.setdefault(bin(m).count("1"), []).append(m)
+    for h, masks in by_h.items():
+        ranks = [O.rank(m) for m in masks]      # masks ascend numerically
+        assert ranks == list(range(math.comb(k, h)))
+
+
+# --------------------------------------------------------------- brute force pins
+
+SMALL_TREES = [
+    (2, [(0, 1)]),
+    (3, [(0, 1), (1, 2)]),
+    (4, [(0, 1), (1, 2), (2, 3)]),
+    (4, [(0, 1), (0, 2), (0, 3)]),
+    (5, [(0, 1), (1, 2), (1, 3), (3, 4)]),
+    (5, [(0, 1), (0, 2), (0, 3), (0, 4)]),
+    (5, [(0, 1), (1, 2), (2, 3), (3, 4)]),
+]
+
+
+@pytest.mark.parametrize("ti", range(len(SMALL_TREES)))
+@pytest.mark.parametrize("gseed", [1, 2, 3])
+def test_count_matches_brute_force_all_plans(ti, gseed):
+    t, edges = SMALL_TREES[ti]
+    g = I.random_small_graph(9 if t <= 4 else 8, 0.45, gseed)
+    for k in (t, t + 1):
+        col = O.colors(gseed * 7 + k, 0, g.n, k)
+        truth = sum(brute_maps(g, t, edges, 0, col).values())
+        for plan in plans_for(t, edges):
+            X, f = O.count_colored(g, t, plan, k, col)
+            assert (X, f) == (truth, 0)
+            Xu, _ = O.count_colored(g, t, plan, k, col, unpruned=True)
+            assert Xu == truth
+
+
+@pytest.mark.parametrize("ti", [1, 2, 3, 4, 5])
+def test_every_root_table_entry_matches_brute_force(ti):
+    """M_root[v][I(C)] = number of colourful maps with root -> v using colours C."""
+    t, edges = SMALL_TREES[ti]
+    g = I.random_small_graph(8, 0.5, 11 + ti)
+    k = t + 1
+    col = O.colors(5, 0, g.n, k)
+    for root in range(t):
+        plan = O.root_plan(t, edges, root, "small")
+        table, f = O.root_table(g, t, plan, k, col)
+        bf = brute_maps(g, t, edges, root, col)
+        expect = np.zeros_like(table)
+        for (v, cs), cnt in bf.items():
+            expect[v, colex_rank(sorted(cs))] = cnt
+        assert f == 0
+        assert np.array_equal(table, expect)
+
+
+def test_isolated_vertices_and_t1():
+    g = I.csr_from_edges(6, np.array([0, 1]), np.array([1, 2]))   # 3 isolated vertices
+    col = np.array([0, 1, 0, 1, 0, 1], np.uint8)
+    X, f = O.count_colored(g, 1, O.root_plan(1, [], 0), 1, np.zeros(6, np.uint8))
+    assert (X, f) == (6, 0)                     # t = 1: every vertex is a map
+    X, f = O.count_colored(g, 2, O.root_plan(2, [(0, 1)], 0), 2, col)
+    assert (X, f) == (4, 0)                     # 2 edges, both directions, colours differ
+    e = I.csr_from_edges(4, np.array([], np.int64), np.array([], np.int64))
+    X, f = O.count_colored(e, 3, O.root_plan(3, [(0, 1), (1, 2)], 1), 3, np.zeros(4, np.uint8))
+    assert (X, f) == (0, 0)
+
+
+# --------------------------------------------------------------- exact identities
+
+@pytest.mark.parametrize("t,edges,k", [
+    (3, [(0, 1), (1, 2)], 3),
+    (3, [(0, 1), (1, 2)], 4),
+    (4, [(0, 1), (0, 2), (0, 3)], 4),
+])
+def test_sum_over_all_colourings_identity(t, edges, k):
+    """sum_{col in [k]^n} X(col) = M(T,G) * k!/(k-t)! * k^(n-t): each injective
+    map is colourful in exactly that many colourings (Section 2.1, phase 1)."""
+    g = I.random_small_graph(6, 0.6, 4)
+    plan = O.root_plan(t, edges, 0, "given")
+    total = 0
+    for col in itertools.product(range(k), repeat=g.n):
+        X, f = O.count_colored(g, t, plan, k, np.array(col, np.uint8))
+        assert f == 0
+        total += X
+    M = brute_maps(g, t, edges, 0)
+    assert total == M * math.factorial(k) // math.factorial(k - t) * k ** (g.n - t)
+
+
+def _neighbour_colour_counts(g, col, k):
+    cnt = np.zeros((g.n, k), dtype=object)
+    for v in range(g.n):
+        for j in g.col_idx[g.row_ptr[v]:g.row_ptr[v + 1]]:
+            cnt[v, int(col[j])] += 1
+    return cnt
+
+
+def _esym(vals, r):
+    e = [1] + [0] * r
+    for x in vals:
+        for q in range(r, 0, -1):
+            e[q] += e[q - 1] * x
+    return e[r]
+
+
+def star_closed_form(g, col, k, t):
+    """Colourful maps of the t-star: sum_v (t-1)! e_{t-1}(n_c(v) : c != col v)."""
+    cnt = _neighbour_colour_counts(g, col, k)
+    return sum(math.factorial(t - 1) * _esym([int(cnt[v, c]) for c in range(k) if c != col[v]], t - 1)
+               for v in range(g.n))
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_star_closed_form_per_colouring(seed):
+    g = I.erdos_renyi(60, 400, seed)
+    for t, k in [(4, 4), (5, 5), (5, 7), (6, 6)]:
+        col = O.colors(seed, 0, g.n, k)
+        truth = star_closed_form(g, col, k, t)
+        for root in (0, 1):                      # centre, then a leaf
+            X, _ = O.count_colored(g, t, O.root_plan(t, I.star(t), root), k, col)
+            assert X == truth % M64
+
+
+def test_overflow_boundary_star_on_k1d():
+    """K_{1,d} with chosen colour multiplicities: X = (t-1)! * prod n_c, and the
+    flag under the centre-rooted plan is exactly [X >= 2^64] (every
+    intermediate table entry is a factor of X).  Straddles 2^64."""
+    t = k = 12
+    base = [11] * 11
+    cases = []
+    for bump in range(0, 12):
+        ns = list(base)
+        for i in range(bump):
+            ns[i] += 1
+        cases.append(ns)
+    seen = set()
+    for ns in cases:
+        d = sum(ns)
+        src = np.zeros(d, np.int64)
+        dst = np.arange(1, d + 1, dtype=np.int64)
+        g = I.csr_from_edges(d + 1, src, dst)
+        col = np.zeros(d + 1, np.uint8)
+        pos = 1
+        for c, m in enumerate(ns, start=1):
+            col[pos:pos + m] = c
+            pos += m
+        exact = math.factorial(t - 1) * math.prod(ns)
+        X, f = O.count_colored(g, t, O.root_plan(t, I.star(t), 0), k, col)
+        assert X == exact % M64
+        assert f == int(exact >= M64)
+        seen.add(f)
+    assert seen == {0, 1}
+
+
+def hubby_graph(seed, n=1500, m=4000, hubs=3, hub_deg=900):
+    """Sparse random graph plus a few high-degree hubs, so counts pass 2^64."""
+    rng = np.random.default_rng(seed)
+    g0 = I.erdos_renyi(n, m, seed)
+    e = g0.edges()
+    src, dst = [e[:, 0]], [e[:, 1]]
+    for h in range(hubs):
+        nb = rng.choice(np.arange(hubs, n), size=hub_deg, replace=False)
+        src.append(np.full(hub_deg, h))
+        dst.append(nb)
+    return I.csr_from_edges(n, np.concatenate(src), np.concatenate(dst))
+
+
+def test_residue_is_plan_independent_under_overflow():
+    """X mod 2^64 is a ring image of the exact DP, so every rooting and child
+    order gives the same residue even when the counts overflow."""
+    g = hubby_graph(3, hubs=8, hub_deg=1400)
+    t, k = 11, 11
+    edges = I.prufer_tree(t, 3)
+    col = O.colors(17, 0, g.n, k)
+    results = {O.count_colored(g, t, plan, k, col) for plan in plans_for(t, edges)}
+    residues = {x for x, _ in results}
+    flags = {f for _, f in results}
+    assert len(residues) == 1
+    assert 1 in flags   # this instance does overflow
+
+
+# --------------------------------------------------------------- estimator
+
+def aut_brute(t, edges):
+    E = {frozenset(e) for e in edges}
+    return sum(1 for p in itertools.permutations(range(t))
+               if all(frozenset((p[u], p[v])) in E for u, v in edges))
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_aut_matches_permutation_count(seed):
+    for t in range(2, 8):
+        edges = I.prufer_tree(t, seed * 10 + t)
+        assert O.aut(t, edges) == aut_brute(t, edges)
+
+
+def test_aut_closed_forms():
+    for t in range(3, 17):
+        assert O.aut(t, I.star(t)) == math.factorial(t - 1)
+        assert O.aut(t, I.path(t)) == 2
+    assert O.aut(2, [(0, 1)]) == 2
+
+
+def _convergence(g, t, edges, k, truth_maps, R, seed):
+    plan = O.root_plan(t, edges, 0, "small")
+    counts, flags = O.count(g, t, plan, k, seed, 0, R)
+    assert not flags.any()
+    P = O.colorful_probability(k, t)
+    x = counts.astype(np.float64) / P
+    est, s = x.mean(), x.std(ddof=1)
+    assert abs(est - truth_maps) <= 4 * s / math.sqrt(R) + 1e-9
+    maps, copies = O.estimate(counts, flags, k, t, O.aut(t, edges))
+    assert maps == pytest.approx(est)
+    return copies
+
+
+def test_estimator_converges_star():
+    g = I.erdos_renyi(80, 400, 21)
+    t = k = 4
+    deg = g.degrees()
+    copies = sum(math.comb(int(d), t - 1) for d in deg)
+    est_copies = _convergence(g, t, I.star(t), k, copies * math.factorial(t - 1), 1500, 3)
+    assert est_copies == pytest.approx(copies, rel=0.1)
+
+
+def test_estimator_converges_paths():
+    g = I.erdos_renyi(80, 400, 22)
+    deg = g.degrees().astype(np.int64)
+    p3 = int((deg * (deg - 1)).sum())
+    _convergence(g, 3, I.path(3), 3, p3, 1500, 4)
+    adj = _adj_sets(g)
+    tri6 = sum(len(adj[b] & adj[c]) for b in range(g.n) for c in adj[b])
+    p4 = sum((deg[b] - 1) * (deg[c] - 1) for b in range(g.n) for c in adj[b]) - tri6
+    _convergence(g, 4, I.path(4), 4, int(p4), 1500, 5)
+
+
+def test_estimator_converges_p5_enumerated():
+    g = I.erdos_renyi(40, 90, 23)
+    p5 = brute_maps(g, 5, I.path(5), 0)
+    _convergence(g, 5, I.path(5), 5, p5, 2500, 6)
+
+
+def test_estimate_nan_on_overflow():
+    maps, copies = O.estimate(np.array([1, 2], np.uint64), np.array([0, 1], np.uint8), 3, 3, 2)
+    assert math.isnan(maps) and math.isnan(copies)
