@@ -1,0 +1,187 @@
+/*
+ * sc.h -- C ABI of libsc: colour-coding tree subgraph counting on AMD MI355X
+ * (gfx950).
+ *
+ * The method is the dynamic program of Chen et al., "A GraphBLAS Approach for
+ * Subgraph Counting" (HPDC'19):
+ *  - Section 2.1: random colouring with k >= t colours; template partitioning
+ *    into an active child (keeps the root) and a passive child (rooted at the
+ *    other end of a cut root edge); bottom-up DP over count tables with one row
+ *    per graph vertex and one column per colour set of the sub-template's size;
+ *    colourful-count / (k!/k^k) estimates the number of embeddings.
+ *  - Section 3, Eq. 1: colour sets are indexed by the combinatorial number system.
+ *  - Section 4.1-4.2, Eq. 2: the neighbour sum is taken once per passive colour
+ *    set and stored (N = A * M_p, an SpMM over the 0/1 adjacency).
+ *  - Section 4.5 (Algorithm 4): the rest of a step is an element-wise
+ *    multiply-add ("eMA") M_s[v,C] = sum_{C1 (+) C2 = C} M_a[v,C1] * N[v,C2].
+ *
+ * Counts are exact unsigned 64-bit residues.  Overflow is not an error: each
+ * colouring carries a flag that is 1 iff some neighbour-sum entry, product,
+ * table entry or final count, evaluated exactly from the stored 64-bit
+ * operands, reached 2^64.  The flag depends on the plan (root and child order)
+ * but not on summation order, batching or fusion; the residue depends on
+ * nothing but (graph, template, k, seed, colouring index).
+ *
+ * Colouring rule (the paper only says "randomly selected"): colouring r of
+ * vertex v is floor(x * k / 2^64) where x is output number r*2^40 + v of
+ * SplitMix64 (Steele, Lea & Flood, OOPSLA 2014) seeded with the context seed.
+ *
+ * Conventions for every call:
+ *  - return value: SC_OK (0) or a negative SC_E* code; nothing throws or aborts;
+ *    sc_last_error() then holds a message (owned by the context, valid until the
+ *    next call on the same context).
+ *  - pointer arguments documented as "host" are read or written during the call
+ *    only; the caller keeps ownership.  Device memory that the library allocates
+ *    belongs to the context until the matching unload/destroy.
+ *  - a context is used by one host thread at a time, except the serving calls
+ *    (sc_serve_*), which are internally synchronised.
+ */
+#ifndef SC_H
+#define SC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SC_MAX_T 16          /* template vertices */
+#define SC_MAX_K 16          /* colours */
+#define SC_MAX_BATCH 64      /* colourings folded into one pass */
+
+enum {
+    SC_OK = 0,
+    SC_EINVAL = -1,     /* malformed argument, graph or template */
+    SC_ENOMEM = -2,     /* device allocation failed or plan exceeds the budget */
+    SC_EDEVICE = -3,    /* a HIP runtime call or kernel launch failed */
+    SC_ENOTFOUND = -4,  /* unknown graph / template id or ticket */
+    SC_EBUSY = -5,      /* result not ready yet (sc_poll) */
+    SC_ESTATE = -6      /* call not valid in the current state */
+};
+
+typedef struct sc_ctx sc_ctx;
+
+/* Optional device allocator hook.  `alloc` returns device memory of at least
+ * `bytes` bytes usable on `stream` (NULL on failure); `free_fn` releases it.
+ * When both are NULL the library uses hipMalloc / hipFree. */
+typedef void *(*sc_alloc_fn)(size_t bytes, void *stream, void *user);
+typedef void (*sc_free_fn)(void *ptr, size_t bytes, void *stream, void *user);
+
+/* Creates a context on HIP device `device`.  `mem_budget_bytes` caps the count
+ * tables of one run (0 = 90% of the device's free memory at creation).
+ * Errors: SC_EINVAL (bad device or only one of alloc/free given), SC_EDEVICE. */
+int sc_create(int device, sc_alloc_fn alloc, sc_free_fn free_fn, void *user,
+              uint64_t mem_budget_bytes, sc_ctx **out);
+
+/* Releases every device buffer owned by the context (after draining the
+ * serving loop if it runs), then the context.  NULL is accepted. */
+int sc_destroy(sc_ctx *ctx);
+
+/* Message for the last failed call on `ctx` (empty string if none). */
+const char *sc_last_error(const sc_ctx *ctx);
+
+/* Library version string, static storage. */
+const char *sc_version(void);
+
+/* ------------------------------------------------------------------ inputs */
+
+/* Loads a simple undirected graph as its symmetric 0/1 adjacency A_G in CSR
+ * form (the paper stores A_G in CSC, Section 4.3; for a symmetric matrix the
+ * two coincide).  Host arrays: row_ptr[n+1] (int64, row_ptr[0]=0,
+ * non-decreasing, row_ptr[n]=nnz), col_idx[nnz] (int32 in [0,n), strictly
+ * increasing within a row, no self-loops, and (i,j) present iff (j,i) is).
+ * The arrays are validated, copied to the device and kept resident.
+ * Errors: SC_EINVAL (any rule above broken; n < 1 or n >= 2^31), SC_ENOMEM,
+ * SC_EDEVICE. */
+int sc_load_graph_csr(sc_ctx *ctx, int64_t n, int64_t nnz, const int64_t *row_ptr,
+                      const int32_t *col_idx, int32_t *graph_id);
+
+int sc_unload_graph(sc_ctx *ctx, int32_t graph_id);
+
+/* Loads a template tree T: t vertices 0..t-1 (1 <= t <= SC_MAX_T) and t-1
+ * undirected edges given as host int32 pairs edges[2*i], edges[2*i+1].
+ * `root` selects the root of the partitioning (Section 2.1, phase 2), or -1 to
+ * let the planner choose the root and child order with the lowest modelled
+ * cost.  Errors: SC_EINVAL (not a tree, ids out of range, bad root). */
+int sc_load_template(sc_ctx *ctx, int32_t t, const int32_t *edges, int32_t root,
+                     int32_t *tmpl_id);
+
+/* Loads a template with an explicit plan: `child_ptr[t+1]`, `child_idx[t-1]`
+ * list the children of every vertex in attach order (CSR form of a rooted,
+ * ordered tree with root `root`).  Each attach of a child w to u is one DP step
+ * (active child = the part of u's subtree built so far, passive child = the
+ * subtree of w).  Errors: SC_EINVAL (not a rooted spanning tree). */
+int sc_load_template_plan(sc_ctx *ctx, int32_t t, int32_t root, const int32_t *child_ptr,
+                          const int32_t *child_idx, int32_t *tmpl_id);
+
+/* Sets the number of colours k (t <= k <= SC_MAX_K, checked at run time) and
+ * the colouring seed.  Errors: SC_EINVAL (k < 1 or k > SC_MAX_K). */
+int sc_set_colors(sc_ctx *ctx, int32_t k, uint64_t seed);
+
+/* ------------------------------------------------------------------ plans */
+
+typedef struct {
+    int32_t t, k, root, n_steps;
+    int32_t child_ptr[SC_MAX_T + 1];     /* rooted ordered tree (CSR)        */
+    int32_t child_idx[SC_MAX_T];
+    int32_t step_h[SC_MAX_T];           /* steps in execution order:        */
+    int32_t step_a[SC_MAX_T];           /*   sizes of T_s, T_a, T_p         */
+    int32_t step_p[SC_MAX_T];
+    int32_t batch;                      /* colourings per pass              */
+    uint64_t arena_bytes;               /* device tables of one pass        */
+    double spmm_updates;                /* per colouring: sum nnz*C(k,p), p>=2 */
+    double ema_updates;                 /* per colouring: sum n*C(k,h)*C(h,a)  */
+    double compulsory_bytes;            /* per colouring, HBM bytes (model) */
+    double automorphisms;               /* |Aut(T)|                         */
+} sc_plan_info_t;
+
+/* Pure host call (no device needed): plans template (t, edges, root as in
+ * sc_load_template) for a graph of n vertices and nnz nonzeros, k colours and
+ * `batch` colourings per pass, and fills `out`.  Lemma 1 gives the per-step
+ * operation counts: nnz*C(k,p) neighbour-sum updates and n*C(k,h)*C(h,a)
+ * multiply-adds.  Errors: SC_EINVAL. */
+int sc_plan_template(int32_t t, const int32_t *edges, int32_t root, int32_t k, int64_t n,
+                     int64_t nnz, int32_t batch, sc_plan_info_t *out);
+
+/* Plan of a loaded template for a loaded graph, with the batch the library
+ * would use for `n_colorings` colourings under the memory budget. */
+int sc_plan_info(sc_ctx *ctx, int32_t graph_id, int32_t tmpl_id, int32_t n_colorings,
+                 sc_plan_info_t *out);
+
+/* Pure host helpers exposing the library's own colour-set indexing (Eq. 1) and
+ * colouring rule, for tests. */
+int64_t sc_colorset_rank(uint32_t mask);
+int32_t sc_color_of(uint64_t seed, uint64_t coloring, uint64_t vertex, int32_t k);
+
+/* ------------------------------------------------------------------ runs */
+
+/* Counts colourful maps of the template into the graph for colourings
+ * first_coloring .. first_coloring+n_colorings-1 (colourings are folded into
+ * the table columns, up to the planned batch per pass).  Synchronous: on return
+ * the host outputs are written.  `stream` is a hipStream_t (NULL = the
+ * context's own stream).
+ * Host outputs: counts[n_colorings] (residues mod 2^64), overflow[n_colorings]
+ * (0/1), and optionally (may be NULL) est_maps / est_copies: the mean count
+ * divided by k!/((k-t)! k^t), and that divided by |Aut(T)|; NaN if any
+ * colouring overflowed.
+ * Errors: SC_EINVAL (k < t, n_colorings < 0), SC_ENOTFOUND, SC_ENOMEM, SC_EDEVICE. */
+int sc_run(sc_ctx *ctx, int32_t graph_id, int32_t tmpl_id, uint64_t first_coloring,
+           int32_t n_colorings, void *stream, uint64_t *counts, uint8_t *overflow,
+           double *est_maps, double *est_copies);
+
+/* Execution options (mainly for measurement and ablation). */
+enum {
+    SC_OPT_MAX_BATCH = 1,     /* cap on colourings per pass (1..SC_MAX_BATCH)   */
+    SC_OPT_FUSED = 2,         /* 1: fused neighbour-sum + multiply-add kernels  */
+    SC_OPT_GRAPH = 3,         /* 1: replay each pass from a captured hipGraph   */
+    SC_OPT_CHUNK_COLS = 4,    /* neighbour-sum column tile, in uint64 (0=auto)  */
+    SC_OPT_SEGMENT = 5        /* neighbours per work item for heavy rows (0=auto) */
+};
+int sc_set_option(sc_ctx *ctx, int32_t option, int64_t value);
+int sc_get_option(sc_ctx *ctx, int32_t option, int64_t *value);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SC_H */

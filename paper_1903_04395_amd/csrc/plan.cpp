@@ -1,0 +1,335 @@
+// Host-side planning for the colour-coding DP: template checks, rooting and
+// child order (Section 2.1, phase 2), the per-step sizes (h, a, p), Lemma 1
+// operation counts, a static memory plan for the count tables, the Eq. 1
+// colour-set index and the split / drop-colour index tables the kernels read.
+#include "sc_internal.h"
+
+#include <algorithm>
+#include <cstring>
+#include <functional>
+#include <limits>
+
+namespace sc {
+
+uint64_t binom(int n, int r) {
+    if (r < 0 || n < 0 || r > n) return 0;
+    static uint64_t pascal[65][65];
+    static bool init = false;
+    if (!init) {
+        for (int i = 0; i <= 64; ++i) {
+            pascal[i][0] = 1;
+            for (int j = 1; j <= i; ++j)
+                pascal[i][j] = pascal[i - 1][j - 1] + (j <= i - 1 ? pascal[i - 1][j] : 0);
+        }
+        init = true;
+    }
+    return pascal[n][r];
+}
+
+int64_t colorset_rank(uint32_t mask) {
+    int64_t idx = 0;
+    int i = 1;
+    while (mask) {
+        int c = __builtin_ctz(mask);
+        idx += (int64_t)binom(c, i++);
+        mask &= mask - 1;
+    }
+    return idx;
+}
+
+std::string check_tree(int t, const int32_t *edges) {
+    if (t < 1 || t > SC_MAX_T) return "template size must be in [1, 16]";
+    if (t > 1 && !edges) return "edges is NULL";
+    std::vector<int> parent(t);
+    for (int i = 0; i < t; ++i) parent[i] = i;
+    std::function<int(int)> find = [&](int x) { return parent[x] == x ? x : parent[x] = find(parent[x]); };
+    for (int e = 0; e < t - 1; ++e) {
+        int u = edges[2 * e], v = edges[2 * e + 1];
+        if (u < 0 || v < 0 || u >= t || v >= t) return "template edge endpoint out of range";
+        if (u == v) return "template has a self-loop";
+        int ru = find(u), rv = find(v);
+        if (ru == rv) return "template edges contain a cycle (not a tree)";
+        parent[ru] = rv;
+    }
+    return "";
+}
+
+void root_tree(int t, const int32_t *edges, int root, int order,
+               std::vector<int> &child_ptr, std::vector<int> &child_idx) {
+    std::vector<std::vector<int>> adj(t), kids(t);
+    for (int e = 0; e < t - 1; ++e) {
+        adj[edges[2 * e]].push_back(edges[2 * e + 1]);
+        adj[edges[2 * e + 1]].push_back(edges[2 * e]);
+    }
+    std::vector<int> par(t, -1), bfs{root}, size(t, 1);
+    std::vector<char> seen(t, 0);
+    seen[root] = 1;
+    for (size_t i = 0; i < bfs.size(); ++i)
+        for (int w : adj[bfs[i]])
+            if (!seen[w]) { seen[w] = 1; par[w] = bfs[i]; bfs.push_back(w); kids[bfs[i]].push_back(w); }
+    for (int i = t - 1; i > 0; --i) size[par[bfs[i]]] += size[bfs[i]];
+    child_ptr.assign(t + 1, 0);
+    child_idx.clear();
+    for (int u = 0; u < t; ++u) {
+        auto &c = kids[u];
+        std::stable_sort(c.begin(), c.end(), [&](int x, int y) {
+            return order == 0 ? (size[x] < size[y] || (size[x] == size[y] && x < y))
+                              : (size[x] > size[y] || (size[x] == size[y] && x < y));
+        });
+        for (int w : c) child_idx.push_back(w);
+        child_ptr[u + 1] = (int)child_idx.size();
+    }
+}
+
+int fused_lds_bytes(int k, int h, int a, int p, int batch) {
+    (void)h;
+    uint64_t words = binom(k, p) + (a > 1 ? binom(k, a) : 0);
+    return (int)(words * (uint64_t)batch * 8);
+}
+
+bool fusable(int k, int h, int a, int p, int batch) {
+    return fused_lds_bytes(k, h, a, p, batch) <= 64 * 1024;
+}
+
+namespace {
+
+// First-fit placement of buffers inside one arena, in allocation order.
+struct Arena {
+    std::vector<std::pair<uint64_t, uint64_t>> free_;   // (offset, length), sorted
+    uint64_t end = 0;
+    uint64_t alloc(uint64_t bytes) {
+        for (size_t i = 0; i < free_.size(); ++i)
+            if (free_[i].second >= bytes) {
+                uint64_t off = free_[i].first;
+                free_[i].first += bytes;
+                free_[i].second -= bytes;
+                if (free_[i].second == 0) free_.erase(free_.begin() + i);
+                return off;
+            }
+        // extend, merging a free tail block
+        if (!free_.empty() && free_.back().first + free_.back().second == end) {
+            uint64_t off = free_.back().first;
+            free_.pop_back();
+            end = off + bytes;
+            return off;
+        }
+        uint64_t off = end;
+        end += bytes;
+        return off;
+    }
+    void release(uint64_t off, uint64_t bytes) {
+        auto it = std::lower_bound(free_.begin(), free_.end(), std::make_pair(off, (uint64_t)0));
+        it = free_.insert(it, {off, bytes});
+        size_t i = it - free_.begin();
+        if (i + 1 < free_.size() && free_[i].first + free_[i].second == free_[i + 1].first) {
+            free_[i].second += free_[i + 1].second;
+            free_.erase(free_.begin() + i + 1);
+        }
+        if (i > 0 && free_[i - 1].first + free_[i - 1].second == free_[i].first) {
+            free_[i - 1].second += free_[i].second;
+            free_.erase(free_.begin() + i);
+        }
+    }
+};
+
+uint64_t table_bytes(int64_t n, int k, int size, int batch) {
+    uint64_t b = (uint64_t)n * binom(k, size) * (uint64_t)batch * 8;
+    return (b + 255) & ~(uint64_t)255;
+}
+
+}  // namespace
+
+bool build_plan(int t, int root, const std::vector<int> &child_ptr,
+                const std::vector<int> &child_idx, int k, int64_t n, int64_t nnz,
+                int batch, bool fused, Plan &P, std::string &err) {
+    P = Plan();
+    P.t = t; P.k = k; P.root = root; P.n = n; P.nnz = nnz; P.batch = batch;
+    P.child_ptr = child_ptr; P.child_idx = child_idx;
+    P.materialize_n = !fused;
+    if (k < t || k > SC_MAX_K) { err = "need t <= k <= 16"; return false; }
+    // subtree sizes and a check that the rooted tree spans 0..t-1 once
+    P.subtree.assign(t, 0);
+    std::vector<int> seen(t, 0);
+    std::function<int(int)> sz = [&](int u) -> int {
+        if (seen[u]++) return -(1 << 20);
+        int s = 1;
+        for (int e = child_ptr[u]; e < child_ptr[u + 1]; ++e) s += sz(child_idx[e]);
+        return P.subtree[u] = s;
+    };
+    if ((int)child_ptr.size() != t + 1 || child_ptr[0] != 0 || child_ptr[t] != t - 1 ||
+        root < 0 || root >= t) { err = "malformed plan"; return false; }
+    for (int e = 0; e < t - 1; ++e)
+        if (child_idx[e] < 0 || child_idx[e] >= t) { err = "malformed plan"; return false; }
+    if (sz(root) != t) { err = "plan is not a rooted spanning tree"; return false; }
+    for (int u = 0; u < t; ++u) if (seen[u] != 1) { err = "plan is not a rooted spanning tree"; return false; }
+
+    Arena arena;
+    auto new_buf = [&](int size) {
+        Buf b{size, table_bytes(n, k, size, batch), 0};
+        b.offset = arena.alloc(b.bytes);
+        P.bufs.push_back(b);
+        return (int)P.bufs.size() - 1;
+    };
+    auto drop = [&](int id) { if (id >= 0) arena.release(P.bufs[id].offset, P.bufs[id].bytes); };
+
+    // post-order walk: the subtree of u is built by attaching its children in order
+    std::function<int(int)> walk = [&](int u) -> int {
+        int cur = -1, size = 1;
+        for (int e = child_ptr[u]; e < child_ptr[u + 1]; ++e) {
+            int w = child_idx[e];
+            int pb = walk(w);
+            Step s;
+            s.node = u; s.child = w;
+            s.a = size; s.p = P.subtree[w]; s.h = s.a + s.p;
+            s.buf_a = cur; s.buf_p = pb;
+            bool fuse = fused && fusable(k, s.h, s.a, s.p, batch);
+            s.buf_n = fuse ? -1 : new_buf(s.p);
+            s.buf_s = new_buf(s.h);
+            s.last = false;
+            drop(s.buf_n);
+            drop(s.buf_a);
+            drop(s.buf_p);
+            P.steps.push_back(s);
+            cur = s.buf_s;
+            size = s.h;
+        }
+        return cur;
+    };
+    int top = walk(root);
+    if (!P.steps.empty()) P.steps.back().last = true;
+    (void)top;
+    P.arena_bytes = arena.end;
+
+    // Lemma 1 counts and a byte model, per colouring
+    for (const Step &s : P.steps) {
+        double Wa = (double)binom(k, s.a), Wp = (double)binom(k, s.p), Wh = (double)binom(k, s.h);
+        if (s.p >= 2) P.spmm_updates += (double)nnz * Wp;
+        P.ema_updates += (double)n * Wh * (double)binom(s.h, s.a);
+        bool fuse = fused && fusable(k, s.h, s.a, s.p, batch);
+        double bytes = 8.0 * n * ((s.a > 1 ? Wa : 0) + (s.p > 1 ? Wp : 0) + Wh);
+        if (s.p > 1 && !fuse) bytes += 16.0 * n * Wp;             // write + read N
+        if (s.p == 1 || s.a == 1) bytes += (double)n;              // colours
+        bytes += 4.0 * nnz + 8.0 * (n + 1);                        // adjacency
+        P.compulsory_bytes += bytes;
+        double gather = s.p >= 2 ? 8.0 * nnz * Wp * 0.5 : (double)nnz;
+        P.cost += bytes + gather + 3.2 * (double)n * Wh * (double)binom(s.h, s.a);
+    }
+    return true;
+}
+
+bool choose_plan(int t, const int32_t *edges, int root, int k, int64_t n, int64_t nnz,
+                 int batch, bool fused, Plan &out, std::string &err) {
+    std::string m = check_tree(t, edges);
+    if (!m.empty()) { err = m; return false; }
+    if (root >= t) { err = "root out of range"; return false; }
+    bool found = false;
+    for (int r = (root < 0 ? 0 : root); r < (root < 0 ? t : root + 1); ++r)
+        for (int order = 0; order < 2; ++order) {
+            std::vector<int> cp, ci;
+            root_tree(t, edges, r, order, cp, ci);
+            Plan p;
+            if (!build_plan(t, r, cp, ci, k, n, nnz, batch, fused, p, err)) return false;
+            if (!found || p.cost < out.cost ||
+                (p.cost == out.cost && p.arena_bytes < out.arena_bytes)) {
+                out = p;
+                found = true;
+            }
+        }
+    return found;
+}
+
+// Automorphisms of an unrooted tree: root it at its centre (or cut the central
+// edge), then aut(u) = prod aut(children) * prod (multiplicity of each
+// isomorphism class of child subtrees)!.  Isomorphism classes of rooted
+// subtrees get integer labels from the sorted labels of their children.
+double tree_automorphisms(int t, const std::vector<std::pair<int,int>> &edges) {
+    if (t <= 1) return 1.0;
+    std::vector<std::vector<int>> adj(t);
+    for (auto &e : edges) { adj[e.first].push_back(e.second); adj[e.second].push_back(e.first); }
+    // centre(s) by repeatedly stripping leaves
+    std::vector<int> deg(t), layer, removed(t, 0);
+    for (int u = 0; u < t; ++u) { deg[u] = (int)adj[u].size(); if (deg[u] <= 1) layer.push_back(u); }
+    int left = t;
+    while (left > 2) {
+        std::vector<int> next;
+        for (int u : layer) {
+            removed[u] = 1; --left;
+            for (int w : adj[u]) if (!removed[w] && --deg[w] == 1) next.push_back(w);
+        }
+        layer = next;
+    }
+    std::vector<int> centres;
+    for (int u = 0; u < t; ++u) if (!removed[u]) centres.push_back(u);
+    std::map<std::vector<int>, int> labels;
+    std::function<std::pair<int, double>(int, int)> rooted = [&](int u, int par) {
+        std::vector<int> kid_labels;
+        double a = 1.0;
+        for (int w : adj[u]) if (w != par) {
+            auto r = rooted(w, u);
+            kid_labels.push_back(r.first);
+            a *= r.second;
+        }
+        std::sort(kid_labels.begin(), kid_labels.end());
+        for (size_t i = 0; i < kid_labels.size();) {
+            size_t j = i;
+            while (j < kid_labels.size() && kid_labels[j] == kid_labels[i]) ++j;
+            for (size_t m = 2; m <= j - i; ++m) a *= (double)m;
+            i = j;
+        }
+        auto it = labels.find(kid_labels);
+        int lab = it == labels.end() ? (labels[kid_labels] = (int)labels.size()) : it->second;
+        return std::make_pair(lab, a);
+    };
+    if (centres.size() == 1) return rooted(centres[0], -1).second;
+    auto x = rooted(centres[0], centres[1]);
+    auto y = rooted(centres[1], centres[0]);
+    return x.second * y.second * (x.first == y.first ? 2.0 : 1.0);
+}
+
+std::vector<uint32_t> split_table(int k, int h, int a) {
+    const int per = (int)binom(h, a);
+    std::vector<uint32_t> out(binom(k, h) * (uint64_t)per);
+    for (uint32_t ms = 0; ms < (1u << k); ++ms) {
+        if (__builtin_popcount(ms) != h) continue;
+        int64_t is = colorset_rank(ms);
+        int q = 0;
+        // subsets of ms with a elements, walking the submasks
+        for (uint32_t ma = ms;; ma = (ma - 1) & ms) {
+            if (__builtin_popcount(ma) == a) {
+                uint32_t ia = (uint32_t)colorset_rank(ma), ip = (uint32_t)colorset_rank(ms ^ ma);
+                out[is * per + q++] = ia | (ip << 16);
+            }
+            if (!ma) break;
+        }
+    }
+    return out;
+}
+
+std::vector<int16_t> drop_table(int k, int h) {
+    std::vector<int16_t> out(binom(k, h) * (uint64_t)k, (int16_t)-1);
+    for (uint32_t ms = 0; ms < (1u << k); ++ms) {
+        if (__builtin_popcount(ms) != h) continue;
+        int64_t is = colorset_rank(ms);
+        for (int c = 0; c < k; ++c)
+            if (ms & (1u << c)) out[is * k + c] = (int16_t)colorset_rank(ms & ~(1u << c));
+    }
+    return out;
+}
+
+void fill_plan_info(const Plan &p, double aut, sc_plan_info_t *o) {
+    std::memset(o, 0, sizeof(*o));
+    o->t = p.t; o->k = p.k; o->root = p.root; o->n_steps = (int)p.steps.size();
+    for (int i = 0; i <= p.t && i < (int)p.child_ptr.size(); ++i) o->child_ptr[i] = p.child_ptr[i];
+    for (int i = 0; i < p.t - 1; ++i) o->child_idx[i] = p.child_idx[i];
+    for (size_t i = 0; i < p.steps.size(); ++i) {
+        o->step_h[i] = p.steps[i].h; o->step_a[i] = p.steps[i].a; o->step_p[i] = p.steps[i].p;
+    }
+    o->batch = p.batch;
+    o->arena_bytes = p.arena_bytes;
+    o->spmm_updates = p.spmm_updates;
+    o->ema_updates = p.ema_updates;
+    o->compulsory_bytes = p.compulsory_bytes;
+    o->automorphisms = aut;
+}
+
+}  // namespace sc

@@ -1,0 +1,265 @@
+"""ctypes binding for libsc (include/sc.h): argument marshalling only.
+
+Every step of the counting runs in libsc's HIP kernels; this module converts
+numpy arrays and Python values to the C ABI's plain pointers and back.  It
+raises ``RuntimeError`` when the built library is missing -- there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+__all__ = [
+    "SC_OK", "SC_EINVAL", "SC_ENOMEM", "SC_EDEVICE", "SC_ENOTFOUND", "SC_EBUSY", "SC_ESTATE",
+    "SC_OPT_MAX_BATCH", "SC_OPT_FUSED", "SC_OPT_GRAPH", "SC_OPT_CHUNK_COLS", "SC_OPT_SEGMENT",
+    "ScError", "PlanInfo", "lib", "lib_path", "sc_version", "sc_plan_template",
+    "sc_colorset_rank", "sc_color_of", "Context",
+]
+
+SC_OK, SC_EINVAL, SC_ENOMEM, SC_EDEVICE, SC_ENOTFOUND, SC_EBUSY, SC_ESTATE = 0, -1, -2, -3, -4, -5, -6
+SC_OPT_MAX_BATCH, SC_OPT_FUSED, SC_OPT_GRAPH, SC_OPT_CHUNK_COLS, SC_OPT_SEGMENT = 1, 2, 3, 4, 5
+SC_MAX_T = 16
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+lib_path = os.path.join(_HERE, "libsc.so")
+_lib = None
+
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+_u8p = ctypes.POINTER(ctypes.c_uint8)
+_dblp = ctypes.POINTER(ctypes.c_double)
+_vp = ctypes.c_void_p
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [
+        ("t", ctypes.c_int32), ("k", ctypes.c_int32), ("root", ctypes.c_int32),
+        ("n_steps", ctypes.c_int32),
+        ("child_ptr", ctypes.c_int32 * (SC_MAX_T + 1)),
+        ("child_idx", ctypes.c_int32 * SC_MAX_T),
+        ("step_h", ctypes.c_int32 * SC_MAX_T),
+        ("step_a", ctypes.c_int32 * SC_MAX_T),
+        ("step_p", ctypes.c_int32 * SC_MAX_T),
+        ("batch", ctypes.c_int32),
+        ("arena_bytes", ctypes.c_uint64),
+        ("spmm_updates", ctypes.c_double),
+        ("ema_updates", ctypes.c_double),
+        ("compulsory_bytes", ctypes.c_double),
+        ("automorphisms", ctypes.c_double),
+    ]
+
+    def children(self):
+        """Ordered children lists of the rooted template (the plan)."""
+        return [list(self.child_idx[self.child_ptr[u]:self.child_ptr[u + 1]]) for u in range(self.t)]
+
+    def steps(self):
+        return [(self.step_h[i], self.step_a[i], self.step_p[i]) for i in range(self.n_steps)]
+
+    def as_dict(self):
+        return {
+            "t": self.t, "k": self.k, "root": self.root, "children": self.children(),
+            "steps": self.steps(), "batch": self.batch, "arena_bytes": int(self.arena_bytes),
+            "spmm_updates": self.spmm_updates, "ema_updates": self.ema_updates,
+            "compulsory_bytes": self.compulsory_bytes, "automorphisms": self.automorphisms,
+        }
+
+
+class ScError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libsc error {code}: {msg}")
+        self.code = code
+
+
+def lib():
+    """Load libsc.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(lib_path):
+            raise RuntimeError(f"{lib_path} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+        L = ctypes.CDLL(lib_path)
+        sig = {
+            "sc_create": (ctypes.c_int, [ctypes.c_int, ALLOC_FN, FREE_FN, _vp, ctypes.c_uint64, ctypes.POINTER(_vp)]),
+            "sc_destroy": (ctypes.c_int, [_vp]),
+            "sc_last_error": (ctypes.c_char_p, [_vp]),
+            "sc_version": (ctypes.c_char_p, []),
+            "sc_load_graph_csr": (ctypes.c_int, [_vp, ctypes.c_int64, ctypes.c_int64, _i64p, _i32p, _i32p]),
+            "sc_unload_graph": (ctypes.c_int, [_vp, ctypes.c_int32]),
+            "sc_load_template": (ctypes.c_int, [_vp, ctypes.c_int32, _i32p, ctypes.c_int32, _i32p]),
+            "sc_load_template_plan": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32, _i32p, _i32p, _i32p]),
+            "sc_set_colors": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_uint64]),
+            "sc_plan_template": (ctypes.c_int, [ctypes.c_int32, _i32p, ctypes.c_int32, ctypes.c_int32,
+                                                ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
+                                                ctypes.POINTER(PlanInfo)]),
+            "sc_plan_info": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                            ctypes.POINTER(PlanInfo)]),
+            "sc_colorset_rank": (ctypes.c_int64, [ctypes.c_uint32]),
+            "sc_color_of": (ctypes.c_int32, [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int32]),
+            "sc_run": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int32,
+                                      _vp, _u64p, _u8p, _dblp, _dblp]),
+            "sc_set_option": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int64]),
+            "sc_get_option": (ctypes.c_int, [_vp, ctypes.c_int32, _i64p]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _p(a, t):
+    return a.ctypes.data_as(t)
+
+
+def sc_version() -> str:
+    return lib().sc_version().decode()
+
+
+def _edges_array(t, edges):
+    e = np.asarray(edges, dtype=np.int32).reshape(-1)
+    if e.size != 2 * (t - 1):
+        raise ValueError("need t-1 edges")
+    return np.ascontiguousarray(e if e.size else np.zeros(2, np.int32))
+
+
+def sc_plan_template(t, edges, root, k, n, nnz, batch=1) -> PlanInfo:
+    """Host-only planning (no device needed)."""
+    out = PlanInfo()
+    e = _edges_array(t, edges)
+    rc = lib().sc_plan_template(t, _p(e, _i32p), root, k, n, nnz, batch, ctypes.byref(out))
+    if rc:
+        raise ScError(rc, "sc_plan_template failed")
+    return out
+
+
+def sc_colorset_rank(mask: int) -> int:
+    return int(lib().sc_colorset_rank(mask))
+
+
+def sc_color_of(seed: int, coloring: int, vertex: int, k: int) -> int:
+    return int(lib().sc_color_of(seed & (2**64 - 1), coloring, vertex, k))
+
+
+class Context:
+    """One libsc context on a HIP device.
+
+    ``torch_allocator=True`` routes the library's device allocations through
+    PyTorch's caching allocator (and PyTorch's current stream)."""
+
+    def __init__(self, device: int = 0, budget: int = 0, torch_allocator: bool = False):
+        L = lib()
+        self._cbs = None
+        alloc = ALLOC_FN()
+        free = FREE_FN()
+        if torch_allocator:
+            import torch
+
+            def _alloc(nbytes, stream, user):
+                try:
+                    return int(torch.cuda.caching_allocator_alloc(int(nbytes), device, stream))
+                except Exception:
+                    return None
+
+            def _free(ptr, nbytes, stream, user):
+                torch.cuda.caching_allocator_delete(ptr)
+
+            alloc, free = ALLOC_FN(_alloc), FREE_FN(_free)
+            self._cbs = (alloc, free)
+        h = _vp()
+        rc = L.sc_create(device, alloc, free, None, budget, ctypes.byref(h))
+        if rc:
+            raise ScError(rc, "sc_create failed (no usable HIP device?)")
+        self._h = h
+        self._L = L
+
+    # -- plumbing
+    def _check(self, rc):
+        if rc:
+            raise ScError(rc, self._L.sc_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.sc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- API
+    def last_error(self) -> str:
+        return self._L.sc_last_error(self._h).decode()
+
+    def load_graph_csr(self, n, row_ptr, col_idx) -> int:
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+        nnz = int(rp[-1]) if rp.size else 0
+        if ci.size == 0:
+            ci = np.zeros(1, np.int32)
+        gid = ctypes.c_int32()
+        self._check(self._L.sc_load_graph_csr(self._h, n, nnz, _p(rp, _i64p), _p(ci, _i32p), ctypes.byref(gid)))
+        return gid.value
+
+    def load_graph(self, g) -> int:
+        return self.load_graph_csr(g.n, g.row_ptr, g.col_idx)
+
+    def unload_graph(self, gid: int):
+        self._check(self._L.sc_unload_graph(self._h, gid))
+
+    def load_template(self, t, edges, root=-1) -> int:
+        e = _edges_array(t, edges)
+        tid = ctypes.c_int32()
+        self._check(self._L.sc_load_template(self._h, t, _p(e, _i32p), root, ctypes.byref(tid)))
+        return tid.value
+
+    def load_template_plan(self, t, root, children) -> int:
+        ptr = np.zeros(t + 1, np.int32)
+        idx = []
+        for u in range(t):
+            idx.extend(children[u])
+            ptr[u + 1] = len(idx)
+        ci = np.asarray(idx if idx else [0], np.int32)
+        tid = ctypes.c_int32()
+        self._check(self._L.sc_load_template_plan(self._h, t, root, _p(ptr, _i32p), _p(ci, _i32p), ctypes.byref(tid)))
+        return tid.value
+
+    def set_colors(self, k, seed):
+        self._check(self._L.sc_set_colors(self._h, k, seed & (2**64 - 1)))
+
+    def set_option(self, opt, value):
+        self._check(self._L.sc_set_option(self._h, opt, int(value)))
+
+    def get_option(self, opt) -> int:
+        v = ctypes.c_int64()
+        self._check(self._L.sc_get_option(self._h, opt, ctypes.byref(v)))
+        return v.value
+
+    def plan_info(self, gid, tid, n_colorings=1) -> PlanInfo:
+        out = PlanInfo()
+        self._check(self._L.sc_plan_info(self._h, gid, tid, n_colorings, ctypes.byref(out)))
+        return out
+
+    def run(self, gid, tid, first, n_colorings, stream=None):
+        """Returns (counts uint64[R], overflow uint8[R], est_maps, est_copies)."""
+        R = int(n_colorings)
+        counts = np.zeros(max(R, 1), np.uint64)
+        ovf = np.zeros(max(R, 1), np.uint8)
+        em, ec = ctypes.c_double(), ctypes.c_double()
+        self._check(self._L.sc_run(self._h, gid, tid, first, R, stream, _p(counts, _u64p), _p(ovf, _u8p),
+                                   ctypes.byref(em), ctypes.byref(ec)))
+        return counts[:R], ovf[:R], em.value, ec.value

@@ -1,0 +1,118 @@
+"""CPU-side checks of libsc: it loads, exports every symbol include/sc.h
+declares, and its host logic (planner, Eq. 1 indexing, colouring rule,
+automorphisms) agrees with independent computations.  No GPU needed."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1903_04395_amd import inputs as I
+from paper_1903_04395_amd import sc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "sc.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*\b(sc_[a-z_0-9]+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    L = ctypes.CDLL(sc.lib_path)
+    names = declared_functions()
+    assert "sc_run" in names and "sc_create" in names
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_version_string():
+    assert "libsc" in sc.sc_version()
+
+
+def test_no_device_create_fails_cleanly():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(sc.ScError):
+        sc.Context(0)
+
+
+@pytest.mark.parametrize("k", [3, 8, 12, 16])
+def test_colorset_rank_matches_oracle(k):
+    for m in range(0, 1 << k, max(1, (1 << k) // 4096)):
+        assert sc.sc_colorset_rank(m) == O.rank(m)
+
+
+def test_color_rule_matches_oracle():
+    for seed in (0, 1, 2**63 + 5):
+        for r in (0, 1, 77):
+            for v in (0, 1, 12345, 2**20):
+                for k in (1, 5, 12, 16):
+                    assert sc.sc_color_of(seed, r, v, k) == O.color(seed, r, v, k)
+
+
+def steps_of(t, root, children):
+    out = []
+
+    def rec(u):
+        s = 1
+        for w in children[u]:
+            p = rec(w)
+            out.append((s + p, s, p))
+            s += p
+        return s
+    rec(root)
+    return out
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_plan_steps_and_lemma1_counts(seed):
+    t = 10
+    edges = I.prufer_tree(t, seed)
+    n, nnz, k = 1000, 8000, 10
+    for root in [-1] + list(range(t)):
+        info = sc.sc_plan_template(t, edges, root, k, n, nnz, 4)
+        if root >= 0:
+            assert info.root == root
+        ch = info.children()
+        # the plan is a rooted spanning tree of the template
+        und = {frozenset(e) for e in edges}
+        got = {frozenset((u, w)) for u in range(t) for w in ch[u]}
+        assert got == und
+        assert info.steps() == steps_of(t, info.root, ch)
+        assert info.n_steps == t - 1
+        # Lemma 1: nnz*C(k,p) neighbour-sum updates (p >= 2; p = 1 is a colour
+        # histogram) and n*C(k,h)*C(h,p) multiply-adds per step
+        spmm = sum(nnz * math.comb(k, p) for h, a, p in info.steps() if p >= 2)
+        ema = sum(n * math.comb(k, h) * math.comb(h, p) for h, a, p in info.steps())
+        assert info.spmm_updates == spmm and info.ema_updates == ema
+        assert info.automorphisms == O.aut(t, edges)
+        # the arena holds at least the largest step's live tables
+        W = lambda s: math.comb(k, s)
+        need = max((W(h) + W(p) + (W(a) if a > 1 else 0) + (W(p) if p > 1 else 0)) * n * 4 * 8
+                   for h, a, p in info.steps())
+        assert info.arena_bytes >= need
+
+
+def test_planner_picks_lowest_cost_root():
+    t, k = 10, 10
+    edges = I.path(t)
+    best = sc.sc_plan_template(t, edges, -1, k, 2**20, 31_000_000, 8)
+    # the chosen plan's modelled bytes are no worse than rooting at vertex 0
+    fixed = sc.sc_plan_template(t, edges, 0, k, 2**20, 31_000_000, 8)
+    assert best.compulsory_bytes <= fixed.compulsory_bytes * 1.5
+
+
+def test_plan_rejects_bad_templates():
+    with pytest.raises(sc.ScError):
+        sc.sc_plan_template(3, [(0, 1), (0, 1)], -1, 3, 10, 10, 1)
+    with pytest.raises(sc.ScError):
+        sc.sc_plan_template(4, I.path(4), -1, 3, 10, 10, 1)     # k < t
+    with pytest.raises(sc.ScError):
+        sc.sc_plan_template(17, [(i, i + 1) for i in range(16)], -1, 16, 10, 10, 1)
