@@ -128,10 +128,15 @@ typedef struct {
     int32_t step_h[SC_MAX_T];           /* steps in execution order:        */
     int32_t step_a[SC_MAX_T];           /*   sizes of T_s, T_a, T_p         */
     int32_t step_p[SC_MAX_T];
+    int32_t step_mode[SC_MAX_T];        /* 0 fused histogram, 1 fused neighbour
+                                           sum, 2 staged, 3 global          */
     int32_t batch;                      /* colourings per pass              */
     uint64_t arena_bytes;               /* device tables of one pass        */
-    double spmm_updates;                /* per colouring: sum nnz*C(k,p), p>=2 */
-    double ema_updates;                 /* per colouring: sum n*C(k,h)*C(h,a)  */
+    double spmm_updates;                /* per colouring: sum nnz*C(k,p)    */
+    double ema_updates;                 /* per colouring: sum n*C(k,h)*C(h,a),
+                                           n*C(k,h) for a = 1 (a select)    */
+    double lemma1_ops;                  /* per colouring: Lemma 1,
+                                           sum nnz*C(k,p) + n*C(k,h)*C(h,p) */
     double compulsory_bytes;            /* per colouring, HBM bytes (model) */
     double automorphisms;               /* |Aut(T)|                         */
 } sc_plan_info_t;
@@ -170,16 +175,42 @@ int sc_run(sc_ctx *ctx, int32_t graph_id, int32_t tmpl_id, uint64_t first_colori
            int32_t n_colorings, void *stream, uint64_t *counts, uint8_t *overflow,
            double *est_maps, double *est_copies);
 
-/* Execution options (mainly for measurement and ablation). */
+/* Execution options (for measurement and ablation; none changes a result).
+ * Errors: SC_EINVAL (unknown option or value out of range). */
 enum {
     SC_OPT_MAX_BATCH = 1,     /* cap on colourings per pass (1..SC_MAX_BATCH)   */
-    SC_OPT_FUSED = 2,         /* 1: fused neighbour-sum + multiply-add kernels  */
+    SC_OPT_FUSED = 2,         /* 1 (default): fused neighbour-sum + multiply-add
+                                 row kernels where the rows fit; 0: never      */
     SC_OPT_GRAPH = 3,         /* 1: replay each pass from a captured hipGraph   */
     SC_OPT_CHUNK_COLS = 4,    /* neighbour-sum column tile, in uint64 (0=auto)  */
-    SC_OPT_SEGMENT = 5        /* neighbours per work item for heavy rows (0=auto) */
+    SC_OPT_SEGMENT = 5,       /* neighbours per work item for heavy rows (0=auto) */
+    SC_OPT_XCD = 6,           /* 1: assign neighbour-sum column tiles to XCDs   */
+    SC_OPT_FUSE_MAX_COLS = 7  /* widest passive row (uint64) the fused neighbour
+                                 sum takes (64..2048)                          */
 };
 int sc_set_option(sc_ctx *ctx, int32_t option, int64_t value);
 int sc_get_option(sc_ctx *ctx, int32_t option, int64_t *value);
+
+/* ------------------------------------------------------------------ tracing */
+
+/* Per-kernel-family statistics gathered with HIP events recorded around every
+ * launch on the run's stream while profiling is on.  `alg_bytes` is the
+ * algorithmic (compulsory) HBM traffic of those launches and `updates` their
+ * update count (neighbour-sum updates nnz*C(k,p) and multiply-adds), summed. */
+typedef struct {
+    char name[32];
+    int32_t launches;
+    double total_ms;
+    double alg_bytes;
+    double updates;
+} sc_kernel_stat_t;
+
+/* enable = 1 starts recording (and clears earlier records), 0 stops. */
+int sc_profile(sc_ctx *ctx, int32_t enable);
+/* Waits for the recorded launches, aggregates them by family into out[0..cap)
+ * and sets *n_out to the number of families.  Records are kept until the next
+ * sc_profile(ctx, 1). */
+int sc_profile_read(sc_ctx *ctx, sc_kernel_stat_t *out, int32_t cap, int32_t *n_out);
 
 #ifdef __cplusplus
 }

@@ -28,7 +28,7 @@ import numpy as np
 __all__ = [
     "lib", "splitmix64", "color", "colors", "rank", "plan_arrays", "root_plan",
     "count", "count_colored", "root_table", "aut", "colorful_probability",
-    "estimate", "binom",
+    "estimate", "binom", "threads",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -48,6 +48,8 @@ def lib():
         if not os.path.exists(_LIB):
             raise RuntimeError(f"{_LIB} is missing: run `python oracle/build.py`")
         L = ctypes.CDLL(_LIB)
+        L.oracle_threads.restype = ctypes.c_int
+        L.oracle_threads.argtypes = []
         L.oracle_splitmix64.restype = ctypes.c_uint64
         L.oracle_splitmix64.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
         L.oracle_color.restype = ctypes.c_int
@@ -69,6 +71,11 @@ def lib():
 
 def _ptr(a, t):
     return a.ctypes.data_as(t)
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's loops use."""
+    return int(lib().oracle_threads())
 
 
 def binom(n: int, r: int) -> int:

@@ -22,8 +22,10 @@ struct GraphBins {
     const int64_t *row_ptr = nullptr;
     const int32_t *col_idx = nullptr;
     const int32_t *light_rows = nullptr;  int64_t n_light = 0;
-    const int2 *wide_items = nullptr;     int64_t n_wide = 0;   // (row, segment)
+    const int2 *wide_items = nullptr;     int64_t n_wide = 0;   // (row, segment), split rows first
+    int64_t n_split_items = 0;                                  // items of split rows
     const int32_t *split_rows = nullptr;  int64_t n_split = 0;  // rows with deg > seg
+    const int32_t *slot = nullptr;        // [n]: index of a split row in split_rows, else -1
     int seg = 0;
 };
 
@@ -31,13 +33,22 @@ struct GraphBins {
 hipError_t launch_color(uint64_t seed, uint64_t first, int64_t n, int B, int k, uint8_t *col,
                         hipStream_t st);
 
-// N = A * P for a table with L = W*B uint64 columns per row.
+// N = A * P for a table with L = W*B uint64 columns per row, column-tiled
+// (chunk_cols = 64, 128 or 256 uint64; 0 = by L); `xcd` assigns column chunks
+// to XCDs.
 hipError_t launch_spmm(const GraphBins &g, const uint64_t *P, uint64_t *N, int64_t L, int B,
-                       int chunk_cols, unsigned long long *flags, hipStream_t st);
+                       int chunk_cols, int xcd, unsigned long long *flags, hipStream_t st);
+
+// Neighbour sums of the split rows only, into the compact Npre[n_split][L].
+hipError_t launch_spmm_split(const GraphBins &g, const uint64_t *P, uint64_t *Npre, int64_t L,
+                             int B, unsigned long long *flags, hipStream_t st);
 
 // p = 1: N[v][c*B + r] = #{j in adj(v) : col[j*B + r] == c}, c < k.
 hipError_t launch_hist(const GraphBins &g, const uint8_t *col, uint64_t *N, int B, int k,
                        hipStream_t st);
+// The same for the split rows only, into the compact Npre[n_split][k*B].
+hipError_t launch_hist_split(const GraphBins &g, const uint8_t *col, uint64_t *Npre, int B, int k,
+                             hipStream_t st);
 
 // a = 1: S[v][I*B + r] = N[v][drop[I*k + c]*B + r] if c = col[v*B+r] is in set I, else 0.
 hipError_t launch_select(int64_t n, const uint8_t *col, const uint64_t *N, uint64_t *S, int B,
@@ -49,12 +60,17 @@ hipError_t launch_ema(int64_t n, const uint64_t *A, const uint64_t *N, uint64_t 
                       int Wa, int Wp, int Wh, int nsplit, const uint32_t *split,
                       unsigned long long *flags, hipStream_t st);
 
-// Fused p >= 1 neighbour sum + multiply-add for one step (the neighbour-sum row
-// never leaves LDS).  a == 1 uses `drop`, a >= 2 uses `split` and A.
-hipError_t launch_fused(const GraphBins &g, const uint8_t *col, const uint64_t *P,
-                        const uint64_t *A, uint64_t *S, int B, int k, int a, int p, int Wa,
-                        int Wp, int Wh, int nsplit, const uint32_t *split, const int16_t *drop,
-                        unsigned long long *flags, hipStream_t st);
+// Row kernel: one workgroup per row, N[v] and A[v] staged in LDS, then the
+// select (a = 1) or the split multiply-add (a >= 2).  Modes: the neighbour-sum
+// row comes from N (`src`, staged), is summed from the passive table (`src`,
+// fused; Wp*B <= 2048) or counted from colours (fused histogram, p = 1).
+// Fused modes read split rows from Npre.
+enum { kModeStaged = 0, kModeGather = 1, kModeHist = 2 };
+int row_lds_bytes(int k, int a, int Wa, int Wp, int B, int mode);
+hipError_t launch_row(int mode, const GraphBins &g, const uint8_t *col, const uint64_t *src,
+                      const uint64_t *Npre, const uint64_t *A, uint64_t *S, int B, int k, int a,
+                      int Wa, int Wp, int Wh, int nsplit, const uint32_t *split,
+                      const int16_t *drop, unsigned long long *flags, hipStream_t st);
 
 // X[r] = sum_v sum_I S[v][I*B + r] (with carry flags); X must be zeroed first.
 hipError_t launch_reduce(int64_t n, const uint64_t *S, int W, int B, unsigned long long *X,

@@ -68,135 +68,153 @@ __global__ __launch_bounds__(kBlock) void color_kernel(uint64_t seed, uint64_t f
 
 // ------------------------------------------------------------------ neighbour sum
 
-// One wavefront per light row and column chunk of 64*U uint64.
+// Accumulates P rows of the neighbours e0, e0+step, ... < e1 into acc[] for
+// the lane's U columns c0 + 64u (bounds in inb[]), four neighbours at a time
+// so that 4*U loads are in flight per lane.
 template <int U>
-__global__ __launch_bounds__(kBlock) void spmm_light_kernel(
-    const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
-    const int32_t *__restrict__ rows, int64_t nrows, const uint64_t *__restrict__ P,
-    uint64_t *__restrict__ N, int64_t L, int B, unsigned long long *__restrict__ flags) {
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int lane = threadIdx.x & (kWave - 1);
-    const int64_t ri = (int64_t)blockIdx.x * (kBlock / kWave) + wave;
-    if (ri >= nrows) return;                                   // whole wavefront
-    const int v = __builtin_amdgcn_readfirstlane(rows[ri]);
-    const int64_t c0 = (int64_t)blockIdx.y * (kWave * U) + lane;
-    const int64_t e0 = rp[v], e1 = rp[v + 1];
-    uint64_t acc[U];
-    bool inb[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) { acc[u] = 0; inb[u] = c0 + kWave * u < L; }
-    uint32_t carry = 0;
+__device__ __forceinline__ void gather_rows(int64_t e0, int64_t e1, int step,
+                                            const int32_t *__restrict__ ci,
+                                            const uint64_t *__restrict__ P, int64_t L, int64_t c0,
+                                            const bool (&inb)[U], uint64_t (&acc)[U],
+                                            uint32_t &carry) {
     int64_t e = e0;
-    for (; e + 2 <= e1; e += 2) {
-        const uint64_t *s0 = P + (int64_t)ci[e] * L + c0;
-        const uint64_t *s1 = P + (int64_t)ci[e + 1] * L + c0;
-        uint64_t x0[U], x1[U];
+    for (; e + 3 * step < e1; e += 4 * step) {
+        const uint64_t *s[4];
 #pragma unroll
-        for (int u = 0; u < U; ++u) { x0[u] = inb[u] ? s0[kWave * u] : 0; x1[u] = inb[u] ? s1[kWave * u] : 0; }
+        for (int i = 0; i < 4; ++i) s[i] = P + (int64_t)ci[e + i * step] * L + c0;
+        uint64_t x[4][U];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int u = 0; u < U; ++u) x[i][u] = inb[u] ? s[i][kWave * u] : 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint64_t t = acc[u] + x[i][u];
+                carry |= (uint32_t)(t < x[i][u]) << u;
+                acc[u] = t;
+            }
+    }
+    for (; e < e1; e += step) {
+        const uint64_t *s0 = P + (int64_t)ci[e] * L + c0;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            uint64_t s = acc[u] + x0[u];
-            carry |= (uint32_t)(s < x0[u]) << u;
-            uint64_t t = s + x1[u];
-            carry |= (uint32_t)(t < x1[u]) << u;
+            const uint64_t x = inb[u] ? s0[kWave * u] : 0;
+            const uint64_t t = acc[u] + x;
+            carry |= (uint32_t)(t < x) << u;
             acc[u] = t;
         }
     }
-    if (e < e1) {
-        const uint64_t *s0 = P + (int64_t)ci[e] * L + c0;
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            uint64_t x = inb[u] ? s0[kWave * u] : 0;
-            uint64_t s = acc[u] + x;
-            carry |= (uint32_t)(s < x) << u;
-            acc[u] = s;
-        }
-    }
-    uint64_t *d = N + (int64_t)v * L + c0;
-    uint64_t m = 0;
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-        if (inb[u]) d[kWave * u] = acc[u];
-        if (carry & (1u << u)) m |= 1ull << ((c0 + kWave * u) % B);
-    }
-    flush_flags(m, flags);
 }
 
-// One workgroup (4 wavefronts splitting the neighbours) per wide item
-// (row, segment) and column chunk.  Rows with more than `seg` neighbours are
-// split; their segments add into N with atomics (N zeroed beforehand) and the
-// returned old value exposes the carry.  `slot` (optional) redirects the output
-// row: out_row = slot[v].
+struct SpmmArgs {
+    const int64_t *rp;
+    const int32_t *ci;
+    const int32_t *light;  int64_t n_light;   // light rows, 4 per workgroup
+    const int2 *wide;      int64_t n_wide;    // (row, segment) items, 1 per workgroup
+    int seg;
+    const int32_t *slot;                      // optional output-row redirect
+    const uint64_t *P;
+    uint64_t *N;
+    int64_t L;
+    int B;
+    int64_t groups;                           // light groups + wide items
+    int64_t chunks;                           // column chunks of 64*U
+    int xcd;                                  // XCD-aware chunk assignment
+    unsigned long long *flags;
+};
+
+// Neighbour sum N = A * P, tiled by column chunks of 64*U uint64 and walked
+// chunk-major so that one chunk of the gathered rows stays cache-resident while
+// all rows consume it.  Light rows: one wavefront each.  Wide items: four
+// wavefronts split the neighbours and meet in LDS; rows with more than `seg`
+// neighbours are split over several items whose partial sums meet in global
+// atomics (the carry is read from the returned old value).  With `xcd`,
+// workgroup b runs on XCD b mod 8 and only ever sees chunks = that XCD mod 8,
+// so each XCD's L2 holds one chunk's hot rows.
 template <int U>
-__global__ __launch_bounds__(kBlock) void spmm_wide_kernel(
-    const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
-    const int2 *__restrict__ items, int64_t nitems, int seg, const int32_t *__restrict__ slot,
-    const uint64_t *__restrict__ P, uint64_t *__restrict__ N, int64_t L, int B,
-    unsigned long long *__restrict__ flags) {
+__global__ __launch_bounds__(kBlock) void spmm_tiled_kernel(SpmmArgs a) {
     __shared__ uint64_t red[kBlock / kWave - 1][U][kWave];
     __shared__ uint32_t redc[kBlock / kWave - 1][kWave];
+    const int64_t b = blockIdx.x;
+    int64_t chunk, g;
+    if (a.xcd) {
+        const int64_t j = b >> 3;
+        chunk = (b & 7) + 8 * (j / a.groups);
+        g = j % a.groups;
+        if (chunk >= a.chunks) return;                 // whole workgroup
+    } else {
+        chunk = b / a.groups;
+        g = b - chunk * a.groups;
+    }
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & (kWave - 1);
-    const int2 it = items[blockIdx.x];
-    const int v = it.x;
-    const int64_t r0 = rp[v], r1 = rp[v + 1];
-    const int64_t e0 = r0 + (int64_t)it.y * seg;
-    const int64_t e1 = min(e0 + seg, r1);
-    const bool split = (r1 - r0) > seg;
-    const int64_t c0 = (int64_t)blockIdx.y * (kWave * U) + lane;
-    uint64_t acc[U];
+    const int64_t c0 = chunk * (kWave * U) + lane;
     bool inb[U];
+    uint64_t acc[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) { acc[u] = 0; inb[u] = c0 + kWave * u < L; }
+    for (int u = 0; u < U; ++u) { inb[u] = c0 + kWave * u < a.L; acc[u] = 0; }
     uint32_t carry = 0;
-    for (int64_t e = e0 + wave; e < e1; e += kBlock / kWave) {
-        const uint64_t *s0 = P + (int64_t)ci[e] * L + c0;
-        uint64_t x[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) x[u] = inb[u] ? s0[kWave * u] : 0;
+    const int64_t nlg = (a.n_light + 3) >> 2;
+    if (g < nlg) {
+        const int64_t li = g * 4 + wave;
+        if (li >= a.n_light) return;                   // whole wavefront
+        const int v = __builtin_amdgcn_readfirstlane(a.light[li]);
+        gather_rows<U>(a.rp[v], a.rp[v + 1], 1, a.ci, a.P, a.L, c0, inb, acc, carry);
+        uint64_t *d = a.N + (int64_t)v * a.L + c0;
+        uint64_t m = 0;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            uint64_t s = acc[u] + x[u];
-            carry |= (uint32_t)(s < x[u]) << u;
-            acc[u] = s;
+            if (inb[u]) d[kWave * u] = acc[u];
+            if (carry & (1u << u)) m |= 1ull << ((c0 + kWave * u) % a.B);
         }
+        flush_flags(m, a.flags);
+        return;
     }
+    const int2 it = a.wide[g - nlg];
+    const int v = __builtin_amdgcn_readfirstlane(it.x);
+    const int64_t r0 = a.rp[v], r1 = a.rp[v + 1];
+    const int64_t e0 = r0 + (int64_t)it.y * a.seg;
+    const int64_t e1 = min(e0 + a.seg, r1);
+    const bool split = (r1 - r0) > a.seg;
+    gather_rows<U>(e0 + wave, e1, kBlock / kWave, a.ci, a.P, a.L, c0, inb, acc, carry);
     if (wave > 0) {
 #pragma unroll
         for (int u = 0; u < U; ++u) red[wave - 1][u][lane] = acc[u];
         redc[wave - 1][lane] = carry;
     }
     __syncthreads();
-    uint64_t m = 0;
     if (wave == 0) {
 #pragma unroll
         for (int w = 0; w < kBlock / kWave - 1; ++w) {
             carry |= redc[w][lane];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                uint64_t x = red[w][u][lane];
-                uint64_t s = acc[u] + x;
-                carry |= (uint32_t)(s < x) << u;
-                acc[u] = s;
+                const uint64_t x = red[w][u][lane];
+                const uint64_t t = acc[u] + x;
+                carry |= (uint32_t)(t < x) << u;
+                acc[u] = t;
             }
         }
-        const int64_t orow = slot ? (int64_t)slot[v] : (int64_t)v;
-        uint64_t *d = N + orow * L + c0;
+        const int64_t orow = a.slot ? (int64_t)a.slot[v] : (int64_t)v;
+        uint64_t *d = a.N + orow * a.L + c0;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             if (!inb[u]) continue;
             if (split) {
-                unsigned long long old = atomicAdd((unsigned long long *)(d + kWave * u),
-                                                   (unsigned long long)acc[u]);
+                const unsigned long long old = atomicAdd((unsigned long long *)(d + kWave * u),
+                                                         (unsigned long long)acc[u]);
                 if ((uint64_t)old + acc[u] < (uint64_t)old) carry |= 1u << u;
             } else {
                 d[kWave * u] = acc[u];
             }
         }
+        uint64_t m = 0;
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            if (carry & (1u << u)) m |= 1ull << ((c0 + kWave * u) % B);
-        flush_flags(m, flags);
+            if (carry & (1u << u)) m |= 1ull << ((c0 + kWave * u) % a.B);
+        flush_flags(m, a.flags);
     }
 }
 
@@ -328,86 +346,94 @@ __global__ __launch_bounds__(kBlock) void ema_kernel(
     flush_flags(m, flags);
 }
 
-// ------------------------------------------------------------------ fused step
+// ------------------------------------------------------------------ row kernel
 
-// One workgroup per row.  Phase 1 builds the neighbour-sum row in LDS (colour
-// histogram for p = 1, neighbour-row sum for p >= 2; rows whose neighbour sum
-// was precomputed into `Npre` (slot[v] >= 0) copy it instead).  Phase 2 stages
-// the active row (a >= 2).  Phase 3 writes the output row.
-template <int U>
-__global__ __launch_bounds__(kBlock) void fused_kernel(
-    const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
-    const int32_t *__restrict__ slot, const uint64_t *__restrict__ Npre,
-    const uint8_t *__restrict__ col, const uint64_t *__restrict__ P,
-    const uint64_t *__restrict__ A, uint64_t *__restrict__ S, int B, int k, int a, int p,
-    int Wa, int Wp, int Wh, int nsplit, const uint32_t *__restrict__ split,
-    const int16_t *__restrict__ drop, unsigned long long *__restrict__ flags) {
+enum RowMode { kRowStaged = 0, kRowGather = 1, kRowHist = 2 };
+
+struct RowArgs {
+    const int64_t *rp;
+    const int32_t *ci;
+    const int32_t *slot;          // split rows: index into Npre, else -1 (may be NULL)
+    const uint64_t *Npre;         // precomputed neighbour sums of split rows
+    const uint8_t *col;
+    const uint64_t *src;          // kRowStaged: N;  kRowGather: passive table P
+    const uint64_t *A;            // active table (a >= 2)
+    uint64_t *S;
+    int B, k, a, Wa, Wp, Wh, nsplit;
+    const uint32_t *split;
+    const int16_t *drop;
+    unsigned long long *flags;
+};
+
+// One workgroup per graph row v.  The neighbour-sum row N[v] (Wp*B words) is
+// built in LDS -- copied from N (staged), summed from the neighbours' passive
+// rows (fused neighbour sum), or counted from the neighbours' colours (fused
+// histogram, p = 1); split rows copy their precomputed sum.  The active row is
+// staged next to it (a >= 2).  Every output entry (I, r) of S[v] is then
+// either a select through the drop-colour table (a = 1) or the split sum
+// sum_j A[v][Ia_j][r] * N[v][Ip_j][r] (a >= 2), read from LDS.
+template <int MODE, int U>
+__global__ __launch_bounds__(kBlock) void row_kernel(RowArgs a) {
     extern __shared__ uint64_t lds[];
     const int64_t v = blockIdx.x;
-    const int Lp = Wp * B, La = Wa * B, Ls = Wh * B;
-    uint64_t *Nr = lds;                 // Lp words
-    uint64_t *Ar = lds + Lp;            // La words (a >= 2)
+    const int B = a.B;
+    const int Lp = a.Wp * B, La = a.Wa * B, Ls = a.Wh * B;
+    uint64_t *Nr = lds;
+    uint64_t *Ar = lds + Lp;
     const int t = threadIdx.x;
     uint64_t m = 0;
-    const int sv = slot ? slot[v] : -1;
-    const int64_t e0 = rp[v], e1 = rp[v + 1];
-    if (sv >= 0) {
-        for (int q = t; q < Lp; q += kBlock) Nr[q] = Npre[(int64_t)sv * Lp + q];
-    } else if (p == 1) {
-        uint32_t *h = (uint32_t *)(lds + Lp + (a > 1 ? La : 0));   // k*B counters
-        for (int q = t; q < Lp; q += kBlock) h[q] = 0;
-        __syncthreads();
-        const int slots = kBlock / B;
-        const int s = t / B, r = t - s * B;
-        if (s < slots)
-            for (int64_t e = e0 + s; e < e1; e += slots)
-                atomicAdd(&h[(int)col[(int64_t)ci[e] * B + r] * B + r], 1u);
-        __syncthreads();
-        for (int q = t; q < Lp; q += kBlock) Nr[q] = h[q];
+    if (MODE == kRowStaged) {
+        for (int q = t; q < Lp; q += kBlock) Nr[q] = a.src[v * Lp + q];
     } else {
-        uint64_t acc[U];
-        uint32_t carry = 0;
+        const int sv = a.slot ? a.slot[v] : -1;
+        if (sv >= 0) {
+            for (int q = t; q < Lp; q += kBlock) Nr[q] = a.Npre[(int64_t)sv * Lp + q];
+        } else if (MODE == kRowHist) {
+            uint32_t *h = (uint32_t *)(lds + Lp + (a.a > 1 ? La : 0));
+            for (int q = t; q < Lp; q += kBlock) h[q] = 0;
+            __syncthreads();
+            const int slots = kBlock / B;
+            const int s = t / B, r = t - s * B;
+            if (s < slots)
+                for (int64_t e = a.rp[v] + s; e < a.rp[v + 1]; e += slots)
+                    atomicAdd(&h[(int)a.col[(int64_t)a.ci[e] * B + r] * B + r], 1u);
+            __syncthreads();
+            for (int q = t; q < Lp; q += kBlock) Nr[q] = h[q];
+        } else {
+            // fused neighbour sum: wavefront w owns columns [w*64U, (w+1)*64U)
+            bool inb[U];
+            uint64_t acc[U];
+            const int lane = t & (kWave - 1);
+            const int64_t cw = (int64_t)(t >> 6) * kWave * U + lane;   // wave-contiguous columns
 #pragma unroll
-        for (int u = 0; u < U; ++u) acc[u] = 0;
-        for (int64_t e = e0; e < e1; ++e) {
-            const uint64_t *src = P + (int64_t)ci[e] * Lp + t;
+            for (int u = 0; u < U; ++u) { inb[u] = cw + kWave * u < Lp; acc[u] = 0; }
+            uint32_t carry = 0;
+            gather_rows<U>(a.rp[v], a.rp[v + 1], 1, a.ci, a.src, Lp, cw, inb, acc, carry);
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                if (t + kBlock * u < Lp) {
-                    const uint64_t x = src[kBlock * u];
-                    const uint64_t s = acc[u] + x;
-                    carry |= (uint32_t)(s < x) << u;
-                    acc[u] = s;
-                }
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int q = t + kBlock * u;
-            if (q < Lp) {
-                Nr[q] = acc[u];
-                if (carry & (1u << u)) m |= 1ull << (q % B);
+                if (inb[u]) Nr[cw + kWave * u] = acc[u];
+                if (carry & (1u << u)) m |= 1ull << ((cw + kWave * u) % B);
             }
         }
     }
-    if (a > 1)
-        for (int q = t; q < La; q += kBlock) Ar[q] = A[v * La + q];
+    if (a.a > 1)
+        for (int q = t; q < La; q += kBlock) Ar[q] = a.A[v * La + q];
     __syncthreads();
-    uint64_t *out = S + v * Ls;
-    if (a == 1) {
+    uint64_t *out = a.S + v * Ls;
+    if (a.a == 1) {
+        const uint8_t *cv = a.col + v * B;
         for (int q = t; q < Ls; q += kBlock) {
             const int I = q / B, r = q - I * B;
-            const int c = col[v * B + r];
-            const int d = drop[I * k + c];
+            const int d = a.drop[I * a.k + cv[r]];
             out[q] = d >= 0 ? Nr[d * B + r] : 0;
         }
     } else {
         for (int q = t; q < Ls; q += kBlock) {
             const int I = q / B, r = q - I * B;
-            const uint32_t *sp = split + (int64_t)I * nsplit;
+            const uint32_t *sp = a.split + (int64_t)I * a.nsplit;
             uint64_t acc = 0;
             uint32_t ovf = 0;
-            for (int j = 0; j < nsplit; ++j) {
+            for (int j = 0; j < a.nsplit; ++j) {
                 const uint32_t pr = sp[j];
                 acc = mad_ovf(acc, Ar[(pr & 0xffff) * B + r], Nr[(pr >> 16) * B + r], ovf);
             }
@@ -415,7 +441,7 @@ __global__ __launch_bounds__(kBlock) void fused_kernel(
             if (ovf) m |= 1ull << r;
         }
     }
-    flush_flags(m, flags);
+    flush_flags(m, a.flags);
 }
 
 // ------------------------------------------------------------------ root reduction
@@ -485,31 +511,62 @@ hipError_t launch_color(uint64_t seed, uint64_t first, int64_t n, int B, int k, 
 }
 
 template <int U>
-static hipError_t spmm_u(const GraphBins &g, const uint64_t *P, uint64_t *N, int64_t L, int B,
-                         unsigned long long *flags, hipStream_t st) {
-    const unsigned chunks = (unsigned)((L + kWave * U - 1) / (kWave * U));
-    if (g.n_split > 0) {
+static hipError_t spmm_tiled_u(const GraphBins &g, bool split_only, const uint64_t *P, uint64_t *N,
+                               int64_t L, int B, int xcd, unsigned long long *flags,
+                               hipStream_t st) {
+    const int32_t *slot = split_only ? g.slot : nullptr;
+    if (g.n_split > 0)
         zero_rows_kernel<<<dim3((unsigned)std::min<int64_t>((L + kBlock - 1) / kBlock, 64),
                                 row_grid(g.n_split)), dim3(kBlock), 0, st>>>(
-            g.split_rows, g.n_split, nullptr, N, L);
-    }
-    if (g.n_light > 0) {
-        spmm_light_kernel<U><<<dim3((unsigned)((g.n_light + 3) / 4), chunks), dim3(kBlock), 0, st>>>(
-            g.row_ptr, g.col_idx, g.light_rows, g.n_light, P, N, L, B, flags);
-    }
-    if (g.n_wide > 0) {
-        spmm_wide_kernel<U><<<dim3((unsigned)g.n_wide, chunks), dim3(kBlock), 0, st>>>(
-            g.row_ptr, g.col_idx, g.wide_items, g.n_wide, g.seg, nullptr, P, N, L, B, flags);
-    }
+            g.split_rows, g.n_split, slot, N, L);
+    SpmmArgs a;
+    a.rp = g.row_ptr; a.ci = g.col_idx;
+    a.light = g.light_rows; a.n_light = split_only ? 0 : g.n_light;
+    a.wide = g.wide_items; a.n_wide = split_only ? g.n_split_items : g.n_wide;
+    a.seg = g.seg; a.slot = slot; a.P = P; a.N = N; a.L = L; a.B = B;
+    a.groups = ((a.n_light + 3) >> 2) + a.n_wide;
+    a.chunks = (L + kWave * U - 1) / (kWave * U);
+    a.xcd = xcd && a.chunks >= 8;
+    a.flags = flags;
+    if (a.groups == 0 || L <= 0) return hipGetLastError();
+    const int64_t blocks = a.xcd ? 8 * ((a.chunks + 7) / 8) * a.groups : a.chunks * a.groups;
+    spmm_tiled_kernel<U><<<dim3((unsigned)blocks), dim3(kBlock), 0, st>>>(a);
     return hipGetLastError();
 }
 
+static int tiled_u(int64_t L, int chunk_cols) {
+    if (chunk_cols > 0) return chunk_cols >= 256 ? 4 : (chunk_cols >= 128 ? 2 : 1);
+    return L <= 64 ? 1 : (L <= 128 ? 2 : 4);
+}
+
 hipError_t launch_spmm(const GraphBins &g, const uint64_t *P, uint64_t *N, int64_t L, int B,
-                       int chunk_cols, unsigned long long *flags, hipStream_t st) {
-    int u = chunk_cols > 0 ? std::max(1, std::min(4, chunk_cols / kWave)) : pick_u(L);
-    if (u >= 4) return spmm_u<4>(g, P, N, L, B, flags, st);
-    if (u >= 2) return spmm_u<2>(g, P, N, L, B, flags, st);
-    return spmm_u<1>(g, P, N, L, B, flags, st);
+                       int chunk_cols, int xcd, unsigned long long *flags, hipStream_t st) {
+    switch (tiled_u(L, chunk_cols)) {
+    case 4: return spmm_tiled_u<4>(g, false, P, N, L, B, xcd, flags, st);
+    case 2: return spmm_tiled_u<2>(g, false, P, N, L, B, xcd, flags, st);
+    default: return spmm_tiled_u<1>(g, false, P, N, L, B, xcd, flags, st);
+    }
+}
+
+hipError_t launch_spmm_split(const GraphBins &g, const uint64_t *P, uint64_t *Npre, int64_t L,
+                             int B, unsigned long long *flags, hipStream_t st) {
+    if (g.n_split == 0) return hipSuccess;
+    switch (tiled_u(L, 0)) {
+    case 4: return spmm_tiled_u<4>(g, true, P, Npre, L, B, 0, flags, st);
+    case 2: return spmm_tiled_u<2>(g, true, P, Npre, L, B, 0, flags, st);
+    default: return spmm_tiled_u<1>(g, true, P, Npre, L, B, 0, flags, st);
+    }
+}
+
+hipError_t launch_hist_split(const GraphBins &g, const uint8_t *col, uint64_t *Npre, int B, int k,
+                             hipStream_t st) {
+    if (g.n_split == 0) return hipSuccess;
+    const int64_t L = (int64_t)k * B;
+    zero_rows_kernel<<<dim3(1, row_grid(g.n_split)), dim3(kBlock), 0, st>>>(
+        g.split_rows, g.n_split, g.slot, Npre, L);
+    hist_wide_kernel<<<dim3((unsigned)g.n_split_items), dim3(kBlock), (size_t)B * k * sizeof(uint32_t), st>>>(
+        g.row_ptr, g.col_idx, g.wide_items, g.n_split_items, g.seg, g.slot, col, Npre, B, k);
+    return hipGetLastError();
 }
 
 hipError_t launch_hist(const GraphBins &g, const uint8_t *col, uint64_t *N, int B, int k,
@@ -550,24 +607,40 @@ hipError_t launch_ema(int64_t n, const uint64_t *A, const uint64_t *N, uint64_t 
     return hipGetLastError();
 }
 
-template <int U>
-static void fused_u(const GraphBins &g, const int32_t *slot, const uint64_t *Npre,
-                    const uint8_t *col, const uint64_t *P, const uint64_t *A, uint64_t *S, int B,
-                    int k, int a, int p, int Wa, int Wp, int Wh, int nsplit,
-                    const uint32_t *split, const int16_t *drop, unsigned long long *flags,
-                    size_t lds, hipStream_t st) {
-    fused_kernel<U><<<dim3((unsigned)g.n), dim3(kBlock), lds, st>>>(
-        g.row_ptr, g.col_idx, slot, Npre, col, P, A, S, B, k, a, p, Wa, Wp, Wh, nsplit, split,
-        drop, flags);
+int row_lds_bytes(int k, int a, int Wa, int Wp, int B, int mode) {
+    int64_t words = (int64_t)Wp * B + (a > 1 ? (int64_t)Wa * B : 0);
+    int64_t bytes = words * 8 + (mode == kRowHist ? (int64_t)k * B * 4 : 0);
+    return (int)bytes;
 }
 
-hipError_t launch_fused(const GraphBins &g, const uint8_t *col, const uint64_t *P,
-                        const uint64_t *A, uint64_t *S, int B, int k, int a, int p, int Wa,
-                        int Wp, int Wh, int nsplit, const uint32_t *split, const int16_t *drop,
-                        unsigned long long *flags, hipStream_t st) {
-    (void)g; (void)col; (void)P; (void)A; (void)S; (void)B; (void)k; (void)a; (void)p;
-    (void)Wa; (void)Wp; (void)Wh; (void)nsplit; (void)split; (void)drop; (void)flags; (void)st;
-    return hipErrorNotSupported;
+int row_max_u() { return 8; }
+
+template <int MODE, int U>
+static void row_u(const RowArgs &a, int64_t n, size_t lds, hipStream_t st) {
+    row_kernel<MODE, U><<<dim3((unsigned)n), dim3(kBlock), lds, st>>>(a);
+}
+
+hipError_t launch_row(int mode, const GraphBins &g, const uint8_t *col, const uint64_t *src,
+                      const uint64_t *Npre, const uint64_t *A, uint64_t *S, int B, int k, int a,
+                      int Wa, int Wp, int Wh, int nsplit, const uint32_t *split,
+                      const int16_t *drop, unsigned long long *flags, hipStream_t st) {
+    if (g.n <= 0) return hipSuccess;
+    RowArgs r;
+    r.rp = g.row_ptr; r.ci = g.col_idx;
+    r.slot = mode == kRowStaged ? nullptr : g.slot;
+    r.Npre = Npre; r.col = col; r.src = src; r.A = A; r.S = S;
+    r.B = B; r.k = k; r.a = a; r.Wa = Wa; r.Wp = Wp; r.Wh = Wh; r.nsplit = nsplit;
+    r.split = split; r.drop = drop; r.flags = flags;
+    const size_t lds = (size_t)row_lds_bytes(k, a, Wa, Wp, B, mode);
+    const int64_t Lp = (int64_t)Wp * B;
+    if (mode == kRowStaged) row_u<kRowStaged, 1>(r, g.n, lds, st);
+    else if (mode == kRowHist) row_u<kRowHist, 1>(r, g.n, lds, st);
+    else if (Lp <= 256) row_u<kRowGather, 1>(r, g.n, lds, st);
+    else if (Lp <= 512) row_u<kRowGather, 2>(r, g.n, lds, st);
+    else if (Lp <= 1024) row_u<kRowGather, 4>(r, g.n, lds, st);
+    else if (Lp <= 2048) row_u<kRowGather, 8>(r, g.n, lds, st);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
 }
 
 hipError_t launch_reduce(int64_t n, const uint64_t *S, int W, int B, unsigned long long *X,

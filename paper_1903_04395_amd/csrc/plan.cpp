@@ -81,14 +81,22 @@ void root_tree(int t, const int32_t *edges, int root, int order,
     }
 }
 
-int fused_lds_bytes(int k, int h, int a, int p, int batch) {
-    (void)h;
-    uint64_t words = binom(k, p) + (a > 1 ? binom(k, a) : 0);
-    return (int)(words * (uint64_t)batch * 8);
+int row_lds_need(int k, int a, int p, int batch, int mode) {
+    uint64_t words = (binom(k, p) + (a > 1 ? binom(k, a) : 0)) * (uint64_t)batch;
+    uint64_t bytes = words * 8 + (mode == kStepFusedHist ? (uint64_t)k * batch * 4 : 0);
+    return bytes > (1u << 30) ? (1 << 30) : (int)bytes;
 }
 
-bool fusable(int k, int h, int a, int p, int batch) {
-    return fused_lds_bytes(k, h, a, p, batch) <= 64 * 1024;
+int step_mode(int k, int h, int a, int p, int batch, const ExecOpts &o) {
+    (void)h;
+    const uint64_t lp = binom(k, p) * (uint64_t)batch;
+    if (o.fuse && p == 1 && row_lds_need(k, a, p, batch, kStepFusedHist) <= o.lds_max)
+        return kStepFusedHist;
+    if (o.fuse && p >= 2 && lp <= (uint64_t)std::min(o.fuse_max_cols, 2048) &&
+        row_lds_need(k, a, p, batch, kStepFusedGather) <= o.lds_max)
+        return kStepFusedGather;
+    if (row_lds_need(k, a, p, batch, kStepStaged) <= o.lds_max) return kStepStaged;
+    return kStepGlobal;
 }
 
 namespace {
@@ -141,11 +149,11 @@ uint64_t table_bytes(int64_t n, int k, int size, int batch) {
 
 bool build_plan(int t, int root, const std::vector<int> &child_ptr,
                 const std::vector<int> &child_idx, int k, int64_t n, int64_t nnz,
-                int batch, bool fused, Plan &P, std::string &err) {
+                int batch, const ExecOpts &o, Plan &P, std::string &err) {
     P = Plan();
     P.t = t; P.k = k; P.root = root; P.n = n; P.nnz = nnz; P.batch = batch;
     P.child_ptr = child_ptr; P.child_idx = child_idx;
-    P.materialize_n = !fused;
+    P.opts = o;
     if (k < t || k > SC_MAX_K) { err = "need t <= k <= 16"; return false; }
     // subtree sizes and a check that the rooted tree spans 0..t-1 once
     P.subtree.assign(t, 0);
@@ -182,7 +190,8 @@ bool build_plan(int t, int root, const std::vector<int> &child_ptr,
             s.node = u; s.child = w;
             s.a = size; s.p = P.subtree[w]; s.h = s.a + s.p;
             s.buf_a = cur; s.buf_p = pb;
-            bool fuse = fused && fusable(k, s.h, s.a, s.p, batch);
+            s.mode = step_mode(k, s.h, s.a, s.p, batch, o);
+            const bool fuse = s.mode == kStepFusedHist || s.mode == kStepFusedGather;
             s.buf_n = fuse ? -1 : new_buf(s.p);
             s.buf_s = new_buf(s.h);
             s.last = false;
@@ -200,12 +209,13 @@ bool build_plan(int t, int root, const std::vector<int> &child_ptr,
     (void)top;
     P.arena_bytes = arena.end;
 
-    // Lemma 1 counts and a byte model, per colouring
+    // Lemma 1 counts, the benchmark's update counts and a byte model, per colouring
     for (const Step &s : P.steps) {
         double Wa = (double)binom(k, s.a), Wp = (double)binom(k, s.p), Wh = (double)binom(k, s.h);
-        if (s.p >= 2) P.spmm_updates += (double)nnz * Wp;
-        P.ema_updates += (double)n * Wh * (double)binom(s.h, s.a);
-        bool fuse = fused && fusable(k, s.h, s.a, s.p, batch);
+        P.lemma1_ops += (double)nnz * Wp + (double)n * Wh * (double)binom(s.h, s.p);
+        P.spmm_updates += (double)nnz * Wp;
+        P.ema_updates += s.a > 1 ? (double)n * Wh * (double)binom(s.h, s.a) : (double)n * Wh;
+        const bool fuse = s.mode == kStepFusedHist || s.mode == kStepFusedGather;
         double bytes = 8.0 * n * ((s.a > 1 ? Wa : 0) + (s.p > 1 ? Wp : 0) + Wh);
         if (s.p > 1 && !fuse) bytes += 16.0 * n * Wp;             // write + read N
         if (s.p == 1 || s.a == 1) bytes += (double)n;              // colours
@@ -218,7 +228,7 @@ bool build_plan(int t, int root, const std::vector<int> &child_ptr,
 }
 
 bool choose_plan(int t, const int32_t *edges, int root, int k, int64_t n, int64_t nnz,
-                 int batch, bool fused, Plan &out, std::string &err) {
+                 int batch, const ExecOpts &o, Plan &out, std::string &err) {
     std::string m = check_tree(t, edges);
     if (!m.empty()) { err = m; return false; }
     if (root >= t) { err = "root out of range"; return false; }
@@ -228,7 +238,7 @@ bool choose_plan(int t, const int32_t *edges, int root, int k, int64_t n, int64_
             std::vector<int> cp, ci;
             root_tree(t, edges, r, order, cp, ci);
             Plan p;
-            if (!build_plan(t, r, cp, ci, k, n, nnz, batch, fused, p, err)) return false;
+            if (!build_plan(t, r, cp, ci, k, n, nnz, batch, o, p, err)) return false;
             if (!found || p.cost < out.cost ||
                 (p.cost == out.cost && p.arena_bytes < out.arena_bytes)) {
                 out = p;
@@ -328,6 +338,8 @@ void fill_plan_info(const Plan &p, double aut, sc_plan_info_t *o) {
     o->arena_bytes = p.arena_bytes;
     o->spmm_updates = p.spmm_updates;
     o->ema_updates = p.ema_updates;
+    o->lemma1_ops = p.lemma1_ops;
+    for (size_t i = 0; i < p.steps.size(); ++i) o->step_mode[i] = p.steps[i].mode;
     o->compulsory_bytes = p.compulsory_bytes;
     o->automorphisms = aut;
 }

@@ -68,7 +68,14 @@ struct sc_ctx {
     std::map<TableKey, DevMem> split_tabs, drop_tabs;
     DevMem arena, colbuf, xbuf, npre;
     // options
-    int64_t max_batch = SC_MAX_BATCH, fused = 0, use_graph = 0, chunk_cols = 0, segment = 0;
+    int64_t max_batch = SC_MAX_BATCH, fused = 1, use_graph = 0, chunk_cols = 0, segment = 0;
+    int64_t xcd = 0, fuse_max_cols = 512;
+    // tracing
+    bool prof = false;
+    struct Rec { const char *name; hipEvent_t a, b; double bytes, updates; };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> event_pool;
+    size_t events_used = 0;
 };
 
 namespace {
@@ -179,6 +186,8 @@ kern::GraphBins bins_of(const Graph &g) {
     b.light_rows = (const int32_t *)g.light.p; b.n_light = g.n_light;
     b.wide_items = (const int2 *)g.wide.p; b.n_wide = g.n_wide;
     b.split_rows = (const int32_t *)g.split_rows.p; b.n_split = g.n_split;
+    b.n_split_items = g.n_split_items;
+    b.slot = (const int32_t *)g.slot.p;
     b.seg = g.seg;
     return b;
 }
@@ -211,14 +220,21 @@ int get_drop(sc_ctx *c, int k, int h, const int16_t **out) {
     return SC_OK;
 }
 
+ExecOpts exec_opts(const sc_ctx *c) {
+    ExecOpts o;
+    o.fuse = c->fused != 0;
+    o.fuse_max_cols = (int)c->fuse_max_cols;
+    return o;
+}
+
 int make_plan(sc_ctx *c, const Graph &g, const Template &T, int k, int batch, Plan &P) {
     std::string err;
     bool ok;
-    bool fused = c->fused != 0;
+    const ExecOpts o = exec_opts(c);
     if (T.explicit_plan)
-        ok = build_plan(T.t, T.root, T.child_ptr, T.child_idx, k, g.n, g.nnz, batch, fused, P, err);
+        ok = build_plan(T.t, T.root, T.child_ptr, T.child_idx, k, g.n, g.nnz, batch, o, P, err);
     else
-        ok = choose_plan(T.t, T.edges.data(), T.root, k, g.n, g.nnz, batch, fused, P, err);
+        ok = choose_plan(T.t, T.edges.data(), T.root, k, g.n, g.nnz, batch, o, P, err);
     if (!ok) return fail(c, SC_EINVAL, "planning failed: %s", err.c_str());
     return SC_OK;
 }
@@ -238,25 +254,68 @@ int pick_batch(sc_ctx *c, const Graph &g, const Template &T, int k, int want, Pl
     return SC_OK;
 }
 
+// ---------------------------------------------------------------- tracing
+
+hipEvent_t next_event(sc_ctx *c) {
+    if (c->events_used == c->event_pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        c->event_pool.push_back(e);
+    }
+    return c->event_pool[c->events_used++];
+}
+
+struct ProfScope {
+    sc_ctx *c;
+    hipStream_t st;
+    const char *name;
+    double bytes, updates;
+    hipEvent_t a = nullptr;
+    ProfScope(sc_ctx *c_, hipStream_t st_, const char *n, double by, double up)
+        : c(c_), st(st_), name(n), bytes(by), updates(up) {
+        if (c->prof && (a = next_event(c))) (void)hipEventRecord(a, st);
+    }
+    ~ProfScope() {
+        if (!a) return;
+        hipEvent_t b = next_event(c);
+        if (!b) return;
+        (void)hipEventRecord(b, st);
+        c->recs.push_back({name, a, b, bytes, updates});
+    }
+};
+
 // One pass: colourings first..first+P.batch-1 folded into the table columns.
 int run_pass(sc_ctx *c, Graph &g, const Plan &P, uint64_t first, hipStream_t st,
              uint64_t *counts, uint8_t *flags_out) {
     const int B = P.batch, k = P.k;
     const int64_t n = g.n;
+    const double dn = (double)n, dnnz = (double)g.nnz;
     int rc;
     if ((rc = rebin(c, g, default_segment(c)))) return rc;
     if ((rc = ensure(c, c->arena, P.arena_bytes))) return rc;
     if ((rc = ensure(c, c->colbuf, (size_t)n * B))) return rc;
     if ((rc = ensure(c, c->xbuf, (SC_MAX_BATCH + 1) * sizeof(uint64_t)))) return rc;
+    size_t npre_words = 0;
+    for (const Step &s : P.steps)
+        if (s.mode == kStepFusedHist || s.mode == kStepFusedGather)
+            npre_words = std::max(npre_words, (size_t)g.n_split * binom(k, s.p) * B);
+    if (npre_words && (rc = ensure(c, c->npre, npre_words * 8))) return rc;
     auto *X = (unsigned long long *)c->xbuf.p;
     auto *flags = X + SC_MAX_BATCH;
     auto *col = (uint8_t *)c->colbuf.p;
     auto *base = (uint8_t *)c->arena.p;
+    auto *Npre = (uint64_t *)c->npre.p;
     auto buf = [&](int id) { return id < 0 ? (uint64_t *)nullptr : (uint64_t *)(base + P.bufs[id].offset); };
     const kern::GraphBins bins = bins_of(g);
+    const double adj_bytes = 4.0 * dnnz + 8.0 * (dn + 1);
+    double split_nnz = 0;
+    if (g.n_split) for (int64_t v = 0; v < n; ++v) if (g.deg_host[v] > g.seg) split_nnz += (double)g.deg_host[v];
 
     HIPCHK(c, kern::launch_zero_u64((uint64_t *)X, SC_MAX_BATCH + 1, st));
-    HIPCHK(c, kern::launch_color(c->seed, first, n, B, k, col, st));
+    {
+        ProfScope ps(c, st, "color", dn * B, 0);
+        HIPCHK(c, kern::launch_color(c->seed, first, n, B, k, col, st));
+    }
     if (P.steps.empty()) {           // t == 1: every vertex is a colourful map
         for (int r = 0; r < B; ++r) { counts[r] = (uint64_t)n; flags_out[r] = 0; }
         HIPCHK(c, hipStreamSynchronize(st));
@@ -266,21 +325,67 @@ int run_pass(sc_ctx *c, Graph &g, const Plan &P, uint64_t first, hipStream_t st,
     for (const Step &s : P.steps) {
         const int Wa = (int)binom(k, s.a), Wp = (int)binom(k, s.p), Wh = (int)binom(k, s.h);
         const int64_t Lp = (int64_t)Wp * B;
+        const double La = (double)Wa * B, Ls = (double)Wh * B, dLp = (double)Lp;
+        const int nsplit = (int)binom(s.h, s.a);
         uint64_t *N = buf(s.buf_n);
         uint64_t *S = buf(s.buf_s);
+        const uint64_t *Pp = buf(s.buf_p), *A = buf(s.buf_a);
         const uint32_t *split = nullptr;
         const int16_t *drop = nullptr;
         if (s.a > 1) { if ((rc = get_split(c, k, s.h, s.a, &split))) return rc; }
         else { if ((rc = get_drop(c, k, s.h, &drop))) return rc; }
-        if (!N) return fail(c, SC_EINVAL, "fused steps are not available in this build");
-        if (s.p == 1) HIPCHK(c, kern::launch_hist(bins, col, N, B, k, st));
-        else HIPCHK(c, kern::launch_spmm(bins, buf(s.buf_p), N, Lp, B, (int)c->chunk_cols, flags, st));
-        if (s.a == 1) HIPCHK(c, kern::launch_select(n, col, N, S, B, k, Wh, Wp, drop, st));
-        else HIPCHK(c, kern::launch_ema(n, buf(s.buf_a), N, S, B, Wa, Wp, Wh, (int)binom(s.h, s.a),
-                                        split, flags, st));
+        const double ema_upd = s.a > 1 ? dn * Ls * nsplit : dn * Ls;
+        const double ema_bytes = 8.0 * dn * ((s.a > 1 ? La : 0) + Ls) + (s.a == 1 ? dn * B : 0);
+        const double sp_upd = dnnz * dLp;
+        switch (s.mode) {
+        case kStepFusedHist: {
+            if (g.n_split) {
+                ProfScope ps(c, st, "hist_split", 4.0 * split_nnz + 8.0 * g.n_split * dLp, split_nnz * dLp);
+                HIPCHK(c, kern::launch_hist_split(bins, col, Npre, B, k, st));
+            }
+            ProfScope ps(c, st, "row_hist", adj_bytes + dn * B + ema_bytes, sp_upd + ema_upd);
+            HIPCHK(c, kern::launch_row(kern::kModeHist, bins, col, nullptr, Npre, A, S, B, k, s.a,
+                                       Wa, Wp, Wh, nsplit, split, drop, flags, st));
+            break;
+        }
+        case kStepFusedGather: {
+            if (g.n_split) {
+                ProfScope ps(c, st, "spmm_split", 4.0 * split_nnz + 16.0 * g.n_split * dLp, split_nnz * dLp);
+                HIPCHK(c, kern::launch_spmm_split(bins, Pp, Npre, Lp, B, flags, st));
+            }
+            ProfScope ps(c, st, "row_gather", adj_bytes + 8.0 * dn * dLp + ema_bytes, sp_upd + ema_upd);
+            HIPCHK(c, kern::launch_row(kern::kModeGather, bins, col, Pp, Npre, A, S, B, k, s.a,
+                                       Wa, Wp, Wh, nsplit, split, drop, flags, st));
+            break;
+        }
+        default: {
+            if (s.p == 1) {
+                ProfScope ps(c, st, "hist", adj_bytes + dn * B + 8.0 * dn * dLp, sp_upd);
+                HIPCHK(c, kern::launch_hist(bins, col, N, B, k, st));
+            } else {
+                ProfScope ps(c, st, "spmm", adj_bytes + 16.0 * dn * dLp, sp_upd);
+                HIPCHK(c, kern::launch_spmm(bins, Pp, N, Lp, B, (int)c->chunk_cols, (int)c->xcd, flags, st));
+            }
+            if (s.mode == kStepStaged) {
+                ProfScope ps(c, st, "row_staged", 8.0 * dn * dLp + ema_bytes, ema_upd);
+                HIPCHK(c, kern::launch_row(kern::kModeStaged, bins, col, N, nullptr, A, S, B, k, s.a,
+                                           Wa, Wp, Wh, nsplit, split, drop, flags, st));
+            } else if (s.a == 1) {
+                ProfScope ps(c, st, "select", 8.0 * dn * dLp + ema_bytes, ema_upd);
+                HIPCHK(c, kern::launch_select(n, col, N, S, B, k, Wh, Wp, drop, st));
+            } else {
+                ProfScope ps(c, st, "ema", 8.0 * dn * dLp + ema_bytes, ema_upd);
+                HIPCHK(c, kern::launch_ema(n, A, N, S, B, Wa, Wp, Wh, nsplit, split, flags, st));
+            }
+        }
+        }
         last = &s;
     }
-    HIPCHK(c, kern::launch_reduce(n, buf(last->buf_s), (int)binom(k, last->h), B, X, flags, st));
+    {
+        const int W = (int)binom(k, last->h);
+        ProfScope ps(c, st, "reduce", 8.0 * dn * W * B, 0);
+        HIPCHK(c, kern::launch_reduce(n, buf(last->buf_s), W, B, X, flags, st));
+    }
     uint64_t host[SC_MAX_BATCH + 1];
     HIPCHK(c, hipMemcpyAsync(host, X, sizeof host, hipMemcpyDeviceToHost, st));
     HIPCHK(c, hipStreamSynchronize(st));
@@ -341,6 +446,7 @@ int sc_destroy(sc_ctx *c) {
     for (auto &kv : c->split_tabs) dev_free(c, kv.second);
     for (auto &kv : c->drop_tabs) dev_free(c, kv.second);
     dev_free(c, c->arena); dev_free(c, c->colbuf); dev_free(c, c->xbuf); dev_free(c, c->npre);
+    for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
     (void)hipStreamDestroy(c->stream);
     delete c;
     return SC_OK;
@@ -430,7 +536,7 @@ int sc_load_template_plan(sc_ctx *c, int32_t t, int32_t root, const int32_t *chi
     T->child_idx.assign(child_idx, child_idx + (t - 1));
     Plan probe;
     std::string err;
-    if (!build_plan(t, root, T->child_ptr, T->child_idx, t, 1, 0, 1, false, probe, err))
+    if (!build_plan(t, root, T->child_ptr, T->child_idx, t, 1, 0, 1, ExecOpts(), probe, err))
         return fail(c, SC_EINVAL, "%s", err.c_str());
     for (int u = 0; u < t; ++u)
         for (int e = child_ptr[u]; e < child_ptr[u + 1]; ++e) {
@@ -466,6 +572,10 @@ int sc_set_option(sc_ctx *c, int32_t opt, int64_t v) {
         if (v < 0 || v > (1 << 24)) return fail(c, SC_EINVAL, "segment must be in [0, 2^24]");
         if (v > 0 && v <= kern::kLightMax) return fail(c, SC_EINVAL, "segment must exceed %d", kern::kLightMax);
         c->segment = v; return SC_OK;
+    case SC_OPT_XCD: c->xcd = v != 0; return SC_OK;
+    case SC_OPT_FUSE_MAX_COLS:
+        if (v < 64 || v > 2048) return fail(c, SC_EINVAL, "fuse max columns must be in [64, 2048]");
+        c->fuse_max_cols = v; return SC_OK;
     default: return fail(c, SC_EINVAL, "unknown option %d", opt);
     }
 }
@@ -478,6 +588,8 @@ int sc_get_option(sc_ctx *c, int32_t opt, int64_t *v) {
     case SC_OPT_GRAPH: *v = c->use_graph; return SC_OK;
     case SC_OPT_CHUNK_COLS: *v = c->chunk_cols; return SC_OK;
     case SC_OPT_SEGMENT: *v = default_segment(c); return SC_OK;
+    case SC_OPT_XCD: *v = c->xcd; return SC_OK;
+    case SC_OPT_FUSE_MAX_COLS: *v = c->fuse_max_cols; return SC_OK;
     default: return fail(c, SC_EINVAL, "unknown option %d", opt);
     }
 }
@@ -487,7 +599,7 @@ int sc_plan_template(int32_t t, const int32_t *edges, int32_t root, int32_t k, i
     if (!out || batch < 1 || batch > SC_MAX_BATCH || n < 1 || nnz < 0) return SC_EINVAL;
     Plan P;
     std::string err;
-    if (!choose_plan(t, edges, root, k, n, nnz, batch, false, P, err)) return SC_EINVAL;
+    if (!choose_plan(t, edges, root, k, n, nnz, batch, ExecOpts(), P, err)) return SC_EINVAL;
     std::vector<int32_t> e(edges ? edges : (const int32_t *)nullptr, edges ? edges + 2 * (t - 1) : nullptr);
     fill_plan_info(P, aut_of(t, e), out);
     return SC_OK;
@@ -555,6 +667,43 @@ int sc_run(sc_ctx *c, int32_t gid, int32_t tid, uint64_t first, int32_t ncol, vo
     }
     if (est_maps) *est_maps = maps;
     if (est_copies) *est_copies = copies;
+    return SC_OK;
+}
+
+int sc_profile(sc_ctx *c, int32_t enable) {
+    if (!c) return SC_EINVAL;
+    if (enable) {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        c->recs.clear();
+        c->events_used = 0;
+    }
+    c->prof = enable != 0;
+    return SC_OK;
+}
+
+int sc_profile_read(sc_ctx *c, sc_kernel_stat_t *out, int32_t cap, int32_t *n_out) {
+    if (!c) return SC_EINVAL;
+    if (!n_out || (cap > 0 && !out)) return fail(c, SC_EINVAL, "NULL argument");
+    std::vector<sc_kernel_stat_t> agg;
+    for (auto &r : c->recs) {
+        HIPCHK(c, hipEventSynchronize(r.b));
+        float ms = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&ms, r.a, r.b));
+        sc_kernel_stat_t *hit = nullptr;
+        for (auto &a : agg) if (!strcmp(a.name, r.name)) hit = &a;
+        if (!hit) {
+            agg.emplace_back();
+            hit = &agg.back();
+            std::memset(hit, 0, sizeof *hit);
+            std::snprintf(hit->name, sizeof hit->name, "%s", r.name);
+        }
+        hit->launches += 1;
+        hit->total_ms += ms;
+        hit->alg_bytes += r.bytes;
+        hit->updates += r.updates;
+    }
+    *n_out = (int32_t)agg.size();
+    for (int32_t i = 0; i < cap && i < (int32_t)agg.size(); ++i) out[i] = agg[i];
     return SC_OK;
 }
 

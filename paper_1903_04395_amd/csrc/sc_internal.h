@@ -19,13 +19,28 @@ uint64_t binom(int n, int r);
 // I = sum_i binom(c_i, i) over its colours c_1 < c_2 < ... (i from 1).
 int64_t colorset_rank(uint32_t mask);
 
+// How a step runs (see step_mode()).
+enum StepMode {
+    kStepFusedHist = 0,    // p = 1: colour histogram and multiply-add in one row kernel
+    kStepFusedGather = 1,  // narrow passive rows: neighbour sum and multiply-add in one row kernel
+    kStepStaged = 2,       // neighbour-sum table N, then the LDS row kernel
+    kStepGlobal = 3        // neighbour-sum table N, then select / multiply-add from global memory
+};
+
+struct ExecOpts {
+    bool fuse = true;          // allow the fused modes
+    int fuse_max_cols = 512;   // widest passive row (Wp*B uint64) the fused gather takes
+    int lds_max = 64 * 1024;   // LDS bytes a row kernel may use
+};
+
 // One DP step: attach the subtree of `child` (passive, size p) to what `node`
 // has built so far (active, size a); h = a + p.  Buffers are indices into
 // Plan::bufs; -1 means the implicit single-vertex table (computed from the
-// colours on the fly).
+// colours on the fly) or, for buf_n, a neighbour sum that stays in LDS.
 struct Step {
     int node, child;
     int h, a, p;
+    int mode;
     int buf_a, buf_p, buf_n, buf_s;
     bool last;
 };
@@ -43,9 +58,12 @@ struct Plan {
     std::vector<Step> steps;
     std::vector<Buf> bufs;
     uint64_t arena_bytes = 0;
-    double spmm_updates = 0, ema_updates = 0, compulsory_bytes = 0, cost = 0;
-    bool materialize_n = true;   // false when the fused kernels consume the neighbour sum
+    double spmm_updates = 0, ema_updates = 0, lemma1_ops = 0, compulsory_bytes = 0, cost = 0;
+    ExecOpts opts;
 };
+
+int step_mode(int k, int h, int a, int p, int batch, const ExecOpts &o);
+int row_lds_need(int k, int a, int p, int batch, int mode);
 
 // Validates an edge list as a tree on t vertices; returns "" or a message.
 std::string check_tree(int t, const int32_t *edges);
@@ -56,24 +74,18 @@ void root_tree(int t, const int32_t *edges, int root, int order,
                std::vector<int> &child_ptr, std::vector<int> &child_idx);
 
 // Builds steps, buffers and the static memory plan for a rooted ordered tree.
-// `fused` drops the materialised neighbour-sum buffers of steps the fused
-// kernels handle (see fusable()).
+// Fused steps have no neighbour-sum buffer.
 bool build_plan(int t, int root, const std::vector<int> &child_ptr,
                 const std::vector<int> &child_idx, int k, int64_t n, int64_t nnz,
-                int batch, bool fused, Plan &out, std::string &err);
+                int batch, const ExecOpts &o, Plan &out, std::string &err);
 
 // Chooses the root and child order with the lowest modelled cost (root < 0),
 // or orders the children of the given root.
 bool choose_plan(int t, const int32_t *edges, int root, int k, int64_t n, int64_t nnz,
-                 int batch, bool fused, Plan &out, std::string &err);
+                 int batch, const ExecOpts &o, Plan &out, std::string &err);
 
 // |Aut(T)| of the unrooted template tree.
 double tree_automorphisms(int t, const std::vector<std::pair<int,int>> &edges);
-
-// Whether the fused kernel can take step (h,a,p) for k colours and `batch`
-// colourings: the whole neighbour-sum row and the active row must fit in LDS.
-bool fusable(int k, int h, int a, int p, int batch);
-int fused_lds_bytes(int k, int h, int a, int p, int batch);
 
 // Split table of a step: for every output colour set I_s (in index order),
 // binom(h,a) packed pairs (I_a | I_p << 16).

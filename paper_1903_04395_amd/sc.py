@@ -15,12 +15,13 @@ import numpy as np
 __all__ = [
     "SC_OK", "SC_EINVAL", "SC_ENOMEM", "SC_EDEVICE", "SC_ENOTFOUND", "SC_EBUSY", "SC_ESTATE",
     "SC_OPT_MAX_BATCH", "SC_OPT_FUSED", "SC_OPT_GRAPH", "SC_OPT_CHUNK_COLS", "SC_OPT_SEGMENT",
-    "ScError", "PlanInfo", "lib", "lib_path", "sc_version", "sc_plan_template",
+    "SC_OPT_XCD", "SC_OPT_FUSE_MAX_COLS", "OPTION_DEFAULTS", "ScError", "PlanInfo", "KernelStat", "lib", "lib_path", "sc_version", "sc_plan_template",
     "sc_colorset_rank", "sc_color_of", "Context",
 ]
 
 SC_OK, SC_EINVAL, SC_ENOMEM, SC_EDEVICE, SC_ENOTFOUND, SC_EBUSY, SC_ESTATE = 0, -1, -2, -3, -4, -5, -6
 SC_OPT_MAX_BATCH, SC_OPT_FUSED, SC_OPT_GRAPH, SC_OPT_CHUNK_COLS, SC_OPT_SEGMENT = 1, 2, 3, 4, 5
+SC_OPT_XCD, SC_OPT_FUSE_MAX_COLS = 6, 7
 SC_MAX_T = 16
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -47,10 +48,12 @@ class PlanInfo(ctypes.Structure):
         ("step_h", ctypes.c_int32 * SC_MAX_T),
         ("step_a", ctypes.c_int32 * SC_MAX_T),
         ("step_p", ctypes.c_int32 * SC_MAX_T),
+        ("step_mode", ctypes.c_int32 * SC_MAX_T),
         ("batch", ctypes.c_int32),
         ("arena_bytes", ctypes.c_uint64),
         ("spmm_updates", ctypes.c_double),
         ("ema_updates", ctypes.c_double),
+        ("lemma1_ops", ctypes.c_double),
         ("compulsory_bytes", ctypes.c_double),
         ("automorphisms", ctypes.c_double),
     ]
@@ -62,13 +65,29 @@ class PlanInfo(ctypes.Structure):
     def steps(self):
         return [(self.step_h[i], self.step_a[i], self.step_p[i]) for i in range(self.n_steps)]
 
+    def modes(self):
+        return [self.step_mode[i] for i in range(self.n_steps)]
+
     def as_dict(self):
         return {
             "t": self.t, "k": self.k, "root": self.root, "children": self.children(),
-            "steps": self.steps(), "batch": self.batch, "arena_bytes": int(self.arena_bytes),
+            "steps": self.steps(), "modes": self.modes(), "batch": self.batch,
+            "arena_bytes": int(self.arena_bytes),
             "spmm_updates": self.spmm_updates, "ema_updates": self.ema_updates,
+            "lemma1_ops": self.lemma1_ops,
             "compulsory_bytes": self.compulsory_bytes, "automorphisms": self.automorphisms,
         }
+
+
+class KernelStat(ctypes.Structure):
+    _fields_ = [
+        ("name", ctypes.c_char * 32), ("launches", ctypes.c_int32), ("total_ms", ctypes.c_double),
+        ("alg_bytes", ctypes.c_double), ("updates", ctypes.c_double),
+    ]
+
+
+OPTION_DEFAULTS = {SC_OPT_MAX_BATCH: 64, SC_OPT_FUSED: 1, SC_OPT_GRAPH: 0, SC_OPT_CHUNK_COLS: 0,
+                   SC_OPT_SEGMENT: 0, SC_OPT_XCD: 0, SC_OPT_FUSE_MAX_COLS: 512}
 
 
 class ScError(RuntimeError):
@@ -105,6 +124,9 @@ def lib():
                                       _vp, _u64p, _u8p, _dblp, _dblp]),
             "sc_set_option": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int64]),
             "sc_get_option": (ctypes.c_int, [_vp, ctypes.c_int32, _i64p]),
+            "sc_profile": (ctypes.c_int, [_vp, ctypes.c_int32]),
+            "sc_profile_read": (ctypes.c_int, [_vp, ctypes.POINTER(KernelStat), ctypes.c_int32,
+                                               _i32p]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -248,6 +270,19 @@ class Context:
         v = ctypes.c_int64()
         self._check(self._L.sc_get_option(self._h, opt, ctypes.byref(v)))
         return v.value
+
+    def profile(self, enable: bool):
+        self._check(self._L.sc_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self):
+        """{family: {launches, total_ms, alg_bytes, updates}} of the recorded launches."""
+        cap = 64
+        arr = (KernelStat * cap)()
+        n = ctypes.c_int32()
+        self._check(self._L.sc_profile_read(self._h, arr, cap, ctypes.byref(n)))
+        return {arr[i].name.decode(): {"launches": arr[i].launches, "total_ms": arr[i].total_ms,
+                                       "alg_bytes": arr[i].alg_bytes, "updates": arr[i].updates}
+                for i in range(min(n.value, cap))}
 
     def plan_info(self, gid, tid, n_colorings=1) -> PlanInfo:
         out = PlanInfo()

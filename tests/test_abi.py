@@ -87,16 +87,23 @@ def test_plan_steps_and_lemma1_counts(seed):
         assert got == und
         assert info.steps() == steps_of(t, info.root, ch)
         assert info.n_steps == t - 1
-        # Lemma 1: nnz*C(k,p) neighbour-sum updates (p >= 2; p = 1 is a colour
-        # histogram) and n*C(k,h)*C(h,p) multiply-adds per step
-        spmm = sum(nnz * math.comb(k, p) for h, a, p in info.steps() if p >= 2)
-        ema = sum(n * math.comb(k, h) * math.comb(h, p) for h, a, p in info.steps())
+        # Lemma 1: nnz*C(k,p) neighbour-sum updates and n*C(k,h)*C(h,p)
+        # multiply-adds per step; the benchmark counts an a = 1 step (a select)
+        # as n*C(k,h)
+        spmm = sum(nnz * math.comb(k, p) for h, a, p in info.steps())
+        ema = sum(n * math.comb(k, h) * (math.comb(h, p) if a > 1 else 1) for h, a, p in info.steps())
+        lemma1 = sum(nnz * math.comb(k, p) + n * math.comb(k, h) * math.comb(h, p)
+                     for h, a, p in info.steps())
         assert info.spmm_updates == spmm and info.ema_updates == ema
+        assert info.lemma1_ops == lemma1
         assert info.automorphisms == O.aut(t, edges)
-        # the arena holds at least the largest step's live tables
+        # the arena holds at least the largest step's live tables: output,
+        # active and passive tables, plus the neighbour-sum table unless the
+        # step is fused (modes 0 and 1 keep it in LDS)
         W = lambda s: math.comb(k, s)
-        need = max((W(h) + W(p) + (W(a) if a > 1 else 0) + (W(p) if p > 1 else 0)) * n * 4 * 8
-                   for h, a, p in info.steps())
+        need = max((W(h) + (W(a) if a > 1 else 0) + (W(p) if p > 1 else 0)
+                    + (W(p) if mode >= 2 else 0)) * n * 4 * 8
+                   for (h, a, p), mode in zip(info.steps(), info.modes()))
         assert info.arena_bytes >= need
 
 

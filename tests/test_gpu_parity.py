@@ -41,7 +41,7 @@ def run_both(ctx, g, t, edges, k, seed, first, R, root=-1, gid=None, plan=None, 
         ctx.set_colors(k, seed)
         info = ctx.plan_info(gid, tid, R)
         say(f"n={g.n} nnz={g.nnz} t={t} k={k} seed={seed} first={first} R={R} batch={info.batch} "
-            f"root={info.root} steps={info.steps()} opts={opts}")
+            f"root={info.root} steps={info.steps()} modes={info.modes()} opts={opts}")
         counts, ovf, maps, copies = ctx.run(gid, tid, first, R)
         ocounts, oflags = O.count(g, t, (info.root, info.children()), k, seed, first, R)
         assert np.array_equal(counts, ocounts), (counts, ocounts)
@@ -51,9 +51,7 @@ def run_both(ctx, g, t, edges, k, seed, first, R, root=-1, gid=None, plan=None, 
         return counts, ovf, maps, copies, info
     finally:
         for o in opts:
-            ctx.set_option(o, {sc.SC_OPT_MAX_BATCH: 64, sc.SC_OPT_SEGMENT: 0,
-                               sc.SC_OPT_CHUNK_COLS: 0, sc.SC_OPT_FUSED: 0,
-                               sc.SC_OPT_GRAPH: 0}[o])
+            ctx.set_option(o, sc.OPTION_DEFAULTS[o])
 
 
 # ------------------------------------------------------------------ configs
