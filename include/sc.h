@@ -182,11 +182,15 @@ enum {
     SC_OPT_FUSED = 2,         /* 1 (default): fused neighbour-sum + multiply-add
                                  row kernels where the rows fit; 0: never      */
     SC_OPT_GRAPH = 3,         /* 1: replay each pass from a captured hipGraph   */
-    SC_OPT_CHUNK_COLS = 4,    /* neighbour-sum column tile, in uint64 (0=auto)  */
-    SC_OPT_SEGMENT = 5,       /* neighbours per work item for heavy rows (0=auto) */
-    SC_OPT_XCD = 6,           /* 1: assign neighbour-sum column tiles to XCDs   */
-    SC_OPT_FUSE_MAX_COLS = 7  /* widest passive row (uint64) the fused neighbour
+    SC_OPT_TILE_COLS = 4,     /* neighbour-sum column tile: 8, 16, 32 or 64 uint64
+                                 (0 = default, 16)                             */
+    SC_OPT_SEGMENT = 5,       /* neighbours per work item of heavy rows, > 64
+                                 (0 = default, 256)                            */
+    SC_OPT_FUSE_MAX_COLS = 7, /* widest passive row (uint64) the fused neighbour
                                  sum takes (64..2048)                          */
+    SC_OPT_REORDER = 8        /* 1 (default): graphs loaded afterwards are kept
+                                 relabelled by descending degree (colours still
+                                 follow the caller's vertex ids)               */
 };
 int sc_set_option(sc_ctx *ctx, int32_t option, int64_t value);
 int sc_get_option(sc_ctx *ctx, int32_t option, int64_t *value);

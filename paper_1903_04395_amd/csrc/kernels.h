@@ -11,37 +11,42 @@ namespace sc {
 namespace kern {
 
 // Rows are binned by degree once per graph:
-//  light rows  (deg <= kLightMax): one wavefront per row;
+//  light rows  (deg <= kLightMax): one wavefront per row (colour histogram);
 //  wide items  (deg >  kLightMax): one workgroup per (row, segment of `seg`
-//              neighbours); rows with deg > seg are split into several
-//              segments whose partial sums meet in global atomics.
+//              neighbours) (colour histogram);
+//  tasks       every row with deg <= seg, and every `seg`-neighbour segment of
+//              the rows with more (neighbour sum);
+// rows with deg > seg ("split rows") are summed over several segments whose
+// partial sums meet in global atomics.
 constexpr int kLightMax = 64;
 
 struct GraphBins {
-    int64_t n = 0, nnz = 0;
+    int64_t n = 0, nnz = 0;   // n: rows the tables hold (isolated vertices dropped when relabelled)
     const int64_t *row_ptr = nullptr;
     const int32_t *col_idx = nullptr;
     const int32_t *light_rows = nullptr;  int64_t n_light = 0;
     const int2 *wide_items = nullptr;     int64_t n_wide = 0;   // (row, segment), split rows first
     int64_t n_split_items = 0;                                  // items of split rows
+    const int2 *tasks = nullptr;          int64_t n_tasks = 0;  // neighbour-sum tasks, split rows first
+    int64_t n_split_tasks = 0;
     const int32_t *split_rows = nullptr;  int64_t n_split = 0;  // rows with deg > seg
     const int32_t *slot = nullptr;        // [n]: index of a split row in split_rows, else -1
     int seg = 0;
 };
 
-// col[v*B + r] = colour of vertex v in colouring first+r (SplitMix64 rule).
-hipError_t launch_color(uint64_t seed, uint64_t first, int64_t n, int B, int k, uint8_t *col,
-                        hipStream_t st);
+// col[v*B + r] = colour of vertex v in colouring first+r (SplitMix64 rule),
+// drawn from the original id perm[v] when the graph was relabelled (perm != NULL).
+hipError_t launch_color(uint64_t seed, uint64_t first, int64_t n, int B, int k,
+                        const int32_t *perm, uint8_t *col, hipStream_t st);
 
-// N = A * P for a table with L = W*B uint64 columns per row, column-tiled
-// (chunk_cols = 64, 128 or 256 uint64; 0 = by L); `xcd` assigns column chunks
-// to XCDs.
+// N = A * P for a table with L = W*B uint64 columns per row, in column tiles
+// of tile_cols = 8, 16, 32 or 64 uint64.
 hipError_t launch_spmm(const GraphBins &g, const uint64_t *P, uint64_t *N, int64_t L, int B,
-                       int chunk_cols, int xcd, unsigned long long *flags, hipStream_t st);
+                       int tile_cols, unsigned long long *flags, hipStream_t st);
 
 // Neighbour sums of the split rows only, into the compact Npre[n_split][L].
 hipError_t launch_spmm_split(const GraphBins &g, const uint64_t *P, uint64_t *Npre, int64_t L,
-                             int B, unsigned long long *flags, hipStream_t st);
+                             int B, int tile_cols, unsigned long long *flags, hipStream_t st);
 
 // p = 1: N[v][c*B + r] = #{j in adj(v) : col[j*B + r] == c}, c < k.
 hipError_t launch_hist(const GraphBins &g, const uint8_t *col, uint64_t *N, int B, int k,

@@ -22,6 +22,10 @@ namespace {
 
 constexpr int kWave = 64;
 constexpr int kBlock = 256;
+// A launch may hold at most 2^32 - 1 work-items per grid dimension; kernels
+// that stride over their items are launched with at most this many workgroups.
+constexpr int64_t kMaxStrideBlocks = 1 << 16;
+constexpr int64_t kMaxGridBlocks = ((int64_t)1 << 32) / kBlock - 1;
 
 __device__ __forceinline__ uint64_t wave_or(uint64_t m) {
     uint32_t lo = (uint32_t)m, hi = (uint32_t)(m >> 32);
@@ -52,18 +56,23 @@ __device__ __forceinline__ uint64_t mad_ovf(uint64_t acc, uint64_t a, uint64_t b
 
 // ------------------------------------------------------------------ colours
 
+// col[v*B + r]: colour of internal vertex v (original id perm[v], or v) in
+// colouring first + r.
 __global__ __launch_bounds__(kBlock) void color_kernel(uint64_t seed, uint64_t first, int64_t n,
-                                                      int B, int k, uint8_t *__restrict__ col) {
-    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n * B) return;
-    int64_t v = i / B;
-    int64_t r = i - v * B;
-    uint64_t idx = ((first + (uint64_t)r) << 40) + (uint64_t)v;
-    uint64_t z = seed + (idx + 1) * 0x9E3779B97F4A7C15ull;     // SplitMix64 state
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;                // its finaliser
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    z ^= z >> 31;
-    col[i] = (uint8_t)__umul64hi(z, (uint64_t)k);
+                                                      int B, int k, const int32_t *__restrict__ perm,
+                                                      uint8_t *__restrict__ col) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n * B;
+         i += (int64_t)gridDim.x * kBlock) {
+        const int64_t v = i / B;
+        const int64_t r = i - v * B;
+        const uint64_t orig = perm ? (uint64_t)perm[v] : (uint64_t)v;
+        const uint64_t idx = ((first + (uint64_t)r) << 40) + orig;
+        uint64_t z = seed + (idx + 1) * 0x9E3779B97F4A7C15ull;     // SplitMix64 state
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;                // its finaliser
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        col[i] = (uint8_t)__umul64hi(z, (uint64_t)k);
+    }
 }
 
 // ------------------------------------------------------------------ neighbour sum
@@ -108,112 +117,97 @@ __device__ __forceinline__ void gather_rows(int64_t e0, int64_t e1, int step,
     }
 }
 
-struct SpmmArgs {
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t x, int mask) {
+    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)x, mask, kWave);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(x >> 32), mask, kWave);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+struct NarrowArgs {
     const int64_t *rp;
     const int32_t *ci;
-    const int32_t *light;  int64_t n_light;   // light rows, 4 per workgroup
-    const int2 *wide;      int64_t n_wide;    // (row, segment) items, 1 per workgroup
+    const int2 *tasks;        // (row, segment of `seg` neighbours)
+    int64_t n_tasks;
     int seg;
-    const int32_t *slot;                      // optional output-row redirect
+    const int32_t *slot;      // optional output-row redirect
     const uint64_t *P;
     uint64_t *N;
     int64_t L;
     int B;
-    int64_t groups;                           // light groups + wide items
-    int64_t chunks;                           // column chunks of 64*U
-    int xcd;                                  // XCD-aware chunk assignment
+    int64_t tiles;            // column tiles of Z uint64
     unsigned long long *flags;
 };
 
-// Neighbour sum N = A * P, tiled by column chunks of 64*U uint64 and walked
-// chunk-major so that one chunk of the gathered rows stays cache-resident while
-// all rows consume it.  Light rows: one wavefront each.  Wide items: four
-// wavefronts split the neighbours and meet in LDS; rows with more than `seg`
-// neighbours are split over several items whose partial sums meet in global
-// atomics (the carry is read from the returned old value).  With `xcd`,
-// workgroup b runs on XCD b mod 8 and only ever sees chunks = that XCD mod 8,
-// so each XCD's L2 holds one chunk's hot rows.
-template <int U>
-__global__ __launch_bounds__(kBlock) void spmm_tiled_kernel(SpmmArgs a) {
-    __shared__ uint64_t red[kBlock / kWave - 1][U][kWave];
-    __shared__ uint32_t redc[kBlock / kWave - 1][kWave];
-    const int64_t b = blockIdx.x;
-    int64_t chunk, g;
-    if (a.xcd) {
-        const int64_t j = b >> 3;
-        chunk = (b & 7) + 8 * (j / a.groups);
-        g = j % a.groups;
-        if (chunk >= a.chunks) return;                 // whole workgroup
-    } else {
-        chunk = b / a.groups;
-        g = b - chunk * a.groups;
-    }
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+// Neighbour sum N = A * P in narrow column tiles of Z uint64 (Z*8 bytes of
+// every gathered row per tile).  The tiles are walked one after another over
+// all rows, so while a tile is in flight only n*Z*8 bytes of P are live: the
+// hub rows' tile slices stay in L2 and the whole tile fits the last-level
+// cache.  One wavefront per (tile, task): its 64 lanes are 64/Z groups of Z
+// lanes; each group walks every (64/Z)-th neighbour of the task (four in
+// flight) and the groups are summed with cross-lane shuffles.  A task is a
+// whole row, or a `seg`-neighbour segment of a row with more neighbours,
+// whose partial sums meet in global atomics (N zeroed beforehand; the carry is
+// read from the returned old value).
+template <int Z>
+__global__ __launch_bounds__(kBlock) void spmm_narrow_kernel(NarrowArgs a) {
+    constexpr int G = kWave / Z;
     const int lane = threadIdx.x & (kWave - 1);
-    const int64_t c0 = chunk * (kWave * U) + lane;
-    bool inb[U];
-    uint64_t acc[U];
+    const int grp = lane / Z, cz = lane - (lane / Z) * Z;
+    const int64_t total = a.tiles * a.n_tasks;
+    const int64_t stride = (int64_t)gridDim.x * (kBlock / kWave);
+    // items in (tile, task) order; the grid strides over them, so the items in
+    // flight at any time belong to one or two consecutive tiles
+    for (int64_t wid = (int64_t)blockIdx.x * (kBlock / kWave) + (threadIdx.x >> 6); wid < total;
+         wid += stride) {
+        const int64_t tile = wid / a.n_tasks;
+        const int64_t ti = wid - tile * a.n_tasks;
+        const int2 tk = a.tasks[ti];
+        const int v = tk.x;
+        const int64_t r0 = a.rp[v], r1 = a.rp[v + 1];
+        const int64_t e0 = r0 + (int64_t)tk.y * a.seg;
+        const int64_t e1 = min(e0 + a.seg, r1);
+        const bool split = (r1 - r0) > a.seg;
+        const int64_t c = tile * Z + cz;
+        const bool inb = c < a.L;
+        const uint64_t *Pc = a.P + c;
+        uint64_t acc = 0;
+        uint32_t carry = 0;
+        int64_t e = e0 + grp;
+        for (; e + 3 * G < e1; e += 4 * G) {
+            const int64_t j0 = a.ci[e], j1 = a.ci[e + G], j2 = a.ci[e + 2 * G], j3 = a.ci[e + 3 * G];
+            const uint64_t x0 = inb ? Pc[j0 * a.L] : 0, x1 = inb ? Pc[j1 * a.L] : 0;
+            const uint64_t x2 = inb ? Pc[j2 * a.L] : 0, x3 = inb ? Pc[j3 * a.L] : 0;
+            uint64_t t = acc + x0; carry |= t < x0;
+            acc = t + x1;          carry |= acc < x1;
+            t = acc + x2;          carry |= t < x2;
+            acc = t + x3;          carry |= acc < x3;
+        }
+        for (; e < e1; e += G) {
+            const uint64_t x = inb ? Pc[(int64_t)a.ci[e] * a.L] : 0;
+            const uint64_t t = acc + x;
+            carry |= t < x;
+            acc = t;
+        }
 #pragma unroll
-    for (int u = 0; u < U; ++u) { inb[u] = c0 + kWave * u < a.L; acc[u] = 0; }
-    uint32_t carry = 0;
-    const int64_t nlg = (a.n_light + 3) >> 2;
-    if (g < nlg) {
-        const int64_t li = g * 4 + wave;
-        if (li >= a.n_light) return;                   // whole wavefront
-        const int v = __builtin_amdgcn_readfirstlane(a.light[li]);
-        gather_rows<U>(a.rp[v], a.rp[v + 1], 1, a.ci, a.P, a.L, c0, inb, acc, carry);
-        uint64_t *d = a.N + (int64_t)v * a.L + c0;
+        for (int o = Z; o < kWave; o <<= 1) {
+            const uint64_t y = shfl_xor_u64(acc, o);
+            carry |= (uint32_t)__shfl_xor((int)carry, o, kWave);
+            const uint64_t t = acc + y;
+            carry |= t < y;
+            acc = t;
+        }
         uint64_t m = 0;
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if (inb[u]) d[kWave * u] = acc[u];
-            if (carry & (1u << u)) m |= 1ull << ((c0 + kWave * u) % a.B);
-        }
-        flush_flags(m, a.flags);
-        return;
-    }
-    const int2 it = a.wide[g - nlg];
-    const int v = __builtin_amdgcn_readfirstlane(it.x);
-    const int64_t r0 = a.rp[v], r1 = a.rp[v + 1];
-    const int64_t e0 = r0 + (int64_t)it.y * a.seg;
-    const int64_t e1 = min(e0 + a.seg, r1);
-    const bool split = (r1 - r0) > a.seg;
-    gather_rows<U>(e0 + wave, e1, kBlock / kWave, a.ci, a.P, a.L, c0, inb, acc, carry);
-    if (wave > 0) {
-#pragma unroll
-        for (int u = 0; u < U; ++u) red[wave - 1][u][lane] = acc[u];
-        redc[wave - 1][lane] = carry;
-    }
-    __syncthreads();
-    if (wave == 0) {
-#pragma unroll
-        for (int w = 0; w < kBlock / kWave - 1; ++w) {
-            carry |= redc[w][lane];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const uint64_t x = red[w][u][lane];
-                const uint64_t t = acc[u] + x;
-                carry |= (uint32_t)(t < x) << u;
-                acc[u] = t;
-            }
-        }
-        const int64_t orow = a.slot ? (int64_t)a.slot[v] : (int64_t)v;
-        uint64_t *d = a.N + orow * a.L + c0;
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if (!inb[u]) continue;
+        if (grp == 0 && inb) {
+            const int64_t orow = a.slot ? (int64_t)a.slot[v] : (int64_t)v;
+            uint64_t *d = a.N + orow * a.L + c;
             if (split) {
-                const unsigned long long old = atomicAdd((unsigned long long *)(d + kWave * u),
-                                                         (unsigned long long)acc[u]);
-                if ((uint64_t)old + acc[u] < (uint64_t)old) carry |= 1u << u;
+                const unsigned long long old = atomicAdd((unsigned long long *)d, (unsigned long long)acc);
+                if ((uint64_t)old + acc < (uint64_t)old) carry = 1;
             } else {
-                d[kWave * u] = acc[u];
+                *d = acc;
             }
+            if (carry) m = 1ull << (c % a.B);
         }
-        uint64_t m = 0;
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (carry & (1u << u)) m |= 1ull << ((c0 + kWave * u) % a.B);
         flush_flags(m, a.flags);
     }
 }
@@ -363,19 +357,19 @@ struct RowArgs {
     const uint32_t *split;
     const int16_t *drop;
     unsigned long long *flags;
+    int64_t n;                    // rows
 };
 
-// One workgroup per graph row v.  The neighbour-sum row N[v] (Wp*B words) is
-// built in LDS -- copied from N (staged), summed from the neighbours' passive
+// One workgroup per graph row v (the grid strides over the rows).  The
+// neighbour-sum row N[v] (Wp*B words) is built in LDS -- copied from N
+// (staged), summed from the neighbours' passive
 // rows (fused neighbour sum), or counted from the neighbours' colours (fused
 // histogram, p = 1); split rows copy their precomputed sum.  The active row is
 // staged next to it (a >= 2).  Every output entry (I, r) of S[v] is then
 // either a select through the drop-colour table (a = 1) or the split sum
 // sum_j A[v][Ia_j][r] * N[v][Ip_j][r] (a >= 2), read from LDS.
 template <int MODE, int U>
-__global__ __launch_bounds__(kBlock) void row_kernel(RowArgs a) {
-    extern __shared__ uint64_t lds[];
-    const int64_t v = blockIdx.x;
+__device__ __forceinline__ void row_body(const RowArgs &a, int64_t v, uint64_t *lds) {
     const int B = a.B;
     const int Lp = a.Wp * B, La = a.Wa * B, Ls = a.Wh * B;
     uint64_t *Nr = lds;
@@ -444,6 +438,16 @@ __global__ __launch_bounds__(kBlock) void row_kernel(RowArgs a) {
     flush_flags(m, a.flags);
 }
 
+template <int MODE, int U>
+__global__ __launch_bounds__(kBlock) void row_kernel(RowArgs a) {
+    extern __shared__ uint64_t lds[];
+    for (int64_t v = blockIdx.x; v < a.n; v += gridDim.x) {
+        row_body<MODE, U>(a, v, lds);
+        __syncthreads();                      // LDS is reused by the next row
+    }
+}
+
+
 // ------------------------------------------------------------------ root reduction
 
 // grid: (blocks, B); block y = colouring r sums entries (v, I) of that colouring.
@@ -501,67 +505,63 @@ hipError_t launch_zero_u64(uint64_t *p, int64_t count, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_color(uint64_t seed, uint64_t first, int64_t n, int B, int k, uint8_t *col,
-                        hipStream_t st) {
+hipError_t launch_color(uint64_t seed, uint64_t first, int64_t n, int B, int k,
+                        const int32_t *perm, uint8_t *col, hipStream_t st) {
     const int64_t total = n * B;
     if (total <= 0) return hipSuccess;
-    color_kernel<<<dim3((unsigned)((total + kBlock - 1) / kBlock)), dim3(kBlock), 0, st>>>(
-        seed, first, n, B, k, col);
+    const int64_t blocks = std::min<int64_t>((total + kBlock - 1) / kBlock, kMaxStrideBlocks);
+    color_kernel<<<dim3((unsigned)blocks), dim3(kBlock), 0, st>>>(seed, first, n, B, k, perm, col);
     return hipGetLastError();
 }
 
-template <int U>
-static hipError_t spmm_tiled_u(const GraphBins &g, bool split_only, const uint64_t *P, uint64_t *N,
-                               int64_t L, int B, int xcd, unsigned long long *flags,
-                               hipStream_t st) {
+template <int Z>
+static hipError_t spmm_narrow_z(const GraphBins &g, bool split_only, const uint64_t *P,
+                                uint64_t *N, int64_t L, int B, unsigned long long *flags,
+                                hipStream_t st) {
     const int32_t *slot = split_only ? g.slot : nullptr;
     if (g.n_split > 0)
         zero_rows_kernel<<<dim3((unsigned)std::min<int64_t>((L + kBlock - 1) / kBlock, 64),
                                 row_grid(g.n_split)), dim3(kBlock), 0, st>>>(
             g.split_rows, g.n_split, slot, N, L);
-    SpmmArgs a;
+    NarrowArgs a;
     a.rp = g.row_ptr; a.ci = g.col_idx;
-    a.light = g.light_rows; a.n_light = split_only ? 0 : g.n_light;
-    a.wide = g.wide_items; a.n_wide = split_only ? g.n_split_items : g.n_wide;
+    a.tasks = g.tasks; a.n_tasks = split_only ? g.n_split_tasks : g.n_tasks;
     a.seg = g.seg; a.slot = slot; a.P = P; a.N = N; a.L = L; a.B = B;
-    a.groups = ((a.n_light + 3) >> 2) + a.n_wide;
-    a.chunks = (L + kWave * U - 1) / (kWave * U);
-    a.xcd = xcd && a.chunks >= 8;
+    a.tiles = (L + Z - 1) / Z;
     a.flags = flags;
-    if (a.groups == 0 || L <= 0) return hipGetLastError();
-    const int64_t blocks = a.xcd ? 8 * ((a.chunks + 7) / 8) * a.groups : a.chunks * a.groups;
-    spmm_tiled_kernel<U><<<dim3((unsigned)blocks), dim3(kBlock), 0, st>>>(a);
+    if (a.n_tasks == 0 || L <= 0) return hipGetLastError();
+    const int64_t waves = a.tiles * a.n_tasks;
+    const int64_t blocks = std::min<int64_t>((waves + kBlock / kWave - 1) / (kBlock / kWave), kMaxStrideBlocks);
+    spmm_narrow_kernel<Z><<<dim3((unsigned)blocks), dim3(kBlock), 0, st>>>(a);
     return hipGetLastError();
 }
 
-static int tiled_u(int64_t L, int chunk_cols) {
-    if (chunk_cols > 0) return chunk_cols >= 256 ? 4 : (chunk_cols >= 128 ? 2 : 1);
-    return L <= 64 ? 1 : (L <= 128 ? 2 : 4);
+static hipError_t spmm_any(int tile_cols, const GraphBins &g, bool split_only, const uint64_t *P,
+                           uint64_t *N, int64_t L, int B, unsigned long long *flags, hipStream_t st) {
+    switch (tile_cols) {
+    case 8: return spmm_narrow_z<8>(g, split_only, P, N, L, B, flags, st);
+    case 32: return spmm_narrow_z<32>(g, split_only, P, N, L, B, flags, st);
+    case 64: return spmm_narrow_z<64>(g, split_only, P, N, L, B, flags, st);
+    default: return spmm_narrow_z<16>(g, split_only, P, N, L, B, flags, st);
+    }
 }
 
 hipError_t launch_spmm(const GraphBins &g, const uint64_t *P, uint64_t *N, int64_t L, int B,
-                       int chunk_cols, int xcd, unsigned long long *flags, hipStream_t st) {
-    switch (tiled_u(L, chunk_cols)) {
-    case 4: return spmm_tiled_u<4>(g, false, P, N, L, B, xcd, flags, st);
-    case 2: return spmm_tiled_u<2>(g, false, P, N, L, B, xcd, flags, st);
-    default: return spmm_tiled_u<1>(g, false, P, N, L, B, xcd, flags, st);
-    }
+                       int tile_cols, unsigned long long *flags, hipStream_t st) {
+    return spmm_any(tile_cols, g, false, P, N, L, B, flags, st);
 }
 
 hipError_t launch_spmm_split(const GraphBins &g, const uint64_t *P, uint64_t *Npre, int64_t L,
-                             int B, unsigned long long *flags, hipStream_t st) {
+                             int B, int tile_cols, unsigned long long *flags, hipStream_t st) {
     if (g.n_split == 0) return hipSuccess;
-    switch (tiled_u(L, 0)) {
-    case 4: return spmm_tiled_u<4>(g, true, P, Npre, L, B, 0, flags, st);
-    case 2: return spmm_tiled_u<2>(g, true, P, Npre, L, B, 0, flags, st);
-    default: return spmm_tiled_u<1>(g, true, P, Npre, L, B, 0, flags, st);
-    }
+    return spmm_any(tile_cols, g, true, P, Npre, L, B, flags, st);
 }
 
 hipError_t launch_hist_split(const GraphBins &g, const uint8_t *col, uint64_t *Npre, int B, int k,
                              hipStream_t st) {
     if (g.n_split == 0) return hipSuccess;
     const int64_t L = (int64_t)k * B;
+    if (g.n_split_items > kMaxGridBlocks) return hipErrorInvalidValue;
     zero_rows_kernel<<<dim3(1, row_grid(g.n_split)), dim3(kBlock), 0, st>>>(
         g.split_rows, g.n_split, g.slot, Npre, L);
     hist_wide_kernel<<<dim3((unsigned)g.n_split_items), dim3(kBlock), (size_t)B * k * sizeof(uint32_t), st>>>(
@@ -576,6 +576,7 @@ hipError_t launch_hist(const GraphBins &g, const uint8_t *col, uint64_t *N, int 
         zero_rows_kernel<<<dim3(1, row_grid(g.n_split)), dim3(kBlock), 0, st>>>(
             g.split_rows, g.n_split, nullptr, N, L);
     }
+    if ((g.n_light + 3) / 4 > kMaxGridBlocks || g.n_wide > kMaxGridBlocks) return hipErrorInvalidValue;
     if (g.n_light > 0) {
         hist_light_kernel<<<dim3((unsigned)((g.n_light + 3) / 4)), dim3(kBlock),
                             (size_t)4 * B * k * sizeof(uint32_t), st>>>(
@@ -617,7 +618,8 @@ int row_max_u() { return 8; }
 
 template <int MODE, int U>
 static void row_u(const RowArgs &a, int64_t n, size_t lds, hipStream_t st) {
-    row_kernel<MODE, U><<<dim3((unsigned)n), dim3(kBlock), lds, st>>>(a);
+    const int64_t blocks = std::min<int64_t>(n, kMaxGridBlocks);
+    row_kernel<MODE, U><<<dim3((unsigned)blocks), dim3(kBlock), lds, st>>>(a);
 }
 
 hipError_t launch_row(int mode, const GraphBins &g, const uint8_t *col, const uint64_t *src,
@@ -630,7 +632,7 @@ hipError_t launch_row(int mode, const GraphBins &g, const uint8_t *col, const ui
     r.slot = mode == kRowStaged ? nullptr : g.slot;
     r.Npre = Npre; r.col = col; r.src = src; r.A = A; r.S = S;
     r.B = B; r.k = k; r.a = a; r.Wa = Wa; r.Wp = Wp; r.Wh = Wh; r.nsplit = nsplit;
-    r.split = split; r.drop = drop; r.flags = flags;
+    r.split = split; r.drop = drop; r.flags = flags; r.n = g.n;
     const size_t lds = (size_t)row_lds_bytes(k, a, Wa, Wp, B, mode);
     const int64_t Lp = (int64_t)Wp * B;
     if (mode == kRowStaged) row_u<kRowStaged, 1>(r, g.n, lds, st);

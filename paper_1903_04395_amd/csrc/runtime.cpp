@@ -29,11 +29,14 @@ struct DevMem {
 struct Graph {
     int64_t n = 0, nnz = 0;
     DevMem rp, ci;
+    DevMem perm;                             // [n] original id of each internal vertex (relabelled graphs)
+    int64_t n_rows = 0;                      // rows of every count table (relabelled graphs
+                                             // drop the isolated vertices, whose rows are 0)
     std::vector<int64_t> deg_host;           // degrees, for re-binning
     // bins for the current segment size
     int seg = 0;
-    DevMem light, wide, split_rows, slot;
-    int64_t n_light = 0, n_wide = 0, n_split = 0, n_split_items = 0;
+    DevMem light, wide, split_rows, slot, tasks;
+    int64_t n_light = 0, n_wide = 0, n_split = 0, n_split_items = 0, n_tasks = 0, n_split_tasks = 0;
 };
 
 struct Template {
@@ -68,8 +71,8 @@ struct sc_ctx {
     std::map<TableKey, DevMem> split_tabs, drop_tabs;
     DevMem arena, colbuf, xbuf, npre;
     // options
-    int64_t max_batch = SC_MAX_BATCH, fused = 1, use_graph = 0, chunk_cols = 0, segment = 0;
-    int64_t xcd = 0, fuse_max_cols = 512;
+    int64_t max_batch = SC_MAX_BATCH, fused = 1, use_graph = 0, tile_cols = 0, segment = 0;
+    int64_t fuse_max_cols = 512, reorder = 1;
     // tracing
     bool prof = false;
     struct Rec { const char *name; hipEvent_t a, b; double bytes, updates; };
@@ -141,26 +144,31 @@ int upload(sc_ctx *c, DevMem &m, const void *host, size_t bytes) {
     return SC_OK;
 }
 
-int default_segment(const sc_ctx *c) { return c->segment > 0 ? (int)c->segment : 1024; }
+int default_segment(const sc_ctx *c) { return c->segment > 0 ? (int)c->segment : 256; }
+int default_tile(const sc_ctx *c) { return c->tile_cols > 0 ? (int)c->tile_cols : 16; }
 
 // Degree bins (see kernels.h): light rows, wide items (split rows first), and
 // the compact slot of every split row for precomputed neighbour sums.
 int rebin(sc_ctx *c, Graph &g, int seg) {
-    if (g.seg == seg && g.light.p) return SC_OK;
+    if (g.seg == seg && g.slot.p) return SC_OK;
     HIPCHK(c, hipStreamSynchronize(c->stream));
     dev_free(c, g.light); dev_free(c, g.wide); dev_free(c, g.split_rows); dev_free(c, g.slot);
-    std::vector<int32_t> light, split_rows, slot(g.n, -1);
-    std::vector<int2> split_items, wide_items;
-    for (int64_t v = 0; v < g.n; ++v) {
-        int64_t d = g.deg_host[v];
-        if (d <= kern::kLightMax) {
-            light.push_back((int32_t)v);
-        } else if (d <= seg) {
-            wide_items.push_back(make_int2((int)v, 0));
+    dev_free(c, g.tasks);
+    std::vector<int32_t> light, split_rows, slot(std::max<int64_t>(g.n_rows, 1), -1);
+    std::vector<int2> split_items, wide_items, split_tasks, tasks;
+    for (int64_t v = 0; v < g.n_rows; ++v) {
+        const int64_t d = g.deg_host[v];
+        if (d <= kern::kLightMax) light.push_back((int32_t)v);
+        else if (d <= seg) wide_items.push_back(make_int2((int)v, 0));
+        if (d <= seg) {
+            tasks.push_back(make_int2((int)v, 0));
         } else {
             slot[v] = (int32_t)split_rows.size();
             split_rows.push_back((int32_t)v);
-            for (int64_t s = 0; s * seg < d; ++s) split_items.push_back(make_int2((int)v, (int)s));
+            for (int64_t s = 0; s * seg < d; ++s) {
+                split_items.push_back(make_int2((int)v, (int)s));
+                split_tasks.push_back(make_int2((int)v, (int)s));
+            }
         }
     }
     g.n_light = (int64_t)light.size();
@@ -169,18 +177,22 @@ int rebin(sc_ctx *c, Graph &g, int seg) {
     std::vector<int2> items = split_items;
     items.insert(items.end(), wide_items.begin(), wide_items.end());
     g.n_wide = (int64_t)items.size();
+    g.n_split_tasks = (int64_t)split_tasks.size();
+    split_tasks.insert(split_tasks.end(), tasks.begin(), tasks.end());
+    g.n_tasks = (int64_t)split_tasks.size();
     int rc;
     if ((rc = upload(c, g.light, light.data(), light.size() * sizeof(int32_t)))) return rc;
     if ((rc = upload(c, g.wide, items.data(), items.size() * sizeof(int2)))) return rc;
     if ((rc = upload(c, g.split_rows, split_rows.data(), split_rows.size() * sizeof(int32_t)))) return rc;
     if ((rc = upload(c, g.slot, slot.data(), slot.size() * sizeof(int32_t)))) return rc;
+    if ((rc = upload(c, g.tasks, split_tasks.data(), split_tasks.size() * sizeof(int2)))) return rc;
     g.seg = seg;
     return SC_OK;
 }
 
 kern::GraphBins bins_of(const Graph &g) {
     kern::GraphBins b;
-    b.n = g.n; b.nnz = g.nnz;
+    b.n = g.n_rows; b.nnz = g.nnz;
     b.row_ptr = (const int64_t *)g.rp.p;
     b.col_idx = (const int32_t *)g.ci.p;
     b.light_rows = (const int32_t *)g.light.p; b.n_light = g.n_light;
@@ -188,6 +200,7 @@ kern::GraphBins bins_of(const Graph &g) {
     b.split_rows = (const int32_t *)g.split_rows.p; b.n_split = g.n_split;
     b.n_split_items = g.n_split_items;
     b.slot = (const int32_t *)g.slot.p;
+    b.tasks = (const int2 *)g.tasks.p; b.n_tasks = g.n_tasks; b.n_split_tasks = g.n_split_tasks;
     b.seg = g.seg;
     return b;
 }
@@ -231,10 +244,11 @@ int make_plan(sc_ctx *c, const Graph &g, const Template &T, int k, int batch, Pl
     std::string err;
     bool ok;
     const ExecOpts o = exec_opts(c);
+    const int64_t rows = std::max<int64_t>(g.n_rows, 1);
     if (T.explicit_plan)
-        ok = build_plan(T.t, T.root, T.child_ptr, T.child_idx, k, g.n, g.nnz, batch, o, P, err);
+        ok = build_plan(T.t, T.root, T.child_ptr, T.child_idx, k, rows, g.nnz, batch, o, P, err);
     else
-        ok = choose_plan(T.t, T.edges.data(), T.root, k, g.n, g.nnz, batch, o, P, err);
+        ok = choose_plan(T.t, T.edges.data(), T.root, k, rows, g.nnz, batch, o, P, err);
     if (!ok) return fail(c, SC_EINVAL, "planning failed: %s", err.c_str());
     return SC_OK;
 }
@@ -245,7 +259,7 @@ int pick_batch(sc_ctx *c, const Graph &g, const Template &T, int k, int want, Pl
     for (int b = want; b >= 1; --b) {
         int rc = make_plan(c, g, T, k, b, P);
         if (rc) return rc;
-        uint64_t need = P.arena_bytes + (uint64_t)g.n * b;
+        uint64_t need = P.arena_bytes + (uint64_t)g.n_rows * b;
         if (need <= c->budget) return SC_OK;
         if (b == 1)
             return fail(c, SC_ENOMEM, "one colouring needs %.3f GB of tables, budget is %.3f GB",
@@ -288,9 +302,13 @@ struct ProfScope {
 int run_pass(sc_ctx *c, Graph &g, const Plan &P, uint64_t first, hipStream_t st,
              uint64_t *counts, uint8_t *flags_out) {
     const int B = P.batch, k = P.k;
-    const int64_t n = g.n;
+    const int64_t n = g.n_rows;            // table rows
     const double dn = (double)n, dnnz = (double)g.nnz;
     int rc;
+    if (P.steps.empty() || n == 0) {       // t == 1: every vertex is a map; no edges: no map
+        for (int r = 0; r < B; ++r) { counts[r] = P.steps.empty() ? (uint64_t)g.n : 0; flags_out[r] = 0; }
+        return SC_OK;
+    }
     if ((rc = rebin(c, g, default_segment(c)))) return rc;
     if ((rc = ensure(c, c->arena, P.arena_bytes))) return rc;
     if ((rc = ensure(c, c->colbuf, (size_t)n * B))) return rc;
@@ -314,12 +332,7 @@ int run_pass(sc_ctx *c, Graph &g, const Plan &P, uint64_t first, hipStream_t st,
     HIPCHK(c, kern::launch_zero_u64((uint64_t *)X, SC_MAX_BATCH + 1, st));
     {
         ProfScope ps(c, st, "color", dn * B, 0);
-        HIPCHK(c, kern::launch_color(c->seed, first, n, B, k, col, st));
-    }
-    if (P.steps.empty()) {           // t == 1: every vertex is a colourful map
-        for (int r = 0; r < B; ++r) { counts[r] = (uint64_t)n; flags_out[r] = 0; }
-        HIPCHK(c, hipStreamSynchronize(st));
-        return SC_OK;
+        HIPCHK(c, kern::launch_color(c->seed, first, n, B, k, (const int32_t *)g.perm.p, col, st));
     }
     const Step *last = nullptr;
     for (const Step &s : P.steps) {
@@ -351,7 +364,7 @@ int run_pass(sc_ctx *c, Graph &g, const Plan &P, uint64_t first, hipStream_t st,
         case kStepFusedGather: {
             if (g.n_split) {
                 ProfScope ps(c, st, "spmm_split", 4.0 * split_nnz + 16.0 * g.n_split * dLp, split_nnz * dLp);
-                HIPCHK(c, kern::launch_spmm_split(bins, Pp, Npre, Lp, B, flags, st));
+                HIPCHK(c, kern::launch_spmm_split(bins, Pp, Npre, Lp, B, default_tile(c), flags, st));
             }
             ProfScope ps(c, st, "row_gather", adj_bytes + 8.0 * dn * dLp + ema_bytes, sp_upd + ema_upd);
             HIPCHK(c, kern::launch_row(kern::kModeGather, bins, col, Pp, Npre, A, S, B, k, s.a,
@@ -364,7 +377,7 @@ int run_pass(sc_ctx *c, Graph &g, const Plan &P, uint64_t first, hipStream_t st,
                 HIPCHK(c, kern::launch_hist(bins, col, N, B, k, st));
             } else {
                 ProfScope ps(c, st, "spmm", adj_bytes + 16.0 * dn * dLp, sp_upd);
-                HIPCHK(c, kern::launch_spmm(bins, Pp, N, Lp, B, (int)c->chunk_cols, (int)c->xcd, flags, st));
+                HIPCHK(c, kern::launch_spmm(bins, Pp, N, Lp, B, default_tile(c), flags, st));
             }
             if (s.mode == kStepStaged) {
                 ProfScope ps(c, st, "row_staged", 8.0 * dn * dLp + ema_bytes, ema_upd);
@@ -441,7 +454,7 @@ int sc_destroy(sc_ctx *c) {
     for (auto &kv : c->graphs) {
         Graph &g = *kv.second;
         dev_free(c, g.rp); dev_free(c, g.ci); dev_free(c, g.light); dev_free(c, g.wide);
-        dev_free(c, g.split_rows); dev_free(c, g.slot);
+        dev_free(c, g.split_rows); dev_free(c, g.slot); dev_free(c, g.perm); dev_free(c, g.tasks);
     }
     for (auto &kv : c->split_tabs) dev_free(c, kv.second);
     for (auto &kv : c->drop_tabs) dev_free(c, kv.second);
@@ -479,11 +492,43 @@ int sc_load_graph_csr(sc_ctx *c, int64_t n, int64_t nnz, const int64_t *rp, cons
     g->n = n;
     g->nnz = nnz;
     g->deg_host.resize(n);
-    for (int64_t v = 0; v < n; ++v) g->deg_host[v] = rp[v + 1] - rp[v];
     int rc;
-    if ((rc = upload(c, g->rp, rp, (size_t)(n + 1) * sizeof(int64_t)))) return rc;
-    if ((rc = upload(c, g->ci, ci, (size_t)nnz * sizeof(int32_t)))) { dev_free(c, g->rp); return rc; }
-    if ((rc = rebin(c, *g, default_segment(c)))) { dev_free(c, g->rp); dev_free(c, g->ci); return rc; }
+    if (c->reorder) {
+        // Relabel by descending degree: the rows that neighbour sums gather most
+        // often become one contiguous region.  Colours are still drawn from the
+        // original ids (perm), so every count is unchanged.
+        std::vector<int32_t> perm(n), inv(n);
+        for (int64_t v = 0; v < n; ++v) perm[v] = (int32_t)v;
+        std::stable_sort(perm.begin(), perm.end(), [&](int32_t x, int32_t y) {
+            return rp[x + 1] - rp[x] > rp[y + 1] - rp[y];
+        });
+        for (int64_t v = 0; v < n; ++v) inv[perm[v]] = (int32_t)v;
+        std::vector<int64_t> nrp(n + 1, 0);
+        for (int64_t v = 0; v < n; ++v) nrp[v + 1] = nrp[v] + (rp[perm[v] + 1] - rp[perm[v]]);
+        std::vector<int32_t> nci((size_t)std::max<int64_t>(nnz, 1));
+        for (int64_t v = 0; v < n; ++v) {
+            const int32_t u = perm[v];
+            int32_t *dst = nci.data() + nrp[v];
+            for (int64_t e = rp[u]; e < rp[u + 1]; ++e) *dst++ = inv[ci[e]];
+            std::sort(nci.data() + nrp[v], nci.data() + nrp[v + 1]);
+        }
+        for (int64_t v = 0; v < n; ++v) g->deg_host[v] = nrp[v + 1] - nrp[v];
+        g->n_rows = 0;
+        while (g->n_rows < n && g->deg_host[g->n_rows] > 0) ++g->n_rows;
+        if ((rc = upload(c, g->rp, nrp.data(), (size_t)(n + 1) * sizeof(int64_t)))) return rc;
+        if ((rc = upload(c, g->ci, nci.data(), (size_t)nnz * sizeof(int32_t)))) { dev_free(c, g->rp); return rc; }
+        if ((rc = upload(c, g->perm, perm.data(), (size_t)n * sizeof(int32_t)))) {
+            dev_free(c, g->rp); dev_free(c, g->ci); return rc;
+        }
+    } else {
+        for (int64_t v = 0; v < n; ++v) g->deg_host[v] = rp[v + 1] - rp[v];
+        g->n_rows = n;
+        if ((rc = upload(c, g->rp, rp, (size_t)(n + 1) * sizeof(int64_t)))) return rc;
+        if ((rc = upload(c, g->ci, ci, (size_t)nnz * sizeof(int32_t)))) { dev_free(c, g->rp); return rc; }
+    }
+    if ((rc = rebin(c, *g, default_segment(c)))) {
+        dev_free(c, g->rp); dev_free(c, g->ci); dev_free(c, g->perm); return rc;
+    }
     *graph_id = c->next_graph++;
     c->graphs[*graph_id] = std::move(g);
     return SC_OK;
@@ -496,7 +541,7 @@ int sc_unload_graph(sc_ctx *c, int32_t id) {
     (void)hipStreamSynchronize(c->stream);
     Graph &g = *it->second;
     dev_free(c, g.rp); dev_free(c, g.ci); dev_free(c, g.light); dev_free(c, g.wide);
-    dev_free(c, g.split_rows); dev_free(c, g.slot);
+    dev_free(c, g.split_rows); dev_free(c, g.slot); dev_free(c, g.perm); dev_free(c, g.tasks);
     c->graphs.erase(it);
     return SC_OK;
 }
@@ -565,17 +610,18 @@ int sc_set_option(sc_ctx *c, int32_t opt, int64_t v) {
         c->max_batch = v; return SC_OK;
     case SC_OPT_FUSED: c->fused = v != 0; return SC_OK;
     case SC_OPT_GRAPH: c->use_graph = v != 0; return SC_OK;
-    case SC_OPT_CHUNK_COLS:
-        if (v < 0) return fail(c, SC_EINVAL, "chunk must be >= 0");
-        c->chunk_cols = v; return SC_OK;
+    case SC_OPT_TILE_COLS:
+        if (v != 0 && v != 8 && v != 16 && v != 32 && v != 64)
+            return fail(c, SC_EINVAL, "tile columns must be 0, 8, 16, 32 or 64");
+        c->tile_cols = v; return SC_OK;
     case SC_OPT_SEGMENT:
         if (v < 0 || v > (1 << 24)) return fail(c, SC_EINVAL, "segment must be in [0, 2^24]");
         if (v > 0 && v <= kern::kLightMax) return fail(c, SC_EINVAL, "segment must exceed %d", kern::kLightMax);
         c->segment = v; return SC_OK;
-    case SC_OPT_XCD: c->xcd = v != 0; return SC_OK;
     case SC_OPT_FUSE_MAX_COLS:
         if (v < 64 || v > 2048) return fail(c, SC_EINVAL, "fuse max columns must be in [64, 2048]");
         c->fuse_max_cols = v; return SC_OK;
+    case SC_OPT_REORDER: c->reorder = v != 0; return SC_OK;
     default: return fail(c, SC_EINVAL, "unknown option %d", opt);
     }
 }
@@ -586,10 +632,10 @@ int sc_get_option(sc_ctx *c, int32_t opt, int64_t *v) {
     case SC_OPT_MAX_BATCH: *v = c->max_batch; return SC_OK;
     case SC_OPT_FUSED: *v = c->fused; return SC_OK;
     case SC_OPT_GRAPH: *v = c->use_graph; return SC_OK;
-    case SC_OPT_CHUNK_COLS: *v = c->chunk_cols; return SC_OK;
+    case SC_OPT_TILE_COLS: *v = default_tile(c); return SC_OK;
     case SC_OPT_SEGMENT: *v = default_segment(c); return SC_OK;
-    case SC_OPT_XCD: *v = c->xcd; return SC_OK;
     case SC_OPT_FUSE_MAX_COLS: *v = c->fuse_max_cols; return SC_OK;
+    case SC_OPT_REORDER: *v = c->reorder; return SC_OK;
     default: return fail(c, SC_EINVAL, "unknown option %d", opt);
     }
 }

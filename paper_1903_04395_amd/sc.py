@@ -14,14 +14,14 @@ import numpy as np
 
 __all__ = [
     "SC_OK", "SC_EINVAL", "SC_ENOMEM", "SC_EDEVICE", "SC_ENOTFOUND", "SC_EBUSY", "SC_ESTATE",
-    "SC_OPT_MAX_BATCH", "SC_OPT_FUSED", "SC_OPT_GRAPH", "SC_OPT_CHUNK_COLS", "SC_OPT_SEGMENT",
-    "SC_OPT_XCD", "SC_OPT_FUSE_MAX_COLS", "OPTION_DEFAULTS", "ScError", "PlanInfo", "KernelStat", "lib", "lib_path", "sc_version", "sc_plan_template",
+    "SC_OPT_MAX_BATCH", "SC_OPT_FUSED", "SC_OPT_GRAPH", "SC_OPT_TILE_COLS", "SC_OPT_SEGMENT",
+    "SC_OPT_FUSE_MAX_COLS", "SC_OPT_REORDER", "OPTION_DEFAULTS", "ScError", "PlanInfo", "KernelStat", "lib", "lib_path", "sc_version", "sc_plan_template",
     "sc_colorset_rank", "sc_color_of", "Context",
 ]
 
 SC_OK, SC_EINVAL, SC_ENOMEM, SC_EDEVICE, SC_ENOTFOUND, SC_EBUSY, SC_ESTATE = 0, -1, -2, -3, -4, -5, -6
-SC_OPT_MAX_BATCH, SC_OPT_FUSED, SC_OPT_GRAPH, SC_OPT_CHUNK_COLS, SC_OPT_SEGMENT = 1, 2, 3, 4, 5
-SC_OPT_XCD, SC_OPT_FUSE_MAX_COLS = 6, 7
+SC_OPT_MAX_BATCH, SC_OPT_FUSED, SC_OPT_GRAPH, SC_OPT_TILE_COLS, SC_OPT_SEGMENT = 1, 2, 3, 4, 5
+SC_OPT_FUSE_MAX_COLS, SC_OPT_REORDER = 7, 8
 SC_MAX_T = 16
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -86,8 +86,8 @@ class KernelStat(ctypes.Structure):
     ]
 
 
-OPTION_DEFAULTS = {SC_OPT_MAX_BATCH: 64, SC_OPT_FUSED: 1, SC_OPT_GRAPH: 0, SC_OPT_CHUNK_COLS: 0,
-                   SC_OPT_SEGMENT: 0, SC_OPT_XCD: 0, SC_OPT_FUSE_MAX_COLS: 512}
+OPTION_DEFAULTS = {SC_OPT_MAX_BATCH: 64, SC_OPT_FUSED: 1, SC_OPT_GRAPH: 0, SC_OPT_TILE_COLS: 0,
+                   SC_OPT_SEGMENT: 0, SC_OPT_FUSE_MAX_COLS: 512, SC_OPT_REORDER: 1}
 
 
 class ScError(RuntimeError):

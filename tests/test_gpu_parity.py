@@ -117,10 +117,10 @@ def test_segment_sizes_agree(ctx, seg):
     run_both(ctx, g, 8, I.prufer_tree(8, 10), 8, 12, 0, 4, opts={sc.SC_OPT_SEGMENT: seg})
 
 
-@pytest.mark.parametrize("cols", [64, 128, 256])
-def test_chunk_widths_agree(ctx, cols):
+@pytest.mark.parametrize("cols", [8, 16, 32, 64])
+def test_tile_widths_agree(ctx, cols):
     g = I.rmat(11, 16, seed=12)
-    run_both(ctx, g, 9, I.prufer_tree(9, 12), 9, 13, 0, 5, opts={sc.SC_OPT_CHUNK_COLS: cols})
+    run_both(ctx, g, 9, I.prufer_tree(9, 12), 9, 13, 0, 5, opts={sc.SC_OPT_TILE_COLS: cols})
 
 
 # ------------------------------------------------------------------ overflow and edge cases
@@ -208,3 +208,17 @@ def test_full_config2_batch_and_plan_invariance(ctx):
     c2, _, _, _ = ctx.run(gid, tid2, 0, 8)
     assert np.array_equal(c8, c2)
     ctx.unload_graph(gid)
+
+
+def test_relabelling_does_not_change_results(ctx):
+    """Graphs are kept relabelled by descending degree unless SC_OPT_REORDER is
+    0; colours follow the caller's ids, so residues and flags agree."""
+    g = I.rmat(12, 16, seed=21)
+    out = []
+    for reorder in (0, 1):
+        ctx.set_option(sc.SC_OPT_REORDER, reorder)
+        gid = ctx.load_graph(g)
+        out.append(run_both(ctx, g, 9, I.prufer_tree(9, 21), 9, 3, 0, 6, gid=gid)[:2])
+        ctx.unload_graph(gid)
+    ctx.set_option(sc.SC_OPT_REORDER, 1)
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
