@@ -30,7 +30,7 @@ PEAK_HBM_GBS = 8000.0
 
 # HIP kernel behind each libsc kernel family
 KERNEL_OF = {
-    "spmm": "spmm_tiled_kernel", "spmm_split": "spmm_tiled_kernel",
+    "spmm": "spmm_tiled_kernel<2, false>", "spmm_split": "spmm_tiled_kernel<2, true>",
     "row_gather": "row_kernel<1,U>", "row_hist": "row_kernel<2,1>", "row_staged": "row_kernel<0,1>",
     "hist": "hist_light_kernel/hist_wide_kernel", "hist_split": "hist_wide_kernel",
     "select": "select_kernel", "ema": "ema_kernel", "reduce": "reduce_kernel", "color": "color_kernel",

@@ -182,8 +182,8 @@ enum {
     SC_OPT_FUSED = 2,         /* 1 (default): fused neighbour-sum + multiply-add
                                  row kernels where the rows fit; 0: never      */
     SC_OPT_GRAPH = 3,         /* 1: replay each pass from a captured hipGraph   */
-    SC_OPT_TILE_COLS = 4,     /* neighbour-sum column tile: 8, 16, 32 or 64 uint64
-                                 (0 = default, 16)                             */
+    SC_OPT_TILE_COLS = 4,     /* neighbour-sum column tile: 8, 16, 32, 64, 128 or
+                                 256 uint64 (0 = default, 128)                 */
     SC_OPT_SEGMENT = 5,       /* neighbours per work item of heavy rows, > 64
                                  (0 = default, 256)                            */
     SC_OPT_FUSE_MAX_COLS = 7, /* widest passive row (uint64) the fused neighbour

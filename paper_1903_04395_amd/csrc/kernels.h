@@ -39,10 +39,17 @@ struct GraphBins {
 hipError_t launch_color(uint64_t seed, uint64_t first, int64_t n, int B, int k,
                         const int32_t *perm, uint8_t *col, hipStream_t st);
 
-// N = A * P for a table with L = W*B uint64 columns per row, in column tiles
-// of tile_cols = 8, 16, 32 or 64 uint64.
+// N = A * P for a table with L = W*B uint64 columns per row (the split rows of
+// N must be zeroed first, see launch_zero_split_rows), in column tiles
+// of tile_cols = 8, 16, 32 (lane groups over several neighbours) or 64, 128,
+// 256 (wavefront-wide row slices) uint64.
 hipError_t launch_spmm(const GraphBins &g, const uint64_t *P, uint64_t *N, int64_t L, int B,
                        int tile_cols, unsigned long long *flags, hipStream_t st);
+
+// Zeroes the split rows of N (compact: rows of Npre[n_split][L]) before the
+// neighbour sums of their segments add into them.
+hipError_t launch_zero_split_rows(const GraphBins &g, bool compact, uint64_t *N, int64_t L,
+                                  hipStream_t st);
 
 // Neighbour sums of the split rows only, into the compact Npre[n_split][L].
 hipError_t launch_spmm_split(const GraphBins &g, const uint64_t *P, uint64_t *Npre, int64_t L,

@@ -117,6 +117,117 @@ __device__ __forceinline__ void gather_rows(int64_t e0, int64_t e1, int step,
     }
 }
 
+struct SpmmArgs {
+    const int64_t *rp;
+    const int32_t *ci;
+    const int32_t *light;  int64_t n_light;   // light rows, 4 per workgroup
+    const int2 *wide;      int64_t n_wide;    // (row, segment) items, 1 per workgroup
+    int seg;
+    const int32_t *slot;                      // optional output-row redirect
+    const uint64_t *P;
+    uint64_t *N;
+    int64_t L;
+    int B;
+    int64_t groups;                           // light groups + wide items
+    int64_t chunks;                           // column chunks of 64*U
+    unsigned long long *flags;
+};
+
+// Neighbour sum N = A * P, tiled by column chunks of 64*U uint64 (a 2 KB
+// contiguous slice of every gathered row for U = 4) and walked chunk-major so
+// that the rows in flight read one chunk.  Light rows: one wavefront each,
+// four per workgroup.  Wide items: four wavefronts split the neighbours and
+// meet in LDS; rows with more than `seg` neighbours are split over several
+// items whose partial sums meet in global atomics (the carry is read from the
+// returned old value).  The grid strides over (chunk, group) items.
+template <int U>
+__device__ __forceinline__ void spmm_tiled_item(const SpmmArgs &a, int64_t chunk, int64_t g,
+                                                uint64_t (*red)[U][kWave], uint32_t (*redc)[kWave]) {
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t c0 = chunk * (kWave * U) + lane;
+    bool inb[U];
+    uint64_t acc[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) { inb[u] = c0 + kWave * u < a.L; acc[u] = 0; }
+    uint32_t carry = 0;
+    const int64_t nlg = (a.n_light + 3) >> 2;
+    if (g < nlg) {
+        const int64_t li = g * 4 + wave;
+        if (li >= a.n_light) return;                   // whole wavefront, this item only
+        const int v = __builtin_amdgcn_readfirstlane(a.light[li]);
+        gather_rows<U>(a.rp[v], a.rp[v + 1], 1, a.ci, a.P, a.L, c0, inb, acc, carry);
+        uint64_t *d = a.N + (int64_t)v * a.L + c0;
+        uint64_t m = 0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (inb[u]) d[kWave * u] = acc[u];
+            if (carry & (1u << u)) m |= 1ull << ((c0 + kWave * u) % a.B);
+        }
+        flush_flags(m, a.flags);
+        return;
+    }
+    const int2 it = a.wide[g - nlg];
+    const int v = __builtin_amdgcn_readfirstlane(it.x);
+    const int64_t r0 = a.rp[v], r1 = a.rp[v + 1];
+    const int64_t e0 = r0 + (int64_t)it.y * a.seg;
+    const int64_t e1 = min(e0 + a.seg, r1);
+    const bool split = (r1 - r0) > a.seg;
+    gather_rows<U>(e0 + wave, e1, kBlock / kWave, a.ci, a.P, a.L, c0, inb, acc, carry);
+    if (wave > 0) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) red[wave - 1][u][lane] = acc[u];
+        redc[wave - 1][lane] = carry;
+    }
+    __syncthreads();
+    if (wave == 0) {
+#pragma unroll
+        for (int w = 0; w < kBlock / kWave - 1; ++w) {
+            carry |= redc[w][lane];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint64_t x = red[w][u][lane];
+                const uint64_t t = acc[u] + x;
+                carry |= (uint32_t)(t < x) << u;
+                acc[u] = t;
+            }
+        }
+        const int64_t orow = a.slot ? (int64_t)a.slot[v] : (int64_t)v;
+        uint64_t *d = a.N + orow * a.L + c0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (!inb[u]) continue;
+            if (split) {
+                const unsigned long long old = atomicAdd((unsigned long long *)(d + kWave * u),
+                                                         (unsigned long long)acc[u]);
+                if ((uint64_t)old + acc[u] < (uint64_t)old) carry |= 1u << u;
+            } else {
+                d[kWave * u] = acc[u];
+            }
+        }
+        uint64_t m = 0;
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (carry & (1u << u)) m |= 1ull << ((c0 + kWave * u) % a.B);
+        flush_flags(m, a.flags);
+    }
+}
+
+// PRE (a distinct instantiation, so profiles tell the two apart): the pre-pass
+// that sums only the split rows into the compact buffer.
+template <int U, bool PRE>
+__global__ __launch_bounds__(kBlock) void spmm_tiled_kernel(SpmmArgs a) {
+    __shared__ uint64_t red[kBlock / kWave - 1][U][kWave];
+    __shared__ uint32_t redc[kBlock / kWave - 1][kWave];
+    const int64_t total = a.chunks * a.groups;
+    const int64_t nlg = (a.n_light + 3) >> 2;
+    for (int64_t b = blockIdx.x; b < total; b += gridDim.x) {
+        const int64_t chunk = b / a.groups, g = b - chunk * a.groups;
+        spmm_tiled_item<U>(a, chunk, g, red, redc);
+        if (g >= nlg) __syncthreads();                 // red/redc reused by the next wide item
+    }
+}
+
 __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t x, int mask) {
     const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)x, mask, kWave);
     const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(x >> 32), mask, kWave);
@@ -514,15 +625,32 @@ hipError_t launch_color(uint64_t seed, uint64_t first, int64_t n, int B, int k,
     return hipGetLastError();
 }
 
+template <int U>
+static hipError_t spmm_tiled_u(const GraphBins &g, bool split_only, const uint64_t *P, uint64_t *N,
+                               int64_t L, int B, unsigned long long *flags, hipStream_t st) {
+    const int32_t *slot = split_only ? g.slot : nullptr;
+    SpmmArgs a;
+    a.rp = g.row_ptr; a.ci = g.col_idx;
+    a.light = g.light_rows; a.n_light = split_only ? 0 : g.n_light;
+    a.wide = g.wide_items; a.n_wide = split_only ? g.n_split_items : g.n_wide;
+    a.seg = g.seg; a.slot = slot; a.P = P; a.N = N; a.L = L; a.B = B;
+    a.groups = ((a.n_light + 3) >> 2) + a.n_wide;
+    a.chunks = (L + kWave * U - 1) / (kWave * U);
+    a.flags = flags;
+    if (a.groups == 0 || L <= 0) return hipGetLastError();
+    // one workgroup per item while the grid allows it (the dispatcher then
+    // balances uneven items); beyond that the workgroups stride
+    const int64_t blocks = std::min<int64_t>(a.chunks * a.groups, kMaxGridBlocks);
+    if (split_only) spmm_tiled_kernel<U, true><<<dim3((unsigned)blocks), dim3(kBlock), 0, st>>>(a);
+    else spmm_tiled_kernel<U, false><<<dim3((unsigned)blocks), dim3(kBlock), 0, st>>>(a);
+    return hipGetLastError();
+}
+
 template <int Z>
 static hipError_t spmm_narrow_z(const GraphBins &g, bool split_only, const uint64_t *P,
                                 uint64_t *N, int64_t L, int B, unsigned long long *flags,
                                 hipStream_t st) {
     const int32_t *slot = split_only ? g.slot : nullptr;
-    if (g.n_split > 0)
-        zero_rows_kernel<<<dim3((unsigned)std::min<int64_t>((L + kBlock - 1) / kBlock, 64),
-                                row_grid(g.n_split)), dim3(kBlock), 0, st>>>(
-            g.split_rows, g.n_split, slot, N, L);
     NarrowArgs a;
     a.rp = g.row_ptr; a.ci = g.col_idx;
     a.tasks = g.tasks; a.n_tasks = split_only ? g.n_split_tasks : g.n_tasks;
@@ -531,7 +659,7 @@ static hipError_t spmm_narrow_z(const GraphBins &g, bool split_only, const uint6
     a.flags = flags;
     if (a.n_tasks == 0 || L <= 0) return hipGetLastError();
     const int64_t waves = a.tiles * a.n_tasks;
-    const int64_t blocks = std::min<int64_t>((waves + kBlock / kWave - 1) / (kBlock / kWave), kMaxStrideBlocks);
+    const int64_t blocks = std::min<int64_t>((waves + kBlock / kWave - 1) / (kBlock / kWave), kMaxGridBlocks);
     spmm_narrow_kernel<Z><<<dim3((unsigned)blocks), dim3(kBlock), 0, st>>>(a);
     return hipGetLastError();
 }
@@ -540,10 +668,21 @@ static hipError_t spmm_any(int tile_cols, const GraphBins &g, bool split_only, c
                            uint64_t *N, int64_t L, int B, unsigned long long *flags, hipStream_t st) {
     switch (tile_cols) {
     case 8: return spmm_narrow_z<8>(g, split_only, P, N, L, B, flags, st);
+    case 16: return spmm_narrow_z<16>(g, split_only, P, N, L, B, flags, st);
     case 32: return spmm_narrow_z<32>(g, split_only, P, N, L, B, flags, st);
-    case 64: return spmm_narrow_z<64>(g, split_only, P, N, L, B, flags, st);
-    default: return spmm_narrow_z<16>(g, split_only, P, N, L, B, flags, st);
+    case 64: return spmm_tiled_u<1>(g, split_only, P, N, L, B, flags, st);
+    case 128: return spmm_tiled_u<2>(g, split_only, P, N, L, B, flags, st);
+    default: return spmm_tiled_u<4>(g, split_only, P, N, L, B, flags, st);
     }
+}
+
+hipError_t launch_zero_split_rows(const GraphBins &g, bool compact, uint64_t *N, int64_t L,
+                                  hipStream_t st) {
+    if (g.n_split == 0 || L <= 0) return hipSuccess;
+    zero_rows_kernel<<<dim3((unsigned)std::min<int64_t>((L + kBlock - 1) / kBlock, 64),
+                            row_grid(g.n_split)), dim3(kBlock), 0, st>>>(
+        g.split_rows, g.n_split, compact ? g.slot : nullptr, N, L);
+    return hipGetLastError();
 }
 
 hipError_t launch_spmm(const GraphBins &g, const uint64_t *P, uint64_t *N, int64_t L, int B,

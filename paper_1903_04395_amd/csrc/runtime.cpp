@@ -145,7 +145,7 @@ int upload(sc_ctx *c, DevMem &m, const void *host, size_t bytes) {
 }
 
 int default_segment(const sc_ctx *c) { return c->segment > 0 ? (int)c->segment : 256; }
-int default_tile(const sc_ctx *c) { return c->tile_cols > 0 ? (int)c->tile_cols : 16; }
+int default_tile(const sc_ctx *c) { return c->tile_cols > 0 ? (int)c->tile_cols : 128; }
 
 // Degree bins (see kernels.h): light rows, wide items (split rows first), and
 // the compact slot of every split row for precomputed neighbour sums.
@@ -363,6 +363,7 @@ int run_pass(sc_ctx *c, Graph &g, const Plan &P, uint64_t first, hipStream_t st,
         }
         case kStepFusedGather: {
             if (g.n_split) {
+                HIPCHK(c, kern::launch_zero_split_rows(bins, true, Npre, Lp, st));
                 ProfScope ps(c, st, "spmm_split", 4.0 * split_nnz + 16.0 * g.n_split * dLp, split_nnz * dLp);
                 HIPCHK(c, kern::launch_spmm_split(bins, Pp, Npre, Lp, B, default_tile(c), flags, st));
             }
@@ -376,6 +377,7 @@ int run_pass(sc_ctx *c, Graph &g, const Plan &P, uint64_t first, hipStream_t st,
                 ProfScope ps(c, st, "hist", adj_bytes + dn * B + 8.0 * dn * dLp, sp_upd);
                 HIPCHK(c, kern::launch_hist(bins, col, N, B, k, st));
             } else {
+                HIPCHK(c, kern::launch_zero_split_rows(bins, false, N, Lp, st));
                 ProfScope ps(c, st, "spmm", adj_bytes + 16.0 * dn * dLp, sp_upd);
                 HIPCHK(c, kern::launch_spmm(bins, Pp, N, Lp, B, default_tile(c), flags, st));
             }
@@ -611,8 +613,8 @@ int sc_set_option(sc_ctx *c, int32_t opt, int64_t v) {
     case SC_OPT_FUSED: c->fused = v != 0; return SC_OK;
     case SC_OPT_GRAPH: c->use_graph = v != 0; return SC_OK;
     case SC_OPT_TILE_COLS:
-        if (v != 0 && v != 8 && v != 16 && v != 32 && v != 64)
-            return fail(c, SC_EINVAL, "tile columns must be 0, 8, 16, 32 or 64");
+        if (v != 0 && v != 8 && v != 16 && v != 32 && v != 64 && v != 128 && v != 256)
+            return fail(c, SC_EINVAL, "tile columns must be 0, 8, 16, 32, 64, 128 or 256");
         c->tile_cols = v; return SC_OK;
     case SC_OPT_SEGMENT:
         if (v < 0 || v > (1 << 24)) return fail(c, SC_EINVAL, "segment must be in [0, 2^24]");

@@ -117,7 +117,7 @@ def test_segment_sizes_agree(ctx, seg):
     run_both(ctx, g, 8, I.prufer_tree(8, 10), 8, 12, 0, 4, opts={sc.SC_OPT_SEGMENT: seg})
 
 
-@pytest.mark.parametrize("cols", [8, 16, 32, 64])
+@pytest.mark.parametrize("cols", [8, 16, 32, 64, 128, 256])
 def test_tile_widths_agree(ctx, cols):
     g = I.rmat(11, 16, seed=12)
     run_both(ctx, g, 9, I.prufer_tree(9, 12), 9, 13, 0, 5, opts={sc.SC_OPT_TILE_COLS: cols})
