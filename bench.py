@@ -47,7 +47,20 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--opt", action="append", default=[], help="libsc option NUM=VALUE (ablation)")
     ap.add_argument("--breakdown", action="store_true", help="also print the per-family table")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy 1 GiB three times (calibrates rocprofv3 FETCH_SIZE/WRITE_SIZE)")
     return ap.parse_args()
+
+
+def copy_probe():
+    import torch
+    a = torch.empty(1 << 27, dtype=torch.int64, device="cuda")   # 1 GiB
+    a.fill_(1)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": 1 << 30, "copies": 3}), flush=True)
 
 
 def source_hash():
@@ -76,6 +89,9 @@ def traffic_for(family):
 
 def main():
     args = parse()
+    if args.copy_probe:
+        copy_probe()
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the method's multi-GPU "
               "split (colourings across GPUs) is described in DESIGN.md but not built.", file=sys.stderr)
@@ -133,6 +149,9 @@ def main():
         "avg_launch_ms": round(dom["total_ms"] / dom["launches"], 4),
         "alg_bytes_per_launch": dom["alg_bytes"] / dom["launches"],
         "share_of_gpu_time": round(dom["total_ms"] / sum(f["total_ms"] for f in fams.values()), 3),
+        # every neighbour-sum update reads one gathered 8-byte word
+        "gathered_GBps": round(dom["updates"] * 8 / (dom["total_ms"] / 1e3) / 1e9, 1)
+        if dom_name.startswith("spmm") else None,
     }
     out = {
         "metric": "SpMM+eMA G-updates/s & colorings/s (bit-exact); p50/p99 query latency",
@@ -147,6 +166,7 @@ def main():
                    "colorings_per_step": B, "root": info.root, "steps": info.steps(),
                    "modes": info.modes()},
         "roofline": roofline,
+        "families_ms_per_step": {k: round(v["total_ms"] / args.steps, 2) for k, v in fams.items()},
     }
     if args.breakdown:
         print(json.dumps({"breakdown": fams}), file=sys.stderr, flush=True)
