@@ -175,6 +175,89 @@ int sc_run(sc_ctx *ctx, int32_t graph_id, int32_t tmpl_id, uint64_t first_colori
            int32_t n_colorings, void *stream, uint64_t *counts, uint8_t *overflow,
            double *est_maps, double *est_copies);
 
+/* Batched form: many jobs -- each a (graph, template, k, seed, colouring range)
+ * -- planned together and run back to back on one stream with a single host
+ * wait at the end (colourings folded into the table columns, up to the
+ * planned batch per pass; with SC_OPT_GRAPH each pass replays a captured
+ * hipGraph).  Jobs may mix templates of different sizes and different k.
+ * Host outputs per job: counts[n_colorings], overflow[n_colorings],
+ * est_maps / est_copies (NaN if any colouring overflowed), status.
+ * Returns SC_OK, or the first job's error (that job's status is set, the
+ * others still run). */
+typedef struct {
+    int32_t graph_id, tmpl_id, k;
+    uint64_t seed, first_coloring;
+    int32_t n_colorings;
+    uint64_t *counts;
+    uint8_t *overflow;
+    double est_maps, est_copies;   /* out */
+    int32_t status;                /* out */
+} sc_job_t;
+int sc_run_batch(sc_ctx *ctx, sc_job_t *jobs, int32_t n_jobs, void *stream);
+
+/* Autotuner: times real passes of (graph, template) at the batch `n_colorings`
+ * plans to, over neighbour-sum tile widths {64, 128, 256} and fused-row
+ * limits {256, 512, 1024}, and keeps the fastest for that (graph, template,
+ * k, batch).  The choice never changes a result. */
+typedef struct {
+    int32_t tile_cols, fuse_max_cols, batch, trials;
+    double ms;                      /* time of one pass with the chosen knobs */
+} sc_tune_t;
+int sc_autotune(sc_ctx *ctx, int32_t graph_id, int32_t tmpl_id, int32_t n_colorings, sc_tune_t *out);
+/* Tuning cache as text lines keyed by graph shape (n, nnz, max degree),
+ * template edges, k and batch.  Load applies entries to loaded graphs and
+ * templates that match; *n_applied (may be NULL) counts them. */
+int sc_tune_save(sc_ctx *ctx, const char *path);
+int sc_tune_load(sc_ctx *ctx, const char *path, int32_t *n_applied);
+
+/* ------------------------------------------------------------------ serving */
+
+/* Serving loop with continuous batching.  A worker thread owns `max_inflight`
+ * HIP streams.  Submitted queries wait in FIFO order; whenever a stream is
+ * free, the head query gets a pass of as many of its colourings as fit the
+ * device memory still free under `mem_budget_bytes` (0 = the context budget),
+ * so a query that arrives while others run starts as soon as a stream and
+ * memory free up, and passes of different queries overlap on the device.
+ * Results do not depend on how a query was split or what ran beside it.
+ * sc_submit / sc_poll / sc_serve_stats may be called from any thread;
+ * sc_serve_stop waits for every submitted query (poll results first: stop
+ * discards them).  While the loop runs, options other than SC_OPT_GRAPH
+ * cannot change and graphs with passes in flight cannot be unloaded. */
+typedef struct {
+    uint64_t mem_budget_bytes;
+    int32_t max_inflight;           /* streams, 1..16 */
+    int32_t max_batch;              /* colourings per pass, 1..SC_MAX_BATCH */
+} sc_serve_cfg_t;
+
+typedef struct {
+    int32_t graph_id, tmpl_id, k;
+    uint64_t seed, first_coloring;
+    int32_t n_colorings;            /* >= 1 */
+} sc_query_t;
+
+typedef struct {
+    int32_t status;                 /* SC_OK or the query's error */
+    int32_t n_colorings;
+    uint64_t *counts;               /* caller buffers of n_colorings (or NULL) */
+    uint8_t *overflow;
+    double est_maps, est_copies;
+    double submit_s, start_s, done_s;   /* steady-clock seconds */
+} sc_result_t;
+
+typedef struct {
+    uint64_t passes, colorings;
+    int32_t waiting, inflight;
+    uint64_t mem_bytes, peak_mem_bytes;
+} sc_serve_stats_t;
+
+int sc_serve_start(sc_ctx *ctx, const sc_serve_cfg_t *cfg);
+int sc_submit(sc_ctx *ctx, const sc_query_t *query, uint64_t *ticket);
+/* SC_EBUSY until the query is done; then fills *out (copying counts and
+ * overflow into the caller's buffers) and releases the ticket. */
+int sc_poll(sc_ctx *ctx, uint64_t ticket, sc_result_t *out);
+int sc_serve_stats(sc_ctx *ctx, sc_serve_stats_t *out);
+int sc_serve_stop(sc_ctx *ctx);
+
 /* Execution options (for measurement and ablation; none changes a result).
  * Errors: SC_EINVAL (unknown option or value out of range). */
 enum {

@@ -1,0 +1,482 @@
+// libsc executor: one pass = colourings first..first+B-1 folded into the table
+// columns, run as the plan's kernel sequence (directly, or replayed from a
+// captured hipGraph).  sc_run chains passes without host round trips;
+// sc_run_batch does the same for many (graph, template, k, seed) jobs at
+// once; sc_autotune picks tile and fusion widths by timing real passes.
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <functional>
+
+#include "rt.h"
+
+namespace sc {
+
+namespace {
+
+std::atomic<uint64_t> g_buffer_generation{1};
+
+hipEvent_t next_event(sc_ctx *c) {
+    if (c->events_used == c->event_pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        c->event_pool.push_back(e);
+    }
+    return c->event_pool[c->events_used++];
+}
+
+// Brackets one launch with HIP events on its stream while profiling is on.
+struct ProfScope {
+    sc_ctx *c;
+    hipStream_t st;
+    const char *name;
+    double bytes, updates;
+    hipEvent_t a = nullptr;
+    ProfScope(sc_ctx *c_, bool on, hipStream_t st_, const char *n, double by, double up)
+        : c(c_), st(st_), name(n), bytes(by), updates(up) {
+        if (on && (a = next_event(c))) (void)hipEventRecord(a, st);
+    }
+    ~ProfScope() {
+        if (!a) return;
+        hipEvent_t b = next_event(c);
+        if (!b) return;
+        (void)hipEventRecord(b, st);
+        c->recs.push_back({name, a, b, bytes, updates});
+    }
+};
+
+int ensure_gen(sc_ctx *c, DevMem &m, size_t bytes, hipStream_t st, PassBuffers &b) {
+    if (m.p && m.bytes >= bytes) return SC_OK;
+    uint64_t dummy = 0;
+    int rc = ensure(c, m, bytes, st, &dummy);
+    b.gen = g_buffer_generation.fetch_add(1);
+    return rc;
+}
+
+size_t npre_bytes(const Graph &g, const Plan &P) {
+    size_t w = 0;
+    for (const Step &s : P.steps)
+        if (s.mode == kStepFusedHist || s.mode == kStepFusedGather)
+            w = std::max(w, (size_t)g.n_split * binom(P.k, s.p) * P.batch);
+    return w * 8;
+}
+
+}  // namespace
+
+int prepare_pass(sc_ctx *c, const PassSpec &s, PassBuffers &b, hipStream_t st) {
+    Graph &g = *s.g;
+    const Plan &P = *s.P;
+    int rc;
+    if ((rc = rebin(c, g, default_segment(c)))) return rc;
+    if ((rc = ensure_gen(c, b.arena, P.arena_bytes, st, b))) return rc;
+    if ((rc = ensure_gen(c, b.colbuf, (size_t)g.n_rows * P.batch, st, b))) return rc;
+    if ((rc = ensure_gen(c, b.xbuf, (SC_MAX_BATCH + 1) * sizeof(uint64_t), st, b))) return rc;
+    if ((rc = ensure_gen(c, b.desc, 2 * sizeof(uint64_t), st, b))) return rc;
+    const size_t np = npre_bytes(g, P);
+    if (np && (rc = ensure_gen(c, b.npre, np, st, b))) return rc;
+    for (const Step &st_ : P.steps) {
+        const uint32_t *split;
+        const int16_t *drop;
+        if (st_.a > 1) { if ((rc = get_split(c, P.k, st_.h, st_.a, &split))) return rc; }
+        else { if ((rc = get_drop(c, P.k, st_.h, &drop))) return rc; }
+    }
+    return SC_OK;
+}
+
+int enqueue_pass(sc_ctx *c, const PassSpec &sp, PassBuffers &pb, hipStream_t st, bool prof) {
+    Graph &g = *sp.g;
+    const Plan &P = *sp.P;
+    const int B = P.batch, k = P.k;
+    const int64_t n = g.n_rows;
+    const double dn = (double)n, dnnz = (double)g.nnz;
+    int rc;
+    auto *X = (unsigned long long *)pb.xbuf.p;
+    auto *flags = X + SC_MAX_BATCH;
+    auto *col = (uint8_t *)pb.colbuf.p;
+    auto *base = (uint8_t *)pb.arena.p;
+    auto *Npre = (uint64_t *)pb.npre.p;
+    auto buf = [&](int id) { return id < 0 ? (uint64_t *)nullptr : (uint64_t *)(base + P.bufs[id].offset); };
+    const kern::GraphBins bins = bins_of(g);
+    const double adj_bytes = 4.0 * dnnz + 8.0 * (dn + 1);
+    const double split_nnz = g.split_nnz;
+
+    HIPCHK(c, kern::launch_zero_u64((uint64_t *)X, SC_MAX_BATCH + 1, st));
+    {
+        ProfScope ps(c, prof, st, "color", dn * B, 0);
+        HIPCHK(c, kern::launch_color((const uint64_t *)pb.desc.p, n, B, k, (const int32_t *)g.perm.p, col, st));
+    }
+    const Step *last = nullptr;
+    for (const Step &s : P.steps) {
+        const int Wa = (int)binom(k, s.a), Wp = (int)binom(k, s.p), Wh = (int)binom(k, s.h);
+        const int64_t Lp = (int64_t)Wp * B;
+        const double La = (double)Wa * B, Ls = (double)Wh * B, dLp = (double)Lp;
+        const int nsplit = (int)binom(s.h, s.a);
+        uint64_t *N = buf(s.buf_n);
+        uint64_t *S = buf(s.buf_s);
+        const uint64_t *Pp = buf(s.buf_p), *A = buf(s.buf_a);
+        const uint32_t *split = nullptr;
+        const int16_t *drop = nullptr;
+        if (s.a > 1) { if ((rc = get_split(c, k, s.h, s.a, &split))) return rc; }
+        else { if ((rc = get_drop(c, k, s.h, &drop))) return rc; }
+        const double ema_upd = s.a > 1 ? dn * Ls * nsplit : dn * Ls;
+        const double ema_bytes = 8.0 * dn * ((s.a > 1 ? La : 0) + Ls) + (s.a == 1 ? dn * B : 0);
+        const double sp_upd = dnnz * dLp;
+        switch (s.mode) {
+        case kStepFusedHist: {
+            if (g.n_split) {
+                ProfScope ps(c, prof, st, "hist_split", 4.0 * split_nnz + 8.0 * g.n_split * dLp, split_nnz * dLp);
+                HIPCHK(c, kern::launch_hist_split(bins, col, Npre, B, k, st));
+            }
+            ProfScope ps(c, prof, st, "row_hist", adj_bytes + dn * B + ema_bytes, sp_upd + ema_upd);
+            HIPCHK(c, kern::launch_row(kern::kModeHist, bins, col, nullptr, Npre, A, S, B, k, s.a,
+                                       Wa, Wp, Wh, nsplit, split, drop, flags, st));
+            break;
+        }
+        case kStepFusedGather: {
+            if (g.n_split) {
+                HIPCHK(c, kern::launch_zero_split_rows(bins, true, Npre, Lp, st));
+                ProfScope ps(c, prof, st, "spmm_split", 4.0 * split_nnz + 16.0 * g.n_split * dLp, split_nnz * dLp);
+                HIPCHK(c, kern::launch_spmm_split(bins, Pp, Npre, Lp, B, sp.tile_cols, flags, st));
+            }
+            ProfScope ps(c, prof, st, "row_gather", adj_bytes + 8.0 * dn * dLp + ema_bytes, sp_upd + ema_upd);
+            HIPCHK(c, kern::launch_row(kern::kModeGather, bins, col, Pp, Npre, A, S, B, k, s.a,
+                                       Wa, Wp, Wh, nsplit, split, drop, flags, st));
+            break;
+        }
+        default: {
+            if (s.p == 1) {
+                ProfScope ps(c, prof, st, "hist", adj_bytes + dn * B + 8.0 * dn * dLp, sp_upd);
+                HIPCHK(c, kern::launch_hist(bins, col, N, B, k, st));
+            } else {
+                HIPCHK(c, kern::launch_zero_split_rows(bins, false, N, Lp, st));
+                ProfScope ps(c, prof, st, "spmm", adj_bytes + 16.0 * dn * dLp, sp_upd);
+                HIPCHK(c, kern::launch_spmm(bins, Pp, N, Lp, B, sp.tile_cols, flags, st));
+            }
+            if (s.mode == kStepStaged) {
+                ProfScope ps(c, prof, st, "row_staged", 8.0 * dn * dLp + ema_bytes, ema_upd);
+                HIPCHK(c, kern::launch_row(kern::kModeStaged, bins, col, N, nullptr, A, S, B, k, s.a,
+                                           Wa, Wp, Wh, nsplit, split, drop, flags, st));
+            } else if (s.a == 1) {
+                ProfScope ps(c, prof, st, "select", 8.0 * dn * dLp + ema_bytes, ema_upd);
+                HIPCHK(c, kern::launch_select(n, col, N, S, B, k, Wh, Wp, drop, st));
+            } else {
+                ProfScope ps(c, prof, st, "ema", 8.0 * dn * dLp + ema_bytes, ema_upd);
+                HIPCHK(c, kern::launch_ema(n, A, N, S, B, Wa, Wp, Wh, nsplit, split, flags, st));
+            }
+        }
+        }
+        last = &s;
+    }
+    const int W = (int)binom(k, last->h);
+    ProfScope ps(c, prof, st, "reduce", 8.0 * dn * W * B, 0);
+    HIPCHK(c, kern::launch_reduce(n, buf(last->buf_s), W, B, X, flags, st));
+    return SC_OK;
+}
+
+void unpack_pass(const uint64_t *host_res, int B, uint64_t *counts, uint8_t *flags) {
+    for (int r = 0; r < B; ++r) {
+        counts[r] = host_res[r];
+        flags[r] = (uint8_t)((host_res[SC_MAX_BATCH] >> r) & 1);
+    }
+}
+
+int launch_pass(sc_ctx *c, int gid, int tid, const PassSpec &s, PassBuffers &b, hipStream_t st,
+                uint64_t *host_desc, uint64_t *host_res, bool allow_graph) {
+    const Plan &P = *s.P;
+    if (P.steps.empty() || s.g->n_rows == 0) {   // t = 1: every vertex is a map; no edge: no map
+        for (int r = 0; r < SC_MAX_BATCH; ++r) host_res[r] = P.steps.empty() ? (uint64_t)s.g->n : 0;
+        host_res[SC_MAX_BATCH] = 0;
+        return SC_OK;
+    }
+    int rc;
+    if ((rc = prepare_pass(c, s, b, st))) return rc;
+    host_desc[0] = s.seed;
+    host_desc[1] = s.first;
+    HIPCHK(c, hipMemcpyAsync(b.desc.p, host_desc, 2 * sizeof(uint64_t), hipMemcpyHostToDevice, st));
+    if (allow_graph && c->use_graph && !c->prof) {
+        GraphExecKey key{gid, tid, P.k, P.batch, s.tile_cols, P.opts.fuse ? P.opts.fuse_max_cols : 0,
+                         s.g->seg, b.gen};
+        auto it = c->graph_cache.find(key);
+        if (it == c->graph_cache.end()) {
+            hipGraph_t graph = nullptr;
+            HIPCHK(c, hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
+            rc = enqueue_pass(c, s, b, st, false);
+            hipError_t e = hipStreamEndCapture(st, &graph);
+            if (rc) { if (graph) (void)hipGraphDestroy(graph); return rc; }
+            if (e != hipSuccess) return fail(c, SC_EDEVICE, "hipStreamEndCapture failed: %s", hipGetErrorString(e));
+            hipGraphExec_t exec = nullptr;
+            e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) return fail(c, SC_EDEVICE, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
+            it = c->graph_cache.emplace(key, exec).first;
+        }
+        HIPCHK(c, hipGraphLaunch(it->second, st));
+    } else {
+        if ((rc = enqueue_pass(c, s, b, st, c->prof))) return rc;
+    }
+    HIPCHK(c, hipMemcpyAsync(host_res, b.xbuf.p, (SC_MAX_BATCH + 1) * sizeof(uint64_t),
+                             hipMemcpyDeviceToHost, st));
+    return SC_OK;
+}
+
+}  // namespace sc
+
+using namespace sc;
+
+namespace {
+
+constexpr size_t kStageWords = 2 + SC_MAX_BATCH + 1;   // descriptor + results of one pass
+
+struct PassJob {
+    int job, gid, tid, k;
+    uint64_t seed, first;
+    int offset;                // first colouring of this pass within its job
+    Plan P;
+    int tile;
+};
+
+// Plans every pass of the jobs, runs them back to back on `st` and waits once.
+int run_passes(sc_ctx *c, std::vector<PassJob> &passes, hipStream_t st,
+               const std::function<void(const PassJob &, const uint64_t *)> &done) {
+    int rc;
+    if ((rc = host_staging(c, std::max<size_t>(1, passes.size()) * kStageWords))) return rc;
+    // size the buffers for the largest pass first, so no buffer moves mid-chain
+    size_t arena = 0, colb = 0, npre = 0;
+    for (auto &p : passes) {
+        const Graph &g = *c->graphs[p.gid];
+        arena = std::max<size_t>(arena, p.P.arena_bytes);
+        colb = std::max<size_t>(colb, (size_t)g.n_rows * p.P.batch);
+        npre = std::max<size_t>(npre, npre_bytes(g, p.P));
+    }
+    PassBuffers &b = c->main;
+    if ((rc = ensure_gen(c, b.arena, arena, st, b))) return rc;
+    if ((rc = ensure_gen(c, b.colbuf, colb, st, b))) return rc;
+    if (npre && (rc = ensure_gen(c, b.npre, npre, st, b))) return rc;
+    for (size_t i = 0; i < passes.size(); ++i) {
+        auto &p = passes[i];
+        PassSpec s;
+        s.g = c->graphs[p.gid].get();
+        s.P = &p.P;
+        s.k = p.k;
+        s.seed = p.seed;
+        s.first = p.first;
+        s.tile_cols = p.tile;
+        uint64_t *stage = c->host_out + i * kStageWords;
+        if ((rc = launch_pass(c, p.gid, p.tid, s, b, st, stage, stage + 2, true))) return rc;
+    }
+    HIPCHK(c, hipStreamSynchronize(st));
+    for (size_t i = 0; i < passes.size(); ++i) done(passes[i], c->host_out + i * kStageWords + 2);
+    return SC_OK;
+}
+
+// Splits n colourings of one job into passes of the planned batch.
+int plan_job(sc_ctx *c, int job, int gid, int tid, int k, uint64_t seed, uint64_t first, int n,
+             std::vector<PassJob> &out) {
+    int off = 0;
+    while (off < n) {
+        PassJob p;
+        p.job = job; p.gid = gid; p.tid = tid; p.k = k; p.seed = seed;
+        p.first = first + (uint64_t)off;
+        p.offset = off;
+        int rc = pick_batch(c, gid, tid, k, n - off, 0, p.P, &p.tile);
+        if (rc) return rc;
+        off += p.P.batch;
+        out.push_back(std::move(p));
+    }
+    return SC_OK;
+}
+
+void estimates(const uint64_t *counts, const uint8_t *ovf, int n, int k, int t, double aut,
+               double *maps, double *copies) {
+    bool any = false;
+    double sum = 0;
+    for (int i = 0; i < n; ++i) { any |= ovf[i] != 0; sum += (double)counts[i]; }
+    double m = NAN, cp = NAN;
+    if (n > 0 && !any) {
+        m = sum / n / colorful_probability(k, t);
+        cp = m / aut;
+    }
+    if (maps) *maps = m;
+    if (copies) *copies = cp;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sc_run(sc_ctx *c, int32_t gid, int32_t tid, uint64_t first, int32_t ncol, void *stream,
+           uint64_t *counts, uint8_t *overflow, double *est_maps, double *est_copies) {
+    if (!c) return SC_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    if (ncol < 0) return fail(c, SC_EINVAL, "n_colorings < 0");
+    if (ncol > 0 && (!counts || !overflow)) return fail(c, SC_EINVAL, "NULL output");
+    auto gi = c->graphs.find(gid);
+    if (gi == c->graphs.end()) return fail(c, SC_ENOTFOUND, "unknown graph %d", gid);
+    auto ti = c->tmpls.find(tid);
+    if (ti == c->tmpls.end()) return fail(c, SC_ENOTFOUND, "unknown template %d", tid);
+    if (c->k < ti->second->t) return fail(c, SC_EINVAL, "k=%d < t=%d (call sc_set_colors)", c->k, ti->second->t);
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, SC_EDEVICE, "hipSetDevice failed");
+    hipStream_t st = stream ? (hipStream_t)stream : c->stream;
+    std::vector<PassJob> passes;
+    int rc = plan_job(c, 0, gid, tid, c->k, c->seed, first, ncol, passes);
+    if (rc) return rc;
+    rc = run_passes(c, passes, st, [&](const PassJob &p, const uint64_t *res) {
+        unpack_pass(res, p.P.batch, counts + p.offset, overflow + p.offset);
+    });
+    if (rc) return rc;
+    estimates(counts, overflow, ncol, c->k, ti->second->t, ti->second->aut, est_maps, est_copies);
+    return SC_OK;
+}
+
+int sc_run_batch(sc_ctx *c, sc_job_t *jobs, int32_t n_jobs, void *stream) {
+    if (!c) return SC_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    if (n_jobs < 0 || (n_jobs > 0 && !jobs)) return fail(c, SC_EINVAL, "bad job array");
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, SC_EDEVICE, "hipSetDevice failed");
+    hipStream_t st = stream ? (hipStream_t)stream : c->stream;
+    std::vector<PassJob> passes;
+    int first_err = SC_OK;
+    std::string first_msg;
+    for (int j = 0; j < n_jobs; ++j) {
+        sc_job_t &J = jobs[j];
+        J.status = SC_OK;
+        J.est_maps = J.est_copies = NAN;
+        int rc = SC_OK;
+        if (J.n_colorings < 0 || (J.n_colorings > 0 && (!J.counts || !J.overflow)))
+            rc = fail(c, SC_EINVAL, "job %d: bad colouring count or NULL output", j);
+        std::vector<PassJob> mine;
+        if (!rc) rc = plan_job(c, j, J.graph_id, J.tmpl_id, J.k, J.seed, J.first_coloring, J.n_colorings, mine);
+        if (rc) {
+            J.status = rc;
+            if (!first_err) { first_err = rc; first_msg = c->err; }
+            continue;
+        }
+        for (auto &p : mine) passes.push_back(std::move(p));
+    }
+    int rc = run_passes(c, passes, st, [&](const PassJob &p, const uint64_t *res) {
+        sc_job_t &J = jobs[p.job];
+        unpack_pass(res, p.P.batch, J.counts + p.offset, J.overflow + p.offset);
+    });
+    if (rc) {
+        for (int j = 0; j < n_jobs; ++j) if (jobs[j].status == SC_OK) jobs[j].status = rc;
+        return rc;
+    }
+    for (int j = 0; j < n_jobs; ++j) {
+        sc_job_t &J = jobs[j];
+        if (J.status) continue;
+        const Template &T = *c->tmpls[J.tmpl_id];
+        estimates(J.counts, J.overflow, J.n_colorings, J.k, T.t, T.aut, &J.est_maps, &J.est_copies);
+    }
+    if (first_err) c->err = first_msg;
+    return first_err;
+}
+
+int sc_autotune(sc_ctx *c, int32_t gid, int32_t tid, int32_t n_colorings, sc_tune_t *out) {
+    if (!c) return SC_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    if (!out) return fail(c, SC_EINVAL, "NULL argument");
+    Plan P;
+    int rc = pick_batch(c, gid, tid, c->k, std::max(1, n_colorings), 0, P, nullptr);
+    if (rc) return rc;
+    const int B = P.batch;
+    const TuneKey key{gid, tid, c->k, B};
+    c->tuned.erase(key);
+    static const int tiles[] = {64, 128, 256};
+    static const int fuses[] = {256, 512, 1024};
+    std::vector<uint64_t> counts(B);
+    std::vector<uint8_t> ovf(B);
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    Tuned best;
+    best.ms = 1e300;
+    int trials = 0;
+    for (int tile : tiles)
+        for (int fuse : fuses) {
+            Tuned cand;
+            cand.tile_cols = tile;
+            cand.fuse_max_cols = fuse;
+            c->tuned[key] = cand;
+            std::vector<PassJob> passes;
+            if ((rc = plan_job(c, 0, gid, tid, c->k, c->seed, 0, B, passes))) break;
+            auto sink = [&](const PassJob &, const uint64_t *) {};
+            if ((rc = run_passes(c, passes, c->stream, sink))) break;          // warm
+            HIPCHK(c, hipEventRecord(e0, c->stream));
+            if ((rc = run_passes(c, passes, c->stream, sink))) break;
+            HIPCHK(c, hipEventRecord(e1, c->stream));
+            HIPCHK(c, hipEventSynchronize(e1));
+            float ms = 0;
+            HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+            ++trials;
+            if (ms < best.ms) { best = cand; best.ms = ms; }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) { c->tuned.erase(key); return rc; }
+    c->tuned[key] = best;
+    out->tile_cols = best.tile_cols;
+    out->fuse_max_cols = best.fuse_max_cols;
+    out->batch = B;
+    out->ms = best.ms;
+    out->trials = trials;
+    return SC_OK;
+}
+
+int sc_tune_save(sc_ctx *c, const char *path) {
+    if (!c) return SC_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    if (!path) return fail(c, SC_EINVAL, "NULL path");
+    FILE *f = fopen(path, "w");
+    if (!f) return fail(c, SC_EINVAL, "cannot write %s", path);
+    for (auto &kv : c->tuned) {
+        auto gi = c->graphs.find(std::get<0>(kv.first));
+        auto ti = c->tmpls.find(std::get<1>(kv.first));
+        if (gi == c->graphs.end() || ti == c->tmpls.end()) continue;
+        const Graph &g = *gi->second;
+        const Template &T = *ti->second;
+        fprintf(f, "%lld %lld %lld %d %d %d %d %d %.6f", (long long)g.n, (long long)g.nnz,
+                (long long)g.max_deg, std::get<2>(kv.first), std::get<3>(kv.first),
+                kv.second.tile_cols, kv.second.fuse_max_cols, T.t, kv.second.ms);
+        for (int32_t e : T.edges) fprintf(f, " %d", e);
+        fprintf(f, "\n");
+    }
+    fclose(f);
+    return SC_OK;
+}
+
+int sc_tune_load(sc_ctx *c, const char *path, int32_t *n_applied) {
+    if (!c) return SC_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    if (!path) return fail(c, SC_EINVAL, "NULL path");
+    FILE *f = fopen(path, "r");
+    if (!f) return fail(c, SC_ENOTFOUND, "cannot read %s", path);
+    int applied = 0;
+    long long n, nnz, maxd;
+    int k, B, tile, fuse, t;
+    double ms;
+    while (fscanf(f, "%lld %lld %lld %d %d %d %d %d %lf", &n, &nnz, &maxd, &k, &B, &tile, &fuse, &t, &ms) == 9) {
+        if (t < 1 || t > SC_MAX_T) break;
+        std::vector<int32_t> e(2 * (t - 1));
+        bool ok = true;
+        for (auto &x : e) ok &= fscanf(f, "%d", &x) == 1;
+        if (!ok) break;
+        for (auto &gk : c->graphs)
+            for (auto &tk : c->tmpls) {
+                const Graph &g = *gk.second;
+                if (g.n != n || g.nnz != nnz || g.max_deg != maxd || tk.second->edges != e) continue;
+                Tuned tu;
+                tu.tile_cols = tile;
+                tu.fuse_max_cols = fuse;
+                tu.ms = ms;
+                c->tuned[TuneKey{gk.first, tk.first, k, B}] = tu;
+                ++applied;
+            }
+    }
+    fclose(f);
+    if (n_applied) *n_applied = applied;
+    return SC_OK;
+}
+
+}  // extern "C"

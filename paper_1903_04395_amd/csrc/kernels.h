@@ -35,9 +35,10 @@ struct GraphBins {
 };
 
 // col[v*B + r] = colour of vertex v in colouring first+r (SplitMix64 rule),
-// drawn from the original id perm[v] when the graph was relabelled (perm != NULL).
-hipError_t launch_color(uint64_t seed, uint64_t first, int64_t n, int B, int k,
-                        const int32_t *perm, uint8_t *col, hipStream_t st);
+// drawn from the original id perm[v] when the graph was relabelled (perm != NULL);
+// desc[0] = seed and desc[1] = first live in device memory.
+hipError_t launch_color(const uint64_t *desc, int64_t n, int B, int k, const int32_t *perm,
+                        uint8_t *col, hipStream_t st);
 
 // N = A * P for a table with L = W*B uint64 columns per row (the split rows of
 // N must be zeroed first, see launch_zero_split_rows), in column tiles

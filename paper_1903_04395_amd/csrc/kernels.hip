@@ -57,10 +57,12 @@ __device__ __forceinline__ uint64_t mad_ovf(uint64_t acc, uint64_t a, uint64_t b
 // ------------------------------------------------------------------ colours
 
 // col[v*B + r]: colour of internal vertex v (original id perm[v], or v) in
-// colouring first + r.
-__global__ __launch_bounds__(kBlock) void color_kernel(uint64_t seed, uint64_t first, int64_t n,
+// colouring first + r, with desc = {seed, first} read from device memory so a
+// captured pass can be replayed for any colouring range.
+__global__ __launch_bounds__(kBlock) void color_kernel(const uint64_t *__restrict__ desc, int64_t n,
                                                       int B, int k, const int32_t *__restrict__ perm,
                                                       uint8_t *__restrict__ col) {
+    const uint64_t seed = desc[0], first = desc[1];
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n * B;
          i += (int64_t)gridDim.x * kBlock) {
         const int64_t v = i / B;
@@ -616,12 +618,12 @@ hipError_t launch_zero_u64(uint64_t *p, int64_t count, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_color(uint64_t seed, uint64_t first, int64_t n, int B, int k,
-                        const int32_t *perm, uint8_t *col, hipStream_t st) {
+hipError_t launch_color(const uint64_t *desc, int64_t n, int B, int k, const int32_t *perm,
+                        uint8_t *col, hipStream_t st) {
     const int64_t total = n * B;
     if (total <= 0) return hipSuccess;
     const int64_t blocks = std::min<int64_t>((total + kBlock - 1) / kBlock, kMaxStrideBlocks);
-    color_kernel<<<dim3((unsigned)blocks), dim3(kBlock), 0, st>>>(seed, first, n, B, k, perm, col);
+    color_kernel<<<dim3((unsigned)blocks), dim3(kBlock), 0, st>>>(desc, n, B, k, perm, col);
     return hipGetLastError();
 }
 

@@ -232,20 +232,30 @@ bool choose_plan(int t, const int32_t *edges, int root, int k, int64_t n, int64_
     std::string m = check_tree(t, edges);
     if (!m.empty()) { err = m; return false; }
     if (root >= t) { err = "root out of range"; return false; }
+    // The rooted tree is chosen on the cost of one colouring, so the same
+    // template gets the same plan (and the same overflow flags) at any batch.
     bool found = false;
+    double best_cost = 0;
+    uint64_t best_arena = 0;
+    std::vector<int> best_cp, best_ci;
+    int best_root = 0;
     for (int r = (root < 0 ? 0 : root); r < (root < 0 ? t : root + 1); ++r)
         for (int order = 0; order < 2; ++order) {
             std::vector<int> cp, ci;
             root_tree(t, edges, r, order, cp, ci);
             Plan p;
-            if (!build_plan(t, r, cp, ci, k, n, nnz, batch, o, p, err)) return false;
-            if (!found || p.cost < out.cost ||
-                (p.cost == out.cost && p.arena_bytes < out.arena_bytes)) {
-                out = p;
+            if (!build_plan(t, r, cp, ci, k, n, nnz, 1, o, p, err)) return false;
+            if (!found || p.cost < best_cost || (p.cost == best_cost && p.arena_bytes < best_arena)) {
+                best_cost = p.cost;
+                best_arena = p.arena_bytes;
+                best_cp = cp;
+                best_ci = ci;
+                best_root = r;
                 found = true;
             }
         }
-    return found;
+    if (!found) return false;
+    return build_plan(t, best_root, best_cp, best_ci, k, n, nnz, batch, o, out, err);
 }
 
 // Automorphisms of an unrooted tree: root it at its centre (or cut the central

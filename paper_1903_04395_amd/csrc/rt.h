@@ -1,0 +1,177 @@
+// Internal runtime state of libsc shared by runtime.cpp (contexts, graphs,
+// templates, options, tracing), exec.cpp (passes, batches, hipGraph replay,
+// autotuning) and serve.cpp (the serving loop).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "kernels.h"
+#include "sc_internal.h"
+
+namespace sc {
+
+struct DevMem {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+struct Graph {
+    int64_t n = 0, nnz = 0;
+    DevMem rp, ci;
+    DevMem perm;                 // [n] caller id of each internal vertex (relabelled graphs)
+    int64_t n_rows = 0;          // rows of every count table (relabelled graphs drop the
+                                 // isolated vertices, whose rows are identically 0)
+    int64_t max_deg = 0;
+    std::vector<int64_t> deg_host;
+    // degree bins for the current segment size
+    int seg = 0;
+    DevMem light, wide, split_rows, slot, tasks;
+    int64_t n_light = 0, n_wide = 0, n_split = 0, n_split_items = 0, n_tasks = 0, n_split_tasks = 0;
+    double split_nnz = 0;
+    int busy = 0;                // passes of the serving loop in flight on this graph
+};
+
+struct Template {
+    int t = 0;
+    std::vector<int32_t> edges;  // 2*(t-1), caller ids
+    int root = -1;               // requested root (-1: planner chooses)
+    bool explicit_plan = false;
+    std::vector<int> child_ptr, child_idx;
+    double aut = 1.0;
+};
+
+struct TableKey {
+    int k, h, a;
+    bool operator<(const TableKey &o) const { return std::tie(k, h, a) < std::tie(o.k, o.h, o.a); }
+};
+
+// Tuned execution knobs for one (graph, template, k, batch).
+struct Tuned {
+    int tile_cols = 0;
+    int fuse_max_cols = 0;
+    double ms = 0;
+};
+using TuneKey = std::tuple<int, int, int, int>;   // graph id, template id, k, batch
+
+// What one pass computes.
+struct PassSpec {
+    Graph *g = nullptr;
+    const Plan *P = nullptr;
+    int k = 0;
+    uint64_t seed = 0, first = 0;
+    int tile_cols = 128;
+};
+
+// Device buffers one in-flight pass uses besides the resident graph and the
+// index tables.  `gen` changes whenever one of them is reallocated (captured
+// graphs that baked the old addresses are then discarded).
+struct PassBuffers {
+    DevMem arena, colbuf, xbuf, npre, desc;
+    uint64_t gen = 0;
+};
+
+struct GraphExecKey {
+    int graph_id, tmpl_id, k, batch, tile, fuse_max, seg;
+    uint64_t bufgen;
+    bool operator<(const GraphExecKey &o) const {
+        return std::tie(graph_id, tmpl_id, k, batch, tile, fuse_max, seg, bufgen) <
+               std::tie(o.graph_id, o.tmpl_id, o.k, o.batch, o.tile, o.fuse_max, o.seg, o.bufgen);
+    }
+};
+
+struct ServeState;   // serve.cpp
+
+}  // namespace sc
+
+struct sc_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    sc_alloc_fn alloc = nullptr;
+    sc_free_fn free_fn = nullptr;
+    void *user = nullptr;
+    uint64_t budget = 0;
+    std::string err;
+    int k = 0;
+    uint64_t seed = 0;
+    std::map<int, std::unique_ptr<sc::Graph>> graphs;
+    std::map<int, std::unique_ptr<sc::Template>> tmpls;
+    int next_graph = 1, next_tmpl = 1;
+    std::map<sc::TableKey, sc::DevMem> split_tabs, drop_tabs;
+    sc::PassBuffers main;                 // buffers of the synchronous calls
+    uint64_t *host_out = nullptr;         // pinned staging for results and descriptors
+    size_t host_out_words = 0;
+    std::map<sc::GraphExecKey, hipGraphExec_t> graph_cache;
+    std::map<sc::TuneKey, sc::Tuned> tuned;
+    // options
+    int64_t max_batch = SC_MAX_BATCH, fused = 1, use_graph = 0, tile_cols = 0, segment = 0;
+    int64_t fuse_max_cols = 512, reorder = 1;
+    // tracing
+    bool prof = false;
+    struct Rec { const char *name; hipEvent_t a, b; double bytes, updates; };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> event_pool;
+    size_t events_used = 0;
+    // the serving loop and the lock it shares with the caller's thread
+    std::recursive_mutex mu;
+    sc::ServeState *serve = nullptr;      // owned; created by sc_serve_start, freed by serve_shutdown
+};
+
+namespace sc {
+
+int fail(sc_ctx *c, int code, const char *fmt, ...);
+
+#define HIPCHK(ctx, expr)                                                                    \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return ::sc::fail(ctx, SC_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+int dev_alloc(sc_ctx *c, DevMem &m, size_t bytes);
+void dev_free(sc_ctx *c, DevMem &m);
+// Grows m to at least `bytes` (contents not kept); waits for `st` before freeing.
+int ensure(sc_ctx *c, DevMem &m, size_t bytes, hipStream_t st, uint64_t *gen = nullptr);
+int upload(sc_ctx *c, DevMem &m, const void *host, size_t bytes);
+int host_staging(sc_ctx *c, size_t words);
+
+int default_segment(const sc_ctx *c);
+int default_tile(const sc_ctx *c);
+int rebin(sc_ctx *c, Graph &g, int seg);
+kern::GraphBins bins_of(const Graph &g);
+int get_split(sc_ctx *c, int k, int h, int a, const uint32_t **out);
+int get_drop(sc_ctx *c, int k, int h, const int16_t **out);
+
+// Execution options for (graph, template, k, batch): context defaults,
+// overridden by tuned values.
+ExecOpts exec_opts(const sc_ctx *c, int gid, int tid, int k, int batch, int *tile_cols);
+int make_plan(sc_ctx *c, const Graph &g, const Template &T, const ExecOpts &o, int k, int batch,
+              Plan &P);
+// Largest batch <= want whose pass fits `budget` bytes (0: the context budget).
+int pick_batch(sc_ctx *c, int gid, int tid, int k, int want, uint64_t budget, Plan &P,
+               int *tile_cols);
+uint64_t pass_bytes(const Graph &g, const Plan &P);
+double colorful_probability(int k, int t);
+
+// Allocations and uploads a pass needs (not capturable).
+int prepare_pass(sc_ctx *c, const PassSpec &s, PassBuffers &b, hipStream_t st);
+// The pass's kernels on `st`, reading seed and first colouring from b.desc
+// (capturable).  `prof` brackets launches with events.
+int enqueue_pass(sc_ctx *c, const PassSpec &s, PassBuffers &b, hipStream_t st, bool prof);
+// Everything for one pass on `st`: descriptor upload from host_desc[0..1],
+// the kernels (direct or from a captured hipGraph), and the copy of
+// SC_MAX_BATCH + 1 result words into host_res.
+int launch_pass(sc_ctx *c, int gid, int tid, const PassSpec &s, PassBuffers &b, hipStream_t st,
+                uint64_t *host_desc, uint64_t *host_res, bool allow_graph);
+void unpack_pass(const uint64_t *host_res, int B, uint64_t *counts, uint8_t *flags);
+
+void serve_shutdown(sc_ctx *c);
+
+}  // namespace sc

@@ -1,87 +1,14 @@
-// libsc runtime: contexts, resident graphs and templates, the per-pass DP
-// executor and the C ABI of include/sc.h.
-#include <hip/hip_runtime.h>
-
+// libsc runtime: contexts, device memory, resident graphs and templates,
+// options, tracing, planning queries, and the C ABI for all of them.
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
-#include <map>
-#include <memory>
-#include <mutex>
-#include <string>
-#include <tuple>
-#include <vector>
 
-#include "kernels.h"
-#include "sc_internal.h"
+#include "rt.h"
 
-using namespace sc;
-
-namespace {
-
-struct DevMem {
-    void *p = nullptr;
-    size_t bytes = 0;
-};
-
-struct Graph {
-    int64_t n = 0, nnz = 0;
-    DevMem rp, ci;
-    DevMem perm;                             // [n] original id of each internal vertex (relabelled graphs)
-    int64_t n_rows = 0;                      // rows of every count table (relabelled graphs
-                                             // drop the isolated vertices, whose rows are 0)
-    std::vector<int64_t> deg_host;           // degrees, for re-binning
-    // bins for the current segment size
-    int seg = 0;
-    DevMem light, wide, split_rows, slot, tasks;
-    int64_t n_light = 0, n_wide = 0, n_split = 0, n_split_items = 0, n_tasks = 0, n_split_tasks = 0;
-};
-
-struct Template {
-    int t = 0;
-    std::vector<int32_t> edges;     // 2*(t-1)
-    int root = -1;                  // requested root (-1: planner)
-    bool explicit_plan = false;
-    std::vector<int> child_ptr, child_idx;
-    double aut = 1.0;
-};
-
-struct TableKey {
-    int k, h, a;
-    bool operator<(const TableKey &o) const { return std::tie(k, h, a) < std::tie(o.k, o.h, o.a); }
-};
-
-}  // namespace
-
-struct sc_ctx {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    sc_alloc_fn alloc = nullptr;
-    sc_free_fn free_fn = nullptr;
-    void *user = nullptr;
-    uint64_t budget = 0;
-    std::string err;
-    int k = 0;
-    uint64_t seed = 0;
-    std::map<int, std::unique_ptr<Graph>> graphs;
-    std::map<int, std::unique_ptr<Template>> tmpls;
-    int next_graph = 1, next_tmpl = 1;
-    std::map<TableKey, DevMem> split_tabs, drop_tabs;
-    DevMem arena, colbuf, xbuf, npre;
-    // options
-    int64_t max_batch = SC_MAX_BATCH, fused = 1, use_graph = 0, tile_cols = 0, segment = 0;
-    int64_t fuse_max_cols = 512, reorder = 1;
-    // tracing
-    bool prof = false;
-    struct Rec { const char *name; hipEvent_t a, b; double bytes, updates; };
-    std::vector<Rec> recs;
-    std::vector<hipEvent_t> event_pool;
-    size_t events_used = 0;
-};
-
-namespace {
+namespace sc {
 
 int fail(sc_ctx *c, int code, const char *fmt, ...) {
     char buf[512];
@@ -92,13 +19,6 @@ int fail(sc_ctx *c, int code, const char *fmt, ...) {
     if (c) c->err = buf;
     return code;
 }
-
-#define HIPCHK(ctx, expr)                                                                   \
-    do {                                                                                    \
-        hipError_t e_ = (expr);                                                             \
-        if (e_ != hipSuccess)                                                               \
-            return fail(ctx, SC_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));     \
-    } while (0)
 
 int dev_alloc(sc_ctx *c, DevMem &m, size_t bytes) {
     if (bytes == 0) bytes = 256;
@@ -126,13 +46,13 @@ void dev_free(sc_ctx *c, DevMem &m) {
     m.bytes = 0;
 }
 
-// Grows `m` to at least `bytes` (contents are not preserved).
-int ensure(sc_ctx *c, DevMem &m, size_t bytes) {
+int ensure(sc_ctx *c, DevMem &m, size_t bytes, hipStream_t st, uint64_t *gen) {
     if (m.p && m.bytes >= bytes) return SC_OK;
     if (m.p) {
-        if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(c, SC_EDEVICE, "stream sync failed");
+        HIPCHK(c, hipStreamSynchronize(st));
         dev_free(c, m);
     }
+    if (gen) ++*gen;
     return dev_alloc(c, m, bytes);
 }
 
@@ -144,18 +64,36 @@ int upload(sc_ctx *c, DevMem &m, const void *host, size_t bytes) {
     return SC_OK;
 }
 
+int host_staging(sc_ctx *c, size_t words) {
+    if (c->host_out && c->host_out_words >= words) return SC_OK;
+    if (c->host_out) {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        (void)hipHostFree(c->host_out);
+        c->host_out = nullptr;
+        c->host_out_words = 0;
+    }
+    void *p = nullptr;
+    HIPCHK(c, hipHostMalloc(&p, words * sizeof(uint64_t), hipHostMallocDefault));
+    c->host_out = (uint64_t *)p;
+    c->host_out_words = words;
+    return SC_OK;
+}
+
 int default_segment(const sc_ctx *c) { return c->segment > 0 ? (int)c->segment : 256; }
 int default_tile(const sc_ctx *c) { return c->tile_cols > 0 ? (int)c->tile_cols : 128; }
 
-// Degree bins (see kernels.h): light rows, wide items (split rows first), and
-// the compact slot of every split row for precomputed neighbour sums.
+// Degree bins (see kernels.h): light rows, wide items (split rows first),
+// neighbour-sum tasks (split rows first), and the compact slot of every split
+// row for precomputed neighbour sums.
 int rebin(sc_ctx *c, Graph &g, int seg) {
     if (g.seg == seg && g.slot.p) return SC_OK;
-    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (g.busy) return fail(c, SC_ESTATE, "segment size cannot change while the serving loop uses the graph");
+    HIPCHK(c, hipDeviceSynchronize());
     dev_free(c, g.light); dev_free(c, g.wide); dev_free(c, g.split_rows); dev_free(c, g.slot);
     dev_free(c, g.tasks);
     std::vector<int32_t> light, split_rows, slot(std::max<int64_t>(g.n_rows, 1), -1);
     std::vector<int2> split_items, wide_items, split_tasks, tasks;
+    g.split_nnz = 0;
     for (int64_t v = 0; v < g.n_rows; ++v) {
         const int64_t d = g.deg_host[v];
         if (d <= kern::kLightMax) light.push_back((int32_t)v);
@@ -165,6 +103,7 @@ int rebin(sc_ctx *c, Graph &g, int seg) {
         } else {
             slot[v] = (int32_t)split_rows.size();
             split_rows.push_back((int32_t)v);
+            g.split_nnz += (double)d;
             for (int64_t s = 0; s * seg < d; ++s) {
                 split_items.push_back(make_int2((int)v, (int)s));
                 split_tasks.push_back(make_int2((int)v, (int)s));
@@ -187,6 +126,8 @@ int rebin(sc_ctx *c, Graph &g, int seg) {
     if ((rc = upload(c, g.slot, slot.data(), slot.size() * sizeof(int32_t)))) return rc;
     if ((rc = upload(c, g.tasks, split_tasks.data(), split_tasks.size() * sizeof(int2)))) return rc;
     g.seg = seg;
+    for (auto &kv : c->graph_cache) (void)hipGraphExecDestroy(kv.second);
+    c->graph_cache.clear();
     return SC_OK;
 }
 
@@ -233,17 +174,24 @@ int get_drop(sc_ctx *c, int k, int h, const int16_t **out) {
     return SC_OK;
 }
 
-ExecOpts exec_opts(const sc_ctx *c) {
+ExecOpts exec_opts(const sc_ctx *c, int gid, int tid, int k, int batch, int *tile_cols) {
     ExecOpts o;
     o.fuse = c->fused != 0;
     o.fuse_max_cols = (int)c->fuse_max_cols;
+    int tile = default_tile(c);
+    auto it = c->tuned.find(TuneKey{gid, tid, k, batch});
+    if (it != c->tuned.end()) {
+        if (it->second.fuse_max_cols > 0) o.fuse_max_cols = it->second.fuse_max_cols;
+        if (it->second.tile_cols > 0) tile = it->second.tile_cols;
+    }
+    if (tile_cols) *tile_cols = tile;
     return o;
 }
 
-int make_plan(sc_ctx *c, const Graph &g, const Template &T, int k, int batch, Plan &P) {
+int make_plan(sc_ctx *c, const Graph &g, const Template &T, const ExecOpts &o, int k, int batch,
+              Plan &P) {
     std::string err;
     bool ok;
-    const ExecOpts o = exec_opts(c);
     const int64_t rows = std::max<int64_t>(g.n_rows, 1);
     if (T.explicit_plan)
         ok = build_plan(T.t, T.root, T.child_ptr, T.child_idx, k, rows, g.nnz, batch, o, P, err);
@@ -253,162 +201,33 @@ int make_plan(sc_ctx *c, const Graph &g, const Template &T, int k, int batch, Pl
     return SC_OK;
 }
 
-// Largest batch <= want whose arena fits the budget.
-int pick_batch(sc_ctx *c, const Graph &g, const Template &T, int k, int want, Plan &P) {
-    want = std::max(1, std::min<int>(want, (int)std::min<int64_t>(c->max_batch, SC_MAX_BATCH)));
-    for (int b = want; b >= 1; --b) {
-        int rc = make_plan(c, g, T, k, b, P);
-        if (rc) return rc;
-        uint64_t need = P.arena_bytes + (uint64_t)g.n_rows * b;
-        if (need <= c->budget) return SC_OK;
-        if (b == 1)
-            return fail(c, SC_ENOMEM, "one colouring needs %.3f GB of tables, budget is %.3f GB",
-                        need / 1e9, c->budget / 1e9);
-    }
-    return SC_OK;
-}
-
-// ---------------------------------------------------------------- tracing
-
-hipEvent_t next_event(sc_ctx *c) {
-    if (c->events_used == c->event_pool.size()) {
-        hipEvent_t e;
-        if (hipEventCreate(&e) != hipSuccess) return nullptr;
-        c->event_pool.push_back(e);
-    }
-    return c->event_pool[c->events_used++];
-}
-
-struct ProfScope {
-    sc_ctx *c;
-    hipStream_t st;
-    const char *name;
-    double bytes, updates;
-    hipEvent_t a = nullptr;
-    ProfScope(sc_ctx *c_, hipStream_t st_, const char *n, double by, double up)
-        : c(c_), st(st_), name(n), bytes(by), updates(up) {
-        if (c->prof && (a = next_event(c))) (void)hipEventRecord(a, st);
-    }
-    ~ProfScope() {
-        if (!a) return;
-        hipEvent_t b = next_event(c);
-        if (!b) return;
-        (void)hipEventRecord(b, st);
-        c->recs.push_back({name, a, b, bytes, updates});
-    }
-};
-
-// One pass: colourings first..first+P.batch-1 folded into the table columns.
-int run_pass(sc_ctx *c, Graph &g, const Plan &P, uint64_t first, hipStream_t st,
-             uint64_t *counts, uint8_t *flags_out) {
-    const int B = P.batch, k = P.k;
-    const int64_t n = g.n_rows;            // table rows
-    const double dn = (double)n, dnnz = (double)g.nnz;
-    int rc;
-    if (P.steps.empty() || n == 0) {       // t == 1: every vertex is a map; no edges: no map
-        for (int r = 0; r < B; ++r) { counts[r] = P.steps.empty() ? (uint64_t)g.n : 0; flags_out[r] = 0; }
-        return SC_OK;
-    }
-    if ((rc = rebin(c, g, default_segment(c)))) return rc;
-    if ((rc = ensure(c, c->arena, P.arena_bytes))) return rc;
-    if ((rc = ensure(c, c->colbuf, (size_t)n * B))) return rc;
-    if ((rc = ensure(c, c->xbuf, (SC_MAX_BATCH + 1) * sizeof(uint64_t)))) return rc;
-    size_t npre_words = 0;
+uint64_t pass_bytes(const Graph &g, const Plan &P) {
+    uint64_t npre = 0;
     for (const Step &s : P.steps)
         if (s.mode == kStepFusedHist || s.mode == kStepFusedGather)
-            npre_words = std::max(npre_words, (size_t)g.n_split * binom(k, s.p) * B);
-    if (npre_words && (rc = ensure(c, c->npre, npre_words * 8))) return rc;
-    auto *X = (unsigned long long *)c->xbuf.p;
-    auto *flags = X + SC_MAX_BATCH;
-    auto *col = (uint8_t *)c->colbuf.p;
-    auto *base = (uint8_t *)c->arena.p;
-    auto *Npre = (uint64_t *)c->npre.p;
-    auto buf = [&](int id) { return id < 0 ? (uint64_t *)nullptr : (uint64_t *)(base + P.bufs[id].offset); };
-    const kern::GraphBins bins = bins_of(g);
-    const double adj_bytes = 4.0 * dnnz + 8.0 * (dn + 1);
-    double split_nnz = 0;
-    if (g.n_split) for (int64_t v = 0; v < n; ++v) if (g.deg_host[v] > g.seg) split_nnz += (double)g.deg_host[v];
+            npre = std::max<uint64_t>(npre, (uint64_t)g.n_split * binom(P.k, s.p) * P.batch * 8);
+    return P.arena_bytes + npre + (uint64_t)g.n_rows * P.batch;
+}
 
-    HIPCHK(c, kern::launch_zero_u64((uint64_t *)X, SC_MAX_BATCH + 1, st));
-    {
-        ProfScope ps(c, st, "color", dn * B, 0);
-        HIPCHK(c, kern::launch_color(c->seed, first, n, B, k, (const int32_t *)g.perm.p, col, st));
+int pick_batch(sc_ctx *c, int gid, int tid, int k, int want, uint64_t budget, Plan &P,
+               int *tile_cols) {
+    auto gi = c->graphs.find(gid);
+    if (gi == c->graphs.end()) return fail(c, SC_ENOTFOUND, "unknown graph %d", gid);
+    auto ti = c->tmpls.find(tid);
+    if (ti == c->tmpls.end()) return fail(c, SC_ENOTFOUND, "unknown template %d", tid);
+    const Graph &g = *gi->second;
+    const Template &T = *ti->second;
+    if (k < T.t || k > SC_MAX_K) return fail(c, SC_EINVAL, "need t <= k <= 16 (t=%d, k=%d)", T.t, k);
+    if (!budget) budget = c->budget;
+    want = std::max(1, std::min<int>(want, (int)std::min<int64_t>(c->max_batch, SC_MAX_BATCH)));
+    for (int b = want; b >= 1; b = b > 8 ? b / 2 : b - 1) {
+        const ExecOpts o = exec_opts(c, gid, tid, k, b, tile_cols);
+        int rc = make_plan(c, g, T, o, k, b, P);
+        if (rc) return rc;
+        if (pass_bytes(g, P) <= budget) return SC_OK;
     }
-    const Step *last = nullptr;
-    for (const Step &s : P.steps) {
-        const int Wa = (int)binom(k, s.a), Wp = (int)binom(k, s.p), Wh = (int)binom(k, s.h);
-        const int64_t Lp = (int64_t)Wp * B;
-        const double La = (double)Wa * B, Ls = (double)Wh * B, dLp = (double)Lp;
-        const int nsplit = (int)binom(s.h, s.a);
-        uint64_t *N = buf(s.buf_n);
-        uint64_t *S = buf(s.buf_s);
-        const uint64_t *Pp = buf(s.buf_p), *A = buf(s.buf_a);
-        const uint32_t *split = nullptr;
-        const int16_t *drop = nullptr;
-        if (s.a > 1) { if ((rc = get_split(c, k, s.h, s.a, &split))) return rc; }
-        else { if ((rc = get_drop(c, k, s.h, &drop))) return rc; }
-        const double ema_upd = s.a > 1 ? dn * Ls * nsplit : dn * Ls;
-        const double ema_bytes = 8.0 * dn * ((s.a > 1 ? La : 0) + Ls) + (s.a == 1 ? dn * B : 0);
-        const double sp_upd = dnnz * dLp;
-        switch (s.mode) {
-        case kStepFusedHist: {
-            if (g.n_split) {
-                ProfScope ps(c, st, "hist_split", 4.0 * split_nnz + 8.0 * g.n_split * dLp, split_nnz * dLp);
-                HIPCHK(c, kern::launch_hist_split(bins, col, Npre, B, k, st));
-            }
-            ProfScope ps(c, st, "row_hist", adj_bytes + dn * B + ema_bytes, sp_upd + ema_upd);
-            HIPCHK(c, kern::launch_row(kern::kModeHist, bins, col, nullptr, Npre, A, S, B, k, s.a,
-                                       Wa, Wp, Wh, nsplit, split, drop, flags, st));
-            break;
-        }
-        case kStepFusedGather: {
-            if (g.n_split) {
-                HIPCHK(c, kern::launch_zero_split_rows(bins, true, Npre, Lp, st));
-                ProfScope ps(c, st, "spmm_split", 4.0 * split_nnz + 16.0 * g.n_split * dLp, split_nnz * dLp);
-                HIPCHK(c, kern::launch_spmm_split(bins, Pp, Npre, Lp, B, default_tile(c), flags, st));
-            }
-            ProfScope ps(c, st, "row_gather", adj_bytes + 8.0 * dn * dLp + ema_bytes, sp_upd + ema_upd);
-            HIPCHK(c, kern::launch_row(kern::kModeGather, bins, col, Pp, Npre, A, S, B, k, s.a,
-                                       Wa, Wp, Wh, nsplit, split, drop, flags, st));
-            break;
-        }
-        default: {
-            if (s.p == 1) {
-                ProfScope ps(c, st, "hist", adj_bytes + dn * B + 8.0 * dn * dLp, sp_upd);
-                HIPCHK(c, kern::launch_hist(bins, col, N, B, k, st));
-            } else {
-                HIPCHK(c, kern::launch_zero_split_rows(bins, false, N, Lp, st));
-                ProfScope ps(c, st, "spmm", adj_bytes + 16.0 * dn * dLp, sp_upd);
-                HIPCHK(c, kern::launch_spmm(bins, Pp, N, Lp, B, default_tile(c), flags, st));
-            }
-            if (s.mode == kStepStaged) {
-                ProfScope ps(c, st, "row_staged", 8.0 * dn * dLp + ema_bytes, ema_upd);
-                HIPCHK(c, kern::launch_row(kern::kModeStaged, bins, col, N, nullptr, A, S, B, k, s.a,
-                                           Wa, Wp, Wh, nsplit, split, drop, flags, st));
-            } else if (s.a == 1) {
-                ProfScope ps(c, st, "select", 8.0 * dn * dLp + ema_bytes, ema_upd);
-                HIPCHK(c, kern::launch_select(n, col, N, S, B, k, Wh, Wp, drop, st));
-            } else {
-                ProfScope ps(c, st, "ema", 8.0 * dn * dLp + ema_bytes, ema_upd);
-                HIPCHK(c, kern::launch_ema(n, A, N, S, B, Wa, Wp, Wh, nsplit, split, flags, st));
-            }
-        }
-        }
-        last = &s;
-    }
-    {
-        const int W = (int)binom(k, last->h);
-        ProfScope ps(c, st, "reduce", 8.0 * dn * W * B, 0);
-        HIPCHK(c, kern::launch_reduce(n, buf(last->buf_s), W, B, X, flags, st));
-    }
-    uint64_t host[SC_MAX_BATCH + 1];
-    HIPCHK(c, hipMemcpyAsync(host, X, sizeof host, hipMemcpyDeviceToHost, st));
-    HIPCHK(c, hipStreamSynchronize(st));
-    for (int r = 0; r < B; ++r) {
-        counts[r] = host[r];
-        flags_out[r] = (uint8_t)((host[SC_MAX_BATCH] >> r) & 1);
-    }
-    return SC_OK;
+    return fail(c, SC_ENOMEM, "one colouring needs %.3f GB of device tables, the budget is %.3f GB",
+                pass_bytes(g, P) / 1e9, budget / 1e9);
 }
 
 double colorful_probability(int k, int t) {
@@ -417,13 +236,30 @@ double colorful_probability(int k, int t) {
     return p;
 }
 
-}  // namespace
+}  // namespace sc
 
-// ====================================================================== C ABI
+using namespace sc;
+
+namespace {
+
+double aut_of(int t, const std::vector<int32_t> &edges) {
+    std::vector<std::pair<int, int>> e;
+    for (int i = 0; i + 1 < (int)edges.size(); i += 2) e.emplace_back(edges[i], edges[i + 1]);
+    return tree_automorphisms(t, e);
+}
+
+void free_graph(sc_ctx *c, Graph &g) {
+    dev_free(c, g.rp); dev_free(c, g.ci); dev_free(c, g.light); dev_free(c, g.wide);
+    dev_free(c, g.split_rows); dev_free(c, g.slot); dev_free(c, g.perm); dev_free(c, g.tasks);
+}
+
+bool serving(const sc_ctx *c) { return c->serve != nullptr; }
+
+}  // namespace
 
 extern "C" {
 
-const char *sc_version(void) { return "libsc 0.1 (gfx950)"; }
+const char *sc_version(void) { return "libsc 0.2 (gfx950)"; }
 
 const char *sc_last_error(const sc_ctx *ctx) { return ctx ? ctx->err.c_str() : "no context"; }
 
@@ -451,16 +287,16 @@ int sc_create(int device, sc_alloc_fn alloc, sc_free_fn free_fn, void *user, uin
 
 int sc_destroy(sc_ctx *c) {
     if (!c) return SC_OK;
+    serve_shutdown(c);
     (void)hipSetDevice(c->device);
-    (void)hipStreamSynchronize(c->stream);
-    for (auto &kv : c->graphs) {
-        Graph &g = *kv.second;
-        dev_free(c, g.rp); dev_free(c, g.ci); dev_free(c, g.light); dev_free(c, g.wide);
-        dev_free(c, g.split_rows); dev_free(c, g.slot); dev_free(c, g.perm); dev_free(c, g.tasks);
-    }
+    (void)hipDeviceSynchronize();
+    for (auto &kv : c->graph_cache) (void)hipGraphExecDestroy(kv.second);
+    for (auto &kv : c->graphs) free_graph(c, *kv.second);
     for (auto &kv : c->split_tabs) dev_free(c, kv.second);
     for (auto &kv : c->drop_tabs) dev_free(c, kv.second);
-    dev_free(c, c->arena); dev_free(c, c->colbuf); dev_free(c, c->xbuf); dev_free(c, c->npre);
+    PassBuffers &b = c->main;
+    dev_free(c, b.arena); dev_free(c, b.colbuf); dev_free(c, b.xbuf); dev_free(c, b.npre); dev_free(c, b.desc);
+    if (c->host_out) (void)hipHostFree(c->host_out);
     for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
     (void)hipStreamDestroy(c->stream);
     delete c;
@@ -470,6 +306,7 @@ int sc_destroy(sc_ctx *c) {
 int sc_load_graph_csr(sc_ctx *c, int64_t n, int64_t nnz, const int64_t *rp, const int32_t *ci,
                       int32_t *graph_id) {
     if (!c) return SC_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
     if (!rp || !graph_id || (nnz > 0 && !ci)) return fail(c, SC_EINVAL, "NULL argument");
     if (n < 1 || n >= (int64_t)1 << 31) return fail(c, SC_EINVAL, "n must be in [1, 2^31)");
     if (nnz < 0 || rp[0] != 0 || rp[n] != nnz) return fail(c, SC_EINVAL, "row_ptr[0] must be 0 and row_ptr[n] == nnz");
@@ -497,8 +334,9 @@ int sc_load_graph_csr(sc_ctx *c, int64_t n, int64_t nnz, const int64_t *rp, cons
     int rc;
     if (c->reorder) {
         // Relabel by descending degree: the rows that neighbour sums gather most
-        // often become one contiguous region.  Colours are still drawn from the
-        // original ids (perm), so every count is unchanged.
+        // often become one contiguous region and the isolated vertices the tail.
+        // Colours are still drawn from the caller's ids (perm), so every count
+        // is unchanged.
         std::vector<int32_t> perm(n), inv(n);
         for (int64_t v = 0; v < n; ++v) perm[v] = (int32_t)v;
         std::stable_sort(perm.begin(), perm.end(), [&](int32_t x, int32_t y) {
@@ -518,19 +356,16 @@ int sc_load_graph_csr(sc_ctx *c, int64_t n, int64_t nnz, const int64_t *rp, cons
         g->n_rows = 0;
         while (g->n_rows < n && g->deg_host[g->n_rows] > 0) ++g->n_rows;
         if ((rc = upload(c, g->rp, nrp.data(), (size_t)(n + 1) * sizeof(int64_t)))) return rc;
-        if ((rc = upload(c, g->ci, nci.data(), (size_t)nnz * sizeof(int32_t)))) { dev_free(c, g->rp); return rc; }
-        if ((rc = upload(c, g->perm, perm.data(), (size_t)n * sizeof(int32_t)))) {
-            dev_free(c, g->rp); dev_free(c, g->ci); return rc;
-        }
+        if ((rc = upload(c, g->ci, nci.data(), (size_t)nnz * sizeof(int32_t)))) { free_graph(c, *g); return rc; }
+        if ((rc = upload(c, g->perm, perm.data(), (size_t)n * sizeof(int32_t)))) { free_graph(c, *g); return rc; }
     } else {
         for (int64_t v = 0; v < n; ++v) g->deg_host[v] = rp[v + 1] - rp[v];
         g->n_rows = n;
         if ((rc = upload(c, g->rp, rp, (size_t)(n + 1) * sizeof(int64_t)))) return rc;
-        if ((rc = upload(c, g->ci, ci, (size_t)nnz * sizeof(int32_t)))) { dev_free(c, g->rp); return rc; }
+        if ((rc = upload(c, g->ci, ci, (size_t)nnz * sizeof(int32_t)))) { free_graph(c, *g); return rc; }
     }
-    if ((rc = rebin(c, *g, default_segment(c)))) {
-        dev_free(c, g->rp); dev_free(c, g->ci); dev_free(c, g->perm); return rc;
-    }
+    for (int64_t v = 0; v < n; ++v) g->max_deg = std::max(g->max_deg, g->deg_host[v]);
+    if ((rc = rebin(c, *g, default_segment(c)))) { free_graph(c, *g); return rc; }
     *graph_id = c->next_graph++;
     c->graphs[*graph_id] = std::move(g);
     return SC_OK;
@@ -538,24 +373,23 @@ int sc_load_graph_csr(sc_ctx *c, int64_t n, int64_t nnz, const int64_t *rp, cons
 
 int sc_unload_graph(sc_ctx *c, int32_t id) {
     if (!c) return SC_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
     auto it = c->graphs.find(id);
     if (it == c->graphs.end()) return fail(c, SC_ENOTFOUND, "unknown graph %d", id);
-    (void)hipStreamSynchronize(c->stream);
-    Graph &g = *it->second;
-    dev_free(c, g.rp); dev_free(c, g.ci); dev_free(c, g.light); dev_free(c, g.wide);
-    dev_free(c, g.split_rows); dev_free(c, g.slot); dev_free(c, g.perm); dev_free(c, g.tasks);
+    if (it->second->busy) return fail(c, SC_EBUSY, "graph %d has serving passes in flight", id);
+    (void)hipDeviceSynchronize();
+    for (auto g = c->graph_cache.begin(); g != c->graph_cache.end();) {
+        if (g->first.graph_id == id) { (void)hipGraphExecDestroy(g->second); g = c->graph_cache.erase(g); }
+        else ++g;
+    }
+    free_graph(c, *it->second);
     c->graphs.erase(it);
     return SC_OK;
 }
 
-static double aut_of(int t, const std::vector<int32_t> &edges) {
-    std::vector<std::pair<int, int>> e;
-    for (int i = 0; i + 1 < (int)edges.size(); i += 2) e.emplace_back(edges[i], edges[i + 1]);
-    return tree_automorphisms(t, e);
-}
-
 int sc_load_template(sc_ctx *c, int32_t t, const int32_t *edges, int32_t root, int32_t *tmpl_id) {
     if (!c) return SC_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
     if (!tmpl_id) return fail(c, SC_EINVAL, "NULL argument");
     std::string m = check_tree(t, edges);
     if (!m.empty()) return fail(c, SC_EINVAL, "%s", m.c_str());
@@ -573,6 +407,7 @@ int sc_load_template(sc_ctx *c, int32_t t, const int32_t *edges, int32_t root, i
 int sc_load_template_plan(sc_ctx *c, int32_t t, int32_t root, const int32_t *child_ptr,
                           const int32_t *child_idx, int32_t *tmpl_id) {
     if (!c) return SC_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
     if (!child_ptr || !tmpl_id || (t > 1 && !child_idx)) return fail(c, SC_EINVAL, "NULL argument");
     if (t < 1 || t > SC_MAX_T) return fail(c, SC_EINVAL, "template size must be in [1, 16]");
     auto T = std::make_unique<Template>();
@@ -598,6 +433,7 @@ int sc_load_template_plan(sc_ctx *c, int32_t t, int32_t root, const int32_t *chi
 
 int sc_set_colors(sc_ctx *c, int32_t k, uint64_t seed) {
     if (!c) return SC_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
     if (k < 1 || k > SC_MAX_K) return fail(c, SC_EINVAL, "k must be in [1, %d]", SC_MAX_K);
     c->k = k;
     c->seed = seed;
@@ -606,6 +442,9 @@ int sc_set_colors(sc_ctx *c, int32_t k, uint64_t seed) {
 
 int sc_set_option(sc_ctx *c, int32_t opt, int64_t v) {
     if (!c) return SC_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    if (serving(c) && opt != SC_OPT_GRAPH)
+        return fail(c, SC_ESTATE, "options cannot change while the serving loop runs");
     switch (opt) {
     case SC_OPT_MAX_BATCH:
         if (v < 1 || v > SC_MAX_BATCH) return fail(c, SC_EINVAL, "max batch must be in [1, %d]", SC_MAX_BATCH);
@@ -630,6 +469,7 @@ int sc_set_option(sc_ctx *c, int32_t opt, int64_t v) {
 
 int sc_get_option(sc_ctx *c, int32_t opt, int64_t *v) {
     if (!c || !v) return SC_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
     switch (opt) {
     case SC_OPT_MAX_BATCH: *v = c->max_batch; return SC_OK;
     case SC_OPT_FUSED: *v = c->fused; return SC_OK;
@@ -648,23 +488,20 @@ int sc_plan_template(int32_t t, const int32_t *edges, int32_t root, int32_t k, i
     Plan P;
     std::string err;
     if (!choose_plan(t, edges, root, k, n, nnz, batch, ExecOpts(), P, err)) return SC_EINVAL;
-    std::vector<int32_t> e(edges ? edges : (const int32_t *)nullptr, edges ? edges + 2 * (t - 1) : nullptr);
+    std::vector<int32_t> e;
+    if (edges) e.assign(edges, edges + 2 * (t - 1));
     fill_plan_info(P, aut_of(t, e), out);
     return SC_OK;
 }
 
 int sc_plan_info(sc_ctx *c, int32_t gid, int32_t tid, int32_t n_colorings, sc_plan_info_t *out) {
     if (!c) return SC_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
     if (!out) return fail(c, SC_EINVAL, "NULL argument");
-    auto gi = c->graphs.find(gid);
-    if (gi == c->graphs.end()) return fail(c, SC_ENOTFOUND, "unknown graph %d", gid);
-    auto ti = c->tmpls.find(tid);
-    if (ti == c->tmpls.end()) return fail(c, SC_ENOTFOUND, "unknown template %d", tid);
-    if (c->k < ti->second->t) return fail(c, SC_EINVAL, "k=%d < t=%d (call sc_set_colors)", c->k, ti->second->t);
     Plan P;
-    int rc = pick_batch(c, *gi->second, *ti->second, c->k, std::max(1, n_colorings), P);
+    int rc = pick_batch(c, gid, tid, c->k, std::max(1, n_colorings), 0, P, nullptr);
     if (rc) return rc;
-    fill_plan_info(P, ti->second->aut, out);
+    fill_plan_info(P, c->tmpls[tid]->aut, out);
     return SC_OK;
 }
 
@@ -679,47 +516,9 @@ int32_t sc_color_of(uint64_t seed, uint64_t coloring, uint64_t v, int32_t k) {
     return (int32_t)(((unsigned __int128)z * (uint64_t)(uint32_t)k) >> 64);
 }
 
-int sc_run(sc_ctx *c, int32_t gid, int32_t tid, uint64_t first, int32_t ncol, void *stream,
-           uint64_t *counts, uint8_t *overflow, double *est_maps, double *est_copies) {
-    if (!c) return SC_EINVAL;
-    if (ncol < 0) return fail(c, SC_EINVAL, "n_colorings < 0");
-    if (ncol > 0 && (!counts || !overflow)) return fail(c, SC_EINVAL, "NULL output");
-    auto gi = c->graphs.find(gid);
-    if (gi == c->graphs.end()) return fail(c, SC_ENOTFOUND, "unknown graph %d", gid);
-    auto ti = c->tmpls.find(tid);
-    if (ti == c->tmpls.end()) return fail(c, SC_ENOTFOUND, "unknown template %d", tid);
-    Graph &g = *gi->second;
-    const Template &T = *ti->second;
-    const int k = c->k;
-    if (k < T.t) return fail(c, SC_EINVAL, "k=%d < t=%d (call sc_set_colors)", k, T.t);
-    if (hipSetDevice(c->device) != hipSuccess) return fail(c, SC_EDEVICE, "hipSetDevice failed");
-    hipStream_t st = stream ? (hipStream_t)stream : c->stream;
-    int rc;
-    Plan P;
-    int done = 0;
-    bool any_ovf = false;
-    double sum = 0.0;
-    while (done < ncol) {
-        if ((rc = pick_batch(c, g, T, k, ncol - done, P))) return rc;
-        if ((rc = run_pass(c, g, P, first + (uint64_t)done, st, counts + done, overflow + done))) return rc;
-        for (int r = 0; r < P.batch; ++r) {
-            any_ovf |= overflow[done + r] != 0;
-            sum += (double)counts[done + r];
-        }
-        done += P.batch;
-    }
-    double maps = NAN, copies = NAN;
-    if (ncol > 0 && !any_ovf) {
-        maps = sum / ncol / colorful_probability(k, T.t);
-        copies = maps / T.aut;
-    }
-    if (est_maps) *est_maps = maps;
-    if (est_copies) *est_copies = copies;
-    return SC_OK;
-}
-
 int sc_profile(sc_ctx *c, int32_t enable) {
     if (!c) return SC_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
     if (enable) {
         HIPCHK(c, hipStreamSynchronize(c->stream));
         c->recs.clear();
@@ -731,6 +530,7 @@ int sc_profile(sc_ctx *c, int32_t enable) {
 
 int sc_profile_read(sc_ctx *c, sc_kernel_stat_t *out, int32_t cap, int32_t *n_out) {
     if (!c) return SC_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
     if (!n_out || (cap > 0 && !out)) return fail(c, SC_EINVAL, "NULL argument");
     std::vector<sc_kernel_stat_t> agg;
     for (auto &r : c->recs) {

@@ -15,7 +15,9 @@ import numpy as np
 __all__ = [
     "SC_OK", "SC_EINVAL", "SC_ENOMEM", "SC_EDEVICE", "SC_ENOTFOUND", "SC_EBUSY", "SC_ESTATE",
     "SC_OPT_MAX_BATCH", "SC_OPT_FUSED", "SC_OPT_GRAPH", "SC_OPT_TILE_COLS", "SC_OPT_SEGMENT",
-    "SC_OPT_FUSE_MAX_COLS", "SC_OPT_REORDER", "OPTION_DEFAULTS", "ScError", "PlanInfo", "KernelStat", "lib", "lib_path", "sc_version", "sc_plan_template",
+    "SC_OPT_FUSE_MAX_COLS", "SC_OPT_REORDER", "OPTION_DEFAULTS", "ScError", "PlanInfo", "KernelStat",
+    "Job", "Tune", "ServeCfg", "Query", "Result", "ServeStats", "lib", "lib_path", "sc_version",
+    "sc_plan_template",
     "sc_colorset_rank", "sc_color_of", "Context",
 ]
 
@@ -90,6 +92,44 @@ OPTION_DEFAULTS = {SC_OPT_MAX_BATCH: 64, SC_OPT_FUSED: 1, SC_OPT_GRAPH: 0, SC_OP
                    SC_OPT_SEGMENT: 0, SC_OPT_FUSE_MAX_COLS: 512, SC_OPT_REORDER: 1}
 
 
+class Job(ctypes.Structure):
+    _fields_ = [
+        ("graph_id", ctypes.c_int32), ("tmpl_id", ctypes.c_int32), ("k", ctypes.c_int32),
+        ("seed", ctypes.c_uint64), ("first_coloring", ctypes.c_uint64), ("n_colorings", ctypes.c_int32),
+        ("counts", ctypes.POINTER(ctypes.c_uint64)), ("overflow", ctypes.POINTER(ctypes.c_uint8)),
+        ("est_maps", ctypes.c_double), ("est_copies", ctypes.c_double), ("status", ctypes.c_int32),
+    ]
+
+
+class Tune(ctypes.Structure):
+    _fields_ = [("tile_cols", ctypes.c_int32), ("fuse_max_cols", ctypes.c_int32),
+                ("batch", ctypes.c_int32), ("trials", ctypes.c_int32), ("ms", ctypes.c_double)]
+
+
+class ServeCfg(ctypes.Structure):
+    _fields_ = [("mem_budget_bytes", ctypes.c_uint64), ("max_inflight", ctypes.c_int32),
+                ("max_batch", ctypes.c_int32)]
+
+
+class Query(ctypes.Structure):
+    _fields_ = [("graph_id", ctypes.c_int32), ("tmpl_id", ctypes.c_int32), ("k", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("first_coloring", ctypes.c_uint64),
+                ("n_colorings", ctypes.c_int32)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("n_colorings", ctypes.c_int32),
+                ("counts", ctypes.POINTER(ctypes.c_uint64)), ("overflow", ctypes.POINTER(ctypes.c_uint8)),
+                ("est_maps", ctypes.c_double), ("est_copies", ctypes.c_double),
+                ("submit_s", ctypes.c_double), ("start_s", ctypes.c_double), ("done_s", ctypes.c_double)]
+
+
+class ServeStats(ctypes.Structure):
+    _fields_ = [("passes", ctypes.c_uint64), ("colorings", ctypes.c_uint64), ("waiting", ctypes.c_int32),
+                ("inflight", ctypes.c_int32), ("mem_bytes", ctypes.c_uint64),
+                ("peak_mem_bytes", ctypes.c_uint64)]
+
+
 class ScError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"libsc error {code}: {msg}")
@@ -124,6 +164,16 @@ def lib():
                                       _vp, _u64p, _u8p, _dblp, _dblp]),
             "sc_set_option": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int64]),
             "sc_get_option": (ctypes.c_int, [_vp, ctypes.c_int32, _i64p]),
+            "sc_run_batch": (ctypes.c_int, [_vp, ctypes.POINTER(Job), ctypes.c_int32, _vp]),
+            "sc_autotune": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                           ctypes.POINTER(Tune)]),
+            "sc_tune_save": (ctypes.c_int, [_vp, ctypes.c_char_p]),
+            "sc_tune_load": (ctypes.c_int, [_vp, ctypes.c_char_p, _i32p]),
+            "sc_serve_start": (ctypes.c_int, [_vp, ctypes.POINTER(ServeCfg)]),
+            "sc_submit": (ctypes.c_int, [_vp, ctypes.POINTER(Query), ctypes.POINTER(ctypes.c_uint64)]),
+            "sc_poll": (ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.POINTER(Result)]),
+            "sc_serve_stats": (ctypes.c_int, [_vp, ctypes.POINTER(ServeStats)]),
+            "sc_serve_stop": (ctypes.c_int, [_vp]),
             "sc_profile": (ctypes.c_int, [_vp, ctypes.c_int32]),
             "sc_profile_read": (ctypes.c_int, [_vp, ctypes.POINTER(KernelStat), ctypes.c_int32,
                                                _i32p]),
@@ -288,6 +338,78 @@ class Context:
         out = PlanInfo()
         self._check(self._L.sc_plan_info(self._h, gid, tid, n_colorings, ctypes.byref(out)))
         return out
+
+    def run_batch(self, jobs, stream=None):
+        """jobs: list of dicts {graph_id, tmpl_id, k, seed, first, n}.  Returns a
+        list of (counts, overflow, est_maps, est_copies, status) per job."""
+        arr = (Job * max(1, len(jobs)))()
+        bufs = []
+        for i, j in enumerate(jobs):
+            n = int(j["n"])
+            cnt = np.zeros(max(n, 1), np.uint64)
+            ovf = np.zeros(max(n, 1), np.uint8)
+            bufs.append((cnt, ovf, n))
+            arr[i].graph_id, arr[i].tmpl_id, arr[i].k = j["graph_id"], j["tmpl_id"], j["k"]
+            arr[i].seed = j["seed"] & (2**64 - 1)
+            arr[i].first_coloring = j.get("first", 0)
+            arr[i].n_colorings = n
+            arr[i].counts = _p(cnt, _u64p)
+            arr[i].overflow = _p(ovf, _u8p)
+        rc = self._L.sc_run_batch(self._h, arr, len(jobs), stream)
+        out = [(bufs[i][0][:bufs[i][2]], bufs[i][1][:bufs[i][2]], arr[i].est_maps, arr[i].est_copies,
+                arr[i].status) for i in range(len(jobs))]
+        if rc and all(o[4] == 0 for o in out):
+            self._check(rc)
+        return out
+
+    def autotune(self, gid, tid, n_colorings):
+        t = Tune()
+        self._check(self._L.sc_autotune(self._h, gid, tid, n_colorings, ctypes.byref(t)))
+        return {"tile_cols": t.tile_cols, "fuse_max_cols": t.fuse_max_cols, "batch": t.batch,
+                "trials": t.trials, "ms": t.ms}
+
+    def tune_save(self, path):
+        self._check(self._L.sc_tune_save(self._h, str(path).encode()))
+
+    def tune_load(self, path):
+        n = ctypes.c_int32()
+        self._check(self._L.sc_tune_load(self._h, str(path).encode(), ctypes.byref(n)))
+        return n.value
+
+    # -- serving
+    def serve_start(self, mem_budget_bytes=0, max_inflight=4, max_batch=64):
+        cfg = ServeCfg(mem_budget_bytes, max_inflight, max_batch)
+        self._check(self._L.sc_serve_start(self._h, ctypes.byref(cfg)))
+
+    def submit(self, gid, tid, k, seed, first, n_colorings) -> int:
+        q = Query(gid, tid, k, seed & (2**64 - 1), first, n_colorings)
+        t = ctypes.c_uint64()
+        self._check(self._L.sc_submit(self._h, ctypes.byref(q), ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket, n_colorings):
+        """None while the query runs; else a dict with counts, overflow,
+        estimates, status and timestamps."""
+        cnt = np.zeros(max(n_colorings, 1), np.uint64)
+        ovf = np.zeros(max(n_colorings, 1), np.uint8)
+        r = Result()
+        r.counts = _p(cnt, _u64p)
+        r.overflow = _p(ovf, _u8p)
+        rc = self._L.sc_poll(self._h, ticket, ctypes.byref(r))
+        if rc == SC_EBUSY:
+            return None
+        self._check(rc)
+        return {"status": r.status, "counts": cnt[:n_colorings], "overflow": ovf[:n_colorings],
+                "est_maps": r.est_maps, "est_copies": r.est_copies, "submit_s": r.submit_s,
+                "start_s": r.start_s, "done_s": r.done_s}
+
+    def serve_stats(self):
+        st = ServeStats()
+        self._check(self._L.sc_serve_stats(self._h, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in ServeStats._fields_}
+
+    def serve_stop(self):
+        self._check(self._L.sc_serve_stop(self._h))
 
     def run(self, gid, tid, first, n_colorings, stream=None):
         """Returns (counts uint64[R], overflow uint8[R], est_maps, est_copies)."""
