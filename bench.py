@@ -49,7 +49,118 @@ def parse():
     ap.add_argument("--breakdown", action="store_true", help="also print the per-family table")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB three times (calibrates rocprofv3 FETCH_SIZE/WRITE_SIZE)")
+    ap.add_argument("--forms", action="store_true",
+                    help="plain per-colouring launch loop vs batched form (config 1 and the headline workload)")
+    ap.add_argument("--serve", action="store_true",
+                    help="serving mix: RMAT 18/20/22 resident, Poisson query stream, p50/p99 latency")
+    ap.add_argument("--queries", type=int, default=40, help="stream length for --serve")
     return ap.parse_args()
+
+
+def timed(fn):
+    """Wall time of fn(); sc_run returns only after its results are on the host."""
+    t0 = time.perf_counter()
+    out = fn()
+    return time.perf_counter() - t0, out
+
+
+def forms_bench():
+    """Colourings/s of the plain per-colouring launch loop (one colouring per
+    sc_run call, no folding) against the batched form (colourings folded into
+    the columns, each pass replayed from a captured hipGraph, one host wait per
+    call), on the same colourings; results must agree."""
+    import numpy as np
+    from paper_1903_04395_amd import inputs as I
+    from paper_1903_04395_amd import sc
+    out = {}
+    ctx = sc.Context(0)
+    cases = [("er2000-p5-k5", I.erdos_renyi(2000, 10000, seed=1), 5, I.path(5), 0, 256, 64),
+             ("rmat20-tree10-k10", I.rmat(20, 16, seed=0), 10, I.prufer_tree(10, 0), -1, 16, 8)]
+    for name, g, t, edges, root, R, B in cases:
+        gid = ctx.load_graph(g)
+        tid = ctx.load_template(t, edges, root)
+        ctx.set_colors(t, 1)
+        # plain: one colouring per call
+        ctx.set_option(sc.SC_OPT_MAX_BATCH, 1)
+        ctx.set_option(sc.SC_OPT_GRAPH, 0)
+        ctx.run(gid, tid, 0, 1)
+        dt_p, plain = timed(lambda: [ctx.run(gid, tid, r, 1)[0][0] for r in range(R)])
+        # batched: B colourings per pass, hipGraph replay
+        ctx.set_option(sc.SC_OPT_MAX_BATCH, B)
+        ctx.set_option(sc.SC_OPT_GRAPH, 1)
+        ctx.run(gid, tid, 0, R)
+        dt_b, (cb, _, _, _) = timed(lambda: ctx.run(gid, tid, 0, R))
+        ctx.set_option(sc.SC_OPT_GRAPH, 0)
+        ctx.set_option(sc.SC_OPT_MAX_BATCH, 64)
+        assert np.array_equal(np.asarray(plain, np.uint64), cb), name
+        out[name] = {"colorings": R, "batch": B, "plain_colorings_per_s": round(R / dt_p, 1),
+                     "batched_colorings_per_s": round(R / dt_b, 1), "ratio": round(dt_p / dt_b, 2)}
+        print(f"[bench] forms {name}: {out[name]}", file=sys.stderr, flush=True)
+        ctx.unload_graph(gid)
+    ctx.close()
+    print(json.dumps({"forms": out}), flush=True)
+
+
+def serve_bench(nq):
+    """The serving mix: three resident RMAT graphs (scale 18, 20, 22; 16
+    edges/vertex), a seeded Poisson stream at 200 queries/s of (random graph,
+    random 3-12-vertex Pruefer tree, k = t, 1-32 colourings), admission by a
+    200 GB table budget, four streams.  Latency = submit to result."""
+    import numpy as np
+    from paper_1903_04395_amd import inputs as I
+    from paper_1903_04395_amd import sc
+    rng = np.random.default_rng(2019)
+    ctx = sc.Context(0)
+    gids = []
+    for scale in (18, 20, 22):
+        tg = time.time()
+        g = I.rmat(scale, 16, seed=scale)
+        gids.append(ctx.load_graph(g))
+        print(f"[bench] serve graph scale {scale}: n={g.n} nnz={g.nnz} ({time.time() - tg:.0f}s)",
+              file=sys.stderr, flush=True)
+        del g
+    qs = []
+    t_arr = 0.0
+    for i in range(nq):
+        t_arr += rng.exponential(1 / 200.0)
+        t = int(rng.integers(3, 13))
+        qs.append(dict(at=t_arr, graph=int(rng.integers(0, 3)), t=t, edges=I.prufer_tree(t, 10_000 + i),
+                       n=int(rng.integers(1, 33)), seed=int(rng.integers(0, 1 << 40))))
+    tids = [ctx.load_template(q["t"], q["edges"]) for q in qs]
+    ctx.serve_start(mem_budget_bytes=200 * 10**9, max_inflight=4, max_batch=64)
+    pending = {}
+    results = []
+    t0 = time.perf_counter()
+    i = 0
+    while i < nq or pending:
+        now = time.perf_counter() - t0
+        while i < nq and qs[i]["at"] <= now:
+            q = qs[i]
+            tk = ctx.submit(gids[q["graph"]], tids[i], q["t"], q["seed"], 0, q["n"])
+            pending[tk] = q["n"]
+            i += 1
+        for tk in list(pending):
+            r = ctx.poll(tk, pending[tk])
+            if r is not None:
+                assert r["status"] == 0, r["status"]
+                results.append(r)
+                del pending[tk]
+                if len(results) % 10 == 0:
+                    print(f"[bench] serve {len(results)}/{nq} done", file=sys.stderr, flush=True)
+        time.sleep(0.0005)
+    stats = ctx.serve_stats()
+    ctx.serve_stop()
+    lat = np.array([r["done_s"] - r["submit_s"] for r in results])
+    span = max(r["done_s"] for r in results) - min(r["submit_s"] for r in results)
+    ncol = sum(q["n"] for q in qs)
+    out = {"serving": {"queries": nq, "offered_qps": 200, "colorings": ncol,
+                       "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 1),
+                       "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 1),
+                       "colorings_per_s": round(ncol / span, 2), "queries_per_s": round(nq / span, 2),
+                       "passes": int(stats["passes"]), "peak_table_GB": round(stats["peak_mem_bytes"] / 1e9, 1),
+                       "streams": 4, "budget_GB": 200}}
+    ctx.close()
+    print(json.dumps(out), flush=True)
 
 
 def copy_probe():
@@ -91,6 +202,13 @@ def main():
     args = parse()
     if args.copy_probe:
         copy_probe()
+        return
+    if args.forms or args.serve:
+        import torch
+        if not torch.cuda.is_available():
+            print("bench.py needs a GPU", file=sys.stderr)
+            sys.exit(1)
+        forms_bench() if args.forms else serve_bench(args.queries)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the method's multi-GPU "

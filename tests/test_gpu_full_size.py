@@ -1,0 +1,65 @@
+"""Full-size parity: the HIP path on the full workloads (ER 2000 / P5 / k=5;
+RMAT scale 20 / 10-vertex tree / k=10, 8 colourings per pass; Chung-Lu
+n=4,194,304 / 12-vertex tree and 12-star / k=12, 16 colourings; RMAT scale 19
+/ 15-vertex tree / k=15, 4 colourings) against oracle residues and flags
+stored in tests/golden/full_size.json (written by
+tests/golden/make_full_size.py, which calls only the oracle).  The GPU runs
+every colouring of the configured batch; the sampled ones are compared."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_1903_04395_amd import inputs as I
+from paper_1903_04395_amd import sc
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "full_size.json")
+RUN_COLOURINGS = {"er2000_p5_k5": 64, "rmat20_tree10_k10": 8, "chunglu4m_tree12_k12": 16,
+                  "chunglu4m_star12_k12": 16, "rmat19_tree15_k15": 4}
+
+
+def load():
+    return json.load(open(GOLDEN)) if os.path.exists(GOLDEN) else {}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available()
+    c = sc.Context(0)
+    yield c
+    c.close()
+
+
+_graphs = {}
+
+
+def graph_for(ctx, spec):
+    key = json.dumps(spec, sort_keys=True)
+    if key not in _graphs:
+        for k in list(_graphs):
+            ctx.unload_graph(_graphs.pop(k))
+        g = getattr(I, spec["fn"])(*spec["args"], **spec["kwargs"])
+        _graphs[key] = ctx.load_graph(g)
+    return _graphs[key]
+
+
+@pytest.mark.parametrize("name", list(RUN_COLOURINGS))
+def test_full_size_matches_oracle(ctx, name):
+    data = load()
+    if name not in data:
+        pytest.skip(f"no golden values for {name}")
+    e = data[name]
+    print(f"[case] {name}: generating and loading the graph", flush=True)
+    gid = graph_for(ctx, e["graph"])
+    tid = ctx.load_template_plan(e["t"], e["root"], e["children"])
+    ctx.set_colors(e["k"], e["seed"])
+    R = RUN_COLOURINGS[name]
+    print(f"[case] {name}: running {R} colourings", flush=True)
+    counts, ovf, _, _ = ctx.run(gid, tid, 0, R)
+    for r, (cnt, flag) in e["results"].items():
+        assert int(counts[int(r)]) == int(cnt), (name, r)
+        assert int(ovf[int(r)]) == flag, (name, r)
