@@ -24,11 +24,14 @@
  * Arithmetic is uint64.  Readings where the paper is silent:
  *  - the neighbour sum has no self term (N = A * M_p, the adjacency of a simple
  *    graph has a zero diagonal);
- *  - overflow: the per-colouring flag is set iff some N entry, some product
- *    M_a*N, some M_s entry or X, evaluated exactly from the stored uint64
- *    operands, is >= 2^64.  Stored values are residues mod 2^64.  Because every
- *    term is non-negative, whether a sum overflows does not depend on the order
- *    of summation.
+ *  - overflow: the per-colouring flag is set iff some usable N entry, some
+ *    product M_a*N, some M_s entry or X, evaluated exactly from the stored
+ *    uint64 operands, is >= 2^64.  An N entry N[v][C2] is usable when col(v)
+ *    is not in C2: M_a[v][C1] is zero unless C1 holds col(v) (the root of T_a
+ *    maps to v), and C1, C2 are disjoint, so an N entry whose set holds col(v)
+ *    only ever meets zero active entries and cannot reach the count.  Stored
+ *    values are residues mod 2^64.  Because every term is non-negative,
+ *    whether a sum overflows does not depend on the order of summation.
  *  - colours come from SplitMix64 (Steele, Lea & Flood, OOPSLA 2014): colouring
  *    r of vertex v takes output number r*2^40 + v of the generator seeded with
  *    `seed`, mapped to [0,k) by a 64x64 multiply-high.
@@ -158,23 +161,31 @@ static triple *split_list(octx *c, int h, int a, int64_t *count)
     return L;
 }
 
-/* N = A * M_p : the neighbour sum for every passive column. */
-static uint64_t *neighbour_sum(octx *c, const uint64_t *P, int64_t Wp)
+/* N = A * M_p : the neighbour sum for every passive column of size p.  Every
+ * entry is computed; a carry sets the flag only for the usable entries (colour
+ * set without col(v)), see the overflow reading at the top. */
+static uint64_t *neighbour_sum(octx *c, const uint64_t *P, int p)
 {
+    int64_t Wp = (int64_t)binom(c->k, p);
     uint64_t *N = malloc((size_t)c->n * (size_t)Wp * sizeof(uint64_t));
-    if (!N) { c->oom = 1; return NULL; }
+    uint32_t *sets = malloc((size_t)Wp * sizeof(uint32_t));   /* colour set of each column */
+    if (!N || !sets) { free(N); free(sets); c->oom = 1; return NULL; }
+    for (uint32_t m = 0; m < (1u << c->k); ++m)
+        if (popc(m) == p) sets[c->rank[m]] = m;
     int flag = 0;
     #pragma omp parallel for schedule(dynamic, 256) reduction(|:flag)
     for (int64_t v = 0; v < c->n; ++v) {
         uint64_t *row = N + v * Wp;
+        const uint32_t own = 1u << c->col[v];
         for (int64_t q = 0; q < Wp; ++q) row[q] = 0;
         for (int64_t e = c->rp[v]; e < c->rp[v + 1]; ++e) {
             const uint64_t *src = P + (int64_t)c->ci[e] * Wp;
             for (int64_t q = 0; q < Wp; ++q)
-                flag |= __builtin_add_overflow(row[q], src[q], &row[q]);
+                if (__builtin_add_overflow(row[q], src[q], &row[q]) && !(sets[q] & own)) flag = 1;
         }
     }
     c->flag |= flag;
+    free(sets);
     return N;
 }
 
@@ -251,7 +262,7 @@ static uint64_t *subtree_table(octx *c, int u, int *size_out)
             S = combine_unpruned(c, M, size, P, p);
             free(P);
         } else {
-            uint64_t *N = neighbour_sum(c, P, (int64_t)binom(c->k, p));
+            uint64_t *N = neighbour_sum(c, P, p);
             free(P);
             if (!N) { free(M); return NULL; }
             S = combine(c, M, size, N, p);

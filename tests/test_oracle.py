@@ -275,6 +275,46 @@ def test_overflow_boundary_star_on_k1d():
     assert seen == {0, 1}
 
 
+def test_overflow_ignores_neighbour_sums_that_hold_the_own_colour():
+    """Star K_{1,11} rooted at a leaf, k = t = 12.  Two hubs of colour 1, each
+    with 18 neighbours of every colour in {0, 2..10} and none of colour 11; a
+    vertex v of colour 0 is one of the colour-0 neighbours of both hubs.  Each
+    hub's passive table (the 10-leaf star at its centre) is non-zero only on
+    C2 = {0..10}, where it is 10! * 18^10 < 2^64; the neighbour sum at v on that
+    set is twice that, >= 2^64.  No vertex has colour 11, so no root can use a
+    hub's table: X = 0, and the only value past 2^64 is an entry of N[v] whose
+    set holds col(v) = 0.  Such an entry only meets zero active entries
+    (the active set holds col(v), the two sets are disjoint), so the flag stays
+    clear.  Adding one colour-11 vertex next to both hubs makes the count
+    exceed 2^64 and sets it."""
+    t = k = 12
+    per_hub = math.factorial(10) * 18 ** 10
+    assert per_hub < M64 <= 2 * per_hub
+
+    def build(with_eleven):
+        src, dst, col = [], [], [1, 1, 0]              # hubs 0, 1; v = 2
+        for h in (0, 1):
+            src.append(h); dst.append(2)
+        for h in (0, 1):
+            for c in [0] * 17 + [c for c in range(2, 11) for _ in range(18)]:
+                src.append(h); dst.append(len(col)); col.append(c)
+        if with_eleven:
+            for h in (0, 1):
+                src.append(h); dst.append(len(col))
+            col.append(11)
+        g = I.csr_from_edges(len(col), np.array(src), np.array(dst))
+        return g, np.array(col, np.uint8)
+
+    plan = O.root_plan(t, I.star(t), 1)                # leaf 1 -> centre 0 -> 10 leaves
+    g, col = build(False)
+    X, f = O.count_colored(g, t, plan, k, col)
+    assert (X, f) == (0, 0)
+    g, col = build(True)
+    X, f = O.count_colored(g, t, plan, k, col)
+    exact = 22 * per_hub                               # 11 usable neighbours of each hub
+    assert X == exact % M64 and f == 1
+
+
 def hubby_graph(seed, n=1500, m=4000, hubs=3, hub_deg=900):
     """Sparse random graph plus a few high-degree hubs, so counts pass 2^64."""
     rng = np.random.default_rng(seed)
