@@ -19,6 +19,7 @@ colouring's residue and flag against the GPU).
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -30,10 +31,8 @@ PEAK_HBM_GBS = 8000.0
 
 # HIP kernel behind each libsc kernel family
 KERNEL_OF = {
-    "spmm": "spmm_tiled_kernel<2, false>", "spmm_split": "spmm_tiled_kernel<2, true>",
-    "row_gather": "row_kernel<1,U>", "row_hist": "row_kernel<2,1>", "row_staged": "row_kernel<0,1>",
-    "hist": "hist_light_kernel/hist_wide_kernel", "hist_split": "hist_wide_kernel",
-    "select": "select_kernel", "ema": "ema_kernel", "reduce": "reduce_kernel", "color": "color_kernel",
+    "row_gather": "dp_row_kernel<false, *>", "row_hist": "dp_row_kernel<true, *>",
+    "split": "dp_split_kernel<*>", "reduce": "reduce_kernel", "color": "color_kernel",
 }
 
 
@@ -267,16 +266,19 @@ def main():
         "avg_launch_ms": round(dom["total_ms"] / dom["launches"], 4),
         "alg_bytes_per_launch": dom["alg_bytes"] / dom["launches"],
         "share_of_gpu_time": round(dom["total_ms"] / sum(f["total_ms"] for f in fams.values()), 3),
-        # every neighbour-sum update reads one gathered 8-byte word
-        "gathered_GBps": round(dom["updates"] * 8 / (dom["total_ms"] / 1e3) / 1e9, 1)
-        if dom_name.startswith("spmm") else None,
     }
+    # passive rows gathered per pass: nnz * C(k-1, p-1) words per colouring for
+    # every step with p >= 2 (row kernels and the split pre-pass)
+    gathered = sum(g.nnz * math.comb(k - 1, p - 1) * 8 * B for h, a, p in info.steps() if p > 1)
+    gather_ms = sum(fams[f]["total_ms"] for f in ("row_gather", "split") if f in fams) / args.steps
+    roofline["gathered_GBps"] = round(gathered / (gather_ms / 1e3) / 1e9, 1) if gather_ms else None
     out = {
         "metric": "SpMM+eMA G-updates/s & colorings/s (bit-exact); p50/p99 query latency",
         "value": round(value, 2), "unit": "G-updates/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(elapsed / args.steps * 1e3, 3),
         "colorings_per_s": round(colorings / elapsed, 2),
+        "exec_updates_per_s": round(colorings * info.exec_updates / elapsed / 1e9, 2),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "u64", "data": "synthetic",
         "config": {"workload": f"rmat{args.scale}-tree10-k10-b{B}", "graph": f"RMAT scale {args.scale}, 16 edges/vertex",

@@ -128,15 +128,21 @@ typedef struct {
     int32_t step_h[SC_MAX_T];           /* steps in execution order:        */
     int32_t step_a[SC_MAX_T];           /*   sizes of T_s, T_a, T_p         */
     int32_t step_p[SC_MAX_T];
-    int32_t step_mode[SC_MAX_T];        /* 0 fused histogram, 1 fused neighbour
-                                           sum, 2 staged, 3 global          */
+    int32_t step_mode[SC_MAX_T];        /* 0: p = 1, neighbours' colours counted;
+                                           1: p >= 2, neighbours' rows summed
+                                           (both fused with the multiply-add) */
     int32_t batch;                      /* colourings per pass              */
+    int32_t interleave;                 /* colourings interleaved per table
+                                           plane (power of two dividing batch) */
     uint64_t arena_bytes;               /* device tables of one pass        */
     double spmm_updates;                /* per colouring: sum nnz*C(k,p)    */
     double ema_updates;                 /* per colouring: sum n*C(k,h)*C(h,a),
                                            n*C(k,h) for a = 1 (a select)    */
     double lemma1_ops;                  /* per colouring: Lemma 1,
                                            sum nnz*C(k,p) + n*C(k,h)*C(h,p) */
+    double exec_updates;                /* per colouring, executed in the
+                                           rooted-colour layout: sum
+                                           nnz*C(k-1,p-1) + n*C(k-1,h-1)*C(h-1,a-1) */
     double compulsory_bytes;            /* per colouring, HBM bytes (model) */
     double automorphisms;               /* |Aut(T)|                         */
 } sc_plan_info_t;
@@ -196,11 +202,12 @@ typedef struct {
 int sc_run_batch(sc_ctx *ctx, sc_job_t *jobs, int32_t n_jobs, void *stream);
 
 /* Autotuner: times real passes of (graph, template) at the batch `n_colorings`
- * plans to, over neighbour-sum tile widths {64, 128, 256} and fused-row
- * limits {256, 512, 1024}, and keeps the fastest for that (graph, template,
- * k, batch).  The choice never changes a result. */
+ * plans to, over the interleave caps {1, 2, 4, ..., batch} (at most four of
+ * them, the largest ones) and the row-kernel LDS limits {32, 64, 96} KB, and
+ * keeps the fastest for that (graph, template, k, batch).  The choice never
+ * changes a result. */
 typedef struct {
-    int32_t tile_cols, fuse_max_cols, batch, trials;
+    int32_t interleave, lds_max, batch, trials;
     double ms;                      /* time of one pass with the chosen knobs */
 } sc_tune_t;
 int sc_autotune(sc_ctx *ctx, int32_t graph_id, int32_t tmpl_id, int32_t n_colorings, sc_tune_t *out);
@@ -262,18 +269,16 @@ int sc_serve_stop(sc_ctx *ctx);
  * Errors: SC_EINVAL (unknown option or value out of range). */
 enum {
     SC_OPT_MAX_BATCH = 1,     /* cap on colourings per pass (1..SC_MAX_BATCH)   */
-    SC_OPT_FUSED = 2,         /* 1 (default): fused neighbour-sum + multiply-add
-                                 row kernels where the rows fit; 0: never      */
     SC_OPT_GRAPH = 3,         /* 1: replay each pass from a captured hipGraph   */
-    SC_OPT_TILE_COLS = 4,     /* neighbour-sum column tile: 8, 16, 32, 64, 128 or
-                                 256 uint64 (0 = default, 128)                 */
     SC_OPT_SEGMENT = 5,       /* neighbours per work item of heavy rows, > 64
                                  (0 = default, 256)                            */
-    SC_OPT_FUSE_MAX_COLS = 7, /* widest passive row (uint64) the fused neighbour
-                                 sum takes (64..2048)                          */
-    SC_OPT_REORDER = 8        /* 1 (default): graphs loaded afterwards are kept
+    SC_OPT_REORDER = 8,       /* 1 (default): graphs loaded afterwards are kept
                                  relabelled by descending degree (colours still
                                  follow the caller's vertex ids)               */
+    SC_OPT_INTERLEAVE = 9,    /* cap on colourings interleaved per table plane:
+                                 1, 2, 4, ..., 64 (0 = default, no cap)        */
+    SC_OPT_LDS_MAX = 10       /* LDS bytes per row-kernel workgroup,
+                                 16384..163840 (0 = default, 65536)            */
 };
 int sc_set_option(sc_ctx *ctx, int32_t option, int64_t value);
 int sc_get_option(sc_ctx *ctx, int32_t option, int64_t *value);

@@ -2,7 +2,7 @@
 // columns, run as the plan's kernel sequence (directly, or replayed from a
 // captured hipGraph).  sc_run chains passes without host round trips;
 // sc_run_batch does the same for many (graph, template, k, seed) jobs at
-// once; sc_autotune picks tile and fusion widths by timing real passes.
+// once; sc_autotune picks the interleave and LDS limit by timing real passes.
 #include <algorithm>
 #include <atomic>
 #include <cmath>
@@ -57,10 +57,30 @@ int ensure_gen(sc_ctx *c, DevMem &m, size_t bytes, hipStream_t st, PassBuffers &
 
 size_t npre_bytes(const Graph &g, const Plan &P) {
     size_t w = 0;
-    for (const Step &s : P.steps)
-        if (s.mode == kStepFusedHist || s.mode == kStepFusedGather)
-            w = std::max(w, (size_t)g.n_split * binom(P.k, s.p) * P.batch);
+    for (const Step &s : P.steps) w = std::max(w, (size_t)g.n_split * binom(P.k - 1, s.p) * P.batch);
     return w * 8;
+}
+
+// Kernel shape and device index tables of one step (tables are uploaded on
+// first use, so prepare_pass calls this before any capture).
+int step_args(sc_ctx *c, const Plan &P, const Step &s, kern::StepShape &sh, kern::StepTables &tb) {
+    const int k = P.k;
+    sh.k = k; sh.a = s.a; sh.p = s.p;
+    sh.B = P.batch; sh.Bi = P.interleave;
+    sh.Wq = s.p >= 2 ? (int)binom(k - 1, s.p - 1) : 0;
+    sh.Wn = (int)binom(k - 1, s.p);
+    sh.Wa = (int)binom(k - 1, s.a - 1);
+    sh.Wh = (int)binom(k - 1, s.h - 1);
+    sh.nsplit = (int)binom(s.h - 1, s.a - 1);
+    sh.amode = s.amode;
+    int rc;
+    if (s.a > 1 && (rc = get_split(c, k - 1, s.h - 1, s.a - 1, &tb.split))) return rc;
+    if (s.p > 1) {
+        if ((rc = get_unrank(c, k - 1, s.p - 1, &tb.unrank))) return rc;
+        if ((rc = get_rank(c, k - 1, &tb.rank))) return rc;
+        tb.n_rank = kern::rank_entries(k - 1);
+    }
+    return SC_OK;
 }
 
 }  // namespace
@@ -77,10 +97,9 @@ int prepare_pass(sc_ctx *c, const PassSpec &s, PassBuffers &b, hipStream_t st) {
     const size_t np = npre_bytes(g, P);
     if (np && (rc = ensure_gen(c, b.npre, np, st, b))) return rc;
     for (const Step &st_ : P.steps) {
-        const uint32_t *split;
-        const int16_t *drop;
-        if (st_.a > 1) { if ((rc = get_split(c, P.k, st_.h, st_.a, &split))) return rc; }
-        else { if ((rc = get_drop(c, P.k, st_.h, &drop))) return rc; }
+        kern::StepShape sh;
+        kern::StepTables tb;
+        if ((rc = step_args(c, P, st_, sh, tb))) return rc;
     }
     return SC_OK;
 }
@@ -90,7 +109,7 @@ int enqueue_pass(sc_ctx *c, const PassSpec &sp, PassBuffers &pb, hipStream_t st,
     const Plan &P = *sp.P;
     const int B = P.batch, k = P.k;
     const int64_t n = g.n_rows;
-    const double dn = (double)n, dnnz = (double)g.nnz;
+    const double dn = (double)n, dB = (double)B;
     int rc;
     auto *X = (unsigned long long *)pb.xbuf.p;
     auto *flags = X + SC_MAX_BATCH;
@@ -99,8 +118,7 @@ int enqueue_pass(sc_ctx *c, const PassSpec &sp, PassBuffers &pb, hipStream_t st,
     auto *Npre = (uint64_t *)pb.npre.p;
     auto buf = [&](int id) { return id < 0 ? (uint64_t *)nullptr : (uint64_t *)(base + P.bufs[id].offset); };
     const kern::GraphBins bins = bins_of(g);
-    const double adj_bytes = 4.0 * dnnz + 8.0 * (dn + 1);
-    const double split_nnz = g.split_nnz;
+    const double split_nnz = g.split_nnz, row_nnz = (double)g.nnz - split_nnz;
 
     HIPCHK(c, kern::launch_zero_u64((uint64_t *)X, SC_MAX_BATCH + 1, st));
     {
@@ -109,69 +127,32 @@ int enqueue_pass(sc_ctx *c, const PassSpec &sp, PassBuffers &pb, hipStream_t st,
     }
     const Step *last = nullptr;
     for (const Step &s : P.steps) {
-        const int Wa = (int)binom(k, s.a), Wp = (int)binom(k, s.p), Wh = (int)binom(k, s.h);
-        const int64_t Lp = (int64_t)Wp * B;
-        const double La = (double)Wa * B, Ls = (double)Wh * B, dLp = (double)Lp;
-        const int nsplit = (int)binom(s.h, s.a);
-        uint64_t *N = buf(s.buf_n);
+        kern::StepShape sh;
+        kern::StepTables tb;
+        if ((rc = step_args(c, P, s, sh, tb))) return rc;
         uint64_t *S = buf(s.buf_s);
         const uint64_t *Pp = buf(s.buf_p), *A = buf(s.buf_a);
-        const uint32_t *split = nullptr;
-        const int16_t *drop = nullptr;
-        if (s.a > 1) { if ((rc = get_split(c, k, s.h, s.a, &split))) return rc; }
-        else { if ((rc = get_drop(c, k, s.h, &drop))) return rc; }
-        const double ema_upd = s.a > 1 ? dn * Ls * nsplit : dn * Ls;
-        const double ema_bytes = 8.0 * dn * ((s.a > 1 ? La : 0) + Ls) + (s.a == 1 ? dn * B : 0);
-        const double sp_upd = dnnz * dLp;
-        switch (s.mode) {
-        case kStepFusedHist: {
-            if (g.n_split) {
-                ProfScope ps(c, prof, st, "hist_split", 4.0 * split_nnz + 8.0 * g.n_split * dLp, split_nnz * dLp);
-                HIPCHK(c, kern::launch_hist_split(bins, col, Npre, B, k, st));
-            }
-            ProfScope ps(c, prof, st, "row_hist", adj_bytes + dn * B + ema_bytes, sp_upd + ema_upd);
-            HIPCHK(c, kern::launch_row(kern::kModeHist, bins, col, nullptr, Npre, A, S, B, k, s.a,
-                                       Wa, Wp, Wh, nsplit, split, drop, flags, st));
-            break;
+        // updates in the paper's units (Lemma 1): nnz*C(k,p) neighbour-sum
+        // updates, n*C(k,h)*C(h,a) multiply-adds (n*C(k,h) selects for a = 1)
+        const double Wp = (double)binom(k, s.p), Wh = (double)binom(k, s.h);
+        const double ema_upd = dn * Wh * (s.a > 1 ? (double)binom(s.h, s.a) : 1.0) * dB;
+        if (g.n_split) {
+            ProfScope ps(c, prof, st, "split", 4.0 * split_nnz + 16.0 * g.n_split * sh.Wn * dB,
+                         split_nnz * Wp * dB);
+            HIPCHK(c, kern::launch_dp_split(bins, sh, tb, col, Pp, Npre, flags, st));
         }
-        case kStepFusedGather: {
-            if (g.n_split) {
-                HIPCHK(c, kern::launch_zero_split_rows(bins, true, Npre, Lp, st));
-                ProfScope ps(c, prof, st, "spmm_split", 4.0 * split_nnz + 16.0 * g.n_split * dLp, split_nnz * dLp);
-                HIPCHK(c, kern::launch_spmm_split(bins, Pp, Npre, Lp, B, sp.tile_cols, flags, st));
-            }
-            ProfScope ps(c, prof, st, "row_gather", adj_bytes + 8.0 * dn * dLp + ema_bytes, sp_upd + ema_upd);
-            HIPCHK(c, kern::launch_row(kern::kModeGather, bins, col, Pp, Npre, A, S, B, k, s.a,
-                                       Wa, Wp, Wh, nsplit, split, drop, flags, st));
-            break;
-        }
-        default: {
-            if (s.p == 1) {
-                ProfScope ps(c, prof, st, "hist", adj_bytes + dn * B + 8.0 * dn * dLp, sp_upd);
-                HIPCHK(c, kern::launch_hist(bins, col, N, B, k, st));
-            } else {
-                HIPCHK(c, kern::launch_zero_split_rows(bins, false, N, Lp, st));
-                ProfScope ps(c, prof, st, "spmm", adj_bytes + 16.0 * dn * dLp, sp_upd);
-                HIPCHK(c, kern::launch_spmm(bins, Pp, N, Lp, B, sp.tile_cols, flags, st));
-            }
-            if (s.mode == kStepStaged) {
-                ProfScope ps(c, prof, st, "row_staged", 8.0 * dn * dLp + ema_bytes, ema_upd);
-                HIPCHK(c, kern::launch_row(kern::kModeStaged, bins, col, N, nullptr, A, S, B, k, s.a,
-                                           Wa, Wp, Wh, nsplit, split, drop, flags, st));
-            } else if (s.a == 1) {
-                ProfScope ps(c, prof, st, "select", 8.0 * dn * dLp + ema_bytes, ema_upd);
-                HIPCHK(c, kern::launch_select(n, col, N, S, B, k, Wh, Wp, drop, st));
-            } else {
-                ProfScope ps(c, prof, st, "ema", 8.0 * dn * dLp + ema_bytes, ema_upd);
-                HIPCHK(c, kern::launch_ema(n, A, N, S, B, Wa, Wp, Wh, nsplit, split, flags, st));
-            }
-        }
-        }
+        // compulsory bytes: adjacency, colours, the passive and active tables
+        // read once, the output written once, split rows' sums read back
+        const double bytes = 4.0 * (double)g.nnz + 8.0 * (dn + 1) + dn * dB +
+                             8.0 * dn * dB * ((s.p > 1 ? sh.Wq : 0) + (s.a > 1 ? sh.Wa : 0) + sh.Wh) +
+                             8.0 * (double)g.n_split * sh.Wn * dB;
+        ProfScope ps(c, prof, st, s.p == 1 ? "row_hist" : "row_gather", bytes, row_nnz * Wp * dB + ema_upd);
+        HIPCHK(c, kern::launch_dp_row(bins, sh, tb, col, Pp, A, Npre, S, flags, st));
         last = &s;
     }
-    const int W = (int)binom(k, last->h);
+    const int W = (int)binom(k - 1, last->h - 1);
     ProfScope ps(c, prof, st, "reduce", 8.0 * dn * W * B, 0);
-    HIPCHK(c, kern::launch_reduce(n, buf(last->buf_s), W, B, X, flags, st));
+    HIPCHK(c, kern::launch_reduce(n, buf(last->buf_s), W, B, P.interleave, X, flags, st));
     return SC_OK;
 }
 
@@ -196,8 +177,7 @@ int launch_pass(sc_ctx *c, int gid, int tid, const PassSpec &s, PassBuffers &b, 
     host_desc[1] = s.first;
     HIPCHK(c, hipMemcpyAsync(b.desc.p, host_desc, 2 * sizeof(uint64_t), hipMemcpyHostToDevice, st));
     if (allow_graph && c->use_graph && !c->prof) {
-        GraphExecKey key{gid, tid, P.k, P.batch, s.tile_cols, P.opts.fuse ? P.opts.fuse_max_cols : 0,
-                         s.g->seg, b.gen};
+        GraphExecKey key{gid, tid, P.k, P.batch, P.interleave, P.opts.lds_max, s.g->seg, b.gen};
         auto it = c->graph_cache.find(key);
         if (it == c->graph_cache.end()) {
             hipGraph_t graph = nullptr;
@@ -234,7 +214,6 @@ struct PassJob {
     uint64_t seed, first;
     int offset;                // first colouring of this pass within its job
     Plan P;
-    int tile;
 };
 
 // Plans every pass of the jobs, runs them back to back on `st` and waits once.
@@ -262,7 +241,6 @@ int run_passes(sc_ctx *c, std::vector<PassJob> &passes, hipStream_t st,
         s.k = p.k;
         s.seed = p.seed;
         s.first = p.first;
-        s.tile_cols = p.tile;
         uint64_t *stage = c->host_out + i * kStageWords;
         if ((rc = launch_pass(c, p.gid, p.tid, s, b, st, stage, stage + 2, true))) return rc;
     }
@@ -280,7 +258,7 @@ int plan_job(sc_ctx *c, int job, int gid, int tid, int k, uint64_t seed, uint64_
         p.job = job; p.gid = gid; p.tid = tid; p.k = k; p.seed = seed;
         p.first = first + (uint64_t)off;
         p.offset = off;
-        int rc = pick_batch(c, gid, tid, k, n - off, 0, p.P, &p.tile);
+        int rc = pick_batch(c, gid, tid, k, n - off, 0, p.P);
         if (rc) return rc;
         off += p.P.batch;
         out.push_back(std::move(p));
@@ -378,26 +356,27 @@ int sc_autotune(sc_ctx *c, int32_t gid, int32_t tid, int32_t n_colorings, sc_tun
     std::lock_guard<std::recursive_mutex> lk(c->mu);
     if (!out) return fail(c, SC_EINVAL, "NULL argument");
     Plan P;
-    int rc = pick_batch(c, gid, tid, c->k, std::max(1, n_colorings), 0, P, nullptr);
+    int rc = pick_batch(c, gid, tid, c->k, std::max(1, n_colorings), 0, P);
     if (rc) return rc;
     const int B = P.batch;
     const TuneKey key{gid, tid, c->k, B};
     c->tuned.erase(key);
-    static const int tiles[] = {64, 128, 256};
-    static const int fuses[] = {256, 512, 1024};
-    std::vector<uint64_t> counts(B);
-    std::vector<uint8_t> ovf(B);
+    // interleave caps: the four largest powers of two dividing the batch
+    std::vector<int> inter;
+    for (int bi = 64; bi >= 1 && inter.size() < 4; bi /= 2)
+        if (B % bi == 0) inter.push_back(bi);
+    static const int ldss[] = {32 * 1024, 64 * 1024, 96 * 1024};
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));
     Tuned best;
     best.ms = 1e300;
     int trials = 0;
-    for (int tile : tiles)
-        for (int fuse : fuses) {
+    for (int bi : inter)
+        for (int lm : ldss) {
             Tuned cand;
-            cand.tile_cols = tile;
-            cand.fuse_max_cols = fuse;
+            cand.interleave = bi;
+            cand.lds_max = lm;
             c->tuned[key] = cand;
             std::vector<PassJob> passes;
             if ((rc = plan_job(c, 0, gid, tid, c->k, c->seed, 0, B, passes))) break;
@@ -416,8 +395,8 @@ int sc_autotune(sc_ctx *c, int32_t gid, int32_t tid, int32_t n_colorings, sc_tun
     (void)hipEventDestroy(e1);
     if (rc) { c->tuned.erase(key); return rc; }
     c->tuned[key] = best;
-    out->tile_cols = best.tile_cols;
-    out->fuse_max_cols = best.fuse_max_cols;
+    out->interleave = best.interleave;
+    out->lds_max = best.lds_max;
     out->batch = B;
     out->ms = best.ms;
     out->trials = trials;
@@ -438,7 +417,7 @@ int sc_tune_save(sc_ctx *c, const char *path) {
         const Template &T = *ti->second;
         fprintf(f, "%lld %lld %lld %d %d %d %d %d %.6f", (long long)g.n, (long long)g.nnz,
                 (long long)g.max_deg, std::get<2>(kv.first), std::get<3>(kv.first),
-                kv.second.tile_cols, kv.second.fuse_max_cols, T.t, kv.second.ms);
+                kv.second.interleave, kv.second.lds_max, T.t, kv.second.ms);
         for (int32_t e : T.edges) fprintf(f, " %d", e);
         fprintf(f, "\n");
     }
@@ -454,9 +433,9 @@ int sc_tune_load(sc_ctx *c, const char *path, int32_t *n_applied) {
     if (!f) return fail(c, SC_ENOTFOUND, "cannot read %s", path);
     int applied = 0;
     long long n, nnz, maxd;
-    int k, B, tile, fuse, t;
+    int k, B, inter, lmax, t;
     double ms;
-    while (fscanf(f, "%lld %lld %lld %d %d %d %d %d %lf", &n, &nnz, &maxd, &k, &B, &tile, &fuse, &t, &ms) == 9) {
+    while (fscanf(f, "%lld %lld %lld %d %d %d %d %d %lf", &n, &nnz, &maxd, &k, &B, &inter, &lmax, &t, &ms) == 9) {
         if (t < 1 || t > SC_MAX_T) break;
         std::vector<int32_t> e(2 * (t - 1));
         bool ok = true;
@@ -467,8 +446,8 @@ int sc_tune_load(sc_ctx *c, const char *path, int32_t *n_applied) {
                 const Graph &g = *gk.second;
                 if (g.n != n || g.nnz != nnz || g.max_deg != maxd || tk.second->edges != e) continue;
                 Tuned tu;
-                tu.tile_cols = tile;
-                tu.fuse_max_cols = fuse;
+                tu.interleave = inter;
+                tu.lds_max = lmax;
                 tu.ms = ms;
                 c->tuned[TuneKey{gk.first, tk.first, k, B}] = tu;
                 ++applied;

@@ -1,7 +1,17 @@
 // Launchers for the gfx950 kernels of libsc (definitions in kernels.hip).
-// Table layout everywhere: a table for sub-template size s in a pass of B
-// colourings is uint64[n][binom(k,s) * B]; entry (v, colour set I, colouring r)
-// lives at v * binom(k,s) * B + I * B + r.  Colours are uint8[n][B].
+//
+// Rooted-colour table layout.  In colouring r, the table of a sub-template of
+// size s is zero at M_s[v][C] unless C holds col_r(v) (the sub-template's root
+// maps to v), so a row keeps only the colour sets that hold the row's own
+// colour: W(s) = binom(k-1, s-1) entries per colouring.  Entry j of row v is
+// the set {col_r(v)} + D_j, where D_j is the j-th (s-1)-subset, in Eq. 1 order,
+// of the k-1 other colours renumbered 0..k-2 (colour x > col_r(v) becomes
+// x - 1).  Single-vertex tables are all ones and never stored.
+//
+// A pass of B colourings keeps them as `planes` planes of Bi interleaved
+// colourings (B = planes * Bi, Bi a power of two): entry (v, j, r) with
+// r = plane * Bi + ri lives at ((plane * n + v) * W + j) * Bi + ri.
+// Colours are uint8[n][B].
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -10,29 +20,51 @@
 namespace sc {
 namespace kern {
 
-// Rows are binned by degree once per graph:
-//  light rows  (deg <= kLightMax): one wavefront per row (colour histogram);
-//  wide items  (deg >  kLightMax): one workgroup per (row, segment of `seg`
-//              neighbours) (colour histogram);
-//  tasks       every row with deg <= seg, and every `seg`-neighbour segment of
-//              the rows with more (neighbour sum);
-// rows with deg > seg ("split rows") are summed over several segments whose
-// partial sums meet in global atomics.
-constexpr int kLightMax = 64;
-
+// Rows with more than `seg` neighbours ("split rows") have their neighbour
+// sums built by a pre-pass over (row, segment) items whose partial sums meet
+// in global atomics; every other row is summed inside the row kernel.
 struct GraphBins {
     int64_t n = 0, nnz = 0;   // n: rows the tables hold (isolated vertices dropped when relabelled)
     const int64_t *row_ptr = nullptr;
     const int32_t *col_idx = nullptr;
-    const int32_t *light_rows = nullptr;  int64_t n_light = 0;
-    const int2 *wide_items = nullptr;     int64_t n_wide = 0;   // (row, segment), split rows first
-    int64_t n_split_items = 0;                                  // items of split rows
-    const int2 *tasks = nullptr;          int64_t n_tasks = 0;  // neighbour-sum tasks, split rows first
-    int64_t n_split_tasks = 0;
-    const int32_t *split_rows = nullptr;  int64_t n_split = 0;  // rows with deg > seg
+    const int32_t *split_rows = nullptr;  int64_t n_split = 0;        // rows with deg > seg
+    const int2 *split_items = nullptr;    int64_t n_split_items = 0;  // (row, segment)
     const int32_t *slot = nullptr;        // [n]: index of a split row in split_rows, else -1
     int seg = 0;
 };
+
+// How a step reads its active table: a = 1 (the all-ones single-vertex table,
+// so the step's output is the neighbour sum itself), staged in LDS, or read
+// from global memory (rows too wide to stage).
+enum ActiveMode { kActiveLeaf = 0, kActiveLds = 1, kActiveGlobal = 2 };
+
+// Shape of one DP step in the rooted-colour layout (h = a + p).
+struct StepShape {
+    int k = 0, a = 0, p = 0;
+    int B = 1, Bi = 1;                 // colourings per pass; interleaved per plane
+    int Wq = 0;                        // binom(k-1, p-1): passive row entries
+    int Wn = 0;                        // binom(k-1, p):   neighbour-sum entries
+    int Wa = 0;                        // binom(k-1, a-1): active row entries
+    int Wh = 0;                        // binom(k-1, h-1): output row entries
+    int nsplit = 0;                    // binom(h-1, a-1): split pairs per output entry
+    int amode = kActiveLeaf;
+};
+
+// Host-built index tables of a step (device pointers).
+struct StepTables {
+    const uint32_t *split = nullptr;   // a >= 2: per output set, nsplit pairs (Ia | Ip << 16)
+                                       // of the (k-1, h-1, a-1) split table
+    const uint16_t *unrank = nullptr;  // p >= 2: masks of the (p-1)-subsets of k-1 colours
+    const uint16_t *rank = nullptr;    // Eq. 1 rank of a mask of k-1 colours, in two parts
+    int n_rank = 0;                    // entries of `rank`
+};
+
+// Number of rank-table entries for masks of k1 colours: rank(m) =
+// R[m & 255] + R[256 + (m >> 8) * 9 + popcount(m & 255)].
+int rank_entries(int k1);
+
+// Dynamic LDS bytes of the row and split kernels of a step.
+int dp_lds_bytes(const StepShape &s, int amode, int n_rank);
 
 // col[v*B + r] = colour of vertex v in colouring first+r (SplitMix64 rule),
 // drawn from the original id perm[v] when the graph was relabelled (perm != NULL);
@@ -40,54 +72,26 @@ struct GraphBins {
 hipError_t launch_color(const uint64_t *desc, int64_t n, int B, int k, const int32_t *perm,
                         uint8_t *col, hipStream_t st);
 
-// N = A * P for a table with L = W*B uint64 columns per row (the split rows of
-// N must be zeroed first, see launch_zero_split_rows), in column tiles
-// of tile_cols = 8, 16, 32 (lane groups over several neighbours) or 64, 128,
-// 256 (wavefront-wide row slices) uint64.
-hipError_t launch_spmm(const GraphBins &g, const uint64_t *P, uint64_t *N, int64_t L, int B,
-                       int tile_cols, unsigned long long *flags, hipStream_t st);
+// Neighbour sums of the split rows into Npre[planes][n_split][Wn * Bi]
+// (zeroed here first), from the passive table P (p >= 2) or the colours (p = 1).
+hipError_t launch_dp_split(const GraphBins &g, const StepShape &s, const StepTables &t,
+                           const uint8_t *col, const uint64_t *P, uint64_t *Npre,
+                           unsigned long long *flags, hipStream_t st);
 
-// Zeroes the split rows of N (compact: rows of Npre[n_split][L]) before the
-// neighbour sums of their segments add into them.
-hipError_t launch_zero_split_rows(const GraphBins &g, bool compact, uint64_t *N, int64_t L,
-                                  hipStream_t st);
+// One DP step: for every row v and plane, the neighbour sum N'[v] (the sets
+// without col_r(v)) is built in LDS -- scattered from the neighbours' passive
+// rows (p >= 2), counted from their colours (p = 1), or copied from Npre for
+// split rows -- and S[v] = sum over splits of A[v][Ia] * N'[v][Ip] is written
+// (S[v] = N'[v] when a = 1).
+hipError_t launch_dp_row(const GraphBins &g, const StepShape &s, const StepTables &t,
+                         const uint8_t *col, const uint64_t *P, const uint64_t *A,
+                         const uint64_t *Npre, uint64_t *S, unsigned long long *flags,
+                         hipStream_t st);
 
-// Neighbour sums of the split rows only, into the compact Npre[n_split][L].
-hipError_t launch_spmm_split(const GraphBins &g, const uint64_t *P, uint64_t *Npre, int64_t L,
-                             int B, int tile_cols, unsigned long long *flags, hipStream_t st);
-
-// p = 1: N[v][c*B + r] = #{j in adj(v) : col[j*B + r] == c}, c < k.
-hipError_t launch_hist(const GraphBins &g, const uint8_t *col, uint64_t *N, int B, int k,
-                       hipStream_t st);
-// The same for the split rows only, into the compact Npre[n_split][k*B].
-hipError_t launch_hist_split(const GraphBins &g, const uint8_t *col, uint64_t *Npre, int B, int k,
-                             hipStream_t st);
-
-// a = 1: S[v][I*B + r] = N[v][drop[I*k + c]*B + r] if c = col[v*B+r] is in set I, else 0.
-hipError_t launch_select(int64_t n, const uint8_t *col, const uint64_t *N, uint64_t *S, int B,
-                         int k, int Wh, int Wp, const int16_t *drop, hipStream_t st);
-
-// a >= 2: S[v][I*B + r] = sum over the nsplit pairs (Ia, Ip) of set I of
-// A[v][Ia*B + r] * N[v][Ip*B + r].
-hipError_t launch_ema(int64_t n, const uint64_t *A, const uint64_t *N, uint64_t *S, int B,
-                      int Wa, int Wp, int Wh, int nsplit, const uint32_t *split,
-                      unsigned long long *flags, hipStream_t st);
-
-// Row kernel: one workgroup per row, N[v] and A[v] staged in LDS, then the
-// select (a = 1) or the split multiply-add (a >= 2).  Modes: the neighbour-sum
-// row comes from N (`src`, staged), is summed from the passive table (`src`,
-// fused; Wp*B <= 2048) or counted from colours (fused histogram, p = 1).
-// Fused modes read split rows from Npre.
-enum { kModeStaged = 0, kModeGather = 1, kModeHist = 2 };
-int row_lds_bytes(int k, int a, int Wa, int Wp, int B, int mode);
-hipError_t launch_row(int mode, const GraphBins &g, const uint8_t *col, const uint64_t *src,
-                      const uint64_t *Npre, const uint64_t *A, uint64_t *S, int B, int k, int a,
-                      int Wa, int Wp, int Wh, int nsplit, const uint32_t *split,
-                      const int16_t *drop, unsigned long long *flags, hipStream_t st);
-
-// X[r] = sum_v sum_I S[v][I*B + r] (with carry flags); X must be zeroed first.
-hipError_t launch_reduce(int64_t n, const uint64_t *S, int W, int B, unsigned long long *X,
-                         unsigned long long *flags, hipStream_t st);
+// X[r] = sum over rows and the W entries of colouring r of table S (with carry
+// flags); X must be zeroed first.
+hipError_t launch_reduce(int64_t n, const uint64_t *S, int W, int B, int Bi,
+                         unsigned long long *X, unsigned long long *flags, hipStream_t st);
 
 hipError_t launch_zero_u64(uint64_t *p, int64_t count, hipStream_t st);
 

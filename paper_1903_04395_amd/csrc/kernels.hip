@@ -1,19 +1,27 @@
 // gfx950 kernels for the colour-coding DP (Chen et al., HPDC'19).
 //
-//  * colouring            -- SplitMix64 counter-based colours (Section 2.1, phase 1)
-//  * neighbour sum (SpMM) -- N = A * M_p over all passive columns at once
-//                            (Eq. 2 and Section 4.2: one traversal per passive
-//                            colour set; Section 4.5: SpMM)
-//  * colour histogram     -- the same neighbour sum when the passive child is a
-//                            single vertex (its table is the colour indicator)
-//  * select / eMA         -- M_s[v,C] = sum_{C1 (+) C2 = C} M_a[v,C1] * N[v,C2]
-//                            (Algorithm 4's element-wise multiply-add), with
-//                            the a = 1 case reduced to a gather
-//  * fused step           -- neighbour sum kept in LDS and consumed in place
-//  * root reduction       -- colourful count per colouring
+//  * colouring    -- SplitMix64 counter-based colours (Section 2.1, phase 1)
+//  * DP step      -- one row kernel per attach of a passive child: the
+//                    neighbour sum N = A * M_p taken once per passive colour
+//                    set (Eq. 2 with the pruning of Section 4.2; the SpMM of
+//                    Section 4.5) built per row in LDS, then the element-wise
+//                    multiply-add M_s[v,C] = sum_{C1 (+) C2 = C} M_a[v,C1] *
+//                    N[v,C2] (Algorithm 4), fused, in the rooted-colour layout
+//                    described in kernels.h
+//  * split pre-pass -- the neighbour sums of rows with very many neighbours
+//  * root reduction -- colourful count per colouring
 //
 // All arithmetic is exact uint64 modulo 2^64; every carry out of 64 bits sets
 // the colouring's bit in a 64-bit flag mask (bit r = colouring r of the pass).
+//
+// In the rooted-colour layout a neighbour u of v contributes its entry for the
+// set {col(u)} + T (T a subset of the colours other than col(u)) to v's
+// neighbour-sum entry for the same set, when that set does not hold col(v);
+// the entry index is found by re-ranking the set among the colours other than
+// col(v).  Sets that hold col(v) only ever meet zero active entries and are
+// skipped, and neighbours that share v's colour contribute nothing.
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace sc {
@@ -22,10 +30,14 @@ namespace {
 
 constexpr int kWave = 64;
 constexpr int kBlock = 256;
+constexpr int kWaves = kBlock / kWave;
+constexpr int kGatherUnroll = 4;      // passive-row loads in flight per lane
 // A launch may hold at most 2^32 - 1 work-items per grid dimension; kernels
 // that stride over their items are launched with at most this many workgroups.
 constexpr int64_t kMaxStrideBlocks = 1 << 16;
-constexpr int64_t kMaxGridBlocks = ((int64_t)1 << 32) / kBlock - 1;
+constexpr int kCUs = 256;
+constexpr int kMaxBlocksPerCU = 8;    // 32 wavefronts of 4-wave workgroups
+constexpr int kLdsPerCU = 160 * 1024;
 
 __device__ __forceinline__ uint64_t wave_or(uint64_t m) {
     uint32_t lo = (uint32_t)m, hi = (uint32_t)(m >> 32);
@@ -77,504 +89,236 @@ __global__ __launch_bounds__(kBlock) void color_kernel(const uint64_t *__restric
     }
 }
 
-// ------------------------------------------------------------------ neighbour sum
+// ------------------------------------------------------------------ DP step
 
-// Accumulates P rows of the neighbours e0, e0+step, ... < e1 into acc[] for
-// the lane's U columns c0 + 64u (bounds in inb[]), four neighbours at a time
-// so that 4*U loads are in flight per lane.
-template <int U>
-__device__ __forceinline__ void gather_rows(int64_t e0, int64_t e1, int step,
-                                            const int32_t *__restrict__ ci,
-                                            const uint64_t *__restrict__ P, int64_t L, int64_t c0,
-                                            const bool (&inb)[U], uint64_t (&acc)[U],
-                                            uint32_t &carry) {
-    int64_t e = e0;
-    for (; e + 3 * step < e1; e += 4 * step) {
-        const uint64_t *s[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) s[i] = P + (int64_t)ci[e + i * step] * L + c0;
-        uint64_t x[4][U];
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int u = 0; u < U; ++u) x[i][u] = inb[u] ? s[i][kWave * u] : 0;
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const uint64_t t = acc[u] + x[i][u];
-                carry |= (uint32_t)(t < x[i][u]) << u;
-                acc[u] = t;
-            }
-    }
-    for (; e < e1; e += step) {
-        const uint64_t *s0 = P + (int64_t)ci[e] * L + c0;
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const uint64_t x = inb[u] ? s0[kWave * u] : 0;
-            const uint64_t t = acc[u] + x;
-            carry |= (uint32_t)(t < x) << u;
-            acc[u] = t;
-        }
-    }
-}
-
-struct SpmmArgs {
+struct DpArgs {
     const int64_t *rp;
     const int32_t *ci;
-    const int32_t *light;  int64_t n_light;   // light rows, 4 per workgroup
-    const int2 *wide;      int64_t n_wide;    // (row, segment) items, 1 per workgroup
+    const uint8_t *col;
+    int64_t n;                    // table rows
+    int B, Bi, sh, planes;        // sh = log2(Bi)
+    int p, Wq, Wn, Wa, Wh, nsplit;
+    const uint32_t *split;
+    const uint16_t *unrank, *rank;
+    int n_rank;
+    const uint64_t *P, *A;
+    uint64_t *S;
+    uint64_t *Npre;
+    const int32_t *slot;
+    int64_t n_split;
+    const int2 *items;            // split pre-pass: (row, segment)
+    int64_t n_items;
     int seg;
-    const int32_t *slot;                      // optional output-row redirect
-    const uint64_t *P;
-    uint64_t *N;
-    int64_t L;
-    int B;
-    int64_t groups;                           // light groups + wide items
-    int64_t chunks;                           // column chunks of 64*U
+    int a_off, tab_off;           // LDS: staged active row (words), index tables (bytes)
     unsigned long long *flags;
 };
 
-// Neighbour sum N = A * P, tiled by column chunks of 64*U uint64 (a 2 KB
-// contiguous slice of every gathered row for U = 4) and walked chunk-major so
-// that the rows in flight read one chunk.  Light rows: one wavefront each,
-// four per workgroup.  Wide items: four wavefronts split the neighbours and
-// meet in LDS; rows with more than `seg` neighbours are split over several
-// items whose partial sums meet in global atomics (the carry is read from the
-// returned old value).  The grid strides over (chunk, group) items.
-template <int U>
-__device__ __forceinline__ void spmm_tiled_item(const SpmmArgs &a, int64_t chunk, int64_t g,
-                                                uint64_t (*red)[U][kWave], uint32_t (*redc)[kWave]) {
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+// Inserts a zero bit at position c (renumbered colours -> colours).
+__device__ __forceinline__ uint32_t widen_at(uint32_t m, int c) {
+    const uint32_t lo = m & ((1u << c) - 1u);
+    return lo | ((m ^ lo) << 1);
+}
+// Removes bit c, which must be zero (colours -> colours other than c, renumbered).
+__device__ __forceinline__ uint32_t narrow_at(uint32_t m, int c) {
+    const uint32_t lo = m & ((1u << c) - 1u);
+    return lo | ((m ^ lo) >> 1);
+}
+
+// Copies the index tables a step needs into LDS (called by the whole block).
+__device__ __forceinline__ void stage_tables(const DpArgs &a, uint16_t *tab) {
+    if (a.p < 2) return;
+    for (int i = threadIdx.x; i < a.Wq; i += kBlock) tab[i] = a.unrank[i];
+    for (int i = threadIdx.x; i < a.n_rank; i += kBlock) tab[a.Wq + i] = a.rank[i];
+}
+
+// p >= 2: scatters the passive rows of neighbours [e0, e1) of row v (plane pl)
+// into the LDS neighbour sum Nl.  The wavefronts take every fourth neighbour;
+// a wavefront reads one neighbour's row (Wq * Bi contiguous uint64) with
+// kGatherUnroll loads in flight per lane.  Lane `ri` of every group of Bi
+// lanes serves colouring pl*Bi + ri, so the neighbour's colour is loaded once
+// per lane per neighbour.  Distinct entries of one row land on distinct sets,
+// so a wavefront's adds never collide; adds of different wavefronts meet in
+// LDS atomics, whose returned old value gives the carry.
+__device__ __forceinline__ void scatter_rows(const DpArgs &a, int64_t v, int pl, int64_t e0,
+                                             int64_t e1, uint64_t *Nl, const uint16_t *tab,
+                                             uint64_t &m) {
     const int lane = threadIdx.x & (kWave - 1);
-    const int64_t c0 = chunk * (kWave * U) + lane;
-    bool inb[U];
-    uint64_t acc[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) { inb[u] = c0 + kWave * u < a.L; acc[u] = 0; }
+    const int wave = threadIdx.x >> 6;
+    const int ri = lane & (a.Bi - 1);
+    const int r = pl * a.Bi + ri;
+    const int cv = a.col[v * a.B + r];
+    const int Lq = a.Wq * a.Bi;
+    const uint16_t *unr = tab, *rk = tab + a.Wq;
     uint32_t carry = 0;
-    const int64_t nlg = (a.n_light + 3) >> 2;
-    if (g < nlg) {
-        const int64_t li = g * 4 + wave;
-        if (li >= a.n_light) return;                   // whole wavefront, this item only
-        const int v = __builtin_amdgcn_readfirstlane(a.light[li]);
-        gather_rows<U>(a.rp[v], a.rp[v + 1], 1, a.ci, a.P, a.L, c0, inb, acc, carry);
-        uint64_t *d = a.N + (int64_t)v * a.L + c0;
-        uint64_t m = 0;
+    for (int64_t e = e0 + wave; e < e1; e += kWaves) {
+        const int u = __builtin_amdgcn_readfirstlane(a.ci[e]);
+        const int cu = a.col[(int64_t)u * a.B + r];
+        const bool live = cu != cv;
+        if (!__any(live)) continue;                  // same colour in every lane's colouring
+        const uint64_t *row = a.P + ((int64_t)pl * a.n + u) * Lq;
+        for (int q0 = 0; q0 < Lq; q0 += kWave * kGatherUnroll) {
+            uint64_t x[kGatherUnroll];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if (inb[u]) d[kWave * u] = acc[u];
-            if (carry & (1u << u)) m |= 1ull << ((c0 + kWave * u) % a.B);
+            for (int i = 0; i < kGatherUnroll; ++i) {
+                const int q = q0 + kWave * i + lane;
+                x[i] = (live && q < Lq) ? row[q] : 0;
+            }
+#pragma unroll
+            for (int i = 0; i < kGatherUnroll; ++i) {
+                if (x[i] == 0) continue;
+                const int j = (q0 + kWave * i + lane) >> a.sh;
+                const uint32_t E = widen_at(unr[j], cu) | (1u << cu);
+                if (E & (1u << cv)) continue;
+                const uint32_t Er = narrow_at(E, cv);
+                const int idx = rk[Er & 255u] + rk[256 + (Er >> 8) * 9 + __popc(Er & 255u)];
+                const unsigned long long old =
+                    atomicAdd((unsigned long long *)&Nl[(idx << a.sh) + ri], (unsigned long long)x[i]);
+                carry |= (uint32_t)((uint64_t)old + x[i] < x[i]);
+            }
         }
-        flush_flags(m, a.flags);
+    }
+    if (carry) m |= 1ull << r;
+}
+
+// p = 1: counts the colours of neighbours [e0, e1) of row v (plane pl): the
+// neighbour sum of single-vertex tables is N'[v][{x}] = #{u : col(u) = x}, x
+// renumbered among the colours other than col(v).  The block's threads are
+// (neighbour slot, colouring) pairs.
+__device__ __forceinline__ void count_colours(const DpArgs &a, int64_t v, int pl, int64_t e0,
+                                              int64_t e1, uint64_t *Nl) {
+    const int ri = threadIdx.x & (a.Bi - 1);
+    const int s = threadIdx.x >> a.sh;
+    const int slots = kBlock >> a.sh;
+    const int r = pl * a.Bi + ri;
+    const int cv = a.col[v * a.B + r];
+    for (int64_t e = e0 + s; e < e1; e += slots) {
+        const int cu = a.col[(int64_t)a.ci[e] * a.B + r];
+        if (cu != cv)
+            atomicAdd((unsigned long long *)&Nl[((cu - (cu > cv)) << a.sh) + ri], 1ull);
+    }
+}
+
+// Output row of (v, pl): S[v] = N'[v] (a = 1) or, for every output set D and
+// colouring, the sum over the nsplit pairs (Ia, Ip) of D of A[v][Ia] * N'[v][Ip].
+template <int AM>
+__device__ __forceinline__ void emit_row(const DpArgs &a, int64_t v, int pl, const uint64_t *Nl,
+                                         const uint64_t *Al, uint64_t &m) {
+    const int Ls = a.Wh * a.Bi;
+    uint64_t *out = a.S + ((int64_t)pl * a.n + v) * Ls;
+    if (AM == kActiveLeaf) {
+        for (int q = threadIdx.x; q < Ls; q += kBlock) out[q] = Nl[q];
         return;
     }
-    const int2 it = a.wide[g - nlg];
-    const int v = __builtin_amdgcn_readfirstlane(it.x);
-    const int64_t r0 = a.rp[v], r1 = a.rp[v + 1];
-    const int64_t e0 = r0 + (int64_t)it.y * a.seg;
-    const int64_t e1 = min(e0 + a.seg, r1);
-    const bool split = (r1 - r0) > a.seg;
-    gather_rows<U>(e0 + wave, e1, kBlock / kWave, a.ci, a.P, a.L, c0, inb, acc, carry);
-    if (wave > 0) {
-#pragma unroll
-        for (int u = 0; u < U; ++u) red[wave - 1][u][lane] = acc[u];
-        redc[wave - 1][lane] = carry;
-    }
-    __syncthreads();
-    if (wave == 0) {
-#pragma unroll
-        for (int w = 0; w < kBlock / kWave - 1; ++w) {
-            carry |= redc[w][lane];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const uint64_t x = red[w][u][lane];
-                const uint64_t t = acc[u] + x;
-                carry |= (uint32_t)(t < x) << u;
-                acc[u] = t;
-            }
-        }
-        const int64_t orow = a.slot ? (int64_t)a.slot[v] : (int64_t)v;
-        uint64_t *d = a.N + orow * a.L + c0;
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if (!inb[u]) continue;
-            if (split) {
-                const unsigned long long old = atomicAdd((unsigned long long *)(d + kWave * u),
-                                                         (unsigned long long)acc[u]);
-                if ((uint64_t)old + acc[u] < (uint64_t)old) carry |= 1u << u;
-            } else {
-                d[kWave * u] = acc[u];
-            }
-        }
-        uint64_t m = 0;
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (carry & (1u << u)) m |= 1ull << ((c0 + kWave * u) % a.B);
-        flush_flags(m, a.flags);
-    }
-}
-
-// PRE (a distinct instantiation, so profiles tell the two apart): the pre-pass
-// that sums only the split rows into the compact buffer.
-template <int U, bool PRE>
-__global__ __launch_bounds__(kBlock) void spmm_tiled_kernel(SpmmArgs a) {
-    __shared__ uint64_t red[kBlock / kWave - 1][U][kWave];
-    __shared__ uint32_t redc[kBlock / kWave - 1][kWave];
-    const int64_t total = a.chunks * a.groups;
-    const int64_t nlg = (a.n_light + 3) >> 2;
-    for (int64_t b = blockIdx.x; b < total; b += gridDim.x) {
-        const int64_t chunk = b / a.groups, g = b - chunk * a.groups;
-        spmm_tiled_item<U>(a, chunk, g, red, redc);
-        if (g >= nlg) __syncthreads();                 // red/redc reused by the next wide item
-    }
-}
-
-__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t x, int mask) {
-    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)x, mask, kWave);
-    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(x >> 32), mask, kWave);
-    return ((uint64_t)hi << 32) | lo;
-}
-
-struct NarrowArgs {
-    const int64_t *rp;
-    const int32_t *ci;
-    const int2 *tasks;        // (row, segment of `seg` neighbours)
-    int64_t n_tasks;
-    int seg;
-    const int32_t *slot;      // optional output-row redirect
-    const uint64_t *P;
-    uint64_t *N;
-    int64_t L;
-    int B;
-    int64_t tiles;            // column tiles of Z uint64
-    unsigned long long *flags;
-};
-
-// Neighbour sum N = A * P in narrow column tiles of Z uint64 (Z*8 bytes of
-// every gathered row per tile).  The tiles are walked one after another over
-// all rows, so while a tile is in flight only n*Z*8 bytes of P are live: the
-// hub rows' tile slices stay in L2 and the whole tile fits the last-level
-// cache.  One wavefront per (tile, task): its 64 lanes are 64/Z groups of Z
-// lanes; each group walks every (64/Z)-th neighbour of the task (four in
-// flight) and the groups are summed with cross-lane shuffles.  A task is a
-// whole row, or a `seg`-neighbour segment of a row with more neighbours,
-// whose partial sums meet in global atomics (N zeroed beforehand; the carry is
-// read from the returned old value).
-template <int Z>
-__global__ __launch_bounds__(kBlock) void spmm_narrow_kernel(NarrowArgs a) {
-    constexpr int G = kWave / Z;
-    const int lane = threadIdx.x & (kWave - 1);
-    const int grp = lane / Z, cz = lane - (lane / Z) * Z;
-    const int64_t total = a.tiles * a.n_tasks;
-    const int64_t stride = (int64_t)gridDim.x * (kBlock / kWave);
-    // items in (tile, task) order; the grid strides over them, so the items in
-    // flight at any time belong to one or two consecutive tiles
-    for (int64_t wid = (int64_t)blockIdx.x * (kBlock / kWave) + (threadIdx.x >> 6); wid < total;
-         wid += stride) {
-        const int64_t tile = wid / a.n_tasks;
-        const int64_t ti = wid - tile * a.n_tasks;
-        const int2 tk = a.tasks[ti];
-        const int v = tk.x;
-        const int64_t r0 = a.rp[v], r1 = a.rp[v + 1];
-        const int64_t e0 = r0 + (int64_t)tk.y * a.seg;
-        const int64_t e1 = min(e0 + a.seg, r1);
-        const bool split = (r1 - r0) > a.seg;
-        const int64_t c = tile * Z + cz;
-        const bool inb = c < a.L;
-        const uint64_t *Pc = a.P + c;
+    const uint64_t *Ar = AM == kActiveLds ? Al : a.A + ((int64_t)pl * a.n + v) * (int64_t)(a.Wa * a.Bi);
+    for (int q = threadIdx.x; q < Ls; q += kBlock) {
+        const int D = q >> a.sh, ri = q & (a.Bi - 1);
+        const uint32_t *sp = a.split + (int64_t)D * a.nsplit;
         uint64_t acc = 0;
-        uint32_t carry = 0;
-        int64_t e = e0 + grp;
-        for (; e + 3 * G < e1; e += 4 * G) {
-            const int64_t j0 = a.ci[e], j1 = a.ci[e + G], j2 = a.ci[e + 2 * G], j3 = a.ci[e + 3 * G];
-            const uint64_t x0 = inb ? Pc[j0 * a.L] : 0, x1 = inb ? Pc[j1 * a.L] : 0;
-            const uint64_t x2 = inb ? Pc[j2 * a.L] : 0, x3 = inb ? Pc[j3 * a.L] : 0;
-            uint64_t t = acc + x0; carry |= t < x0;
-            acc = t + x1;          carry |= acc < x1;
-            t = acc + x2;          carry |= t < x2;
-            acc = t + x3;          carry |= acc < x3;
+        uint32_t ovf = 0;
+        for (int j = 0; j < a.nsplit; ++j) {
+            const uint32_t pr = sp[j];
+            acc = mad_ovf(acc, Ar[((pr & 0xffffu) << a.sh) + ri], Nl[((pr >> 16) << a.sh) + ri], ovf);
         }
-        for (; e < e1; e += G) {
-            const uint64_t x = inb ? Pc[(int64_t)a.ci[e] * a.L] : 0;
-            const uint64_t t = acc + x;
-            carry |= t < x;
-            acc = t;
-        }
-#pragma unroll
-        for (int o = Z; o < kWave; o <<= 1) {
-            const uint64_t y = shfl_xor_u64(acc, o);
-            carry |= (uint32_t)__shfl_xor((int)carry, o, kWave);
-            const uint64_t t = acc + y;
-            carry |= t < y;
-            acc = t;
-        }
-        uint64_t m = 0;
-        if (grp == 0 && inb) {
-            const int64_t orow = a.slot ? (int64_t)a.slot[v] : (int64_t)v;
-            uint64_t *d = a.N + orow * a.L + c;
-            if (split) {
-                const unsigned long long old = atomicAdd((unsigned long long *)d, (unsigned long long)acc);
-                if ((uint64_t)old + acc < (uint64_t)old) carry = 1;
-            } else {
-                *d = acc;
-            }
-            if (carry) m = 1ull << (c % a.B);
-        }
-        flush_flags(m, a.flags);
+        out[q] = acc;
+        if (ovf) m |= 1ull << (pl * a.Bi + ri);
     }
 }
 
-__global__ __launch_bounds__(kBlock) void zero_rows_kernel(const int32_t *__restrict__ rows,
-                                                          int64_t nrows, const int32_t *slot,
-                                                          uint64_t *__restrict__ N, int64_t L) {
-    for (int64_t ri = blockIdx.y; ri < nrows; ri += gridDim.y) {
-        const int v = rows[ri];
-        const int64_t orow = slot ? (int64_t)slot[v] : (int64_t)v;
-        for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < L; c += (int64_t)gridDim.x * kBlock)
-            N[orow * L + c] = 0;
-    }
-}
-
-// ------------------------------------------------------------------ colour histogram (p = 1)
-
-// One wavefront per light row; lanes are (neighbour slot, colouring) pairs;
-// per-wavefront histograms of B*k uint32 counters live in LDS.
-__global__ __launch_bounds__(kBlock) void hist_light_kernel(
-    const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
-    const int32_t *__restrict__ rows, int64_t nrows, const uint8_t *__restrict__ col,
-    uint64_t *__restrict__ N, int B, int k) {
-    extern __shared__ uint32_t hist_lds[];
-    const int wave = threadIdx.x >> 6;
-    const int lane = threadIdx.x & (kWave - 1);
-    uint32_t *h = hist_lds + wave * B * k;
-    const int64_t ri = (int64_t)blockIdx.x * (kBlock / kWave) + wave;
-    const bool valid = ri < nrows;
-    for (int q = lane; q < B * k; q += kWave) h[q] = 0;
-    __syncthreads();
-    int v = 0;
-    if (valid) {
-        v = rows[ri];
-        const int slots = kWave / B;
-        const int s = lane / B, r = lane - (lane / B) * B;
-        if (s < slots) {
-            for (int64_t e = rp[v] + s; e < rp[v + 1]; e += slots) {
-                const int c = col[(int64_t)ci[e] * B + r];
-                atomicAdd(&h[r * k + c], 1u);
-            }
-        }
-    }
-    __syncthreads();
-    if (valid) {
-        uint64_t *d = N + (int64_t)v * k * B;
-        for (int q = lane; q < B * k; q += kWave) {
-            const int c = q / B, r = q - c * B;
-            d[q] = h[r * k + c];
-        }
-    }
-}
-
-// One workgroup per wide item; rows split over several items add with atomics.
-__global__ __launch_bounds__(kBlock) void hist_wide_kernel(
-    const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
-    const int2 *__restrict__ items, int64_t nitems, int seg, const int32_t *__restrict__ slot,
-    const uint8_t *__restrict__ col, uint64_t *__restrict__ N, int B, int k) {
-    extern __shared__ uint32_t hist_lds[];
-    for (int q = threadIdx.x; q < B * k; q += kBlock) hist_lds[q] = 0;
-    __syncthreads();
-    const int2 it = items[blockIdx.x];
-    const int v = it.x;
-    const int64_t r0 = rp[v], r1 = rp[v + 1];
-    const int64_t e0 = r0 + (int64_t)it.y * seg;
-    const int64_t e1 = min(e0 + seg, r1);
-    const bool split = (r1 - r0) > seg;
-    const int slots = kBlock / B;
-    const int s = threadIdx.x / B, r = threadIdx.x - s * B;
-    if (s < slots)
-        for (int64_t e = e0 + s; e < e1; e += slots) {
-            const int c = col[(int64_t)ci[e] * B + r];
-            atomicAdd(&hist_lds[r * k + c], 1u);
-        }
-    __syncthreads();
-    const int64_t orow = slot ? (int64_t)slot[v] : (int64_t)v;
-    uint64_t *d = N + orow * k * B;
-    for (int q = threadIdx.x; q < B * k; q += kBlock) {
-        const int c = q / B, rr = q - c * B;
-        const uint64_t x = hist_lds[rr * k + c];
-        if (split) {
-            if (x) atomicAdd((unsigned long long *)(d + q), (unsigned long long)x);
-        } else {
-            d[q] = x;
-        }
-    }
-}
-
-// ------------------------------------------------------------------ select (a = 1) and eMA (a >= 2)
-
-// grid: x over output columns of a row (Wh*B), y strides over rows.
-__global__ __launch_bounds__(kBlock) void select_kernel(
-    int64_t n, const uint8_t *__restrict__ col, const uint64_t *__restrict__ N,
-    uint64_t *__restrict__ S, int B, int k, int Wh, int Wp, const int16_t *__restrict__ drop) {
-    const int q = blockIdx.x * kBlock + threadIdx.x;
-    const int Ls = Wh * B, Lp = Wp * B;
-    if (q >= Ls) return;
-    const int I = q / B, r = q - I * B;
-    for (int64_t v = blockIdx.y; v < n; v += gridDim.y) {
-        const int c = col[v * B + r];
-        const int d = drop[I * k + c];
-        S[v * Ls + q] = d >= 0 ? N[v * Lp + d * B + r] : 0;
-    }
-}
-
-__global__ __launch_bounds__(kBlock) void ema_kernel(
-    int64_t n, const uint64_t *__restrict__ A, const uint64_t *__restrict__ N,
-    uint64_t *__restrict__ S, int B, int Wa, int Wp, int Wh, int nsplit,
-    const uint32_t *__restrict__ split, unsigned long long *__restrict__ flags) {
-    const int q = blockIdx.x * kBlock + threadIdx.x;
-    const int Ls = Wh * B, La = Wa * B, Lp = Wp * B;
-    const bool valid = q < Ls;
-    const int I = valid ? q / B : 0, r = valid ? q - I * B : 0;
+// One workgroup per (plane, row) item, the grid striding over the items
+// (rows are sorted by descending degree, so every workgroup gets a similar
+// mix).  LDS: the neighbour-sum row N' (Wn * Bi), the staged active row
+// (Wa * Bi, AM == kActiveLds) and the index tables.
+template <bool HIST, int AM>
+__global__ __launch_bounds__(kBlock) void dp_row_kernel(DpArgs a) {
+    extern __shared__ uint64_t lds[];
+    uint64_t *Nl = lds;
+    uint64_t *Al = lds + a.a_off;
+    uint16_t *tab = (uint16_t *)((char *)lds + a.tab_off);
+    if (!HIST) stage_tables(a, tab);
+    const int Ln = a.Wn * a.Bi, La = a.Wa * a.Bi;
+    const int64_t total = a.n * a.planes;
     uint64_t m = 0;
-    for (int64_t v = blockIdx.y; v < n; v += gridDim.y) {
-        if (valid) {
-            const uint64_t *ra = A + v * La + r;
-            const uint64_t *rn = N + v * Lp + r;
-            const uint32_t *sp = split + (int64_t)I * nsplit;
-            uint64_t acc = 0;
-            uint32_t ovf = 0;
-            for (int j = 0; j < nsplit; ++j) {
-                const uint32_t pr = sp[j];
-                acc = mad_ovf(acc, ra[(pr & 0xffff) * B], rn[(pr >> 16) * B], ovf);
-            }
-            S[v * Ls + q] = acc;
-            if (ovf) m |= 1ull << r;
-        }
-    }
-    flush_flags(m, flags);
-}
-
-// ------------------------------------------------------------------ row kernel
-
-enum RowMode { kRowStaged = 0, kRowGather = 1, kRowHist = 2 };
-
-struct RowArgs {
-    const int64_t *rp;
-    const int32_t *ci;
-    const int32_t *slot;          // split rows: index into Npre, else -1 (may be NULL)
-    const uint64_t *Npre;         // precomputed neighbour sums of split rows
-    const uint8_t *col;
-    const uint64_t *src;          // kRowStaged: N;  kRowGather: passive table P
-    const uint64_t *A;            // active table (a >= 2)
-    uint64_t *S;
-    int B, k, a, Wa, Wp, Wh, nsplit;
-    const uint32_t *split;
-    const int16_t *drop;
-    unsigned long long *flags;
-    int64_t n;                    // rows
-};
-
-// One workgroup per graph row v (the grid strides over the rows).  The
-// neighbour-sum row N[v] (Wp*B words) is built in LDS -- copied from N
-// (staged), summed from the neighbours' passive
-// rows (fused neighbour sum), or counted from the neighbours' colours (fused
-// histogram, p = 1); split rows copy their precomputed sum.  The active row is
-// staged next to it (a >= 2).  Every output entry (I, r) of S[v] is then
-// either a select through the drop-colour table (a = 1) or the split sum
-// sum_j A[v][Ia_j][r] * N[v][Ip_j][r] (a >= 2), read from LDS.
-template <int MODE, int U>
-__device__ __forceinline__ void row_body(const RowArgs &a, int64_t v, uint64_t *lds) {
-    const int B = a.B;
-    const int Lp = a.Wp * B, La = a.Wa * B, Ls = a.Wh * B;
-    uint64_t *Nr = lds;
-    uint64_t *Ar = lds + Lp;
-    const int t = threadIdx.x;
-    uint64_t m = 0;
-    if (MODE == kRowStaged) {
-        for (int q = t; q < Lp; q += kBlock) Nr[q] = a.src[v * Lp + q];
-    } else {
+    for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
+        const int pl = (int)(it / a.n);
+        const int64_t v = it - (int64_t)pl * a.n;
         const int sv = a.slot ? a.slot[v] : -1;
         if (sv >= 0) {
-            for (int q = t; q < Lp; q += kBlock) Nr[q] = a.Npre[(int64_t)sv * Lp + q];
-        } else if (MODE == kRowHist) {
-            uint32_t *h = (uint32_t *)(lds + Lp + (a.a > 1 ? La : 0));
-            for (int q = t; q < Lp; q += kBlock) h[q] = 0;
-            __syncthreads();
-            const int slots = kBlock / B;
-            const int s = t / B, r = t - s * B;
-            if (s < slots)
-                for (int64_t e = a.rp[v] + s; e < a.rp[v + 1]; e += slots)
-                    atomicAdd(&h[(int)a.col[(int64_t)a.ci[e] * B + r] * B + r], 1u);
-            __syncthreads();
-            for (int q = t; q < Lp; q += kBlock) Nr[q] = h[q];
+            const uint64_t *src = a.Npre + ((int64_t)pl * a.n_split + sv) * Ln;
+            for (int q = threadIdx.x; q < Ln; q += kBlock) Nl[q] = src[q];
         } else {
-            // fused neighbour sum: wavefront w owns columns [w*64U, (w+1)*64U)
-            bool inb[U];
-            uint64_t acc[U];
-            const int lane = t & (kWave - 1);
-            const int64_t cw = (int64_t)(t >> 6) * kWave * U + lane;   // wave-contiguous columns
-#pragma unroll
-            for (int u = 0; u < U; ++u) { inb[u] = cw + kWave * u < Lp; acc[u] = 0; }
-            uint32_t carry = 0;
-            gather_rows<U>(a.rp[v], a.rp[v + 1], 1, a.ci, a.src, Lp, cw, inb, acc, carry);
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                if (inb[u]) Nr[cw + kWave * u] = acc[u];
-                if (carry & (1u << u)) m |= 1ull << ((cw + kWave * u) % B);
-            }
+            for (int q = threadIdx.x; q < Ln; q += kBlock) Nl[q] = 0;
         }
-    }
-    if (a.a > 1)
-        for (int q = t; q < La; q += kBlock) Ar[q] = a.A[v * La + q];
-    __syncthreads();
-    uint64_t *out = a.S + v * Ls;
-    if (a.a == 1) {
-        const uint8_t *cv = a.col + v * B;
-        for (int q = t; q < Ls; q += kBlock) {
-            const int I = q / B, r = q - I * B;
-            const int d = a.drop[I * a.k + cv[r]];
-            out[q] = d >= 0 ? Nr[d * B + r] : 0;
+        if (AM == kActiveLds) {
+            const uint64_t *src = a.A + ((int64_t)pl * a.n + v) * La;
+            for (int q = threadIdx.x; q < La; q += kBlock) Al[q] = src[q];
         }
-    } else {
-        for (int q = t; q < Ls; q += kBlock) {
-            const int I = q / B, r = q - I * B;
-            const uint32_t *sp = a.split + (int64_t)I * a.nsplit;
-            uint64_t acc = 0;
-            uint32_t ovf = 0;
-            for (int j = 0; j < a.nsplit; ++j) {
-                const uint32_t pr = sp[j];
-                acc = mad_ovf(acc, Ar[(pr & 0xffff) * B + r], Nr[(pr >> 16) * B + r], ovf);
-            }
-            out[q] = acc;
-            if (ovf) m |= 1ull << r;
+        __syncthreads();
+        if (sv < 0) {
+            if (HIST) count_colours(a, v, pl, a.rp[v], a.rp[v + 1], Nl);
+            else scatter_rows(a, v, pl, a.rp[v], a.rp[v + 1], Nl, tab, m);
         }
+        __syncthreads();
+        emit_row<AM>(a, v, pl, Nl, Al, m);
+        __syncthreads();                         // LDS is reused by the next item
     }
     flush_flags(m, a.flags);
 }
 
-template <int MODE, int U>
-__global__ __launch_bounds__(kBlock) void row_kernel(RowArgs a) {
+// Split rows: one workgroup per (plane, row, segment of `seg` neighbours)
+// item; the segment's sum is built in LDS as in the row kernel and added into
+// Npre with global atomics (carry from the returned old value).
+template <bool HIST>
+__global__ __launch_bounds__(kBlock) void dp_split_kernel(DpArgs a) {
     extern __shared__ uint64_t lds[];
-    for (int64_t v = blockIdx.x; v < a.n; v += gridDim.x) {
-        row_body<MODE, U>(a, v, lds);
-        __syncthreads();                      // LDS is reused by the next row
+    uint64_t *Nl = lds;
+    uint16_t *tab = (uint16_t *)((char *)lds + a.tab_off);
+    if (!HIST) stage_tables(a, tab);
+    const int Ln = a.Wn * a.Bi;
+    const int64_t total = a.n_items * a.planes;
+    uint64_t m = 0;
+    for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
+        const int pl = (int)(it / a.n_items);
+        const int2 item = a.items[it - (int64_t)pl * a.n_items];
+        const int64_t v = item.x;
+        const int64_t r1 = a.rp[v + 1];
+        const int64_t e0 = a.rp[v] + (int64_t)item.y * a.seg;
+        const int64_t e1 = e0 + a.seg < r1 ? e0 + a.seg : r1;
+        for (int q = threadIdx.x; q < Ln; q += kBlock) Nl[q] = 0;
+        __syncthreads();
+        if (HIST) count_colours(a, v, pl, e0, e1, Nl);
+        else scatter_rows(a, v, pl, e0, e1, Nl, tab, m);
+        __syncthreads();
+        unsigned long long *dst =
+            (unsigned long long *)a.Npre + ((int64_t)pl * a.n_split + a.slot[v]) * Ln;
+        for (int q = threadIdx.x; q < Ln; q += kBlock) {
+            const uint64_t x = Nl[q];
+            if (x == 0) continue;
+            const unsigned long long old = atomicAdd(dst + q, (unsigned long long)x);
+            if ((uint64_t)old + x < x) m |= 1ull << (pl * a.Bi + (q & (a.Bi - 1)));
+        }
+        __syncthreads();
     }
+    flush_flags(m, a.flags);
 }
-
 
 // ------------------------------------------------------------------ root reduction
 
-// grid: (blocks, B); block y = colouring r sums entries (v, I) of that colouring.
+// grid: (blocks, B); block y = colouring r = pl*Bi + ri sums the n*W entries of
+// that colouring (stride Bi inside plane pl).
 __global__ __launch_bounds__(kBlock) void reduce_kernel(int64_t n, const uint64_t *__restrict__ S,
-                                                       int W, int B, unsigned long long *__restrict__ X,
+                                                       int W, int Bi,
+                                                       unsigned long long *__restrict__ X,
                                                        unsigned long long *__restrict__ flags) {
     __shared__ uint64_t part[kBlock];
     __shared__ uint32_t cpart[kBlock];
     const int r = blockIdx.y;
+    const int pl = r / Bi, ri = r - pl * Bi;
     const int64_t total = n * W;
+    const uint64_t *base = S + (int64_t)pl * total * Bi + ri;
     uint64_t acc = 0;
     uint32_t carry = 0;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < total; i += (int64_t)gridDim.x * kBlock) {
-        const uint64_t x = S[i * B + r];
+        const uint64_t x = base[i * Bi];
         const uint64_t s = acc + x;
         carry |= s < x;
         acc = s;
@@ -602,14 +346,76 @@ __global__ __launch_bounds__(kBlock) void zero_kernel(uint64_t *p, int64_t count
         p[i] = 0;
 }
 
-inline unsigned row_grid(int64_t n) { return (unsigned)std::min<int64_t>(n, 65535); }
+int log2_exact(int x) {
+    int s = 0;
+    while ((1 << s) < x) ++s;
+    return s;
+}
 
-inline int pick_u(int64_t L) {
-    // columns per lane for the neighbour-sum kernels: one chunk of 64*U per wavefront
-    return L <= 64 ? 1 : (L <= 128 ? 2 : 4);
+// Workgroups that stay resident on the chip for a given dynamic LDS size.
+int64_t resident_blocks(int lds_bytes) {
+    const int per_cu = std::max(1, std::min(kMaxBlocksPerCU, kLdsPerCU / std::max(lds_bytes, 1)));
+    return (int64_t)per_cu * kCUs;
+}
+
+template <typename K>
+hipError_t allow_lds(K kernel, int bytes) {
+    if (bytes <= 64 * 1024) return hipSuccess;
+    return hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               kLdsPerCU);
+}
+
+DpArgs make_args(const GraphBins &g, const StepShape &s, const StepTables &t, const uint8_t *col,
+                 const uint64_t *P, const uint64_t *A, const uint64_t *Npre, uint64_t *S,
+                 unsigned long long *flags) {
+    DpArgs a{};
+    a.rp = g.row_ptr; a.ci = g.col_idx; a.col = col; a.n = g.n;
+    a.B = s.B; a.Bi = s.Bi; a.sh = log2_exact(s.Bi); a.planes = s.B / s.Bi;
+    a.p = s.p; a.Wq = s.Wq; a.Wn = s.Wn; a.Wa = s.Wa; a.Wh = s.Wh; a.nsplit = s.nsplit;
+    a.split = t.split; a.unrank = t.unrank; a.rank = t.rank; a.n_rank = t.n_rank;
+    a.P = P; a.A = A; a.S = S; a.Npre = const_cast<uint64_t *>(Npre);
+    a.slot = g.n_split ? g.slot : nullptr; a.n_split = g.n_split;
+    a.items = g.split_items; a.n_items = g.n_split_items; a.seg = g.seg;
+    a.a_off = s.Wn * s.Bi;
+    a.tab_off = 8 * (s.Wn * s.Bi + (s.amode == kActiveLds ? s.Wa * s.Bi : 0));
+    a.flags = flags;
+    return a;
+}
+
+template <bool HIST, int AM>
+hipError_t row_launch(const DpArgs &a, int lds, hipStream_t st) {
+    hipError_t e = allow_lds(dp_row_kernel<HIST, AM>, lds);
+    if (e != hipSuccess) return e;
+    const int64_t blocks = std::min<int64_t>(a.n * a.planes, 2 * resident_blocks(lds));
+    dp_row_kernel<HIST, AM><<<dim3((unsigned)blocks), dim3(kBlock), lds, st>>>(a);
+    return hipGetLastError();
+}
+
+template <bool HIST>
+hipError_t split_launch(const DpArgs &a, int lds, hipStream_t st) {
+    hipError_t e = allow_lds(dp_split_kernel<HIST>, lds);
+    if (e != hipSuccess) return e;
+    const int64_t blocks = std::min<int64_t>(a.n_items * a.planes, 2 * resident_blocks(lds));
+    dp_split_kernel<HIST><<<dim3((unsigned)blocks), dim3(kBlock), lds, st>>>(a);
+    return hipGetLastError();
+}
+
+bool shape_ok(const StepShape &s) {
+    return s.Bi >= 1 && s.Bi <= kWave && (s.Bi & (s.Bi - 1)) == 0 && s.B % s.Bi == 0 &&
+           s.Wn >= 1 && s.Wh >= 1 && (s.p < 2 || s.Wq >= 1);
 }
 
 }  // namespace
+
+int rank_entries(int k1) { return 256 + 9 * (k1 > 8 ? (1 << (k1 - 8)) : 1); }
+
+int dp_lds_bytes(const StepShape &s, int amode, int n_rank) {
+    int64_t bytes = 8LL * s.Wn * s.Bi;
+    if (amode == kActiveLds) bytes += 8LL * s.Wa * s.Bi;
+    if (s.p >= 2) bytes += 2LL * (s.Wq + n_rank);
+    bytes = (bytes + 15) & ~15LL;
+    return bytes > (1 << 30) ? (1 << 30) : (int)bytes;
+}
 
 hipError_t launch_zero_u64(uint64_t *p, int64_t count, hipStream_t st) {
     if (count <= 0) return hipSuccess;
@@ -627,171 +433,47 @@ hipError_t launch_color(const uint64_t *desc, int64_t n, int B, int k, const int
     return hipGetLastError();
 }
 
-template <int U>
-static hipError_t spmm_tiled_u(const GraphBins &g, bool split_only, const uint64_t *P, uint64_t *N,
-                               int64_t L, int B, unsigned long long *flags, hipStream_t st) {
-    const int32_t *slot = split_only ? g.slot : nullptr;
-    SpmmArgs a;
-    a.rp = g.row_ptr; a.ci = g.col_idx;
-    a.light = g.light_rows; a.n_light = split_only ? 0 : g.n_light;
-    a.wide = g.wide_items; a.n_wide = split_only ? g.n_split_items : g.n_wide;
-    a.seg = g.seg; a.slot = slot; a.P = P; a.N = N; a.L = L; a.B = B;
-    a.groups = ((a.n_light + 3) >> 2) + a.n_wide;
-    a.chunks = (L + kWave * U - 1) / (kWave * U);
-    a.flags = flags;
-    if (a.groups == 0 || L <= 0) return hipGetLastError();
-    // one workgroup per item while the grid allows it (the dispatcher then
-    // balances uneven items); beyond that the workgroups stride
-    const int64_t blocks = std::min<int64_t>(a.chunks * a.groups, kMaxGridBlocks);
-    if (split_only) spmm_tiled_kernel<U, true><<<dim3((unsigned)blocks), dim3(kBlock), 0, st>>>(a);
-    else spmm_tiled_kernel<U, false><<<dim3((unsigned)blocks), dim3(kBlock), 0, st>>>(a);
-    return hipGetLastError();
+hipError_t launch_dp_split(const GraphBins &g, const StepShape &s, const StepTables &t,
+                           const uint8_t *col, const uint64_t *P, uint64_t *Npre,
+                           unsigned long long *flags, hipStream_t st) {
+    if (g.n_split == 0 || g.n_split_items == 0) return hipSuccess;
+    if (!shape_ok(s) || (s.p >= 2 && (!P || !t.unrank || !t.rank))) return hipErrorInvalidValue;
+    hipError_t e = launch_zero_u64(Npre, g.n_split * (int64_t)s.Wn * s.B, st);
+    if (e != hipSuccess) return e;
+    StepShape s1 = s;
+    s1.amode = kActiveGlobal;                          // the pre-pass stages no active row
+    const DpArgs a = make_args(g, s1, t, col, P, nullptr, Npre, nullptr, flags);
+    const int lds = dp_lds_bytes(s1, kActiveGlobal, t.n_rank);
+    return s.p == 1 ? split_launch<true>(a, lds, st) : split_launch<false>(a, lds, st);
 }
 
-template <int Z>
-static hipError_t spmm_narrow_z(const GraphBins &g, bool split_only, const uint64_t *P,
-                                uint64_t *N, int64_t L, int B, unsigned long long *flags,
-                                hipStream_t st) {
-    const int32_t *slot = split_only ? g.slot : nullptr;
-    NarrowArgs a;
-    a.rp = g.row_ptr; a.ci = g.col_idx;
-    a.tasks = g.tasks; a.n_tasks = split_only ? g.n_split_tasks : g.n_tasks;
-    a.seg = g.seg; a.slot = slot; a.P = P; a.N = N; a.L = L; a.B = B;
-    a.tiles = (L + Z - 1) / Z;
-    a.flags = flags;
-    if (a.n_tasks == 0 || L <= 0) return hipGetLastError();
-    const int64_t waves = a.tiles * a.n_tasks;
-    const int64_t blocks = std::min<int64_t>((waves + kBlock / kWave - 1) / (kBlock / kWave), kMaxGridBlocks);
-    spmm_narrow_kernel<Z><<<dim3((unsigned)blocks), dim3(kBlock), 0, st>>>(a);
-    return hipGetLastError();
-}
-
-static hipError_t spmm_any(int tile_cols, const GraphBins &g, bool split_only, const uint64_t *P,
-                           uint64_t *N, int64_t L, int B, unsigned long long *flags, hipStream_t st) {
-    switch (tile_cols) {
-    case 8: return spmm_narrow_z<8>(g, split_only, P, N, L, B, flags, st);
-    case 16: return spmm_narrow_z<16>(g, split_only, P, N, L, B, flags, st);
-    case 32: return spmm_narrow_z<32>(g, split_only, P, N, L, B, flags, st);
-    case 64: return spmm_tiled_u<1>(g, split_only, P, N, L, B, flags, st);
-    case 128: return spmm_tiled_u<2>(g, split_only, P, N, L, B, flags, st);
-    default: return spmm_tiled_u<4>(g, split_only, P, N, L, B, flags, st);
-    }
-}
-
-hipError_t launch_zero_split_rows(const GraphBins &g, bool compact, uint64_t *N, int64_t L,
-                                  hipStream_t st) {
-    if (g.n_split == 0 || L <= 0) return hipSuccess;
-    zero_rows_kernel<<<dim3((unsigned)std::min<int64_t>((L + kBlock - 1) / kBlock, 64),
-                            row_grid(g.n_split)), dim3(kBlock), 0, st>>>(
-        g.split_rows, g.n_split, compact ? g.slot : nullptr, N, L);
-    return hipGetLastError();
-}
-
-hipError_t launch_spmm(const GraphBins &g, const uint64_t *P, uint64_t *N, int64_t L, int B,
-                       int tile_cols, unsigned long long *flags, hipStream_t st) {
-    return spmm_any(tile_cols, g, false, P, N, L, B, flags, st);
-}
-
-hipError_t launch_spmm_split(const GraphBins &g, const uint64_t *P, uint64_t *Npre, int64_t L,
-                             int B, int tile_cols, unsigned long long *flags, hipStream_t st) {
-    if (g.n_split == 0) return hipSuccess;
-    return spmm_any(tile_cols, g, true, P, Npre, L, B, flags, st);
-}
-
-hipError_t launch_hist_split(const GraphBins &g, const uint8_t *col, uint64_t *Npre, int B, int k,
-                             hipStream_t st) {
-    if (g.n_split == 0) return hipSuccess;
-    const int64_t L = (int64_t)k * B;
-    if (g.n_split_items > kMaxGridBlocks) return hipErrorInvalidValue;
-    zero_rows_kernel<<<dim3(1, row_grid(g.n_split)), dim3(kBlock), 0, st>>>(
-        g.split_rows, g.n_split, g.slot, Npre, L);
-    hist_wide_kernel<<<dim3((unsigned)g.n_split_items), dim3(kBlock), (size_t)B * k * sizeof(uint32_t), st>>>(
-        g.row_ptr, g.col_idx, g.wide_items, g.n_split_items, g.seg, g.slot, col, Npre, B, k);
-    return hipGetLastError();
-}
-
-hipError_t launch_hist(const GraphBins &g, const uint8_t *col, uint64_t *N, int B, int k,
-                       hipStream_t st) {
-    const int64_t L = (int64_t)k * B;
-    if (g.n_split > 0) {
-        zero_rows_kernel<<<dim3(1, row_grid(g.n_split)), dim3(kBlock), 0, st>>>(
-            g.split_rows, g.n_split, nullptr, N, L);
-    }
-    if ((g.n_light + 3) / 4 > kMaxGridBlocks || g.n_wide > kMaxGridBlocks) return hipErrorInvalidValue;
-    if (g.n_light > 0) {
-        hist_light_kernel<<<dim3((unsigned)((g.n_light + 3) / 4)), dim3(kBlock),
-                            (size_t)4 * B * k * sizeof(uint32_t), st>>>(
-            g.row_ptr, g.col_idx, g.light_rows, g.n_light, col, N, B, k);
-    }
-    if (g.n_wide > 0) {
-        hist_wide_kernel<<<dim3((unsigned)g.n_wide), dim3(kBlock), (size_t)B * k * sizeof(uint32_t), st>>>(
-            g.row_ptr, g.col_idx, g.wide_items, g.n_wide, g.seg, nullptr, col, N, B, k);
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_select(int64_t n, const uint8_t *col, const uint64_t *N, uint64_t *S, int B,
-                         int k, int Wh, int Wp, const int16_t *drop, hipStream_t st) {
-    const int Ls = Wh * B;
-    if (n <= 0 || Ls <= 0) return hipSuccess;
-    select_kernel<<<dim3((unsigned)((Ls + kBlock - 1) / kBlock), row_grid(n)), dim3(kBlock), 0, st>>>(
-        n, col, N, S, B, k, Wh, Wp, drop);
-    return hipGetLastError();
-}
-
-hipError_t launch_ema(int64_t n, const uint64_t *A, const uint64_t *N, uint64_t *S, int B,
-                      int Wa, int Wp, int Wh, int nsplit, const uint32_t *split,
-                      unsigned long long *flags, hipStream_t st) {
-    const int Ls = Wh * B;
-    if (n <= 0 || Ls <= 0) return hipSuccess;
-    ema_kernel<<<dim3((unsigned)((Ls + kBlock - 1) / kBlock), row_grid(n)), dim3(kBlock), 0, st>>>(
-        n, A, N, S, B, Wa, Wp, Wh, nsplit, split, flags);
-    return hipGetLastError();
-}
-
-int row_lds_bytes(int k, int a, int Wa, int Wp, int B, int mode) {
-    int64_t words = (int64_t)Wp * B + (a > 1 ? (int64_t)Wa * B : 0);
-    int64_t bytes = words * 8 + (mode == kRowHist ? (int64_t)k * B * 4 : 0);
-    return (int)bytes;
-}
-
-int row_max_u() { return 8; }
-
-template <int MODE, int U>
-static void row_u(const RowArgs &a, int64_t n, size_t lds, hipStream_t st) {
-    const int64_t blocks = std::min<int64_t>(n, kMaxGridBlocks);
-    row_kernel<MODE, U><<<dim3((unsigned)blocks), dim3(kBlock), lds, st>>>(a);
-}
-
-hipError_t launch_row(int mode, const GraphBins &g, const uint8_t *col, const uint64_t *src,
-                      const uint64_t *Npre, const uint64_t *A, uint64_t *S, int B, int k, int a,
-                      int Wa, int Wp, int Wh, int nsplit, const uint32_t *split,
-                      const int16_t *drop, unsigned long long *flags, hipStream_t st) {
+hipError_t launch_dp_row(const GraphBins &g, const StepShape &s, const StepTables &t,
+                         const uint8_t *col, const uint64_t *P, const uint64_t *A,
+                         const uint64_t *Npre, uint64_t *S, unsigned long long *flags,
+                         hipStream_t st) {
     if (g.n <= 0) return hipSuccess;
-    RowArgs r;
-    r.rp = g.row_ptr; r.ci = g.col_idx;
-    r.slot = mode == kRowStaged ? nullptr : g.slot;
-    r.Npre = Npre; r.col = col; r.src = src; r.A = A; r.S = S;
-    r.B = B; r.k = k; r.a = a; r.Wa = Wa; r.Wp = Wp; r.Wh = Wh; r.nsplit = nsplit;
-    r.split = split; r.drop = drop; r.flags = flags; r.n = g.n;
-    const size_t lds = (size_t)row_lds_bytes(k, a, Wa, Wp, B, mode);
-    const int64_t Lp = (int64_t)Wp * B;
-    if (mode == kRowStaged) row_u<kRowStaged, 1>(r, g.n, lds, st);
-    else if (mode == kRowHist) row_u<kRowHist, 1>(r, g.n, lds, st);
-    else if (Lp <= 256) row_u<kRowGather, 1>(r, g.n, lds, st);
-    else if (Lp <= 512) row_u<kRowGather, 2>(r, g.n, lds, st);
-    else if (Lp <= 1024) row_u<kRowGather, 4>(r, g.n, lds, st);
-    else if (Lp <= 2048) row_u<kRowGather, 8>(r, g.n, lds, st);
-    else return hipErrorInvalidValue;
-    return hipGetLastError();
+    if (!shape_ok(s) || !S || (s.p >= 2 && (!P || !t.unrank || !t.rank)) ||
+        (s.amode != kActiveLeaf && (!A || !t.split)) || (g.n_split && !Npre))
+        return hipErrorInvalidValue;
+    const DpArgs a = make_args(g, s, t, col, P, A, Npre, S, flags);
+    const int lds = dp_lds_bytes(s, s.amode, t.n_rank);
+    if (s.p == 1) {
+        if (s.amode == kActiveLeaf) return row_launch<true, kActiveLeaf>(a, lds, st);
+        if (s.amode == kActiveLds) return row_launch<true, kActiveLds>(a, lds, st);
+        return row_launch<true, kActiveGlobal>(a, lds, st);
+    }
+    if (s.amode == kActiveLeaf) return row_launch<false, kActiveLeaf>(a, lds, st);
+    if (s.amode == kActiveLds) return row_launch<false, kActiveLds>(a, lds, st);
+    return row_launch<false, kActiveGlobal>(a, lds, st);
 }
 
-hipError_t launch_reduce(int64_t n, const uint64_t *S, int W, int B, unsigned long long *X,
-                         unsigned long long *flags, hipStream_t st) {
+hipError_t launch_reduce(int64_t n, const uint64_t *S, int W, int B, int Bi,
+                         unsigned long long *X, unsigned long long *flags, hipStream_t st) {
     if (n <= 0 || B <= 0) return hipSuccess;
+    if (Bi < 1 || B % Bi) return hipErrorInvalidValue;
     const int64_t total = n * W;
     const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((total + kBlock - 1) / kBlock, 1024));
-    reduce_kernel<<<dim3(blocks, (unsigned)B), dim3(kBlock), 0, st>>>(n, S, W, B, X, flags);
+    reduce_kernel<<<dim3(blocks, (unsigned)B), dim3(kBlock), 0, st>>>(n, S, W, Bi, X, flags);
     return hipGetLastError();
 }
 

@@ -1,8 +1,9 @@
 // Host-side planning for the colour-coding DP: template checks, rooting and
 // child order (Section 2.1, phase 2), the per-step sizes (h, a, p), Lemma 1
 // operation counts, a static memory plan for the count tables, the Eq. 1
-// colour-set index and the split / drop-colour index tables the kernels read.
+// colour-set index and the split / rank index tables the kernels read.
 #include "sc_internal.h"
+#include "kernels.h"
 
 #include <algorithm>
 #include <cstring>
@@ -81,22 +82,13 @@ void root_tree(int t, const int32_t *edges, int root, int order,
     }
 }
 
-int row_lds_need(int k, int a, int p, int batch, int mode) {
-    uint64_t words = (binom(k, p) + (a > 1 ? binom(k, a) : 0)) * (uint64_t)batch;
-    uint64_t bytes = words * 8 + (mode == kStepFusedHist ? (uint64_t)k * batch * 4 : 0);
-    return bytes > (1u << 30) ? (1 << 30) : (int)bytes;
-}
-
-int step_mode(int k, int h, int a, int p, int batch, const ExecOpts &o) {
-    (void)h;
-    const uint64_t lp = binom(k, p) * (uint64_t)batch;
-    if (o.fuse && p == 1 && row_lds_need(k, a, p, batch, kStepFusedHist) <= o.lds_max)
-        return kStepFusedHist;
-    if (o.fuse && p >= 2 && lp <= (uint64_t)std::min(o.fuse_max_cols, 2048) &&
-        row_lds_need(k, a, p, batch, kStepFusedGather) <= o.lds_max)
-        return kStepFusedGather;
-    if (row_lds_need(k, a, p, batch, kStepStaged) <= o.lds_max) return kStepStaged;
-    return kStepGlobal;
+int step_lds_bytes(int k, int a, int p, int bi, int amode) {
+    kern::StepShape sh;
+    sh.k = k; sh.a = a; sh.p = p; sh.B = bi; sh.Bi = bi;
+    sh.Wq = p >= 2 ? (int)binom(k - 1, p - 1) : 0;
+    sh.Wn = (int)binom(k - 1, p);
+    sh.Wa = (int)binom(k - 1, a - 1);
+    return kern::dp_lds_bytes(sh, amode, kern::rank_entries(k - 1));
 }
 
 namespace {
@@ -141,8 +133,23 @@ struct Arena {
 };
 
 uint64_t table_bytes(int64_t n, int k, int size, int batch) {
-    uint64_t b = (uint64_t)n * binom(k, size) * (uint64_t)batch * 8;
+    uint64_t b = (uint64_t)n * binom(k - 1, size - 1) * (uint64_t)batch * 8;
     return (b + 255) & ~(uint64_t)255;
+}
+
+// Largest power of two dividing `batch`, at most `cap` (0: 64), with which
+// every step's row kernel fits `lds_max` bytes of LDS (without a staged
+// active row); 1 if none does.
+int pick_interleave(const Plan &P, int cap, int lds_max) {
+    int bi = 1;
+    while (bi < 64 && P.batch % (2 * bi) == 0 && (cap == 0 || 2 * bi <= cap)) bi *= 2;
+    for (; bi > 1; bi /= 2) {
+        bool fits = true;
+        for (const Step &s : P.steps)
+            if (step_lds_bytes(P.k, s.a, s.p, bi, s.a > 1 ? kActGlobal : kActLeaf) > lds_max) fits = false;
+        if (fits) break;
+    }
+    return bi;
 }
 
 }  // namespace
@@ -190,12 +197,11 @@ bool build_plan(int t, int root, const std::vector<int> &child_ptr,
             s.node = u; s.child = w;
             s.a = size; s.p = P.subtree[w]; s.h = s.a + s.p;
             s.buf_a = cur; s.buf_p = pb;
-            s.mode = step_mode(k, s.h, s.a, s.p, batch, o);
-            const bool fuse = s.mode == kStepFusedHist || s.mode == kStepFusedGather;
-            s.buf_n = fuse ? -1 : new_buf(s.p);
+            s.mode = s.p == 1 ? kStepHist : kStepGather;
+            s.amode = kActLeaf;
+            s.lds_bytes = 0;
             s.buf_s = new_buf(s.h);
             s.last = false;
-            drop(s.buf_n);
             drop(s.buf_a);
             drop(s.buf_p);
             P.steps.push_back(s);
@@ -209,20 +215,39 @@ bool build_plan(int t, int root, const std::vector<int> &child_ptr,
     (void)top;
     P.arena_bytes = arena.end;
 
-    // Lemma 1 counts, the benchmark's update counts and a byte model, per colouring
+    // Interleave and per-step LDS use.  A row kernel needs at least the
+    // neighbour-sum row of one colouring and the index tables; when even that
+    // exceeds lds_max (k = 16) the kernel takes what it needs, up to 160 KB.
+    P.interleave = pick_interleave(P, o.interleave, o.lds_max);
+    for (Step &s : P.steps) {
+        const int base = step_lds_bytes(k, s.a, s.p, P.interleave, s.a > 1 ? kActGlobal : kActLeaf);
+        if (base > 160 * 1024) { err = "a step's neighbour-sum row does not fit in LDS"; return false; }
+        s.amode = kActLeaf;
+        if (s.a > 1) {
+            const int staged = step_lds_bytes(k, s.a, s.p, P.interleave, kActLds);
+            s.amode = staged <= std::max(o.lds_max, base) ? kActLds : kActGlobal;
+        }
+        s.lds_bytes = step_lds_bytes(k, s.a, s.p, P.interleave, s.amode);
+    }
+
+    // Per colouring: Lemma 1 counts of the paper's layout (the benchmark's
+    // update counts), the updates executed in the rooted-colour layout, and a
+    // byte model of that layout.
     for (const Step &s : P.steps) {
-        double Wa = (double)binom(k, s.a), Wp = (double)binom(k, s.p), Wh = (double)binom(k, s.h);
+        const double Wp = (double)binom(k, s.p), Wh = (double)binom(k, s.h);
         P.lemma1_ops += (double)nnz * Wp + (double)n * Wh * (double)binom(s.h, s.p);
         P.spmm_updates += (double)nnz * Wp;
         P.ema_updates += s.a > 1 ? (double)n * Wh * (double)binom(s.h, s.a) : (double)n * Wh;
-        const bool fuse = s.mode == kStepFusedHist || s.mode == kStepFusedGather;
-        double bytes = 8.0 * n * ((s.a > 1 ? Wa : 0) + (s.p > 1 ? Wp : 0) + Wh);
-        if (s.p > 1 && !fuse) bytes += 16.0 * n * Wp;             // write + read N
-        if (s.p == 1 || s.a == 1) bytes += (double)n;              // colours
+        const double Rq = (double)binom(k - 1, s.p - 1), Rn = (double)binom(k - 1, s.p);
+        const double Ra = (double)binom(k - 1, s.a - 1), Rh = (double)binom(k - 1, s.h - 1);
+        const double madds = s.a > 1 ? (double)n * Rh * (double)binom(s.h - 1, s.a - 1) : (double)n * Rn;
+        P.exec_updates += (s.p > 1 ? (double)nnz * Rq : (double)nnz) + madds;
+        double bytes = 8.0 * n * ((s.a > 1 ? Ra : 0) + (s.p > 1 ? Rq : 0) + Rh);
+        bytes += (double)n;                                        // colours
         bytes += 4.0 * nnz + 8.0 * (n + 1);                        // adjacency
         P.compulsory_bytes += bytes;
-        double gather = s.p >= 2 ? 8.0 * nnz * Wp * 0.5 : (double)nnz;
-        P.cost += bytes + gather + 3.2 * (double)n * Wh * (double)binom(s.h, s.a);
+        const double gather = s.p >= 2 ? 8.0 * nnz * Rq * 0.5 : (double)nnz;
+        P.cost += bytes + gather + 3.2 * madds;
     }
     return true;
 }
@@ -325,14 +350,25 @@ std::vector<uint32_t> split_table(int k, int h, int a) {
     return out;
 }
 
-std::vector<int16_t> drop_table(int k, int h) {
-    std::vector<int16_t> out(binom(k, h) * (uint64_t)k, (int16_t)-1);
-    for (uint32_t ms = 0; ms < (1u << k); ++ms) {
-        if (__builtin_popcount(ms) != h) continue;
-        int64_t is = colorset_rank(ms);
-        for (int c = 0; c < k; ++c)
-            if (ms & (1u << c)) out[is * k + c] = (int16_t)colorset_rank(ms & ~(1u << c));
-    }
+std::vector<uint16_t> unrank_table(int k1, int sz) {
+    std::vector<uint16_t> out(binom(k1, sz));
+    for (uint32_t m = 0; m < (1u << k1); ++m)
+        if (__builtin_popcount(m) == sz) out[colorset_rank(m)] = (uint16_t)m;
+    return out;
+}
+
+std::vector<uint16_t> rank_table(int k1) {
+    std::vector<uint16_t> out(kern::rank_entries(k1), 0);
+    for (uint32_t lo = 0; lo < 256; ++lo) out[lo] = (uint16_t)colorset_rank(lo & ((1u << std::min(k1, 8)) - 1));
+    // high part: colour 8 + c at order m + (its order among the high colours)
+    for (uint32_t hi = 0; k1 > 8 && hi < (1u << (k1 - 8)); ++hi)
+        for (int m = 0; m <= 8; ++m) {
+            uint64_t idx = 0;
+            int order = m;
+            for (int c = 0; c < k1 - 8; ++c)
+                if (hi & (1u << c)) idx += binom(8 + c, ++order);
+            out[256 + hi * 9 + m] = (uint16_t)idx;
+        }
     return out;
 }
 
@@ -349,6 +385,8 @@ void fill_plan_info(const Plan &p, double aut, sc_plan_info_t *o) {
     o->spmm_updates = p.spmm_updates;
     o->ema_updates = p.ema_updates;
     o->lemma1_ops = p.lemma1_ops;
+    o->exec_updates = p.exec_updates;
+    o->interleave = p.interleave;
     for (size_t i = 0; i < p.steps.size(); ++i) o->step_mode[i] = p.steps[i].mode;
     o->compulsory_bytes = p.compulsory_bytes;
     o->automorphisms = aut;

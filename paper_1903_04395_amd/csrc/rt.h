@@ -31,10 +31,10 @@ struct Graph {
                                  // isolated vertices, whose rows are identically 0)
     int64_t max_deg = 0;
     std::vector<int64_t> deg_host;
-    // degree bins for the current segment size
+    // rows with more than `seg` neighbours, for the current segment size
     int seg = 0;
-    DevMem light, wide, split_rows, slot, tasks;
-    int64_t n_light = 0, n_wide = 0, n_split = 0, n_split_items = 0, n_tasks = 0, n_split_tasks = 0;
+    DevMem split_rows, split_items, slot;
+    int64_t n_split = 0, n_split_items = 0;
     double split_nnz = 0;
     int busy = 0;                // passes of the serving loop in flight on this graph
 };
@@ -55,8 +55,8 @@ struct TableKey {
 
 // Tuned execution knobs for one (graph, template, k, batch).
 struct Tuned {
-    int tile_cols = 0;
-    int fuse_max_cols = 0;
+    int interleave = 0;
+    int lds_max = 0;
     double ms = 0;
 };
 using TuneKey = std::tuple<int, int, int, int>;   // graph id, template id, k, batch
@@ -67,7 +67,6 @@ struct PassSpec {
     const Plan *P = nullptr;
     int k = 0;
     uint64_t seed = 0, first = 0;
-    int tile_cols = 128;
 };
 
 // Device buffers one in-flight pass uses besides the resident graph and the
@@ -79,11 +78,11 @@ struct PassBuffers {
 };
 
 struct GraphExecKey {
-    int graph_id, tmpl_id, k, batch, tile, fuse_max, seg;
+    int graph_id, tmpl_id, k, batch, interleave, lds_max, seg;
     uint64_t bufgen;
     bool operator<(const GraphExecKey &o) const {
-        return std::tie(graph_id, tmpl_id, k, batch, tile, fuse_max, seg, bufgen) <
-               std::tie(o.graph_id, o.tmpl_id, o.k, o.batch, o.tile, o.fuse_max, o.seg, o.bufgen);
+        return std::tie(graph_id, tmpl_id, k, batch, interleave, lds_max, seg, bufgen) <
+               std::tie(o.graph_id, o.tmpl_id, o.k, o.batch, o.interleave, o.lds_max, o.seg, o.bufgen);
     }
 };
 
@@ -104,15 +103,15 @@ struct sc_ctx {
     std::map<int, std::unique_ptr<sc::Graph>> graphs;
     std::map<int, std::unique_ptr<sc::Template>> tmpls;
     int next_graph = 1, next_tmpl = 1;
-    std::map<sc::TableKey, sc::DevMem> split_tabs, drop_tabs;
+    std::map<sc::TableKey, sc::DevMem> split_tabs, unrank_tabs, rank_tabs;
     sc::PassBuffers main;                 // buffers of the synchronous calls
     uint64_t *host_out = nullptr;         // pinned staging for results and descriptors
     size_t host_out_words = 0;
     std::map<sc::GraphExecKey, hipGraphExec_t> graph_cache;
     std::map<sc::TuneKey, sc::Tuned> tuned;
     // options
-    int64_t max_batch = SC_MAX_BATCH, fused = 1, use_graph = 0, tile_cols = 0, segment = 0;
-    int64_t fuse_max_cols = 512, reorder = 1;
+    int64_t max_batch = SC_MAX_BATCH, use_graph = 0, segment = 0;
+    int64_t interleave = 0, lds_max = 0, reorder = 1;
     // tracing
     bool prof = false;
     struct Rec { const char *name; hipEvent_t a, b; double bytes, updates; };
@@ -143,20 +142,20 @@ int upload(sc_ctx *c, DevMem &m, const void *host, size_t bytes);
 int host_staging(sc_ctx *c, size_t words);
 
 int default_segment(const sc_ctx *c);
-int default_tile(const sc_ctx *c);
 int rebin(sc_ctx *c, Graph &g, int seg);
 kern::GraphBins bins_of(const Graph &g);
+// Device copies of the host index tables, cached per context.
 int get_split(sc_ctx *c, int k, int h, int a, const uint32_t **out);
-int get_drop(sc_ctx *c, int k, int h, const int16_t **out);
+int get_unrank(sc_ctx *c, int k1, int s, const uint16_t **out);
+int get_rank(sc_ctx *c, int k1, const uint16_t **out);
 
 // Execution options for (graph, template, k, batch): context defaults,
 // overridden by tuned values.
-ExecOpts exec_opts(const sc_ctx *c, int gid, int tid, int k, int batch, int *tile_cols);
+ExecOpts exec_opts(const sc_ctx *c, int gid, int tid, int k, int batch);
 int make_plan(sc_ctx *c, const Graph &g, const Template &T, const ExecOpts &o, int k, int batch,
               Plan &P);
 // Largest batch <= want whose pass fits `budget` bytes (0: the context budget).
-int pick_batch(sc_ctx *c, int gid, int tid, int k, int want, uint64_t budget, Plan &P,
-               int *tile_cols);
+int pick_batch(sc_ctx *c, int gid, int tid, int k, int want, uint64_t budget, Plan &P);
 uint64_t pass_bytes(const Graph &g, const Plan &P);
 double colorful_probability(int k, int t);
 

@@ -80,51 +80,31 @@ int host_staging(sc_ctx *c, size_t words) {
 }
 
 int default_segment(const sc_ctx *c) { return c->segment > 0 ? (int)c->segment : 256; }
-int default_tile(const sc_ctx *c) { return c->tile_cols > 0 ? (int)c->tile_cols : 128; }
 
-// Degree bins (see kernels.h): light rows, wide items (split rows first),
-// neighbour-sum tasks (split rows first), and the compact slot of every split
-// row for precomputed neighbour sums.
+// Rows with more than `seg` neighbours ("split rows"): their (row, segment)
+// items and the compact slot of every split row for precomputed neighbour sums.
 int rebin(sc_ctx *c, Graph &g, int seg) {
     if (g.seg == seg && g.slot.p) return SC_OK;
     if (g.busy) return fail(c, SC_ESTATE, "segment size cannot change while the serving loop uses the graph");
     HIPCHK(c, hipDeviceSynchronize());
-    dev_free(c, g.light); dev_free(c, g.wide); dev_free(c, g.split_rows); dev_free(c, g.slot);
-    dev_free(c, g.tasks);
-    std::vector<int32_t> light, split_rows, slot(std::max<int64_t>(g.n_rows, 1), -1);
-    std::vector<int2> split_items, wide_items, split_tasks, tasks;
+    dev_free(c, g.split_rows); dev_free(c, g.split_items); dev_free(c, g.slot);
+    std::vector<int32_t> split_rows, slot(std::max<int64_t>(g.n_rows, 1), -1);
+    std::vector<int2> items;
     g.split_nnz = 0;
     for (int64_t v = 0; v < g.n_rows; ++v) {
         const int64_t d = g.deg_host[v];
-        if (d <= kern::kLightMax) light.push_back((int32_t)v);
-        else if (d <= seg) wide_items.push_back(make_int2((int)v, 0));
-        if (d <= seg) {
-            tasks.push_back(make_int2((int)v, 0));
-        } else {
-            slot[v] = (int32_t)split_rows.size();
-            split_rows.push_back((int32_t)v);
-            g.split_nnz += (double)d;
-            for (int64_t s = 0; s * seg < d; ++s) {
-                split_items.push_back(make_int2((int)v, (int)s));
-                split_tasks.push_back(make_int2((int)v, (int)s));
-            }
-        }
+        if (d <= seg) continue;
+        slot[v] = (int32_t)split_rows.size();
+        split_rows.push_back((int32_t)v);
+        g.split_nnz += (double)d;
+        for (int64_t s = 0; s * seg < d; ++s) items.push_back(make_int2((int)v, (int)s));
     }
-    g.n_light = (int64_t)light.size();
     g.n_split = (int64_t)split_rows.size();
-    g.n_split_items = (int64_t)split_items.size();
-    std::vector<int2> items = split_items;
-    items.insert(items.end(), wide_items.begin(), wide_items.end());
-    g.n_wide = (int64_t)items.size();
-    g.n_split_tasks = (int64_t)split_tasks.size();
-    split_tasks.insert(split_tasks.end(), tasks.begin(), tasks.end());
-    g.n_tasks = (int64_t)split_tasks.size();
+    g.n_split_items = (int64_t)items.size();
     int rc;
-    if ((rc = upload(c, g.light, light.data(), light.size() * sizeof(int32_t)))) return rc;
-    if ((rc = upload(c, g.wide, items.data(), items.size() * sizeof(int2)))) return rc;
     if ((rc = upload(c, g.split_rows, split_rows.data(), split_rows.size() * sizeof(int32_t)))) return rc;
+    if ((rc = upload(c, g.split_items, items.data(), items.size() * sizeof(int2)))) return rc;
     if ((rc = upload(c, g.slot, slot.data(), slot.size() * sizeof(int32_t)))) return rc;
-    if ((rc = upload(c, g.tasks, split_tasks.data(), split_tasks.size() * sizeof(int2)))) return rc;
     g.seg = seg;
     for (auto &kv : c->graph_cache) (void)hipGraphExecDestroy(kv.second);
     c->graph_cache.clear();
@@ -136,12 +116,9 @@ kern::GraphBins bins_of(const Graph &g) {
     b.n = g.n_rows; b.nnz = g.nnz;
     b.row_ptr = (const int64_t *)g.rp.p;
     b.col_idx = (const int32_t *)g.ci.p;
-    b.light_rows = (const int32_t *)g.light.p; b.n_light = g.n_light;
-    b.wide_items = (const int2 *)g.wide.p; b.n_wide = g.n_wide;
     b.split_rows = (const int32_t *)g.split_rows.p; b.n_split = g.n_split;
-    b.n_split_items = g.n_split_items;
+    b.split_items = (const int2 *)g.split_items.p; b.n_split_items = g.n_split_items;
     b.slot = (const int32_t *)g.slot.p;
-    b.tasks = (const int2 *)g.tasks.p; b.n_tasks = g.n_tasks; b.n_split_tasks = g.n_split_tasks;
     b.seg = g.seg;
     return b;
 }
@@ -160,31 +137,43 @@ int get_split(sc_ctx *c, int k, int h, int a, const uint32_t **out) {
     return SC_OK;
 }
 
-int get_drop(sc_ctx *c, int k, int h, const int16_t **out) {
-    TableKey key{k, h, 1};
-    auto it = c->drop_tabs.find(key);
-    if (it == c->drop_tabs.end()) {
-        std::vector<int16_t> tab = drop_table(k, h);
+int get_unrank(sc_ctx *c, int k1, int sz, const uint16_t **out) {
+    TableKey key{k1, sz, 0};
+    auto it = c->unrank_tabs.find(key);
+    if (it == c->unrank_tabs.end()) {
+        std::vector<uint16_t> tab = unrank_table(k1, sz);
         DevMem m;
-        int rc = upload(c, m, tab.data(), tab.size() * sizeof(int16_t));
+        int rc = upload(c, m, tab.data(), tab.size() * sizeof(uint16_t));
         if (rc) return rc;
-        it = c->drop_tabs.emplace(key, m).first;
+        it = c->unrank_tabs.emplace(key, m).first;
     }
-    *out = (const int16_t *)it->second.p;
+    *out = (const uint16_t *)it->second.p;
     return SC_OK;
 }
 
-ExecOpts exec_opts(const sc_ctx *c, int gid, int tid, int k, int batch, int *tile_cols) {
+int get_rank(sc_ctx *c, int k1, const uint16_t **out) {
+    TableKey key{k1, 0, 0};
+    auto it = c->rank_tabs.find(key);
+    if (it == c->rank_tabs.end()) {
+        std::vector<uint16_t> tab = rank_table(k1);
+        DevMem m;
+        int rc = upload(c, m, tab.data(), tab.size() * sizeof(uint16_t));
+        if (rc) return rc;
+        it = c->rank_tabs.emplace(key, m).first;
+    }
+    *out = (const uint16_t *)it->second.p;
+    return SC_OK;
+}
+
+ExecOpts exec_opts(const sc_ctx *c, int gid, int tid, int k, int batch) {
     ExecOpts o;
-    o.fuse = c->fused != 0;
-    o.fuse_max_cols = (int)c->fuse_max_cols;
-    int tile = default_tile(c);
+    o.interleave = (int)c->interleave;
+    if (c->lds_max > 0) o.lds_max = (int)c->lds_max;
     auto it = c->tuned.find(TuneKey{gid, tid, k, batch});
     if (it != c->tuned.end()) {
-        if (it->second.fuse_max_cols > 0) o.fuse_max_cols = it->second.fuse_max_cols;
-        if (it->second.tile_cols > 0) tile = it->second.tile_cols;
+        if (it->second.interleave > 0) o.interleave = it->second.interleave;
+        if (it->second.lds_max > 0) o.lds_max = it->second.lds_max;
     }
-    if (tile_cols) *tile_cols = tile;
     return o;
 }
 
@@ -204,13 +193,11 @@ int make_plan(sc_ctx *c, const Graph &g, const Template &T, const ExecOpts &o, i
 uint64_t pass_bytes(const Graph &g, const Plan &P) {
     uint64_t npre = 0;
     for (const Step &s : P.steps)
-        if (s.mode == kStepFusedHist || s.mode == kStepFusedGather)
-            npre = std::max<uint64_t>(npre, (uint64_t)g.n_split * binom(P.k, s.p) * P.batch * 8);
+        npre = std::max<uint64_t>(npre, (uint64_t)g.n_split * binom(P.k - 1, s.p) * P.batch * 8);
     return P.arena_bytes + npre + (uint64_t)g.n_rows * P.batch;
 }
 
-int pick_batch(sc_ctx *c, int gid, int tid, int k, int want, uint64_t budget, Plan &P,
-               int *tile_cols) {
+int pick_batch(sc_ctx *c, int gid, int tid, int k, int want, uint64_t budget, Plan &P) {
     auto gi = c->graphs.find(gid);
     if (gi == c->graphs.end()) return fail(c, SC_ENOTFOUND, "unknown graph %d", gid);
     auto ti = c->tmpls.find(tid);
@@ -220,11 +207,15 @@ int pick_batch(sc_ctx *c, int gid, int tid, int k, int want, uint64_t budget, Pl
     if (k < T.t || k > SC_MAX_K) return fail(c, SC_EINVAL, "need t <= k <= 16 (t=%d, k=%d)", T.t, k);
     if (!budget) budget = c->budget;
     want = std::max(1, std::min<int>(want, (int)std::min<int64_t>(c->max_batch, SC_MAX_BATCH)));
-    for (int b = want; b >= 1; b = b > 8 ? b / 2 : b - 1) {
-        const ExecOpts o = exec_opts(c, gid, tid, k, b, tile_cols);
+    // `want`, then the multiples of 8 below it, then 4, 2, 1: batches with a
+    // large power-of-two factor keep several colourings interleaved per plane
+    for (int b = want; b >= 1;) {
+        const ExecOpts o = exec_opts(c, gid, tid, k, b);
         int rc = make_plan(c, g, T, o, k, b, P);
         if (rc) return rc;
         if (pass_bytes(g, P) <= budget) return SC_OK;
+        if (b > 8) b = b % 8 ? b - b % 8 : b - 8;
+        else b = b > 4 ? 4 : b / 2;
     }
     return fail(c, SC_ENOMEM, "one colouring needs %.3f GB of device tables, the budget is %.3f GB",
                 pass_bytes(g, P) / 1e9, budget / 1e9);
@@ -249,8 +240,8 @@ double aut_of(int t, const std::vector<int32_t> &edges) {
 }
 
 void free_graph(sc_ctx *c, Graph &g) {
-    dev_free(c, g.rp); dev_free(c, g.ci); dev_free(c, g.light); dev_free(c, g.wide);
-    dev_free(c, g.split_rows); dev_free(c, g.slot); dev_free(c, g.perm); dev_free(c, g.tasks);
+    dev_free(c, g.rp); dev_free(c, g.ci); dev_free(c, g.split_rows); dev_free(c, g.split_items);
+    dev_free(c, g.slot); dev_free(c, g.perm);
 }
 
 bool serving(const sc_ctx *c) { return c->serve != nullptr; }
@@ -259,7 +250,7 @@ bool serving(const sc_ctx *c) { return c->serve != nullptr; }
 
 extern "C" {
 
-const char *sc_version(void) { return "libsc 0.2 (gfx950)"; }
+const char *sc_version(void) { return "libsc 0.3 (gfx950)"; }
 
 const char *sc_last_error(const sc_ctx *ctx) { return ctx ? ctx->err.c_str() : "no context"; }
 
@@ -293,7 +284,8 @@ int sc_destroy(sc_ctx *c) {
     for (auto &kv : c->graph_cache) (void)hipGraphExecDestroy(kv.second);
     for (auto &kv : c->graphs) free_graph(c, *kv.second);
     for (auto &kv : c->split_tabs) dev_free(c, kv.second);
-    for (auto &kv : c->drop_tabs) dev_free(c, kv.second);
+    for (auto &kv : c->unrank_tabs) dev_free(c, kv.second);
+    for (auto &kv : c->rank_tabs) dev_free(c, kv.second);
     PassBuffers &b = c->main;
     dev_free(c, b.arena); dev_free(c, b.colbuf); dev_free(c, b.xbuf); dev_free(c, b.npre); dev_free(c, b.desc);
     if (c->host_out) (void)hipHostFree(c->host_out);
@@ -449,19 +441,17 @@ int sc_set_option(sc_ctx *c, int32_t opt, int64_t v) {
     case SC_OPT_MAX_BATCH:
         if (v < 1 || v > SC_MAX_BATCH) return fail(c, SC_EINVAL, "max batch must be in [1, %d]", SC_MAX_BATCH);
         c->max_batch = v; return SC_OK;
-    case SC_OPT_FUSED: c->fused = v != 0; return SC_OK;
     case SC_OPT_GRAPH: c->use_graph = v != 0; return SC_OK;
-    case SC_OPT_TILE_COLS:
-        if (v != 0 && v != 8 && v != 16 && v != 32 && v != 64 && v != 128 && v != 256)
-            return fail(c, SC_EINVAL, "tile columns must be 0, 8, 16, 32, 64, 128 or 256");
-        c->tile_cols = v; return SC_OK;
     case SC_OPT_SEGMENT:
         if (v < 0 || v > (1 << 24)) return fail(c, SC_EINVAL, "segment must be in [0, 2^24]");
-        if (v > 0 && v <= kern::kLightMax) return fail(c, SC_EINVAL, "segment must exceed %d", kern::kLightMax);
+        if (v > 0 && v <= 64) return fail(c, SC_EINVAL, "segment must exceed 64");
         c->segment = v; return SC_OK;
-    case SC_OPT_FUSE_MAX_COLS:
-        if (v < 64 || v > 2048) return fail(c, SC_EINVAL, "fuse max columns must be in [64, 2048]");
-        c->fuse_max_cols = v; return SC_OK;
+    case SC_OPT_INTERLEAVE:
+        if (v < 0 || v > 64 || (v & (v - 1))) return fail(c, SC_EINVAL, "interleave must be 0 or a power of two up to 64");
+        c->interleave = v; return SC_OK;
+    case SC_OPT_LDS_MAX:
+        if (v != 0 && (v < 16384 || v > 163840)) return fail(c, SC_EINVAL, "LDS limit must be 0 or in [16384, 163840]");
+        c->lds_max = v; return SC_OK;
     case SC_OPT_REORDER: c->reorder = v != 0; return SC_OK;
     default: return fail(c, SC_EINVAL, "unknown option %d", opt);
     }
@@ -472,11 +462,10 @@ int sc_get_option(sc_ctx *c, int32_t opt, int64_t *v) {
     std::lock_guard<std::recursive_mutex> lk(c->mu);
     switch (opt) {
     case SC_OPT_MAX_BATCH: *v = c->max_batch; return SC_OK;
-    case SC_OPT_FUSED: *v = c->fused; return SC_OK;
     case SC_OPT_GRAPH: *v = c->use_graph; return SC_OK;
-    case SC_OPT_TILE_COLS: *v = default_tile(c); return SC_OK;
     case SC_OPT_SEGMENT: *v = default_segment(c); return SC_OK;
-    case SC_OPT_FUSE_MAX_COLS: *v = c->fuse_max_cols; return SC_OK;
+    case SC_OPT_INTERLEAVE: *v = c->interleave; return SC_OK;
+    case SC_OPT_LDS_MAX: *v = c->lds_max > 0 ? c->lds_max : ExecOpts().lds_max; return SC_OK;
     case SC_OPT_REORDER: *v = c->reorder; return SC_OK;
     default: return fail(c, SC_EINVAL, "unknown option %d", opt);
     }
@@ -499,7 +488,7 @@ int sc_plan_info(sc_ctx *c, int32_t gid, int32_t tid, int32_t n_colorings, sc_pl
     std::lock_guard<std::recursive_mutex> lk(c->mu);
     if (!out) return fail(c, SC_EINVAL, "NULL argument");
     Plan P;
-    int rc = pick_batch(c, gid, tid, c->k, std::max(1, n_colorings), 0, P, nullptr);
+    int rc = pick_batch(c, gid, tid, c->k, std::max(1, n_colorings), 0, P);
     if (rc) return rc;
     fill_plan_info(P, c->tmpls[tid]->aut, out);
     return SC_OK;

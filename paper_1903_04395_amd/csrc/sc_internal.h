@@ -19,51 +19,55 @@ uint64_t binom(int n, int r);
 // I = sum_i binom(c_i, i) over its colours c_1 < c_2 < ... (i from 1).
 int64_t colorset_rank(uint32_t mask);
 
-// How a step runs (see step_mode()).
+// How a step builds its neighbour sum (both run as one fused row kernel).
 enum StepMode {
-    kStepFusedHist = 0,    // p = 1: colour histogram and multiply-add in one row kernel
-    kStepFusedGather = 1,  // narrow passive rows: neighbour sum and multiply-add in one row kernel
-    kStepStaged = 2,       // neighbour-sum table N, then the LDS row kernel
-    kStepGlobal = 3        // neighbour-sum table N, then select / multiply-add from global memory
+    kStepHist = 0,     // p = 1: counts of the neighbours' colours
+    kStepGather = 1    // p >= 2: scatter of the neighbours' passive rows
 };
 
+// How a step reads its active table (same values as kern::ActiveMode).
+enum ActiveMode { kActLeaf = 0, kActLds = 1, kActGlobal = 2 };
+
 struct ExecOpts {
-    bool fuse = true;          // allow the fused modes
-    int fuse_max_cols = 512;   // widest passive row (Wp*B uint64) the fused gather takes
+    int interleave = 0;        // cap on colourings interleaved per plane (0: no cap)
     int lds_max = 64 * 1024;   // LDS bytes a row kernel may use
 };
 
 // One DP step: attach the subtree of `child` (passive, size p) to what `node`
 // has built so far (active, size a); h = a + p.  Buffers are indices into
-// Plan::bufs; -1 means the implicit single-vertex table (computed from the
-// colours on the fly) or, for buf_n, a neighbour sum that stays in LDS.
+// Plan::bufs; -1 means the implicit single-vertex table (all ones in the
+// rooted-colour layout).
 struct Step {
     int node, child;
     int h, a, p;
-    int mode;
-    int buf_a, buf_p, buf_n, buf_s;
+    int mode;          // StepMode
+    int amode;         // ActiveMode
+    int lds_bytes;     // dynamic LDS of its row kernel
+    int buf_a, buf_p, buf_s;
     bool last;
 };
 
 struct Buf {
-    int size;          // sub-template size (table has binom(k,size) colour-set columns)
-    uint64_t bytes;    // n * binom(k,size) * batch * 8, rounded to 256
+    int size;          // sub-template size (binom(k-1,size-1) entries per row and colouring)
+    uint64_t bytes;    // n * binom(k-1,size-1) * batch * 8, rounded to 256
     uint64_t offset;   // byte offset inside the run arena
 };
 
 struct Plan {
     int t = 0, k = 0, root = 0, batch = 1;
+    int interleave = 1;         // colourings interleaved per plane (power of two dividing batch)
     int64_t n = 0, nnz = 0;
     std::vector<int> child_ptr, child_idx, subtree;
     std::vector<Step> steps;
     std::vector<Buf> bufs;
     uint64_t arena_bytes = 0;
-    double spmm_updates = 0, ema_updates = 0, lemma1_ops = 0, compulsory_bytes = 0, cost = 0;
+    double spmm_updates = 0, ema_updates = 0, lemma1_ops = 0, exec_updates = 0;
+    double compulsory_bytes = 0, cost = 0;
     ExecOpts opts;
 };
 
-int step_mode(int k, int h, int a, int p, int batch, const ExecOpts &o);
-int row_lds_need(int k, int a, int p, int batch, int mode);
+// Dynamic LDS bytes of a step's row kernel with `bi` interleaved colourings.
+int step_lds_bytes(int k, int a, int p, int bi, int amode);
 
 // Validates an edge list as a tree on t vertices; returns "" or a message.
 std::string check_tree(int t, const int32_t *edges);
@@ -87,12 +91,15 @@ bool choose_plan(int t, const int32_t *edges, int root, int k, int64_t n, int64_
 // |Aut(T)| of the unrooted template tree.
 double tree_automorphisms(int t, const std::vector<std::pair<int,int>> &edges);
 
-// Split table of a step: for every output colour set I_s (in index order),
-// binom(h,a) packed pairs (I_a | I_p << 16).
+// Split table over k colours: for every colour set I_s of size h (in index
+// order), binom(h,a) packed pairs (I_a | I_p << 16).  A rooted-colour step
+// (h, a, p) uses the table of (k-1, h-1, a-1).
 std::vector<uint32_t> split_table(int k, int h, int a);
-// "Drop one colour" table for a = 1: entry [I_s * k + c] is the index of
-// C_s \ {c} among (h-1)-sets, or -1 when c is not in C_s.
-std::vector<int16_t> drop_table(int k, int h);
+// Masks of the s-subsets of k1 colours in Eq. 1 order.
+std::vector<uint16_t> unrank_table(int k1, int s);
+// Eq. 1 rank of any mask m of k1 colours in two lookups:
+// rank(m) = R[m & 255] + R[256 + (m >> 8) * 9 + popcount(m & 255)].
+std::vector<uint16_t> rank_table(int k1);
 
 void fill_plan_info(const Plan &p, double aut, sc_plan_info_t *out);
 

@@ -146,10 +146,9 @@ bool admit(sc_ctx *c, ServeState &S) {
         const uint64_t others = S.mem_bytes - slot_bytes(sl);
         const uint64_t avail = S.cfg.mem_budget_bytes > others ? S.cfg.mem_budget_bytes - others : 0;
         Plan P;
-        int tile = 0;
         auto plan = [&](uint64_t budget) {
             return budget ? pick_batch(c, Q->q.graph_id, Q->q.tmpl_id, Q->q.k,
-                                       std::min(remaining, S.cfg.max_batch), budget, P, &tile)
+                                       std::min(remaining, S.cfg.max_batch), budget, P)
                           : SC_ENOMEM;
         };
         int rc = plan(avail);
@@ -185,7 +184,6 @@ bool admit(sc_ctx *c, ServeState &S) {
         spec.k = Q->q.k;
         spec.seed = Q->q.seed;
         spec.first = Q->q.first_coloring + (uint64_t)Q->scheduled;
-        spec.tile_cols = tile;
         rc = launch_pass(c, Q->q.graph_id, Q->q.tmpl_id, spec, sl.buf, sl.st, sl.host, sl.host + 2,
                          c->use_graph != 0);
         if (!rc && hipEventRecord(sl.ev, sl.st) != hipSuccess) rc = SC_EDEVICE;

@@ -14,16 +14,16 @@ import numpy as np
 
 __all__ = [
     "SC_OK", "SC_EINVAL", "SC_ENOMEM", "SC_EDEVICE", "SC_ENOTFOUND", "SC_EBUSY", "SC_ESTATE",
-    "SC_OPT_MAX_BATCH", "SC_OPT_FUSED", "SC_OPT_GRAPH", "SC_OPT_TILE_COLS", "SC_OPT_SEGMENT",
-    "SC_OPT_FUSE_MAX_COLS", "SC_OPT_REORDER", "OPTION_DEFAULTS", "ScError", "PlanInfo", "KernelStat",
+    "SC_OPT_MAX_BATCH", "SC_OPT_GRAPH", "SC_OPT_SEGMENT", "SC_OPT_REORDER", "SC_OPT_INTERLEAVE",
+    "SC_OPT_LDS_MAX", "OPTION_DEFAULTS", "ScError", "PlanInfo", "KernelStat",
     "Job", "Tune", "ServeCfg", "Query", "Result", "ServeStats", "lib", "lib_path", "sc_version",
     "sc_plan_template",
     "sc_colorset_rank", "sc_color_of", "Context",
 ]
 
 SC_OK, SC_EINVAL, SC_ENOMEM, SC_EDEVICE, SC_ENOTFOUND, SC_EBUSY, SC_ESTATE = 0, -1, -2, -3, -4, -5, -6
-SC_OPT_MAX_BATCH, SC_OPT_FUSED, SC_OPT_GRAPH, SC_OPT_TILE_COLS, SC_OPT_SEGMENT = 1, 2, 3, 4, 5
-SC_OPT_FUSE_MAX_COLS, SC_OPT_REORDER = 7, 8
+SC_OPT_MAX_BATCH, SC_OPT_GRAPH, SC_OPT_SEGMENT, SC_OPT_REORDER = 1, 3, 5, 8
+SC_OPT_INTERLEAVE, SC_OPT_LDS_MAX = 9, 10
 SC_MAX_T = 16
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -52,10 +52,12 @@ class PlanInfo(ctypes.Structure):
         ("step_p", ctypes.c_int32 * SC_MAX_T),
         ("step_mode", ctypes.c_int32 * SC_MAX_T),
         ("batch", ctypes.c_int32),
+        ("interleave", ctypes.c_int32),
         ("arena_bytes", ctypes.c_uint64),
         ("spmm_updates", ctypes.c_double),
         ("ema_updates", ctypes.c_double),
         ("lemma1_ops", ctypes.c_double),
+        ("exec_updates", ctypes.c_double),
         ("compulsory_bytes", ctypes.c_double),
         ("automorphisms", ctypes.c_double),
     ]
@@ -74,9 +76,9 @@ class PlanInfo(ctypes.Structure):
         return {
             "t": self.t, "k": self.k, "root": self.root, "children": self.children(),
             "steps": self.steps(), "modes": self.modes(), "batch": self.batch,
-            "arena_bytes": int(self.arena_bytes),
+            "interleave": self.interleave, "arena_bytes": int(self.arena_bytes),
             "spmm_updates": self.spmm_updates, "ema_updates": self.ema_updates,
-            "lemma1_ops": self.lemma1_ops,
+            "lemma1_ops": self.lemma1_ops, "exec_updates": self.exec_updates,
             "compulsory_bytes": self.compulsory_bytes, "automorphisms": self.automorphisms,
         }
 
@@ -88,8 +90,8 @@ class KernelStat(ctypes.Structure):
     ]
 
 
-OPTION_DEFAULTS = {SC_OPT_MAX_BATCH: 64, SC_OPT_FUSED: 1, SC_OPT_GRAPH: 0, SC_OPT_TILE_COLS: 0,
-                   SC_OPT_SEGMENT: 0, SC_OPT_FUSE_MAX_COLS: 512, SC_OPT_REORDER: 1}
+OPTION_DEFAULTS = {SC_OPT_MAX_BATCH: 64, SC_OPT_GRAPH: 0, SC_OPT_SEGMENT: 0, SC_OPT_REORDER: 1,
+                   SC_OPT_INTERLEAVE: 0, SC_OPT_LDS_MAX: 0}
 
 
 class Job(ctypes.Structure):
@@ -102,7 +104,7 @@ class Job(ctypes.Structure):
 
 
 class Tune(ctypes.Structure):
-    _fields_ = [("tile_cols", ctypes.c_int32), ("fuse_max_cols", ctypes.c_int32),
+    _fields_ = [("interleave", ctypes.c_int32), ("lds_max", ctypes.c_int32),
                 ("batch", ctypes.c_int32), ("trials", ctypes.c_int32), ("ms", ctypes.c_double)]
 
 
@@ -365,7 +367,7 @@ class Context:
     def autotune(self, gid, tid, n_colorings):
         t = Tune()
         self._check(self._L.sc_autotune(self._h, gid, tid, n_colorings, ctypes.byref(t)))
-        return {"tile_cols": t.tile_cols, "fuse_max_cols": t.fuse_max_cols, "batch": t.batch,
+        return {"interleave": t.interleave, "lds_max": t.lds_max, "batch": t.batch,
                 "trials": t.trials, "ms": t.ms}
 
     def tune_save(self, path):

@@ -97,14 +97,35 @@ def test_plan_steps_and_lemma1_counts(seed):
         assert info.spmm_updates == spmm and info.ema_updates == ema
         assert info.lemma1_ops == lemma1
         assert info.automorphisms == O.aut(t, edges)
-        # the arena holds at least the largest step's live tables: output,
-        # active and passive tables, plus the neighbour-sum table unless the
-        # step is fused (modes 0 and 1 keep it in LDS)
-        W = lambda s: math.comb(k, s)
-        need = max((W(h) + (W(a) if a > 1 else 0) + (W(p) if p > 1 else 0)
-                    + (W(p) if mode >= 2 else 0)) * n * 4 * 8
-                   for (h, a, p), mode in zip(info.steps(), info.modes()))
+        # executed updates in the rooted-colour layout (a row keeps only the
+        # colour sets that hold its own colour): nnz*C(k-1,p-1) neighbour-sum
+        # adds (nnz for p = 1) and n*C(k-1,h-1)*C(h-1,a-1) multiply-adds
+        # (n*C(k-1,p) copies for a = 1)
+        ex = sum((nnz * math.comb(k - 1, p - 1) if p > 1 else nnz)
+                 + (n * math.comb(k - 1, h - 1) * math.comb(h - 1, a - 1) if a > 1 else n * math.comb(k - 1, p))
+                 for h, a, p in info.steps())
+        assert info.exec_updates == ex
+        assert info.modes() == [0 if p == 1 else 1 for h, a, p in info.steps()]
+        assert info.interleave in (1, 2, 4) and 4 % info.interleave == 0
+        # the arena holds at least the largest step's live tables (output,
+        # active and passive; single-vertex tables are implicit)
+        W = lambda s: math.comb(k - 1, s - 1)
+        need = max((W(h) + (W(a) if a > 1 else 0) + (W(p) if p > 1 else 0)) * n * 4 * 8
+                   for h, a, p in info.steps())
         assert info.arena_bytes >= need
+
+
+def test_interleave_follows_batch_and_lds():
+    t, k = 12, 12
+    edges = I.prufer_tree(t, 3)
+    for batch, want in ((8, 8), (6, 2), (5, 1), (64, None)):
+        info = sc.sc_plan_template(t, edges, -1, k, 10000, 80000, batch)
+        assert batch % info.interleave == 0
+        if want is not None:
+            assert info.interleave <= want
+    # k = 16: the neighbour-sum row of one colouring alone is C(15,7)*8 bytes
+    info = sc.sc_plan_template(16, I.path(16), 0, 16, 1000, 4000, 4)
+    assert info.interleave == 1
 
 
 def test_planner_picks_lowest_cost_root():

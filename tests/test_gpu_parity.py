@@ -105,7 +105,7 @@ def test_random_sweep(ctx, seed):
     ctx.unload_graph(gid)
 
 
-@pytest.mark.parametrize("B", [1, 3, 8])
+@pytest.mark.parametrize("B", [1, 3, 6, 8, 12])
 def test_batch_sizes_agree(ctx, B):
     g = I.rmat(11, 16, seed=9)
     run_both(ctx, g, 7, I.prufer_tree(7, 9), 7, 11, 5, 9, opts={sc.SC_OPT_MAX_BATCH: B})
@@ -117,10 +117,13 @@ def test_segment_sizes_agree(ctx, seg):
     run_both(ctx, g, 8, I.prufer_tree(8, 10), 8, 12, 0, 4, opts={sc.SC_OPT_SEGMENT: seg})
 
 
-@pytest.mark.parametrize("cols", [8, 16, 32, 64, 128, 256])
-def test_tile_widths_agree(ctx, cols):
+@pytest.mark.parametrize("inter,lds", [(1, 0), (2, 0), (4, 0), (8, 0), (8, 16384), (2, 163840)])
+def test_interleave_and_lds_limits_agree(ctx, inter, lds):
+    """Colourings interleaved per table plane, and active rows staged in LDS
+    or read from global memory (a 16 KB limit forces the latter)."""
     g = I.rmat(11, 16, seed=12)
-    run_both(ctx, g, 9, I.prufer_tree(9, 12), 9, 13, 0, 5, opts={sc.SC_OPT_TILE_COLS: cols})
+    run_both(ctx, g, 9, I.prufer_tree(9, 12), 9, 13, 0, 8,
+             opts={sc.SC_OPT_INTERLEAVE: inter, sc.SC_OPT_LDS_MAX: lds})
 
 
 # ------------------------------------------------------------------ overflow and edge cases
