@@ -55,12 +55,14 @@ struct StepTables {
     const uint32_t *split = nullptr;   // a >= 2: per output set, nsplit pairs (Ia | Ip << 16)
                                        // of the (k-1, h-1, a-1) split table
     const uint16_t *unrank = nullptr;  // p >= 2: masks of the (p-1)-subsets of k-1 colours
-    const uint16_t *rank = nullptr;    // Eq. 1 rank of a mask of k-1 colours, in two parts
+    const uint16_t *rank = nullptr;    // Eq. 1 rank of a mask of k-1 colours (see rank_entries)
     int n_rank = 0;                    // entries of `rank`
 };
 
-// Number of rank-table entries for masks of k1 colours: rank(m) =
-// R[m & 255] + R[256 + (m >> 8) * 9 + popcount(m & 255)].
+// Rank table of masks of k1 colours: for k1 <= kDirectRankBits the rank of
+// every mask, R[m]; above, two lookups, rank(m) = R[m & 255] +
+// R[256 + (m >> 8) * 9 + popcount(m & 255)].  rank_entries() is its length.
+constexpr int kDirectRankBits = 12;
 int rank_entries(int k1);
 
 // Dynamic LDS bytes of the row and split kernels of a step.

@@ -31,7 +31,6 @@ namespace {
 constexpr int kWave = 64;
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / kWave;
-constexpr int kGatherUnroll = 4;      // passive-row loads in flight per lane
 // A launch may hold at most 2^32 - 1 work-items per grid dimension; kernels
 // that stride over their items are launched with at most this many workgroups.
 constexpr int64_t kMaxStrideBlocks = 1 << 16;
@@ -98,9 +97,10 @@ struct DpArgs {
     int64_t n;                    // table rows
     int B, Bi, sh, planes;        // sh = log2(Bi)
     int p, Wq, Wn, Wa, Wh, nsplit;
+    int eg, lg_eg;                // lanes per output entry in the multiply-add (power of two)
     const uint32_t *split;
     const uint16_t *unrank, *rank;
-    int n_rank;
+    int n_rank, rank_direct;      // rank_direct: `rank` holds every mask (2^(k-1) entries)
     const uint64_t *P, *A;
     uint64_t *S;
     uint64_t *Npre;
@@ -131,49 +131,90 @@ __device__ __forceinline__ void stage_tables(const DpArgs &a, uint16_t *tab) {
     for (int i = threadIdx.x; i < a.n_rank; i += kBlock) tab[a.Wq + i] = a.rank[i];
 }
 
+// Eq. 1 rank of a mask of the k-1 colours other than the row's own.
+__device__ __forceinline__ int rank_of(const DpArgs &a, const uint16_t *rk, uint32_t m) {
+    return a.rank_direct ? rk[m] : rk[m & 255u] + rk[256 + (m >> 8) * 9 + __popc(m & 255u)];
+}
+
+// The (p-1)-subset masks of the passive-row entries q = 64*i + lane a lane
+// reads (0 past the row).  They do not depend on the neighbour, so rows that
+// fit CH chunks keep them in registers for the whole kernel.
+template <int CH>
+__device__ __forceinline__ void lane_masks(const DpArgs &a, const uint16_t *unr, int base,
+                                           uint32_t (&msk)[CH]) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int Lq = a.Wq * a.Bi;
+#pragma unroll
+    for (int i = 0; i < CH; ++i) {
+        const int q = base + kWave * i + lane;
+        msk[i] = q < Lq ? unr[q >> a.sh] : 0u;
+    }
+}
+
 // p >= 2: scatters the passive rows of neighbours [e0, e1) of row v (plane pl)
-// into the LDS neighbour sum Nl.  The wavefronts take every fourth neighbour;
-// a wavefront reads one neighbour's row (Wq * Bi contiguous uint64) with
-// kGatherUnroll loads in flight per lane.  Lane `ri` of every group of Bi
-// lanes serves colouring pl*Bi + ri, so the neighbour's colour is loaded once
-// per lane per neighbour.  Distinct entries of one row land on distinct sets,
-// so a wavefront's adds never collide; adds of different wavefronts meet in
-// LDS atomics, whose returned old value gives the carry.
+// into the LDS neighbour sum Nl.  Wavefront w takes neighbours e0 + w, e0 +
+// w + 4, ...; it loads NB neighbours' rows at a time, CH chunks of 64
+// contiguous uint64 each (NB * CH = 16 loads in flight per lane), and rows
+// wider than CH chunks (BIG) are walked in groups of CH chunks.  Lane `ri` of
+// every group of Bi lanes serves colouring pl*Bi + ri.  Each entry {col(u)} +
+// T of a neighbour u lands on v's entry for the same set, re-ranked among the
+// colours other than col(v); sets holding col(v) are skipped.  Distinct
+// entries of one row land on distinct sets, so a wavefront's adds never
+// collide; adds of different wavefronts meet in LDS atomics, whose returned
+// old value gives the carry.
+template <int CH, int NB, bool BIG>
 __device__ __forceinline__ void scatter_rows(const DpArgs &a, int64_t v, int pl, int64_t e0,
-                                             int64_t e1, uint64_t *Nl, const uint16_t *tab,
+                                             int64_t e1, uint64_t *Nl, const uint16_t *unr,
+                                             const uint16_t *rk, const uint32_t (&rmsk)[CH],
                                              uint64_t &m) {
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x >> 6;
     const int ri = lane & (a.Bi - 1);
     const int r = pl * a.Bi + ri;
     const int cv = a.col[v * a.B + r];
+    const uint32_t vbit = 1u << cv;
     const int Lq = a.Wq * a.Bi;
-    const uint16_t *unr = tab, *rk = tab + a.Wq;
     uint32_t carry = 0;
-    for (int64_t e = e0 + wave; e < e1; e += kWaves) {
-        const int u = __builtin_amdgcn_readfirstlane(a.ci[e]);
-        const int cu = a.col[(int64_t)u * a.B + r];
-        const bool live = cu != cv;
-        if (!__any(live)) continue;                  // same colour in every lane's colouring
-        const uint64_t *row = a.P + ((int64_t)pl * a.n + u) * Lq;
-        for (int q0 = 0; q0 < Lq; q0 += kWave * kGatherUnroll) {
-            uint64_t x[kGatherUnroll];
+    for (int64_t eb = e0 + wave; eb < e1; eb += (int64_t)kWaves * NB) {
+        for (int base = 0; base < (BIG ? Lq : 1); base += kWave * CH) {
+            uint32_t msk[CH];
+            if (BIG) lane_masks<CH>(a, unr, base, msk);
+            else {
 #pragma unroll
-            for (int i = 0; i < kGatherUnroll; ++i) {
-                const int q = q0 + kWave * i + lane;
-                x[i] = (live && q < Lq) ? row[q] : 0;
+                for (int i = 0; i < CH; ++i) msk[i] = rmsk[i];
+            }
+            int cu[NB];
+            uint64_t x[NB][CH];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const int64_t e = eb + (int64_t)b * kWaves;
+                cu[b] = cv;                                // absent neighbour: skipped below
+#pragma unroll
+                for (int i = 0; i < CH; ++i) x[b][i] = 0;
+                if (e < e1) {
+                    const int u = __builtin_amdgcn_readfirstlane(a.ci[e]);
+                    cu[b] = a.col[(int64_t)u * a.B + r];
+                    const uint64_t *row = a.P + ((int64_t)pl * a.n + u) * Lq + base;
+#pragma unroll
+                    for (int i = 0; i < CH; ++i)
+                        if (base + kWave * i + lane < Lq) x[b][i] = row[kWave * i + lane];
+                }
             }
 #pragma unroll
-            for (int i = 0; i < kGatherUnroll; ++i) {
-                if (x[i] == 0) continue;
-                const int j = (q0 + kWave * i + lane) >> a.sh;
-                const uint32_t E = widen_at(unr[j], cu) | (1u << cu);
-                if (E & (1u << cv)) continue;
-                const uint32_t Er = narrow_at(E, cv);
-                const int idx = rk[Er & 255u] + rk[256 + (Er >> 8) * 9 + __popc(Er & 255u)];
-                const unsigned long long old =
-                    atomicAdd((unsigned long long *)&Nl[(idx << a.sh) + ri], (unsigned long long)x[i]);
-                carry |= (uint32_t)((uint64_t)old + x[i] < x[i]);
+            for (int b = 0; b < NB; ++b) {
+                if (cu[b] == cv) continue;
+                const uint32_t own = 1u << cu[b];
+#pragma unroll
+                for (int i = 0; i < CH; ++i) {
+                    const uint64_t xv = x[b][i];
+                    if (xv == 0) continue;
+                    const uint32_t E = widen_at(msk[i], cu[b]) | own;
+                    if (E & vbit) continue;
+                    const int idx = rank_of(a, rk, narrow_at(E, cv));
+                    const unsigned long long old =
+                        atomicAdd((unsigned long long *)&Nl[(idx << a.sh) + ri], (unsigned long long)xv);
+                    carry |= (uint32_t)((uint64_t)old + xv < xv);
+                }
             }
         }
     }
@@ -198,8 +239,18 @@ __device__ __forceinline__ void count_colours(const DpArgs &a, int64_t v, int pl
     }
 }
 
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t x, int mask) {
+    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)x, mask, kWave);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(x >> 32), mask, kWave);
+    return ((uint64_t)hi << 32) | lo;
+}
+
 // Output row of (v, pl): S[v] = N'[v] (a = 1) or, for every output set D and
 // colouring, the sum over the nsplit pairs (Ia, Ip) of D of A[v][Ia] * N'[v][Ip].
+// Each output entry is summed by a group of eg adjacent lanes (every eg-th
+// pair), whose partial sums meet through cross-lane shuffles; all terms are
+// non-negative, so a carry in any partial sum or in their combination means
+// the exact sum reaches 2^64.
 template <int AM>
 __device__ __forceinline__ void emit_row(const DpArgs &a, int64_t v, int pl, const uint64_t *Nl,
                                          const uint64_t *Al, uint64_t &m) {
@@ -210,31 +261,52 @@ __device__ __forceinline__ void emit_row(const DpArgs &a, int64_t v, int pl, con
         return;
     }
     const uint64_t *Ar = AM == kActiveLds ? Al : a.A + ((int64_t)pl * a.n + v) * (int64_t)(a.Wa * a.Bi);
-    for (int q = threadIdx.x; q < Ls; q += kBlock) {
+    const int g = threadIdx.x & (a.eg - 1);
+    const int per = kBlock >> a.lg_eg;
+    for (int q0 = 0; q0 < Ls; q0 += per) {          // uniform over the block
+        const int q = q0 + (threadIdx.x >> a.lg_eg);
         const int D = q >> a.sh, ri = q & (a.Bi - 1);
-        const uint32_t *sp = a.split + (int64_t)D * a.nsplit;
         uint64_t acc = 0;
         uint32_t ovf = 0;
-        for (int j = 0; j < a.nsplit; ++j) {
-            const uint32_t pr = sp[j];
-            acc = mad_ovf(acc, Ar[((pr & 0xffffu) << a.sh) + ri], Nl[((pr >> 16) << a.sh) + ri], ovf);
+        if (q < Ls) {
+            const uint32_t *sp = a.split + (int64_t)D * a.nsplit;
+            for (int j = g; j < a.nsplit; j += a.eg) {
+                const uint32_t pr = sp[j];
+                acc = mad_ovf(acc, Ar[((pr & 0xffffu) << a.sh) + ri], Nl[((pr >> 16) << a.sh) + ri], ovf);
+            }
         }
-        out[q] = acc;
-        if (ovf) m |= 1ull << (pl * a.Bi + ri);
+        for (int o = 1; o < a.eg; o <<= 1) {
+            const uint64_t y = shfl_xor_u64(acc, o);
+            ovf |= (uint32_t)__shfl_xor((int)ovf, o, kWave);
+            const uint64_t t = acc + y;
+            ovf |= (uint32_t)(t < y);
+            acc = t;
+        }
+        if (q < Ls && g == 0) {
+            out[q] = acc;
+            if (ovf) m |= 1ull << (pl * a.Bi + ri);
+        }
     }
 }
 
 // One workgroup per (plane, row) item, the grid striding over the items
 // (rows are sorted by descending degree, so every workgroup gets a similar
 // mix).  LDS: the neighbour-sum row N' (Wn * Bi), the staged active row
-// (Wa * Bi, AM == kActiveLds) and the index tables.
-template <bool HIST, int AM>
+// (Wa * Bi, AM == kActiveLds) and the index tables.  CH = 0: p = 1.
+template <int CH, int NB, bool BIG, int AM>
 __global__ __launch_bounds__(kBlock) void dp_row_kernel(DpArgs a) {
+    constexpr bool HIST = CH == 0;
+    constexpr int C = HIST ? 1 : CH;
     extern __shared__ uint64_t lds[];
     uint64_t *Nl = lds;
     uint64_t *Al = lds + a.a_off;
     uint16_t *tab = (uint16_t *)((char *)lds + a.tab_off);
-    if (!HIST) stage_tables(a, tab);
+    uint32_t msk[C];
+    if (!HIST) {
+        stage_tables(a, tab);
+        __syncthreads();
+        if (!BIG) lane_masks<C>(a, tab, 0, msk);
+    }
     const int Ln = a.Wn * a.Bi, La = a.Wa * a.Bi;
     const int64_t total = a.n * a.planes;
     uint64_t m = 0;
@@ -255,7 +327,7 @@ __global__ __launch_bounds__(kBlock) void dp_row_kernel(DpArgs a) {
         __syncthreads();
         if (sv < 0) {
             if (HIST) count_colours(a, v, pl, a.rp[v], a.rp[v + 1], Nl);
-            else scatter_rows(a, v, pl, a.rp[v], a.rp[v + 1], Nl, tab, m);
+            else scatter_rows<C, NB, BIG>(a, v, pl, a.rp[v], a.rp[v + 1], Nl, tab, tab + a.Wq, msk, m);
         }
         __syncthreads();
         emit_row<AM>(a, v, pl, Nl, Al, m);
@@ -267,12 +339,19 @@ __global__ __launch_bounds__(kBlock) void dp_row_kernel(DpArgs a) {
 // Split rows: one workgroup per (plane, row, segment of `seg` neighbours)
 // item; the segment's sum is built in LDS as in the row kernel and added into
 // Npre with global atomics (carry from the returned old value).
-template <bool HIST>
+template <int CH, int NB, bool BIG>
 __global__ __launch_bounds__(kBlock) void dp_split_kernel(DpArgs a) {
+    constexpr bool HIST = CH == 0;
+    constexpr int C = HIST ? 1 : CH;
     extern __shared__ uint64_t lds[];
     uint64_t *Nl = lds;
     uint16_t *tab = (uint16_t *)((char *)lds + a.tab_off);
-    if (!HIST) stage_tables(a, tab);
+    uint32_t msk[C];
+    if (!HIST) {
+        stage_tables(a, tab);
+        __syncthreads();
+        if (!BIG) lane_masks<C>(a, tab, 0, msk);
+    }
     const int Ln = a.Wn * a.Bi;
     const int64_t total = a.n_items * a.planes;
     uint64_t m = 0;
@@ -286,7 +365,7 @@ __global__ __launch_bounds__(kBlock) void dp_split_kernel(DpArgs a) {
         for (int q = threadIdx.x; q < Ln; q += kBlock) Nl[q] = 0;
         __syncthreads();
         if (HIST) count_colours(a, v, pl, e0, e1, Nl);
-        else scatter_rows(a, v, pl, e0, e1, Nl, tab, m);
+        else scatter_rows<C, NB, BIG>(a, v, pl, e0, e1, Nl, tab, tab + a.Wq, msk, m);
         __syncthreads();
         unsigned long long *dst =
             (unsigned long long *)a.Npre + ((int64_t)pl * a.n_split + a.slot[v]) * Ln;
@@ -372,7 +451,21 @@ DpArgs make_args(const GraphBins &g, const StepShape &s, const StepTables &t, co
     a.rp = g.row_ptr; a.ci = g.col_idx; a.col = col; a.n = g.n;
     a.B = s.B; a.Bi = s.Bi; a.sh = log2_exact(s.Bi); a.planes = s.B / s.Bi;
     a.p = s.p; a.Wq = s.Wq; a.Wn = s.Wn; a.Wa = s.Wa; a.Wh = s.Wh; a.nsplit = s.nsplit;
+    // lanes per output entry: the power of two that shortens the longest
+    // chain (rounds of outputs times pairs per lane)
+    a.eg = 1; a.lg_eg = 0;
+    {
+        const int Ls = s.Wh * s.Bi;
+        int64_t best = -1;
+        for (int lg = 0, G = 1; G <= kWave; ++lg, G *= 2) {
+            if (G > 1 && G / 2 >= s.nsplit) break;
+            const int64_t rounds = (Ls + (kBlock / G) - 1) / (kBlock / G);
+            const int64_t chain = rounds * (((int64_t)s.nsplit + G - 1) / G + 2 * lg);
+            if (best < 0 || chain < best) { best = chain; a.eg = G; a.lg_eg = lg; }
+        }
+    }
     a.split = t.split; a.unrank = t.unrank; a.rank = t.rank; a.n_rank = t.n_rank;
+    a.rank_direct = s.k - 1 <= kDirectRankBits;
     a.P = P; a.A = A; a.S = S; a.Npre = const_cast<uint64_t *>(Npre);
     a.slot = g.n_split ? g.slot : nullptr; a.n_split = g.n_split;
     a.items = g.split_items; a.n_items = g.n_split_items; a.seg = g.seg;
@@ -382,22 +475,57 @@ DpArgs make_args(const GraphBins &g, const StepShape &s, const StepTables &t, co
     return a;
 }
 
-template <bool HIST, int AM>
+template <int CH, int NB, bool BIG, int AM>
 hipError_t row_launch(const DpArgs &a, int lds, hipStream_t st) {
-    hipError_t e = allow_lds(dp_row_kernel<HIST, AM>, lds);
+    hipError_t e = allow_lds(dp_row_kernel<CH, NB, BIG, AM>, lds);
     if (e != hipSuccess) return e;
     const int64_t blocks = std::min<int64_t>(a.n * a.planes, 2 * resident_blocks(lds));
-    dp_row_kernel<HIST, AM><<<dim3((unsigned)blocks), dim3(kBlock), lds, st>>>(a);
+    dp_row_kernel<CH, NB, BIG, AM><<<dim3((unsigned)blocks), dim3(kBlock), lds, st>>>(a);
     return hipGetLastError();
 }
 
-template <bool HIST>
+template <int CH, int NB, bool BIG>
 hipError_t split_launch(const DpArgs &a, int lds, hipStream_t st) {
-    hipError_t e = allow_lds(dp_split_kernel<HIST>, lds);
+    hipError_t e = allow_lds(dp_split_kernel<CH, NB, BIG>, lds);
     if (e != hipSuccess) return e;
     const int64_t blocks = std::min<int64_t>(a.n_items * a.planes, 2 * resident_blocks(lds));
-    dp_split_kernel<HIST><<<dim3((unsigned)blocks), dim3(kBlock), lds, st>>>(a);
+    dp_split_kernel<CH, NB, BIG><<<dim3((unsigned)blocks), dim3(kBlock), lds, st>>>(a);
     return hipGetLastError();
+}
+
+// Chunks of 64 uint64 per passive row, rounded up to a power of two (0 for
+// p = 1, 32 for rows wider than 16 chunks, walked in groups of 16).
+int row_chunks(const StepShape &s) {
+    if (s.p < 2) return 0;
+    const int ch = (s.Wq * s.Bi + kWave - 1) / kWave;
+    int c = 1;
+    while (c < ch && c < 32) c *= 2;
+    return c;
+}
+
+template <int AM>
+hipError_t row_dispatch(const StepShape &s, const DpArgs &a, int lds, hipStream_t st) {
+    switch (row_chunks(s)) {
+    case 0: return row_launch<0, 1, false, AM>(a, lds, st);
+    case 1: return row_launch<1, 16, false, AM>(a, lds, st);
+    case 2: return row_launch<2, 8, false, AM>(a, lds, st);
+    case 4: return row_launch<4, 4, false, AM>(a, lds, st);
+    case 8: return row_launch<8, 2, false, AM>(a, lds, st);
+    case 16: return row_launch<16, 1, false, AM>(a, lds, st);
+    default: return row_launch<16, 1, true, AM>(a, lds, st);
+    }
+}
+
+hipError_t split_dispatch(const StepShape &s, const DpArgs &a, int lds, hipStream_t st) {
+    switch (row_chunks(s)) {
+    case 0: return split_launch<0, 1, false>(a, lds, st);
+    case 1: return split_launch<1, 16, false>(a, lds, st);
+    case 2: return split_launch<2, 8, false>(a, lds, st);
+    case 4: return split_launch<4, 4, false>(a, lds, st);
+    case 8: return split_launch<8, 2, false>(a, lds, st);
+    case 16: return split_launch<16, 1, false>(a, lds, st);
+    default: return split_launch<16, 1, true>(a, lds, st);
+    }
 }
 
 bool shape_ok(const StepShape &s) {
@@ -407,7 +535,7 @@ bool shape_ok(const StepShape &s) {
 
 }  // namespace
 
-int rank_entries(int k1) { return 256 + 9 * (k1 > 8 ? (1 << (k1 - 8)) : 1); }
+int rank_entries(int k1) { return k1 <= kDirectRankBits ? 1 << k1 : 256 + 9 * (1 << (k1 - 8)); }
 
 int dp_lds_bytes(const StepShape &s, int amode, int n_rank) {
     int64_t bytes = 8LL * s.Wn * s.Bi;
@@ -444,7 +572,7 @@ hipError_t launch_dp_split(const GraphBins &g, const StepShape &s, const StepTab
     s1.amode = kActiveGlobal;                          // the pre-pass stages no active row
     const DpArgs a = make_args(g, s1, t, col, P, nullptr, Npre, nullptr, flags);
     const int lds = dp_lds_bytes(s1, kActiveGlobal, t.n_rank);
-    return s.p == 1 ? split_launch<true>(a, lds, st) : split_launch<false>(a, lds, st);
+    return split_dispatch(s1, a, lds, st);
 }
 
 hipError_t launch_dp_row(const GraphBins &g, const StepShape &s, const StepTables &t,
@@ -457,14 +585,9 @@ hipError_t launch_dp_row(const GraphBins &g, const StepShape &s, const StepTable
         return hipErrorInvalidValue;
     const DpArgs a = make_args(g, s, t, col, P, A, Npre, S, flags);
     const int lds = dp_lds_bytes(s, s.amode, t.n_rank);
-    if (s.p == 1) {
-        if (s.amode == kActiveLeaf) return row_launch<true, kActiveLeaf>(a, lds, st);
-        if (s.amode == kActiveLds) return row_launch<true, kActiveLds>(a, lds, st);
-        return row_launch<true, kActiveGlobal>(a, lds, st);
-    }
-    if (s.amode == kActiveLeaf) return row_launch<false, kActiveLeaf>(a, lds, st);
-    if (s.amode == kActiveLds) return row_launch<false, kActiveLds>(a, lds, st);
-    return row_launch<false, kActiveGlobal>(a, lds, st);
+    if (s.amode == kActiveLeaf) return row_dispatch<kActiveLeaf>(s, a, lds, st);
+    if (s.amode == kActiveLds) return row_dispatch<kActiveLds>(s, a, lds, st);
+    return row_dispatch<kActiveGlobal>(s, a, lds, st);
 }
 
 hipError_t launch_reduce(int64_t n, const uint64_t *S, int W, int B, int Bi,

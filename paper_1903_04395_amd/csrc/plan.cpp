@@ -246,8 +246,11 @@ bool build_plan(int t, int root, const std::vector<int> &child_ptr,
         bytes += (double)n;                                        // colours
         bytes += 4.0 * nnz + 8.0 * (n + 1);                        // adjacency
         P.compulsory_bytes += bytes;
-        const double gather = s.p >= 2 ? 8.0 * nnz * Rq * 0.5 : (double)nnz;
-        P.cost += bytes + gather + 3.2 * madds;
+        // gathered rows miss the caches almost always; a colour read per
+        // neighbour costs about a 16-byte sector; a u64 multiply-add is
+        // about half a byte's time at the HBM rate
+        const double gather = s.p >= 2 ? 8.0 * nnz * Rq : 16.0 * nnz;
+        P.cost += bytes + gather + 0.5 * madds;
     }
     return true;
 }
@@ -359,9 +362,13 @@ std::vector<uint16_t> unrank_table(int k1, int sz) {
 
 std::vector<uint16_t> rank_table(int k1) {
     std::vector<uint16_t> out(kern::rank_entries(k1), 0);
-    for (uint32_t lo = 0; lo < 256; ++lo) out[lo] = (uint16_t)colorset_rank(lo & ((1u << std::min(k1, 8)) - 1));
+    if (k1 <= kern::kDirectRankBits) {
+        for (uint32_t m = 0; m < (1u << k1); ++m) out[m] = (uint16_t)colorset_rank(m);
+        return out;
+    }
+    for (uint32_t lo = 0; lo < 256; ++lo) out[lo] = (uint16_t)colorset_rank(lo);
     // high part: colour 8 + c at order m + (its order among the high colours)
-    for (uint32_t hi = 0; k1 > 8 && hi < (1u << (k1 - 8)); ++hi)
+    for (uint32_t hi = 0; hi < (1u << (k1 - 8)); ++hi)
         for (int m = 0; m <= 8; ++m) {
             uint64_t idx = 0;
             int order = m;

@@ -97,8 +97,8 @@ double tree_automorphisms(int t, const std::vector<std::pair<int,int>> &edges);
 std::vector<uint32_t> split_table(int k, int h, int a);
 // Masks of the s-subsets of k1 colours in Eq. 1 order.
 std::vector<uint16_t> unrank_table(int k1, int s);
-// Eq. 1 rank of any mask m of k1 colours in two lookups:
-// rank(m) = R[m & 255] + R[256 + (m >> 8) * 9 + popcount(m & 255)].
+// Eq. 1 rank of any mask m of k1 colours, laid out as kern::rank_entries()
+// describes (one lookup up to 12 colours, two above).
 std::vector<uint16_t> rank_table(int k1);
 
 void fill_plan_info(const Plan &p, double aut, sc_plan_info_t *out);
