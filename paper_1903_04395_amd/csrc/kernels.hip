@@ -37,6 +37,7 @@ constexpr int64_t kMaxStrideBlocks = 1 << 16;
 constexpr int kCUs = 256;
 constexpr int kMaxBlocksPerCU = 8;    // 32 wavefronts of 4-wave workgroups
 constexpr int kLdsPerCU = 160 * 1024;
+constexpr int kSplitLdsMax = 4096;    // split-table entries staged in LDS (16 KB)
 
 __device__ __forceinline__ uint64_t wave_or(uint64_t m) {
     uint32_t lo = (uint32_t)m, hi = (uint32_t)(m >> 32);
@@ -98,6 +99,7 @@ struct DpArgs {
     int B, Bi, sh, planes;        // sh = log2(Bi)
     int p, Wq, Wn, Wa, Wh, nsplit;
     int eg, lg_eg;                // lanes per output entry in the multiply-add (power of two)
+    int split_lds;                // the split table is staged in LDS after the other tables
     const uint32_t *split;
     const uint16_t *unrank, *rank;
     int n_rank, rank_direct;      // rank_direct: `rank` holds every mask (2^(k-1) entries)
@@ -124,11 +126,24 @@ __device__ __forceinline__ uint32_t narrow_at(uint32_t m, int c) {
     return lo | ((m ^ lo) >> 1);
 }
 
-// Copies the index tables a step needs into LDS (called by the whole block).
+// Copies the index tables a step needs into LDS (called by the whole block):
+// unrank and rank tables (p >= 2), then the split table when it fits.
 __device__ __forceinline__ void stage_tables(const DpArgs &a, uint16_t *tab) {
-    if (a.p < 2) return;
-    for (int i = threadIdx.x; i < a.Wq; i += kBlock) tab[i] = a.unrank[i];
-    for (int i = threadIdx.x; i < a.n_rank; i += kBlock) tab[a.Wq + i] = a.rank[i];
+    const int nt = a.p >= 2 ? a.Wq + a.n_rank : 0;
+    if (a.p >= 2) {
+        for (int i = threadIdx.x; i < a.Wq; i += kBlock) tab[i] = a.unrank[i];
+        for (int i = threadIdx.x; i < a.n_rank; i += kBlock) tab[a.Wq + i] = a.rank[i];
+    }
+    if (a.split_lds) {
+        uint32_t *sp = (uint32_t *)(tab + ((nt + 1) & ~1));
+        for (int i = threadIdx.x; i < a.Wh * a.nsplit; i += kBlock) sp[i] = a.split[i];
+    }
+}
+
+__device__ __forceinline__ const uint32_t *split_of(const DpArgs &a, const uint16_t *tab) {
+    if (!a.split_lds) return a.split;
+    const int nt = a.p >= 2 ? a.Wq + a.n_rank : 0;
+    return (const uint32_t *)(tab + ((nt + 1) & ~1));
 }
 
 // Eq. 1 rank of a mask of the k-1 colours other than the row's own.
@@ -253,7 +268,7 @@ __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t x, int mask) {
 // the exact sum reaches 2^64.
 template <int AM>
 __device__ __forceinline__ void emit_row(const DpArgs &a, int64_t v, int pl, const uint64_t *Nl,
-                                         const uint64_t *Al, uint64_t &m) {
+                                         const uint64_t *Al, const uint32_t *split, uint64_t &m) {
     const int Ls = a.Wh * a.Bi;
     uint64_t *out = a.S + ((int64_t)pl * a.n + v) * Ls;
     if (AM == kActiveLeaf) {
@@ -263,14 +278,29 @@ __device__ __forceinline__ void emit_row(const DpArgs &a, int64_t v, int pl, con
     const uint64_t *Ar = AM == kActiveLds ? Al : a.A + ((int64_t)pl * a.n + v) * (int64_t)(a.Wa * a.Bi);
     const int g = threadIdx.x & (a.eg - 1);
     const int per = kBlock >> a.lg_eg;
+    const int step = a.eg;
     for (int q0 = 0; q0 < Ls; q0 += per) {          // uniform over the block
         const int q = q0 + (threadIdx.x >> a.lg_eg);
         const int D = q >> a.sh, ri = q & (a.Bi - 1);
         uint64_t acc = 0;
         uint32_t ovf = 0;
         if (q < Ls) {
-            const uint32_t *sp = a.split + (int64_t)D * a.nsplit;
-            for (int j = g; j < a.nsplit; j += a.eg) {
+            const uint32_t *sp = split + (int64_t)D * a.nsplit;
+            int j = g;
+            for (; j + 3 * step < a.nsplit; j += 4 * step) {
+                uint32_t pr[4];
+                uint64_t x[4], y[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) pr[i] = sp[j + i * step];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    x[i] = Ar[((pr[i] & 0xffffu) << a.sh) + ri];
+                    y[i] = Nl[((pr[i] >> 16) << a.sh) + ri];
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) acc = mad_ovf(acc, x[i], y[i], ovf);
+            }
+            for (; j < a.nsplit; j += step) {
                 const uint32_t pr = sp[j];
                 acc = mad_ovf(acc, Ar[((pr & 0xffffu) << a.sh) + ri], Nl[((pr >> 16) << a.sh) + ri], ovf);
             }
@@ -302,11 +332,10 @@ __global__ __launch_bounds__(kBlock) void dp_row_kernel(DpArgs a) {
     uint64_t *Al = lds + a.a_off;
     uint16_t *tab = (uint16_t *)((char *)lds + a.tab_off);
     uint32_t msk[C];
-    if (!HIST) {
-        stage_tables(a, tab);
-        __syncthreads();
-        if (!BIG) lane_masks<C>(a, tab, 0, msk);
-    }
+    stage_tables(a, tab);
+    __syncthreads();
+    if (!HIST && !BIG) lane_masks<C>(a, tab, 0, msk);
+    const uint32_t *split = split_of(a, tab);
     const int Ln = a.Wn * a.Bi, La = a.Wa * a.Bi;
     const int64_t total = a.n * a.planes;
     uint64_t m = 0;
@@ -330,7 +359,7 @@ __global__ __launch_bounds__(kBlock) void dp_row_kernel(DpArgs a) {
             else scatter_rows<C, NB, BIG>(a, v, pl, a.rp[v], a.rp[v + 1], Nl, tab, tab + a.Wq, msk, m);
         }
         __syncthreads();
-        emit_row<AM>(a, v, pl, Nl, Al, m);
+        emit_row<AM>(a, v, pl, Nl, Al, split, m);
         __syncthreads();                         // LDS is reused by the next item
     }
     flush_flags(m, a.flags);
@@ -444,6 +473,12 @@ hipError_t allow_lds(K kernel, int bytes) {
                                kLdsPerCU);
 }
 
+// Split-table entries staged in LDS (0: read from global memory).
+int split_lds_words(const StepShape &s) {
+    const int64_t w = (int64_t)s.Wh * s.nsplit;
+    return s.amode != kActiveLeaf && s.a >= 2 && w <= kSplitLdsMax ? (int)w : 0;
+}
+
 DpArgs make_args(const GraphBins &g, const StepShape &s, const StepTables &t, const uint8_t *col,
                  const uint64_t *P, const uint64_t *A, const uint64_t *Npre, uint64_t *S,
                  unsigned long long *flags) {
@@ -471,6 +506,7 @@ DpArgs make_args(const GraphBins &g, const StepShape &s, const StepTables &t, co
     a.items = g.split_items; a.n_items = g.n_split_items; a.seg = g.seg;
     a.a_off = s.Wn * s.Bi;
     a.tab_off = 8 * (s.Wn * s.Bi + (s.amode == kActiveLds ? s.Wa * s.Bi : 0));
+    a.split_lds = s.amode != kActiveLeaf && split_lds_words(s) > 0;
     a.flags = flags;
     return a;
 }
@@ -540,7 +576,11 @@ int rank_entries(int k1) { return k1 <= kDirectRankBits ? 1 << k1 : 256 + 9 * (1
 int dp_lds_bytes(const StepShape &s, int amode, int n_rank) {
     int64_t bytes = 8LL * s.Wn * s.Bi;
     if (amode == kActiveLds) bytes += 8LL * s.Wa * s.Bi;
-    if (s.p >= 2) bytes += 2LL * (s.Wq + n_rank);
+    const int64_t nt = s.p >= 2 ? s.Wq + n_rank : 0;
+    bytes += 2LL * ((nt + 1) & ~1LL);
+    StepShape s2 = s;
+    s2.amode = amode;
+    bytes += 4LL * split_lds_words(s2);
     bytes = (bytes + 15) & ~15LL;
     return bytes > (1 << 30) ? (1 << 30) : (int)bytes;
 }
@@ -569,9 +609,9 @@ hipError_t launch_dp_split(const GraphBins &g, const StepShape &s, const StepTab
     hipError_t e = launch_zero_u64(Npre, g.n_split * (int64_t)s.Wn * s.B, st);
     if (e != hipSuccess) return e;
     StepShape s1 = s;
-    s1.amode = kActiveGlobal;                          // the pre-pass stages no active row
+    s1.amode = kActiveLeaf;                            // the pre-pass stages no active row or split table
     const DpArgs a = make_args(g, s1, t, col, P, nullptr, Npre, nullptr, flags);
-    const int lds = dp_lds_bytes(s1, kActiveGlobal, t.n_rank);
+    const int lds = dp_lds_bytes(s1, kActiveLeaf, t.n_rank);
     return split_dispatch(s1, a, lds, st);
 }
 

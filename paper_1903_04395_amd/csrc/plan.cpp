@@ -88,6 +88,9 @@ int step_lds_bytes(int k, int a, int p, int bi, int amode) {
     sh.Wq = p >= 2 ? (int)binom(k - 1, p - 1) : 0;
     sh.Wn = (int)binom(k - 1, p);
     sh.Wa = (int)binom(k - 1, a - 1);
+    sh.Wh = (int)binom(k - 1, a + p - 1);
+    sh.nsplit = (int)binom(a + p - 1, a - 1);
+    sh.amode = amode;
     return kern::dp_lds_bytes(sh, amode, kern::rank_entries(k - 1));
 }
 
