@@ -178,7 +178,7 @@ __device__ __forceinline__ void lane_masks(const DpArgs &a, const uint16_t *unr,
 // collide; adds of different wavefronts meet in LDS atomics, whose returned
 // old value gives the carry.
 template <int CH, int NB, bool BIG>
-__device__ __forceinline__ void scatter_rows(const DpArgs &a, int64_t v, int pl, int64_t e0,
+__device__ __forceinline__ void scatter_wide(const DpArgs &a, int64_t v, int pl, int64_t e0,
                                              int64_t e1, uint64_t *Nl, const uint16_t *unr,
                                              const uint16_t *rk, const uint32_t (&rmsk)[CH],
                                              uint64_t &m) {
@@ -234,6 +234,86 @@ __device__ __forceinline__ void scatter_rows(const DpArgs &a, int64_t v, int pl,
         }
     }
     if (carry) m |= 1ull << r;
+}
+
+// The same scatter for rounds of many narrow rows (NB >= 4).
+template <int CH, int NB, bool BIG>
+__device__ __forceinline__ void scatter_narrow(const DpArgs &a, int64_t v, int pl, int64_t e0,
+                                             int64_t e1, uint64_t *Nl, const uint16_t *unr,
+                                             const uint16_t *rk, const uint32_t (&rmsk)[CH],
+                                             uint64_t &m) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x >> 6;
+    const int ri = lane & (a.Bi - 1);
+    const int r = pl * a.Bi + ri;
+    const int cv = a.col[v * a.B + r];
+    const uint32_t vbit = 1u << cv;
+    const int Lq = a.Wq * a.Bi;
+    uint32_t carry = 0;
+    for (int64_t eb = e0 + wave; eb < e1; eb += (int64_t)kWaves * NB) {
+        // lane b holds the b-th neighbour id of the round, broadcast to scalars
+        int mine = -1;
+        const int64_t el = eb + (int64_t)lane * kWaves;
+        if (lane < NB && el < e1) mine = a.ci[el];
+        int uid[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) uid[b] = __builtin_amdgcn_readlane(mine, b);
+        for (int base = 0; base < (BIG ? Lq : 1); base += kWave * CH) {
+            uint32_t msk[CH];
+            if (BIG) lane_masks<CH>(a, unr, base, msk);
+            else {
+#pragma unroll
+                for (int i = 0; i < CH; ++i) msk[i] = rmsk[i];
+            }
+            int cu[NB];
+            uint64_t x[NB][CH];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                cu[b] = uid[b] >= 0 ? (int)a.col[(int64_t)uid[b] * a.B + r] : cv;
+                const uint64_t *row = a.P + ((int64_t)pl * a.n + (uid[b] >= 0 ? uid[b] : 0)) * Lq + base;
+#pragma unroll
+                for (int i = 0; i < CH; ++i)
+                    x[b][i] = (uid[b] >= 0 && base + kWave * i + lane < Lq) ? row[kWave * i + lane] : 0;
+            }
+            // adds in groups of up to 8 whose carries are read after the group is issued
+            constexpr int G = NB * CH < 8 ? NB * CH : 8;
+#pragma unroll
+            for (int f0 = 0; f0 < NB * CH; f0 += G) {
+                uint64_t old[G];
+#pragma unroll
+                for (int f = 0; f < G; ++f) {
+                    const int b = (f0 + f) / CH, i = (f0 + f) % CH;
+                    const uint32_t E = widen_at(msk[i], cu[b]) | (1u << cu[b]);
+                    old[f] = 0;
+                    if (x[b][i] != 0 && cu[b] != cv && !(E & vbit)) {
+                        const int idx = rank_of(a, rk, narrow_at(E, cv));
+                        old[f] = atomicAdd((unsigned long long *)&Nl[(idx << a.sh) + ri],
+                                           (unsigned long long)x[b][i]);
+                    } else {
+                        x[b][i] = 0;
+                    }
+                }
+#pragma unroll
+                for (int f = 0; f < G; ++f) {
+                    const uint64_t xv = x[(f0 + f) / CH][(f0 + f) % CH];
+                    carry |= (uint32_t)(old[f] + xv < xv);
+                }
+            }
+        }
+    }
+    if (carry) m |= 1ull << r;
+}
+
+// Rounds of four or more narrow rows fetch their neighbour ids in one load
+// and read the carries of a group of adds at once; rounds of one or two wide
+// rows keep fewer registers live instead.
+template <int CH, int NB, bool BIG>
+__device__ __forceinline__ void scatter_rows(const DpArgs &a, int64_t v, int pl, int64_t e0,
+                                             int64_t e1, uint64_t *Nl, const uint16_t *unr,
+                                             const uint16_t *rk, const uint32_t (&rmsk)[CH],
+                                             uint64_t &m) {
+    if (NB >= 4) scatter_narrow<CH, NB, BIG>(a, v, pl, e0, e1, Nl, unr, rk, rmsk, m);
+    else scatter_wide<CH, NB, BIG>(a, v, pl, e0, e1, Nl, unr, rk, rmsk, m);
 }
 
 // p = 1: counts the colours of neighbours [e0, e1) of row v (plane pl): the
@@ -543,7 +623,7 @@ template <int AM>
 hipError_t row_dispatch(const StepShape &s, const DpArgs &a, int lds, hipStream_t st) {
     switch (row_chunks(s)) {
     case 0: return row_launch<0, 1, false, AM>(a, lds, st);
-    case 1: return row_launch<1, 16, false, AM>(a, lds, st);
+    case 1: return row_launch<1, 8, false, AM>(a, lds, st);
     case 2: return row_launch<2, 8, false, AM>(a, lds, st);
     case 4: return row_launch<4, 4, false, AM>(a, lds, st);
     case 8: return row_launch<8, 2, false, AM>(a, lds, st);
@@ -555,7 +635,7 @@ hipError_t row_dispatch(const StepShape &s, const DpArgs &a, int lds, hipStream_
 hipError_t split_dispatch(const StepShape &s, const DpArgs &a, int lds, hipStream_t st) {
     switch (row_chunks(s)) {
     case 0: return split_launch<0, 1, false>(a, lds, st);
-    case 1: return split_launch<1, 16, false>(a, lds, st);
+    case 1: return split_launch<1, 8, false>(a, lds, st);
     case 2: return split_launch<2, 8, false>(a, lds, st);
     case 4: return split_launch<4, 4, false>(a, lds, st);
     case 8: return split_launch<8, 2, false>(a, lds, st);
