@@ -46,6 +46,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--opt", action="append", default=[], help="libsc option NUM=VALUE (ablation)")
     ap.add_argument("--breakdown", action="store_true", help="also print the per-family table")
+    ap.add_argument("--configs", action="store_true",
+                    help="timings of the other configurations (ER 2000 / Chung-Lu 4M k=12 / RMAT-19 k=15)")
+    ap.add_argument("--gather-probe", action="store_true",
+                    help="only time whole-row gathers of the widest step's rows in RMAT-20 neighbour order")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB three times (calibrates rocprofv3 FETCH_SIZE/WRITE_SIZE)")
     ap.add_argument("--forms", action="store_true",
@@ -73,8 +77,10 @@ def forms_bench():
     from paper_1903_04395_amd import sc
     out = {}
     ctx = sc.Context(0)
+    g20 = I.rmat(20, 16, seed=0)
     cases = [("er2000-p5-k5", I.erdos_renyi(2000, 10000, seed=1), 5, I.path(5), 0, 256, 64),
-             ("rmat20-tree10-k10", I.rmat(20, 16, seed=0), 10, I.prufer_tree(10, 0), -1, 16, 8)]
+             ("rmat20-tree10-k10", g20, 10, I.prufer_tree(10, 0), -1, 16, 8),
+             ("rmat20-tree10-k10-b16", g20, 10, I.prufer_tree(10, 0), -1, 32, 16)]
     for name, g, t, edges, root, R, B in cases:
         gid = ctx.load_graph(g)
         tid = ctx.load_template(t, edges, root)
@@ -162,6 +168,87 @@ def serve_bench(nq):
     print(json.dumps(out), flush=True)
 
 
+def gather_probe():
+    """Ceiling of the DP's dominant access: whole passive rows of the widest
+    step (126 sets x 8 colourings = 1008 uint64, 8064 bytes) gathered in the
+    neighbour order of RMAT scale 20, from a table of one row per non-isolated
+    vertex (rows relabelled by descending degree, as the library keeps them).
+    torch.index_select into a reused 32768-row buffer; GB/s counts the
+    gathered (read) bytes only, so it is a lower bound of the read ceiling."""
+    import numpy as np
+    import torch
+    from paper_1903_04395_amd import inputs as I
+    g = I.rmat(20, 16, seed=0)
+    deg = g.degrees()
+    order = np.argsort(-deg, kind="stable")
+    rows = int((deg > 0).sum())
+    new_id = np.empty(g.n, np.int64)
+    new_id[order] = np.arange(g.n)
+    idx = torch.from_numpy(new_id[g.col_idx.astype(np.int64)]).cuda()
+    W = 1008
+    table = torch.ones((rows, W), dtype=torch.int64, device="cuda")
+    chunk = 32768
+    buf = torch.empty((chunk, W), dtype=torch.int64, device="cuda")
+    def run():
+        for c0 in range(0, idx.numel(), chunk):
+            sel = idx[c0:c0 + chunk]
+            torch.index_select(table, 0, sel, out=buf[:sel.numel()])
+    run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    run()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    gathered = idx.numel() * W * 8
+    print(json.dumps({"gather_probe": {"rows": rows, "row_bytes": W * 8, "gathers": int(idx.numel()),
+                                       "ms": round(ms, 2),
+                                       "read_GBps": round(gathered / (ms / 1e3) / 1e9, 1)}}), flush=True)
+
+
+def configs_bench():
+    """Per-configuration timings after a warm-up pass (allocation excluded):
+    ER 2000 / P5 / k=5 (one colouring per call: launch latency); Chung-Lu
+    n=4,194,304 (mean degree 30, exponent 2.1) / 12-vertex tree and 12-star /
+    k=12 / 16 colourings; RMAT scale 19 / 15-vertex tree / k=15 / 4 colourings."""
+    from paper_1903_04395_amd import inputs as I
+    from paper_1903_04395_amd import sc
+    ctx = sc.Context(0)
+    out = {}
+    cases = [("er2000-p5-k5", lambda: I.erdos_renyi(2000, 10000, seed=1), [("p5", 5, I.path(5), 0)], 5, 1, 200),
+             ("chunglu4m-k12", lambda: I.chung_lu(4194304, 30, 2.1, seed=3),
+              [("tree12", 12, I.prufer_tree(12, 3), -1), ("star12", 12, I.star(12), 0)], 12, 16, 1),
+             ("rmat19-tree15-k15", lambda: I.rmat(19, 16, seed=4), [("tree15", 15, I.prufer_tree(15, 4), -1)], 15, 4, 1)]
+    for gname, gen, tmpls, k, R, reps in cases:
+        tg = time.time()
+        g = gen()
+        gid = ctx.load_graph(g)
+        print(f"[bench] configs {gname}: n={g.n} nnz={g.nnz} ({time.time() - tg:.0f}s)", file=sys.stderr, flush=True)
+        for tname, t, edges, root in tmpls:
+            tid = ctx.load_template(t, edges, root)
+            ctx.set_colors(k, 7)
+            info = ctx.plan_info(gid, tid, R)
+            ctx.run(gid, tid, 0, R)
+            ctx.profile(True)
+            t0 = time.perf_counter()
+            for i in range(reps):
+                ctx.run(gid, tid, R * (i + 1), R)
+            dt = (time.perf_counter() - t0) / reps
+            ctx.profile(False)
+            fams = ctx.profile_read()
+            key = f"{gname}/{tname}"
+            out[key] = {"colorings": R, "batch": info.batch, "interleave": info.interleave,
+                        "passes": -(-R // info.batch), "tables_GB_per_pass": round(info.arena_bytes / 1e9, 1),
+                        "s_per_call": round(dt, 4), "colorings_per_s": round(R / dt, 2),
+                        "families_ms_per_call": {f: round(v["total_ms"] / reps, 2) for f, v in fams.items()}}
+            print(f"[bench] configs {key}: {out[key]}", file=sys.stderr, flush=True)
+        ctx.unload_graph(gid)
+        del g
+    ctx.close()
+    print(json.dumps({"configs": out}), flush=True)
+
+
 def copy_probe():
     import torch
     a = torch.empty(1 << 27, dtype=torch.int64, device="cuda")   # 1 GiB
@@ -181,9 +268,10 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_for(family):
-    """HBM bytes per launch from a committed rocprofv3 counter summary, if it was
-    taken from the current kernel sources; else None."""
+def traffic_per_step():
+    """HBM bytes per DP step (all dp_ kernels of a pass over its steps) from the
+    committed rocprofv3 counter summary, if it was taken from the current
+    kernel sources; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -193,8 +281,7 @@ def traffic_for(family):
         return None
     if d.get("source_hash") != source_hash():
         return None
-    fam = d.get("families", {}).get(family)
-    return None if fam is None else fam.get("hbm_bytes_per_launch")
+    return d.get("hbm_bytes_per_step")
 
 
 def main():
@@ -202,12 +289,20 @@ def main():
     if args.copy_probe:
         copy_probe()
         return
-    if args.forms or args.serve:
+    if args.gather_probe:
+        gather_probe()
+        return
+    if args.forms or args.serve or args.configs:
         import torch
         if not torch.cuda.is_available():
             print("bench.py needs a GPU", file=sys.stderr)
             sys.exit(1)
-        forms_bench() if args.forms else serve_bench(args.queries)
+        if args.forms:
+            forms_bench()
+        elif args.serve:
+            serve_bench(args.queries)
+        else:
+            configs_bench()
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the method's multi-GPU "
@@ -257,15 +352,19 @@ def main():
 
     colorings = args.steps * B
     value = colorings * upd_per_coloring / elapsed / 1e9
-    dom_name, dom = max(fams.items(), key=lambda kv: kv[1]["total_ms"])
-    achieved = dom["alg_bytes"] / (dom["total_ms"] / 1e3) / 1e9
+    # the DP step: each row kernel launch with the split pre-pass before it
+    dp_f = [f for f in ("split", "row_gather", "row_hist") if f in fams]
+    dp = {"total_ms": sum(fams[f]["total_ms"] for f in dp_f),
+          "alg_bytes": sum(fams[f]["alg_bytes"] for f in dp_f),
+          "launches": sum(fams[f]["launches"] for f in ("row_gather", "row_hist") if f in fams)}
+    achieved = dp["alg_bytes"] / (dp["total_ms"] / 1e3) / 1e9
     roofline = {
         "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-        "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic_for(dom_name),
-        "family": dom_name, "kernel": KERNEL_OF.get(dom_name, dom_name),
-        "avg_launch_ms": round(dom["total_ms"] / dom["launches"], 4),
-        "alg_bytes_per_launch": dom["alg_bytes"] / dom["launches"],
-        "share_of_gpu_time": round(dom["total_ms"] / sum(f["total_ms"] for f in fams.values()), 3),
+        "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic_per_step(),
+        "kernel": "DP step = dp_split_kernel (rows above the segment size) + dp_row_kernel",
+        "avg_step_ms": round(dp["total_ms"] / dp["launches"], 4),
+        "alg_bytes_per_step": dp["alg_bytes"] / dp["launches"],
+        "share_of_gpu_time": round(dp["total_ms"] / sum(f["total_ms"] for f in fams.values()), 3),
     }
     # passive rows gathered per pass: nnz * C(k-1, p-1) words per colouring for
     # every step with p >= 2 (row kernels and the split pre-pass)

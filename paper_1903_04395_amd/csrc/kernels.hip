@@ -23,6 +23,7 @@
 #include <algorithm>
 
 #include "kernels.h"
+#include "exact.h"      // after the HIP runtime header (it uses __device__)
 
 namespace sc {
 namespace kern {
@@ -57,14 +58,6 @@ __device__ __forceinline__ void flush_flags(uint64_t m, unsigned long long *flag
     }
 }
 
-// acc + a*b with the exact-overflow rule: flag if a*b >= 2^64 or the sum carries.
-__device__ __forceinline__ uint64_t mad_ovf(uint64_t acc, uint64_t a, uint64_t b, uint32_t &ovf) {
-    uint64_t lo = a * b;
-    uint64_t hi = __umul64hi(a, b);
-    uint64_t s = acc + lo;
-    ovf |= (uint32_t)(hi != 0) | (uint32_t)(s < lo);
-    return s;
-}
 
 // ------------------------------------------------------------------ colours
 

@@ -140,9 +140,9 @@ uint64_t table_bytes(int64_t n, int k, int size, int batch) {
     return (b + 255) & ~(uint64_t)255;
 }
 
-// Largest power of two dividing `batch`, at most `cap` (0: 64), with which
-// every step's row kernel fits `lds_max` bytes of LDS (without a staged
-// active row); 1 if none does.
+// Colourings interleaved per plane: the largest power of two dividing
+// `batch`, at most `cap` (0: 64), with which every step's row kernel fits
+// `lds_max` bytes of LDS (without a staged active row); 1 if none does.
 int pick_interleave(const Plan &P, int cap, int lds_max) {
     int bi = 1;
     while (bi < 64 && P.batch % (2 * bi) == 0 && (cap == 0 || 2 * bi <= cap)) bi *= 2;
@@ -225,6 +225,8 @@ bool build_plan(int t, int root, const std::vector<int> &child_ptr,
     for (Step &s : P.steps) {
         const int base = step_lds_bytes(k, s.a, s.p, P.interleave, s.a > 1 ? kActGlobal : kActLeaf);
         if (base > 160 * 1024) { err = "a step's neighbour-sum row does not fit in LDS"; return false; }
+        // The active row is staged in LDS when it fits the limit; wider rows
+        // are read from global memory, where the row stays in the caches.
         s.amode = kActLeaf;
         if (s.a > 1) {
             const int staged = step_lds_bytes(k, s.a, s.p, P.interleave, kActLds);

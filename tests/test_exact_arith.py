@@ -1,0 +1,68 @@
+"""The device's exact uint64 multiply-add (csrc/exact.h), compiled for the
+host with g++, against unsigned 128-bit arithmetic: residue and overflow flag
+on edge values around every 32-bit and 64-bit boundary and on random pairs."""
+import os
+import subprocess
+import textwrap
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "paper_1903_04395_amd", "csrc", "exact.h")
+
+HARNESS = textwrap.dedent(r"""
+    #include <cstdio>
+    #include <random>
+    #include "exact.h"
+    typedef unsigned __int128 u128;
+    static int check(uint64_t acc, uint64_t a, uint64_t b) {
+        uint32_t ovf = 0;
+        uint64_t got = sc::kern::mad_ovf(acc, a, b, ovf);
+        u128 p = (u128)a * b, s = (u128)acc + (uint64_t)p;
+        uint64_t want = (uint64_t)s;
+        int want_ovf = (p >> 64) != 0 || (s >> 64) != 0;
+        if (got != want || (ovf != 0) != want_ovf) {
+            printf("FAIL %llu %llu %llu\n", (unsigned long long)acc, (unsigned long long)a, (unsigned long long)b);
+            return 1;
+        }
+        return 0;
+    }
+    int main() {
+        const uint64_t edge[] = {0, 1, 2, 3, 0xffffffffull, 0x100000000ull, 0x100000001ull,
+                                 0x1ffffffffull, 0xfffffffeull, 0x80000000ull, 0x7fffffffffffffffull,
+                                 0x8000000000000000ull, 0xffffffffffffffffull, 0xfffffffffffffffeull,
+                                 0x0000000100000000ull, 0x00000000ffffffffull, 4294967296ull * 3 + 7,
+                                 0x123456789abcdefull, 0xfedcba9876543210ull};
+        int bad = 0;
+        long n = 0;
+        for (uint64_t a : edge) for (uint64_t b : edge) for (uint64_t c : edge) { bad += check(c, a, b); ++n; }
+        std::mt19937_64 g(12345);
+        for (long i = 0; i < 2000000; ++i) {
+            uint64_t a = g(), b = g(), c = g();
+            int m = i % 8;                       // vary magnitudes: 0..64-bit operands
+            a >>= (g() % 64) * (m & 1);
+            b >>= (g() % 64) * ((m >> 1) & 1);
+            c >>= (g() % 64) * ((m >> 2) & 1);
+            bad += check(c, a, b);
+            ++n;
+        }
+        // products just below and at 2^64
+        for (uint64_t a = 1; a < 200000; a += 7) {
+            uint64_t b = ~0ull / a;
+            bad += check(0, a, b) + check(0, a, b + 1) + check(~0ull - a * b, a, b) + check(~0ull - a * b + 1, a, b);
+            n += 4;
+        }
+        printf("%s %ld\n", bad ? "BAD" : "OK", n);
+        return bad != 0;
+    }
+""")
+
+
+def test_mad_ovf_matches_128bit(tmp_path):
+    src = tmp_path / "h.cpp"
+    src.write_text(HARNESS)
+    exe = tmp_path / "h"
+    subprocess.run(["g++", "-O2", "-std=c++17", "-D__host__=", "-D__device__=", "-D__forceinline__=inline",
+                    "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0 and out.stdout.startswith("OK"), out.stdout[-500:]

@@ -7,6 +7,7 @@ tests/golden/make_full_size.py, which calls only the oracle).  The GPU runs
 every colouring of the configured batch; the sampled ones are compared."""
 import json
 import os
+import time
 
 import numpy as np
 import pytest
@@ -58,8 +59,12 @@ def test_full_size_matches_oracle(ctx, name):
     tid = ctx.load_template_plan(e["t"], e["root"], e["children"])
     ctx.set_colors(e["k"], e["seed"])
     R = RUN_COLOURINGS[name]
-    print(f"[case] {name}: running {R} colourings", flush=True)
+    info = ctx.plan_info(gid, tid, R)
+    print(f"[case] {name}: running {R} colourings (batch {info.batch}, interleave {info.interleave}, "
+          f"tables {info.arena_bytes / 1e9:.1f} GB per pass)", flush=True)
+    t0 = time.perf_counter()
     counts, ovf, _, _ = ctx.run(gid, tid, 0, R)
+    print(f"[case] {name}: {R} colourings in {time.perf_counter() - t0:.3f} s", flush=True)
     for r, (cnt, flag) in e["results"].items():
         assert int(counts[int(r)]) == int(cnt), (name, r)
         assert int(ovf[int(r)]) == flag, (name, r)
