@@ -262,7 +262,7 @@ def copy_probe():
 
 def source_hash():
     h = hashlib.sha256()
-    for f in ("kernels.hip", "kernels.h"):
+    for f in ("kernels.hip", "kernels.h", "exact.h"):
         with open(os.path.join(ROOT, "paper_1903_04395_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
