@@ -39,6 +39,7 @@ constexpr int kCUs = 256;
 constexpr int kMaxBlocksPerCU = 8;    // 32 wavefronts of 4-wave workgroups
 constexpr int kLdsPerCU = 160 * 1024;
 constexpr int kSplitLdsMax = 4096;    // split-table entries staged in LDS (16 KB)
+constexpr int kGroupRows = 3;         // chunk-count tag of the lane-group scatter
 
 __device__ __forceinline__ uint64_t wave_or(uint64_t m) {
     uint32_t lo = (uint32_t)m, hi = (uint32_t)(m >> 32);
@@ -297,15 +298,84 @@ __device__ __forceinline__ void scatter_narrow(const DpArgs &a, int64_t v, int p
     if (carry) m |= 1ull << r;
 }
 
+// Rows of at most 16 sets (Wq <= 16) with Bi >= 4 interleaved colourings:
+// each group of Bi lanes takes one neighbour (lane ri serving colouring
+// pl*Bi + ri) and walks the row's Wq sets, so a load instruction reads 64/Bi
+// neighbours' entries for one set; U rounds of neighbours are in flight.
+// Groups of one wavefront may add to the same entry, so adds are LDS atomics
+// (carry from the returned old value).
+template <int U>
+__device__ __forceinline__ void scatter_groups(const DpArgs &a, int64_t v, int pl, int64_t e0,
+                                               int64_t e1, uint64_t *Nl, const uint16_t *unr,
+                                               const uint16_t *rk, uint64_t &m) {
+    constexpr int kMaxW = 16;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x >> 6;
+    const int ri = lane & (a.Bi - 1);
+    const int grp = lane >> a.sh;
+    const int groups = kWave >> a.sh;
+    const int r = pl * a.Bi + ri;
+    const int cv = a.col[v * a.B + r];
+    const uint32_t vbit = 1u << cv;
+    const int Lq = a.Wq * a.Bi;
+    // neighbour e0 + wave + kWaves*(grp + groups*i): a short row spreads over
+    // the wavefronts before it fills a wavefront's groups
+    const int64_t round = (int64_t)kWaves * groups;
+    uint32_t carry = 0;
+    for (int64_t eb = e0 + wave + (int64_t)kWaves * grp; eb - (int64_t)kWaves * grp < e1; eb += round * U) {
+        int u[U], cu[U];
+        uint64_t x[U][kMaxW];
+#pragma unroll
+        for (int t = 0; t < U; ++t) {
+            const int64_t e = eb + t * round;
+            u[t] = e < e1 ? a.ci[e] : -1;
+        }
+#pragma unroll
+        for (int t = 0; t < U; ++t) {
+            cu[t] = u[t] >= 0 ? (int)a.col[(int64_t)u[t] * a.B + r] : cv;
+            const uint64_t *row = a.P + ((int64_t)pl * a.n + (u[t] >= 0 ? u[t] : 0)) * Lq + ri;
+#pragma unroll
+            for (int j = 0; j < kMaxW; ++j)
+                x[t][j] = (u[t] >= 0 && j < a.Wq) ? row[j << a.sh] : 0;
+        }
+#pragma unroll
+        for (int t = 0; t < U; ++t) {
+            const uint32_t own = 1u << cu[t];
+#pragma unroll
+            for (int j0 = 0; j0 < kMaxW; j0 += 8) {
+                uint64_t old[8];
+#pragma unroll
+                for (int f = 0; f < 8; ++f) {
+                    const int j = j0 + f;
+                    old[f] = 0;
+                    const uint32_t E = widen_at(unr[j < a.Wq ? j : 0], cu[t]) | own;
+                    if (x[t][j] != 0 && cu[t] != cv && !(E & vbit)) {
+                        const int idx = rank_of(a, rk, narrow_at(E, cv));
+                        old[f] = atomicAdd((unsigned long long *)&Nl[(idx << a.sh) + ri],
+                                           (unsigned long long)x[t][j]);
+                    } else {
+                        x[t][j] = 0;
+                    }
+                }
+#pragma unroll
+                for (int f = 0; f < 8; ++f) carry |= (uint32_t)(old[f] + x[t][j0 + f] < x[t][j0 + f]);
+            }
+        }
+    }
+    if (carry) m |= 1ull << r;
+}
+
 // Rounds of four or more narrow rows fetch their neighbour ids in one load
 // and read the carries of a group of adds at once; rounds of one or two wide
 // rows keep fewer registers live instead.
+// CH == kGroupRows selects the lane-group scatter for rows of at most 16 sets.
 template <int CH, int NB, bool BIG>
 __device__ __forceinline__ void scatter_rows(const DpArgs &a, int64_t v, int pl, int64_t e0,
                                              int64_t e1, uint64_t *Nl, const uint16_t *unr,
                                              const uint16_t *rk, const uint32_t (&rmsk)[CH],
                                              uint64_t &m) {
-    if (NB >= 4) scatter_narrow<CH, NB, BIG>(a, v, pl, e0, e1, Nl, unr, rk, rmsk, m);
+    if constexpr (CH == kGroupRows) scatter_groups<2>(a, v, pl, e0, e1, Nl, unr, rk, m);
+    else if constexpr (NB >= 4) scatter_narrow<CH, NB, BIG>(a, v, pl, e0, e1, Nl, unr, rk, rmsk, m);
     else scatter_wide<CH, NB, BIG>(a, v, pl, e0, e1, Nl, unr, rk, rmsk, m);
 }
 
@@ -407,7 +477,7 @@ __global__ __launch_bounds__(kBlock) void dp_row_kernel(DpArgs a) {
     uint32_t msk[C];
     stage_tables(a, tab);
     __syncthreads();
-    if (!HIST && !BIG) lane_masks<C>(a, tab, 0, msk);
+    if constexpr (!HIST && !BIG && CH != kGroupRows) lane_masks<C>(a, tab, 0, msk);
     const uint32_t *split = split_of(a, tab);
     const int Ln = a.Wn * a.Bi, La = a.Wa * a.Bi;
     const int64_t total = a.n * a.planes;
@@ -428,7 +498,7 @@ __global__ __launch_bounds__(kBlock) void dp_row_kernel(DpArgs a) {
         }
         __syncthreads();
         if (sv < 0) {
-            if (HIST) count_colours(a, v, pl, a.rp[v], a.rp[v + 1], Nl);
+            if constexpr (HIST) count_colours(a, v, pl, a.rp[v], a.rp[v + 1], Nl);
             else scatter_rows<C, NB, BIG>(a, v, pl, a.rp[v], a.rp[v + 1], Nl, tab, tab + a.Wq, msk, m);
         }
         __syncthreads();
@@ -449,10 +519,10 @@ __global__ __launch_bounds__(kBlock) void dp_split_kernel(DpArgs a) {
     uint64_t *Nl = lds;
     uint16_t *tab = (uint16_t *)((char *)lds + a.tab_off);
     uint32_t msk[C];
-    if (!HIST) {
+    if constexpr (!HIST) {
         stage_tables(a, tab);
         __syncthreads();
-        if (!BIG) lane_masks<C>(a, tab, 0, msk);
+        if constexpr (!BIG && CH != kGroupRows) lane_masks<C>(a, tab, 0, msk);
     }
     const int Ln = a.Wn * a.Bi;
     const int64_t total = a.n_items * a.planes;
@@ -466,7 +536,7 @@ __global__ __launch_bounds__(kBlock) void dp_split_kernel(DpArgs a) {
         const int64_t e1 = e0 + a.seg < r1 ? e0 + a.seg : r1;
         for (int q = threadIdx.x; q < Ln; q += kBlock) Nl[q] = 0;
         __syncthreads();
-        if (HIST) count_colours(a, v, pl, e0, e1, Nl);
+        if constexpr (HIST) count_colours(a, v, pl, e0, e1, Nl);
         else scatter_rows<C, NB, BIG>(a, v, pl, e0, e1, Nl, tab, tab + a.Wq, msk, m);
         __syncthreads();
         unsigned long long *dst =
@@ -603,18 +673,23 @@ hipError_t split_launch(const DpArgs &a, int lds, hipStream_t st) {
 }
 
 // Chunks of 64 uint64 per passive row, rounded up to a power of two (0 for
-// p = 1, 32 for rows wider than 16 chunks, walked in groups of 16).
-int row_chunks(const StepShape &s) {
+// p = 1, 32 for rows wider than 16 chunks, walked in groups of 16), or
+// kGroupRows (when `groups`) for rows of at most 16 sets with 4 or more
+// interleaved colourings.
+int row_chunks(const StepShape &s, bool groups) {
     if (s.p < 2) return 0;
+    if (groups && s.Wq <= 16 && s.Bi >= 4) return kGroupRows;
     const int ch = (s.Wq * s.Bi + kWave - 1) / kWave;
     int c = 1;
     while (c < ch && c < 32) c *= 2;
     return c;
 }
 
+// The row kernels keep the chunked scatter for narrow rows too: a light row's
+// few neighbours spread over more lanes that way.
 template <int AM>
 hipError_t row_dispatch(const StepShape &s, const DpArgs &a, int lds, hipStream_t st) {
-    switch (row_chunks(s)) {
+    switch (row_chunks(s, false)) {
     case 0: return row_launch<0, 1, false, AM>(a, lds, st);
     case 1: return row_launch<1, 8, false, AM>(a, lds, st);
     case 2: return row_launch<2, 8, false, AM>(a, lds, st);
@@ -626,8 +701,9 @@ hipError_t row_dispatch(const StepShape &s, const DpArgs &a, int lds, hipStream_
 }
 
 hipError_t split_dispatch(const StepShape &s, const DpArgs &a, int lds, hipStream_t st) {
-    switch (row_chunks(s)) {
+    switch (row_chunks(s, true)) {
     case 0: return split_launch<0, 1, false>(a, lds, st);
+    case kGroupRows: return split_launch<kGroupRows, 1, false>(a, lds, st);
     case 1: return split_launch<1, 8, false>(a, lds, st);
     case 2: return split_launch<2, 8, false>(a, lds, st);
     case 4: return split_launch<4, 4, false>(a, lds, st);
