@@ -87,6 +87,16 @@ def test_config4_shape_rmat_k15(ctx):
     run_both(ctx, g, 15, I.prufer_tree(15, 4), 15, 9, 0, 2)
 
 
+@pytest.mark.parametrize("shape", ["path", "tree"])
+def test_k16_rows_beyond_64kb_lds(ctx, shape):
+    """k = 16: a neighbour-sum row of one colouring holds up to C(15,7) = 6435
+    entries, so with its index tables a row kernel needs more than 64 KB of
+    LDS (the largest templates the library takes)."""
+    g = I.rmat(7, 8, seed=16)
+    edges = I.path(16) if shape == "path" else I.prufer_tree(16, 16)
+    run_both(ctx, g, 16, edges, 16, 21, 0, 2, root=0)
+
+
 # ------------------------------------------------------------------ sweeps
 
 @pytest.mark.parametrize("seed", range(6))
