@@ -203,7 +203,7 @@ int sc_run_batch(sc_ctx *ctx, sc_job_t *jobs, int32_t n_jobs, void *stream);
 
 /* Autotuner: times real passes of (graph, template) at the batch `n_colorings`
  * plans to, over the interleave caps {1, 2, 4, ..., batch} (at most four of
- * them, the largest ones) and the row-kernel LDS limits {32, 64, 96} KB, and
+ * them, the largest ones) and the row-kernel LDS limits {32, 64, 96, 128} KB, and
  * keeps the fastest for that (graph, template, k, batch).  The choice never
  * changes a result. */
 typedef struct {

@@ -11,15 +11,38 @@ namespace sc {
 namespace kern {
 
 // acc + a*b mod 2^64; sets `ovf` when a*b >= 2^64 (the high half of the
-// 128-bit product is non-zero) or the sum carries.  A split into 32-bit
-// halves needing only three multiplies was measured slower in the row
-// kernels: it raises register use more than it saves.
+// 128-bit product is non-zero) or the sum carries.
 __host__ __device__ __forceinline__ uint64_t mad_ovf(uint64_t acc, uint64_t a, uint64_t b,
                                                      uint32_t &ovf) {
     const unsigned __int128 p = (unsigned __int128)a * b;
     const uint64_t lo = (uint64_t)p;
     const uint64_t s = acc + lo;
     ovf |= (uint32_t)((uint64_t)(p >> 64) != 0) | (uint32_t)(s < lo);
+    return s;
+}
+
+// The same result with three 32-bit multiplies instead of the full 128-bit
+// product; fewer vector-ALU cycles, more registers and selects.
+//
+// With a = ah*2^32 + al and b = bh*2^32 + bl:
+//   a*b = ah*bh*2^64 + (ah*bl + al*bh)*2^32 + al*bl.
+// If ah and bh are both non-zero the product is at least 2^64.  Otherwise at
+// most one cross term c is non-zero and a*b = c*2^32 + al*bl, which reaches
+// 2^64 exactly when c >= 2^32 or lo32(c) + hi32(al*bl) >= 2^32.  The residue
+// needs only the low 32 bits of the two cross terms.
+__host__ __device__ __forceinline__ uint64_t mad_ovf3(uint64_t acc, uint64_t a, uint64_t b,
+                                                      uint32_t &ovf) {
+    const uint32_t al = (uint32_t)a, ah = (uint32_t)(a >> 32);
+    const uint32_t bl = (uint32_t)b, bh = (uint32_t)(b >> 32);
+    const uint64_t ll = (uint64_t)al * bl;
+    const uint64_t c = (uint64_t)(ah ? ah : al) * (uint64_t)(ah ? bl : bh);
+    const uint32_t both = (uint32_t)(ah != 0) & (uint32_t)(bh != 0);
+    const uint32_t extra = both ? al * bh : 0u;           // the second cross term, low half
+    const uint64_t mid = (ll >> 32) + (uint32_t)c;
+    ovf |= both | (uint32_t)((c >> 32) != 0) | (uint32_t)(mid >> 32);
+    const uint64_t lo = ll + ((uint64_t)((uint32_t)c + extra) << 32);
+    const uint64_t s = acc + lo;
+    ovf |= (uint32_t)(s < lo);
     return s;
 }
 

@@ -365,7 +365,7 @@ int sc_autotune(sc_ctx *c, int32_t gid, int32_t tid, int32_t n_colorings, sc_tun
     std::vector<int> inter;
     for (int bi = 64; bi >= 1 && inter.size() < 4; bi /= 2)
         if (B % bi == 0) inter.push_back(bi);
-    static const int ldss[] = {32 * 1024, 64 * 1024, 96 * 1024};
+    static const int ldss[] = {32 * 1024, 64 * 1024, 96 * 1024, 128 * 1024};
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));

@@ -40,6 +40,8 @@ constexpr int kMaxBlocksPerCU = 8;    // 32 wavefronts of 4-wave workgroups
 constexpr int kLdsPerCU = 160 * 1024;
 constexpr int kSplitLdsMax = 4096;    // split-table entries staged in LDS (16 KB)
 constexpr int kGroupRows = 3;         // chunk-count tag of the lane-group scatter
+constexpr int kMad3Pairs = 32;        // split pairs per entry from which the three-multiply
+                                      // product is used (vector-ALU-bound multiply-adds)
 
 __device__ __forceinline__ uint64_t wave_or(uint64_t m) {
     uint32_t lo = (uint32_t)m, hi = (uint32_t)(m >> 32);
@@ -422,6 +424,7 @@ __device__ __forceinline__ void emit_row(const DpArgs &a, int64_t v, int pl, con
     const int g = threadIdx.x & (a.eg - 1);
     const int per = kBlock >> a.lg_eg;
     const int step = a.eg;
+    const bool lean = a.nsplit >= kMad3Pairs;      // uniform: the step's form of the product
     for (int q0 = 0; q0 < Ls; q0 += per) {          // uniform over the block
         const int q = q0 + (threadIdx.x >> a.lg_eg);
         const int D = q >> a.sh, ri = q & (a.Bi - 1);
@@ -440,8 +443,13 @@ __device__ __forceinline__ void emit_row(const DpArgs &a, int64_t v, int pl, con
                     x[i] = Ar[((pr[i] & 0xffffu) << a.sh) + ri];
                     y[i] = Nl[((pr[i] >> 16) << a.sh) + ri];
                 }
+                if (lean) {
 #pragma unroll
-                for (int i = 0; i < 4; ++i) acc = mad_ovf(acc, x[i], y[i], ovf);
+                    for (int i = 0; i < 4; ++i) acc = mad_ovf3(acc, x[i], y[i], ovf);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) acc = mad_ovf(acc, x[i], y[i], ovf);
+                }
             }
             for (; j < a.nsplit; j += step) {
                 const uint32_t pr = sp[j];

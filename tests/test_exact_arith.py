@@ -1,4 +1,4 @@
-"""The device's exact uint64 multiply-add (csrc/exact.h), compiled for the
+"""The device's exact uint64 multiply-adds (both forms in csrc/exact.h), compiled for the
 host with g++, against unsigned 128-bit arithmetic: residue and overflow flag
 on edge values around every 32-bit and 64-bit boundary and on random pairs."""
 import os
@@ -16,12 +16,13 @@ HARNESS = textwrap.dedent(r"""
     #include "exact.h"
     typedef unsigned __int128 u128;
     static int check(uint64_t acc, uint64_t a, uint64_t b) {
-        uint32_t ovf = 0;
+        uint32_t ovf = 0, ovf3 = 0;
         uint64_t got = sc::kern::mad_ovf(acc, a, b, ovf);
+        uint64_t got3 = sc::kern::mad_ovf3(acc, a, b, ovf3);
         u128 p = (u128)a * b, s = (u128)acc + (uint64_t)p;
         uint64_t want = (uint64_t)s;
         int want_ovf = (p >> 64) != 0 || (s >> 64) != 0;
-        if (got != want || (ovf != 0) != want_ovf) {
+        if (got != want || (ovf != 0) != want_ovf || got3 != want || (ovf3 != 0) != want_ovf) {
             printf("FAIL %llu %llu %llu\n", (unsigned long long)acc, (unsigned long long)a, (unsigned long long)b);
             return 1;
         }
