@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--serve", action="store_true",
                     help="serving mix: RMAT 18/20/22 resident, Poisson query stream, p50/p99 latency")
     ap.add_argument("--queries", type=int, default=40, help="stream length for --serve")
+    ap.add_argument("--qps", type=float, default=200.0, help="offered queries/s for --serve")
+    ap.add_argument("--streams", type=int, default=4, help="streams of the serving loop for --serve")
     return ap.parse_args()
 
 
@@ -106,11 +108,12 @@ def forms_bench():
     print(json.dumps({"forms": out}), flush=True)
 
 
-def serve_bench(nq):
+def serve_bench(nq, qps=200.0, streams=4):
     """The serving mix: three resident RMAT graphs (scale 18, 20, 22; 16
-    edges/vertex), a seeded Poisson stream at 200 queries/s of (random graph,
-    random 3-12-vertex Pruefer tree, k = t, 1-32 colourings), admission by a
-    200 GB table budget, four streams.  Latency = submit to result."""
+    edges/vertex), a seeded Poisson stream (200 queries/s by default) of
+    (random graph, random 3-12-vertex Pruefer tree, k = t, 1-32 colourings),
+    admission by a 200 GB table budget, four streams by default.  Latency =
+    submit to result."""
     import numpy as np
     from paper_1903_04395_amd import inputs as I
     from paper_1903_04395_amd import sc
@@ -127,12 +130,12 @@ def serve_bench(nq):
     qs = []
     t_arr = 0.0
     for i in range(nq):
-        t_arr += rng.exponential(1 / 200.0)
+        t_arr += rng.exponential(1 / qps)
         t = int(rng.integers(3, 13))
         qs.append(dict(at=t_arr, graph=int(rng.integers(0, 3)), t=t, edges=I.prufer_tree(t, 10_000 + i),
                        n=int(rng.integers(1, 33)), seed=int(rng.integers(0, 1 << 40))))
     tids = [ctx.load_template(q["t"], q["edges"]) for q in qs]
-    ctx.serve_start(mem_budget_bytes=200 * 10**9, max_inflight=4, max_batch=64)
+    ctx.serve_start(mem_budget_bytes=200 * 10**9, max_inflight=streams, max_batch=64)
     pending = {}
     results = []
     t0 = time.perf_counter()
@@ -158,12 +161,12 @@ def serve_bench(nq):
     lat = np.array([r["done_s"] - r["submit_s"] for r in results])
     span = max(r["done_s"] for r in results) - min(r["submit_s"] for r in results)
     ncol = sum(q["n"] for q in qs)
-    out = {"serving": {"queries": nq, "offered_qps": 200, "colorings": ncol,
+    out = {"serving": {"queries": nq, "offered_qps": qps, "colorings": ncol,
                        "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 1),
                        "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 1),
                        "colorings_per_s": round(ncol / span, 2), "queries_per_s": round(nq / span, 2),
                        "passes": int(stats["passes"]), "peak_table_GB": round(stats["peak_mem_bytes"] / 1e9, 1),
-                       "streams": 4, "budget_GB": 200}}
+                       "streams": streams, "budget_GB": 200}}
     ctx.close()
     print(json.dumps(out), flush=True)
 
@@ -304,7 +307,7 @@ def main():
         if args.forms:
             forms_bench()
         elif args.serve:
-            serve_bench(args.queries)
+            serve_bench(args.queries, args.qps, args.streams)
         else:
             configs_bench()
         return
