@@ -277,8 +277,12 @@ enum {
                                  follow the caller's vertex ids)               */
     SC_OPT_INTERLEAVE = 9,    /* cap on colourings interleaved per table plane:
                                  1, 2, 4, ..., 64 (0 = default, no cap)        */
-    SC_OPT_LDS_MAX = 10       /* LDS bytes per row-kernel workgroup,
+    SC_OPT_LDS_MAX = 10,      /* LDS bytes per row-kernel workgroup,
                                  16384..163840 (0 = default, 65536)            */
+    SC_OPT_WAVE_ROW_MAX = 11  /* steps whose per-row LDS is at most this many
+                                 bytes build one row per wavefront instead of
+                                 one per workgroup: 0..40960 (0 = never,
+                                 -1 = default, 8192)                          */
 };
 int sc_set_option(sc_ctx *ctx, int32_t option, int64_t value);
 int sc_get_option(sc_ctx *ctx, int32_t option, int64_t *value);

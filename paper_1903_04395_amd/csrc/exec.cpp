@@ -73,6 +73,7 @@ int step_args(sc_ctx *c, const Plan &P, const Step &s, kern::StepShape &sh, kern
     sh.Wh = (int)binom(k - 1, s.h - 1);
     sh.nsplit = (int)binom(s.h - 1, s.a - 1);
     sh.amode = s.amode;
+    sh.wave_row_max = P.opts.wave_row_max;
     int rc;
     if (s.a > 1 && (rc = get_split(c, k - 1, s.h - 1, s.a - 1, &tb.split))) return rc;
     if (s.p > 1) {
@@ -177,7 +178,8 @@ int launch_pass(sc_ctx *c, int gid, int tid, const PassSpec &s, PassBuffers &b, 
     host_desc[1] = s.first;
     HIPCHK(c, hipMemcpyAsync(b.desc.p, host_desc, 2 * sizeof(uint64_t), hipMemcpyHostToDevice, st));
     if (allow_graph && c->use_graph && !c->prof) {
-        GraphExecKey key{gid, tid, P.k, P.batch, P.interleave, P.opts.lds_max, s.g->seg, b.gen};
+        GraphExecKey key{gid, tid, P.k, P.batch, P.interleave, P.opts.lds_max, P.opts.wave_row_max,
+                         s.g->seg, b.gen};
         auto it = c->graph_cache.find(key);
         if (it == c->graph_cache.end()) {
             hipGraph_t graph = nullptr;

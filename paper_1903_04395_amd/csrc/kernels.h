@@ -48,6 +48,8 @@ struct StepShape {
     int Wh = 0;                        // binom(k-1, h-1): output row entries
     int nsplit = 0;                    // binom(h-1, a-1): split pairs per output entry
     int amode = kActiveLeaf;
+    int wave_row_max = 8192;           // per-row LDS bytes up to which each wavefront
+                                       // builds a row of its own (0: never)
 };
 
 // Host-built index tables of a step (device pointers).
@@ -65,8 +67,9 @@ struct StepTables {
 constexpr int kDirectRankBits = 12;
 int rank_entries(int k1);
 
-// Dynamic LDS bytes of the row and split kernels of a step.
-int dp_lds_bytes(const StepShape &s, int amode, int n_rank);
+// Dynamic LDS bytes of the row and split kernels of a step whose rows are
+// built by `teams` teams per workgroup (1: the workgroup; 4: one per wavefront).
+int dp_lds_bytes(const StepShape &s, int amode, int n_rank, int teams = 1);
 
 // col[v*B + r] = colour of vertex v in colouring first+r (SplitMix64 rule),
 // drawn from the original id perm[v] when the graph was relabelled (perm != NULL);

@@ -107,9 +107,36 @@ struct DpArgs {
     const int2 *items;            // split pre-pass: (row, segment)
     int64_t n_items;
     int seg;
-    int a_off, tab_off;           // LDS: staged active row (words), index tables (bytes)
+    int tab_off;                  // LDS byte offset of the index tables
     unsigned long long *flags;
 };
+
+// The threads that build one row: the whole workgroup (four wavefronts, the
+// row's neighbours split over them), or one wavefront on its own row.
+struct Team {
+    int wave, waves;      // this thread's wavefront within the team, wavefronts in the team
+    int tid, size;        // this thread within the team, threads in the team
+};
+
+__device__ __forceinline__ Team block_team() {
+    return Team{(int)(threadIdx.x >> 6), kWaves, (int)threadIdx.x, kBlock};
+}
+__device__ __forceinline__ Team wave_team() {
+    return Team{0, 1, (int)(threadIdx.x & (kWave - 1)), kWave};
+}
+
+// Orders the team's LDS accesses: a workgroup barrier, or for a single
+// wavefront (whose LDS operations complete in issue order) a fence that keeps
+// the compiler from moving LDS accesses across it.
+template <bool WAVE>
+__device__ __forceinline__ void team_sync() {
+    if constexpr (WAVE) {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    } else {
+        __syncthreads();
+    }
+}
 
 // Inserts a zero bit at position c (renumbered colours -> colours).
 __device__ __forceinline__ uint32_t widen_at(uint32_t m, int c) {
@@ -174,19 +201,20 @@ __device__ __forceinline__ void lane_masks(const DpArgs &a, const uint16_t *unr,
 // collide; adds of different wavefronts meet in LDS atomics, whose returned
 // old value gives the carry.
 template <int CH, int NB, bool BIG>
-__device__ __forceinline__ void scatter_wide(const DpArgs &a, int64_t v, int pl, int64_t e0,
+__device__ __forceinline__ void scatter_wide(const Team &tm, const DpArgs &a, int64_t v, int pl, int64_t e0,
                                              int64_t e1, uint64_t *Nl, const uint16_t *unr,
                                              const uint16_t *rk, const uint32_t (&rmsk)[CH],
                                              uint64_t &m) {
     const int lane = threadIdx.x & (kWave - 1);
-    const int wave = threadIdx.x >> 6;
+    const int wave = tm.wave;
+    const int waves = tm.waves;
     const int ri = lane & (a.Bi - 1);
     const int r = pl * a.Bi + ri;
     const int cv = a.col[v * a.B + r];
     const uint32_t vbit = 1u << cv;
     const int Lq = a.Wq * a.Bi;
     uint32_t carry = 0;
-    for (int64_t eb = e0 + wave; eb < e1; eb += (int64_t)kWaves * NB) {
+    for (int64_t eb = e0 + wave; eb < e1; eb += (int64_t)waves * NB) {
         for (int base = 0; base < (BIG ? Lq : 1); base += kWave * CH) {
             uint32_t msk[CH];
             if (BIG) lane_masks<CH>(a, unr, base, msk);
@@ -198,7 +226,7 @@ __device__ __forceinline__ void scatter_wide(const DpArgs &a, int64_t v, int pl,
             uint64_t x[NB][CH];
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
-                const int64_t e = eb + (int64_t)b * kWaves;
+                const int64_t e = eb + (int64_t)b * waves;
                 cu[b] = cv;                                // absent neighbour: skipped below
 #pragma unroll
                 for (int i = 0; i < CH; ++i) x[b][i] = 0;
@@ -234,22 +262,23 @@ __device__ __forceinline__ void scatter_wide(const DpArgs &a, int64_t v, int pl,
 
 // The same scatter for rounds of many narrow rows (NB >= 4).
 template <int CH, int NB, bool BIG>
-__device__ __forceinline__ void scatter_narrow(const DpArgs &a, int64_t v, int pl, int64_t e0,
+__device__ __forceinline__ void scatter_narrow(const Team &tm, const DpArgs &a, int64_t v, int pl, int64_t e0,
                                              int64_t e1, uint64_t *Nl, const uint16_t *unr,
                                              const uint16_t *rk, const uint32_t (&rmsk)[CH],
                                              uint64_t &m) {
     const int lane = threadIdx.x & (kWave - 1);
-    const int wave = threadIdx.x >> 6;
+    const int wave = tm.wave;
+    const int waves = tm.waves;
     const int ri = lane & (a.Bi - 1);
     const int r = pl * a.Bi + ri;
     const int cv = a.col[v * a.B + r];
     const uint32_t vbit = 1u << cv;
     const int Lq = a.Wq * a.Bi;
     uint32_t carry = 0;
-    for (int64_t eb = e0 + wave; eb < e1; eb += (int64_t)kWaves * NB) {
+    for (int64_t eb = e0 + wave; eb < e1; eb += (int64_t)waves * NB) {
         // lane b holds the b-th neighbour id of the round, broadcast to scalars
         int mine = -1;
-        const int64_t el = eb + (int64_t)lane * kWaves;
+        const int64_t el = eb + (int64_t)lane * waves;
         if (lane < NB && el < e1) mine = a.ci[el];
         int uid[NB];
 #pragma unroll
@@ -307,12 +336,13 @@ __device__ __forceinline__ void scatter_narrow(const DpArgs &a, int64_t v, int p
 // Groups of one wavefront may add to the same entry, so adds are LDS atomics
 // (carry from the returned old value).
 template <int U>
-__device__ __forceinline__ void scatter_groups(const DpArgs &a, int64_t v, int pl, int64_t e0,
+__device__ __forceinline__ void scatter_groups(const Team &tm, const DpArgs &a, int64_t v, int pl, int64_t e0,
                                                int64_t e1, uint64_t *Nl, const uint16_t *unr,
                                                const uint16_t *rk, uint64_t &m) {
     constexpr int kMaxW = 16;
     const int lane = threadIdx.x & (kWave - 1);
-    const int wave = threadIdx.x >> 6;
+    const int wave = tm.wave;
+    const int waves = tm.waves;
     const int ri = lane & (a.Bi - 1);
     const int grp = lane >> a.sh;
     const int groups = kWave >> a.sh;
@@ -320,11 +350,11 @@ __device__ __forceinline__ void scatter_groups(const DpArgs &a, int64_t v, int p
     const int cv = a.col[v * a.B + r];
     const uint32_t vbit = 1u << cv;
     const int Lq = a.Wq * a.Bi;
-    // neighbour e0 + wave + kWaves*(grp + groups*i): a short row spreads over
+    // neighbour e0 + wave + waves*(grp + groups*i): a short row spreads over
     // the wavefronts before it fills a wavefront's groups
-    const int64_t round = (int64_t)kWaves * groups;
+    const int64_t round = (int64_t)waves * groups;
     uint32_t carry = 0;
-    for (int64_t eb = e0 + wave + (int64_t)kWaves * grp; eb - (int64_t)kWaves * grp < e1; eb += round * U) {
+    for (int64_t eb = e0 + wave + (int64_t)waves * grp; eb - (int64_t)waves * grp < e1; eb += round * U) {
         int u[U], cu[U];
         uint64_t x[U][kMaxW];
 #pragma unroll
@@ -372,24 +402,24 @@ __device__ __forceinline__ void scatter_groups(const DpArgs &a, int64_t v, int p
 // rows keep fewer registers live instead.
 // CH == kGroupRows selects the lane-group scatter for rows of at most 16 sets.
 template <int CH, int NB, bool BIG>
-__device__ __forceinline__ void scatter_rows(const DpArgs &a, int64_t v, int pl, int64_t e0,
+__device__ __forceinline__ void scatter_rows(const Team &tm, const DpArgs &a, int64_t v, int pl, int64_t e0,
                                              int64_t e1, uint64_t *Nl, const uint16_t *unr,
                                              const uint16_t *rk, const uint32_t (&rmsk)[CH],
                                              uint64_t &m) {
-    if constexpr (CH == kGroupRows) scatter_groups<2>(a, v, pl, e0, e1, Nl, unr, rk, m);
-    else if constexpr (NB >= 4) scatter_narrow<CH, NB, BIG>(a, v, pl, e0, e1, Nl, unr, rk, rmsk, m);
-    else scatter_wide<CH, NB, BIG>(a, v, pl, e0, e1, Nl, unr, rk, rmsk, m);
+    if constexpr (CH == kGroupRows) scatter_groups<2>(tm, a, v, pl, e0, e1, Nl, unr, rk, m);
+    else if constexpr (NB >= 4) scatter_narrow<CH, NB, BIG>(tm, a, v, pl, e0, e1, Nl, unr, rk, rmsk, m);
+    else scatter_wide<CH, NB, BIG>(tm, a, v, pl, e0, e1, Nl, unr, rk, rmsk, m);
 }
 
 // p = 1: counts the colours of neighbours [e0, e1) of row v (plane pl): the
 // neighbour sum of single-vertex tables is N'[v][{x}] = #{u : col(u) = x}, x
 // renumbered among the colours other than col(v).  The block's threads are
 // (neighbour slot, colouring) pairs.
-__device__ __forceinline__ void count_colours(const DpArgs &a, int64_t v, int pl, int64_t e0,
-                                              int64_t e1, uint64_t *Nl) {
-    const int ri = threadIdx.x & (a.Bi - 1);
-    const int s = threadIdx.x >> a.sh;
-    const int slots = kBlock >> a.sh;
+__device__ __forceinline__ void count_colours(const Team &tm, const DpArgs &a, int64_t v, int pl,
+                                              int64_t e0, int64_t e1, uint64_t *Nl) {
+    const int ri = tm.tid & (a.Bi - 1);
+    const int s = tm.tid >> a.sh;
+    const int slots = tm.size >> a.sh;
     const int r = pl * a.Bi + ri;
     const int cv = a.col[v * a.B + r];
     for (int64_t e = e0 + s; e < e1; e += slots) {
@@ -412,21 +442,22 @@ __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t x, int mask) {
 // non-negative, so a carry in any partial sum or in their combination means
 // the exact sum reaches 2^64.
 template <int AM>
-__device__ __forceinline__ void emit_row(const DpArgs &a, int64_t v, int pl, const uint64_t *Nl,
-                                         const uint64_t *Al, const uint32_t *split, uint64_t &m) {
+__device__ __forceinline__ void emit_row(const Team &tm, const DpArgs &a, int64_t v, int pl,
+                                         const uint64_t *Nl, const uint64_t *Al, const uint32_t *split,
+                                         uint64_t &m) {
     const int Ls = a.Wh * a.Bi;
     uint64_t *out = a.S + ((int64_t)pl * a.n + v) * Ls;
     if (AM == kActiveLeaf) {
-        for (int q = threadIdx.x; q < Ls; q += kBlock) out[q] = Nl[q];
+        for (int q = tm.tid; q < Ls; q += tm.size) out[q] = Nl[q];
         return;
     }
     const uint64_t *Ar = AM == kActiveLds ? Al : a.A + ((int64_t)pl * a.n + v) * (int64_t)(a.Wa * a.Bi);
-    const int g = threadIdx.x & (a.eg - 1);
-    const int per = kBlock >> a.lg_eg;
+    const int g = tm.tid & (a.eg - 1);
+    const int per = tm.size >> a.lg_eg;
     const int step = a.eg;
     const bool lean = a.nsplit >= kMad3Pairs;      // uniform: the step's form of the product
     for (int q0 = 0; q0 < Ls; q0 += per) {          // uniform over the block
-        const int q = q0 + (threadIdx.x >> a.lg_eg);
+        const int q = q0 + (tm.tid >> a.lg_eg);
         const int D = q >> a.sh, ri = q & (a.Bi - 1);
         uint64_t acc = 0;
         uint32_t ovf = 0;
@@ -470,48 +501,55 @@ __device__ __forceinline__ void emit_row(const DpArgs &a, int64_t v, int pl, con
     }
 }
 
-// One workgroup per (plane, row) item, the grid striding over the items
-// (rows are sorted by descending degree, so every workgroup gets a similar
-// mix).  LDS: the neighbour-sum row N' (Wn * Bi), the staged active row
-// (Wa * Bi, AM == kActiveLds) and the index tables.  CH = 0: p = 1.
-template <int CH, int NB, bool BIG, int AM>
+// One team per (plane, row) item, the grid striding over the items (rows are
+// sorted by descending degree, so every team gets a similar mix).  The team is
+// the workgroup, or (WAVE) each of its four wavefronts on its own row, for
+// steps whose rows are small: a light row then needs no workgroup barrier and
+// four times as many rows are in flight.  LDS per team: the neighbour-sum row
+// N' (Wn * Bi) and the staged active row (Wa * Bi, AM == kActiveLds); then the
+// index tables, shared by the workgroup.  CH = 0: p = 1.
+template <int CH, int NB, bool BIG, int AM, bool WAVE>
 __global__ __launch_bounds__(kBlock) void dp_row_kernel(DpArgs a) {
     constexpr bool HIST = CH == 0;
     constexpr int C = HIST ? 1 : CH;
+    constexpr int kTeams = WAVE ? kWaves : 1;
     extern __shared__ uint64_t lds[];
-    uint64_t *Nl = lds;
-    uint64_t *Al = lds + a.a_off;
+    const Team tm = WAVE ? wave_team() : block_team();
+    const int Ln = a.Wn * a.Bi, La = a.Wa * a.Bi;
+    const int region = Ln + (AM == kActiveLds ? La : 0);
+    uint64_t *Nl = lds + (WAVE ? (int)(threadIdx.x >> 6) * region : 0);
+    uint64_t *Al = Nl + Ln;
     uint16_t *tab = (uint16_t *)((char *)lds + a.tab_off);
     uint32_t msk[C];
     stage_tables(a, tab);
     __syncthreads();
     if constexpr (!HIST && !BIG && CH != kGroupRows) lane_masks<C>(a, tab, 0, msk);
     const uint32_t *split = split_of(a, tab);
-    const int Ln = a.Wn * a.Bi, La = a.Wa * a.Bi;
     const int64_t total = a.n * a.planes;
     uint64_t m = 0;
-    for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
+    for (int64_t it = (int64_t)blockIdx.x * kTeams + (WAVE ? (int)(threadIdx.x >> 6) : 0); it < total;
+         it += (int64_t)gridDim.x * kTeams) {
         const int pl = (int)(it / a.n);
         const int64_t v = it - (int64_t)pl * a.n;
         const int sv = a.slot ? a.slot[v] : -1;
         if (sv >= 0) {
             const uint64_t *src = a.Npre + ((int64_t)pl * a.n_split + sv) * Ln;
-            for (int q = threadIdx.x; q < Ln; q += kBlock) Nl[q] = src[q];
+            for (int q = tm.tid; q < Ln; q += tm.size) Nl[q] = src[q];
         } else {
-            for (int q = threadIdx.x; q < Ln; q += kBlock) Nl[q] = 0;
+            for (int q = tm.tid; q < Ln; q += tm.size) Nl[q] = 0;
         }
         if (AM == kActiveLds) {
             const uint64_t *src = a.A + ((int64_t)pl * a.n + v) * La;
-            for (int q = threadIdx.x; q < La; q += kBlock) Al[q] = src[q];
+            for (int q = tm.tid; q < La; q += tm.size) Al[q] = src[q];
         }
-        __syncthreads();
+        team_sync<WAVE>();
         if (sv < 0) {
-            if constexpr (HIST) count_colours(a, v, pl, a.rp[v], a.rp[v + 1], Nl);
-            else scatter_rows<C, NB, BIG>(a, v, pl, a.rp[v], a.rp[v + 1], Nl, tab, tab + a.Wq, msk, m);
+            if constexpr (HIST) count_colours(tm, a, v, pl, a.rp[v], a.rp[v + 1], Nl);
+            else scatter_rows<C, NB, BIG>(tm, a, v, pl, a.rp[v], a.rp[v + 1], Nl, tab, tab + a.Wq, msk, m);
         }
-        __syncthreads();
-        emit_row<AM>(a, v, pl, Nl, Al, split, m);
-        __syncthreads();                         // LDS is reused by the next item
+        team_sync<WAVE>();
+        emit_row<AM>(tm, a, v, pl, Nl, Al, split, m);
+        team_sync<WAVE>();                       // LDS is reused by the next item
     }
     flush_flags(m, a.flags);
 }
@@ -544,8 +582,8 @@ __global__ __launch_bounds__(kBlock) void dp_split_kernel(DpArgs a) {
         const int64_t e1 = e0 + a.seg < r1 ? e0 + a.seg : r1;
         for (int q = threadIdx.x; q < Ln; q += kBlock) Nl[q] = 0;
         __syncthreads();
-        if constexpr (HIST) count_colours(a, v, pl, e0, e1, Nl);
-        else scatter_rows<C, NB, BIG>(a, v, pl, e0, e1, Nl, tab, tab + a.Wq, msk, m);
+        if constexpr (HIST) count_colours(block_team(), a, v, pl, e0, e1, Nl);
+        else scatter_rows<C, NB, BIG>(block_team(), a, v, pl, e0, e1, Nl, tab, tab + a.Wq, msk, m);
         __syncthreads();
         unsigned long long *dst =
             (unsigned long long *)a.Npre + ((int64_t)pl * a.n_split + a.slot[v]) * Ln;
@@ -632,7 +670,7 @@ int split_lds_words(const StepShape &s) {
 
 DpArgs make_args(const GraphBins &g, const StepShape &s, const StepTables &t, const uint8_t *col,
                  const uint64_t *P, const uint64_t *A, const uint64_t *Npre, uint64_t *S,
-                 unsigned long long *flags) {
+                 unsigned long long *flags, int teams) {
     DpArgs a{};
     a.rp = g.row_ptr; a.ci = g.col_idx; a.col = col; a.n = g.n;
     a.B = s.B; a.Bi = s.Bi; a.sh = log2_exact(s.Bi); a.planes = s.B / s.Bi;
@@ -642,10 +680,11 @@ DpArgs make_args(const GraphBins &g, const StepShape &s, const StepTables &t, co
     a.eg = 1; a.lg_eg = 0;
     {
         const int Ls = s.Wh * s.Bi;
+        const int threads = kBlock / teams;              // threads building one row
         int64_t best = -1;
         for (int lg = 0, G = 1; G <= kWave; ++lg, G *= 2) {
             if (G > 1 && G / 2 >= s.nsplit) break;
-            const int64_t rounds = (Ls + (kBlock / G) - 1) / (kBlock / G);
+            const int64_t rounds = (Ls + (threads / G) - 1) / (threads / G);
             const int64_t chain = rounds * (((int64_t)s.nsplit + G - 1) / G + 2 * lg);
             if (best < 0 || chain < best) { best = chain; a.eg = G; a.lg_eg = lg; }
         }
@@ -655,19 +694,19 @@ DpArgs make_args(const GraphBins &g, const StepShape &s, const StepTables &t, co
     a.P = P; a.A = A; a.S = S; a.Npre = const_cast<uint64_t *>(Npre);
     a.slot = g.n_split ? g.slot : nullptr; a.n_split = g.n_split;
     a.items = g.split_items; a.n_items = g.n_split_items; a.seg = g.seg;
-    a.a_off = s.Wn * s.Bi;
-    a.tab_off = 8 * (s.Wn * s.Bi + (s.amode == kActiveLds ? s.Wa * s.Bi : 0));
+    a.tab_off = 8 * teams * (s.Wn * s.Bi + (s.amode == kActiveLds ? s.Wa * s.Bi : 0));
     a.split_lds = s.amode != kActiveLeaf && split_lds_words(s) > 0;
     a.flags = flags;
     return a;
 }
 
-template <int CH, int NB, bool BIG, int AM>
+template <int CH, int NB, bool BIG, int AM, bool WAVE>
 hipError_t row_launch(const DpArgs &a, int lds, hipStream_t st) {
-    hipError_t e = allow_lds(dp_row_kernel<CH, NB, BIG, AM>, lds);
+    hipError_t e = allow_lds(dp_row_kernel<CH, NB, BIG, AM, WAVE>, lds);
     if (e != hipSuccess) return e;
-    const int64_t blocks = std::min<int64_t>(a.n * a.planes, 2 * resident_blocks(lds));
-    dp_row_kernel<CH, NB, BIG, AM><<<dim3((unsigned)blocks), dim3(kBlock), lds, st>>>(a);
+    const int64_t teams = WAVE ? kWaves : 1;
+    const int64_t blocks = std::min<int64_t>((a.n * a.planes + teams - 1) / teams, 2 * resident_blocks(lds));
+    dp_row_kernel<CH, NB, BIG, AM, WAVE><<<dim3((unsigned)blocks), dim3(kBlock), lds, st>>>(a);
     return hipGetLastError();
 }
 
@@ -695,16 +734,16 @@ int row_chunks(const StepShape &s, bool groups) {
 
 // The row kernels keep the chunked scatter for narrow rows too: a light row's
 // few neighbours spread over more lanes that way.
-template <int AM>
+template <int AM, bool WAVE>
 hipError_t row_dispatch(const StepShape &s, const DpArgs &a, int lds, hipStream_t st) {
     switch (row_chunks(s, false)) {
-    case 0: return row_launch<0, 1, false, AM>(a, lds, st);
-    case 1: return row_launch<1, 8, false, AM>(a, lds, st);
-    case 2: return row_launch<2, 8, false, AM>(a, lds, st);
-    case 4: return row_launch<4, 4, false, AM>(a, lds, st);
-    case 8: return row_launch<8, 2, false, AM>(a, lds, st);
-    case 16: return row_launch<16, 1, false, AM>(a, lds, st);
-    default: return row_launch<16, 1, true, AM>(a, lds, st);
+    case 0: return row_launch<0, 1, false, AM, WAVE>(a, lds, st);
+    case 1: return row_launch<1, 8, false, AM, WAVE>(a, lds, st);
+    case 2: return row_launch<2, 8, false, AM, WAVE>(a, lds, st);
+    case 4: return row_launch<4, 4, false, AM, WAVE>(a, lds, st);
+    case 8: return row_launch<8, 2, false, AM, WAVE>(a, lds, st);
+    case 16: return row_launch<16, 1, false, AM, WAVE>(a, lds, st);
+    default: return row_launch<16, 1, true, AM, WAVE>(a, lds, st);
     }
 }
 
@@ -730,9 +769,10 @@ bool shape_ok(const StepShape &s) {
 
 int rank_entries(int k1) { return k1 <= kDirectRankBits ? 1 << k1 : 256 + 9 * (1 << (k1 - 8)); }
 
-int dp_lds_bytes(const StepShape &s, int amode, int n_rank) {
+int dp_lds_bytes(const StepShape &s, int amode, int n_rank, int teams) {
     int64_t bytes = 8LL * s.Wn * s.Bi;
     if (amode == kActiveLds) bytes += 8LL * s.Wa * s.Bi;
+    bytes *= teams;
     const int64_t nt = s.p >= 2 ? s.Wq + n_rank : 0;
     bytes += 2LL * ((nt + 1) & ~1LL);
     StepShape s2 = s;
@@ -767,8 +807,8 @@ hipError_t launch_dp_split(const GraphBins &g, const StepShape &s, const StepTab
     if (e != hipSuccess) return e;
     StepShape s1 = s;
     s1.amode = kActiveLeaf;                            // the pre-pass stages no active row or split table
-    const DpArgs a = make_args(g, s1, t, col, P, nullptr, Npre, nullptr, flags);
-    const int lds = dp_lds_bytes(s1, kActiveLeaf, t.n_rank);
+    const DpArgs a = make_args(g, s1, t, col, P, nullptr, Npre, nullptr, flags, 1);
+    const int lds = dp_lds_bytes(s1, kActiveLeaf, t.n_rank, 1);
     return split_dispatch(s1, a, lds, st);
 }
 
@@ -780,11 +820,20 @@ hipError_t launch_dp_row(const GraphBins &g, const StepShape &s, const StepTable
     if (!shape_ok(s) || !S || (s.p >= 2 && (!P || !t.unrank || !t.rank)) ||
         (s.amode != kActiveLeaf && (!A || !t.split)) || (g.n_split && !Npre))
         return hipErrorInvalidValue;
-    const DpArgs a = make_args(g, s, t, col, P, A, Npre, S, flags);
-    const int lds = dp_lds_bytes(s, s.amode, t.n_rank);
-    if (s.amode == kActiveLeaf) return row_dispatch<kActiveLeaf>(s, a, lds, st);
-    if (s.amode == kActiveLds) return row_dispatch<kActiveLds>(s, a, lds, st);
-    return row_dispatch<kActiveGlobal>(s, a, lds, st);
+    // steps whose per-row LDS is small run one row per wavefront
+    const int region = 8 * (s.Wn * s.Bi + (s.amode == kActiveLds ? s.Wa * s.Bi : 0));
+    const bool wave = region <= s.wave_row_max;
+    const int teams = wave ? kWaves : 1;
+    const DpArgs a = make_args(g, s, t, col, P, A, Npre, S, flags, teams);
+    const int lds = dp_lds_bytes(s, s.amode, t.n_rank, teams);
+    if (wave) {
+        if (s.amode == kActiveLeaf) return row_dispatch<kActiveLeaf, true>(s, a, lds, st);
+        if (s.amode == kActiveLds) return row_dispatch<kActiveLds, true>(s, a, lds, st);
+        return row_dispatch<kActiveGlobal, true>(s, a, lds, st);
+    }
+    if (s.amode == kActiveLeaf) return row_dispatch<kActiveLeaf, false>(s, a, lds, st);
+    if (s.amode == kActiveLds) return row_dispatch<kActiveLds, false>(s, a, lds, st);
+    return row_dispatch<kActiveGlobal, false>(s, a, lds, st);
 }
 
 hipError_t launch_reduce(int64_t n, const uint64_t *S, int W, int B, int Bi,

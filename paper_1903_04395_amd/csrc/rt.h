@@ -78,11 +78,12 @@ struct PassBuffers {
 };
 
 struct GraphExecKey {
-    int graph_id, tmpl_id, k, batch, interleave, lds_max, seg;
+    int graph_id, tmpl_id, k, batch, interleave, lds_max, wave_row_max, seg;
     uint64_t bufgen;
     bool operator<(const GraphExecKey &o) const {
-        return std::tie(graph_id, tmpl_id, k, batch, interleave, lds_max, seg, bufgen) <
-               std::tie(o.graph_id, o.tmpl_id, o.k, o.batch, o.interleave, o.lds_max, o.seg, o.bufgen);
+        return std::tie(graph_id, tmpl_id, k, batch, interleave, lds_max, wave_row_max, seg, bufgen) <
+               std::tie(o.graph_id, o.tmpl_id, o.k, o.batch, o.interleave, o.lds_max, o.wave_row_max, o.seg,
+                        o.bufgen);
     }
 };
 
@@ -111,7 +112,7 @@ struct sc_ctx {
     std::map<sc::TuneKey, sc::Tuned> tuned;
     // options
     int64_t max_batch = SC_MAX_BATCH, use_graph = 0, segment = 0;
-    int64_t interleave = 0, lds_max = 0, reorder = 1;
+    int64_t interleave = 0, lds_max = 0, wave_row_max = -1, reorder = 1;
     // tracing
     bool prof = false;
     struct Rec { const char *name; hipEvent_t a, b; double bytes, updates; };

@@ -169,6 +169,7 @@ ExecOpts exec_opts(const sc_ctx *c, int gid, int tid, int k, int batch) {
     ExecOpts o;
     o.interleave = (int)c->interleave;
     if (c->lds_max > 0) o.lds_max = (int)c->lds_max;
+    if (c->wave_row_max >= 0) o.wave_row_max = (int)c->wave_row_max;
     auto it = c->tuned.find(TuneKey{gid, tid, k, batch});
     if (it != c->tuned.end()) {
         if (it->second.interleave > 0) o.interleave = it->second.interleave;
@@ -452,6 +453,9 @@ int sc_set_option(sc_ctx *c, int32_t opt, int64_t v) {
     case SC_OPT_LDS_MAX:
         if (v != 0 && (v < 16384 || v > 163840)) return fail(c, SC_EINVAL, "LDS limit must be 0 or in [16384, 163840]");
         c->lds_max = v; return SC_OK;
+    case SC_OPT_WAVE_ROW_MAX:
+        if (v < -1 || v > 40960) return fail(c, SC_EINVAL, "wave row limit must be -1 (default) or in [0, 40960]");
+        c->wave_row_max = v; return SC_OK;
     case SC_OPT_REORDER: c->reorder = v != 0; return SC_OK;
     default: return fail(c, SC_EINVAL, "unknown option %d", opt);
     }
@@ -466,6 +470,7 @@ int sc_get_option(sc_ctx *c, int32_t opt, int64_t *v) {
     case SC_OPT_SEGMENT: *v = default_segment(c); return SC_OK;
     case SC_OPT_INTERLEAVE: *v = c->interleave; return SC_OK;
     case SC_OPT_LDS_MAX: *v = c->lds_max > 0 ? c->lds_max : ExecOpts().lds_max; return SC_OK;
+    case SC_OPT_WAVE_ROW_MAX: *v = c->wave_row_max >= 0 ? c->wave_row_max : ExecOpts().wave_row_max; return SC_OK;
     case SC_OPT_REORDER: *v = c->reorder; return SC_OK;
     default: return fail(c, SC_EINVAL, "unknown option %d", opt);
     }

@@ -31,6 +31,7 @@ enum ActiveMode { kActLeaf = 0, kActLds = 1, kActGlobal = 2 };
 struct ExecOpts {
     int interleave = 0;        // cap on colourings interleaved per plane (0: no cap)
     int lds_max = 64 * 1024;   // LDS bytes a row kernel may use
+    int wave_row_max = 8192;   // per-row LDS bytes up to which a wavefront builds a row alone
 };
 
 // One DP step: attach the subtree of `child` (passive, size p) to what `node`

@@ -15,7 +15,7 @@ import numpy as np
 __all__ = [
     "SC_OK", "SC_EINVAL", "SC_ENOMEM", "SC_EDEVICE", "SC_ENOTFOUND", "SC_EBUSY", "SC_ESTATE",
     "SC_OPT_MAX_BATCH", "SC_OPT_GRAPH", "SC_OPT_SEGMENT", "SC_OPT_REORDER", "SC_OPT_INTERLEAVE",
-    "SC_OPT_LDS_MAX", "OPTION_DEFAULTS", "ScError", "PlanInfo", "KernelStat",
+    "SC_OPT_LDS_MAX", "SC_OPT_WAVE_ROW_MAX", "OPTION_DEFAULTS", "ScError", "PlanInfo", "KernelStat",
     "Job", "Tune", "ServeCfg", "Query", "Result", "ServeStats", "lib", "lib_path", "sc_version",
     "sc_plan_template",
     "sc_colorset_rank", "sc_color_of", "Context",
@@ -23,7 +23,7 @@ __all__ = [
 
 SC_OK, SC_EINVAL, SC_ENOMEM, SC_EDEVICE, SC_ENOTFOUND, SC_EBUSY, SC_ESTATE = 0, -1, -2, -3, -4, -5, -6
 SC_OPT_MAX_BATCH, SC_OPT_GRAPH, SC_OPT_SEGMENT, SC_OPT_REORDER = 1, 3, 5, 8
-SC_OPT_INTERLEAVE, SC_OPT_LDS_MAX = 9, 10
+SC_OPT_INTERLEAVE, SC_OPT_LDS_MAX, SC_OPT_WAVE_ROW_MAX = 9, 10, 11
 SC_MAX_T = 16
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -91,7 +91,7 @@ class KernelStat(ctypes.Structure):
 
 
 OPTION_DEFAULTS = {SC_OPT_MAX_BATCH: 64, SC_OPT_GRAPH: 0, SC_OPT_SEGMENT: 0, SC_OPT_REORDER: 1,
-                   SC_OPT_INTERLEAVE: 0, SC_OPT_LDS_MAX: 0}
+                   SC_OPT_INTERLEAVE: 0, SC_OPT_LDS_MAX: 0, SC_OPT_WAVE_ROW_MAX: -1}
 
 
 class Job(ctypes.Structure):
