@@ -271,7 +271,7 @@ enum {
     SC_OPT_MAX_BATCH = 1,     /* cap on colourings per pass (1..SC_MAX_BATCH)   */
     SC_OPT_GRAPH = 3,         /* 1: replay each pass from a captured hipGraph   */
     SC_OPT_SEGMENT = 5,       /* neighbours per work item of heavy rows, > 64
-                                 (0 = default, 256)                            */
+                                 (0 = default, 512)                            */
     SC_OPT_REORDER = 8,       /* 1 (default): graphs loaded afterwards are kept
                                  relabelled by descending degree (colours still
                                  follow the caller's vertex ids)               */

@@ -79,7 +79,7 @@ int host_staging(sc_ctx *c, size_t words) {
     return SC_OK;
 }
 
-int default_segment(const sc_ctx *c) { return c->segment > 0 ? (int)c->segment : 256; }
+int default_segment(const sc_ctx *c) { return c->segment > 0 ? (int)c->segment : 512; }
 
 // Rows with more than `seg` neighbours ("split rows"): their (row, segment)
 // items and the compact slot of every split row for precomputed neighbour sums.
