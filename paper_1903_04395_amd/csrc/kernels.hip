@@ -40,6 +40,7 @@ constexpr int kMaxBlocksPerCU = 8;    // 32 wavefronts of 4-wave workgroups
 constexpr int kLdsPerCU = 160 * 1024;
 constexpr int kSplitLdsMax = 4096;    // split-table entries staged in LDS (16 KB)
 constexpr int kGroupRows = 3;         // chunk-count tag of the lane-group scatter
+constexpr int64_t kWaveRowsMin = (int64_t)kCUs * kMaxBlocksPerCU * kWaves * 4;
 constexpr int kMad3Pairs = 32;        // split pairs per entry from which the three-multiply
                                       // product is used (vector-ALU-bound multiply-adds)
 
@@ -820,9 +821,11 @@ hipError_t launch_dp_row(const GraphBins &g, const StepShape &s, const StepTable
     if (!shape_ok(s) || !S || (s.p >= 2 && (!P || !t.unrank || !t.rank)) ||
         (s.amode != kActiveLeaf && (!A || !t.split)) || (g.n_split && !Npre))
         return hipErrorInvalidValue;
-    // steps whose per-row LDS is small run one row per wavefront
+    // steps whose per-row LDS is small run one row per wavefront, when there
+    // are enough rows to keep every wavefront slot of the chip busy (on a
+    // small graph a row's latency matters more than the rows in flight)
     const int region = 8 * (s.Wn * s.Bi + (s.amode == kActiveLds ? s.Wa * s.Bi : 0));
-    const bool wave = region <= s.wave_row_max;
+    const bool wave = region <= s.wave_row_max && g.n * (s.B / s.Bi) >= kWaveRowsMin;
     const int teams = wave ? kWaves : 1;
     const DpArgs a = make_args(g, s, t, col, P, A, Npre, S, flags, teams);
     const int lds = dp_lds_bytes(s, s.amode, t.n_rank, teams);

@@ -136,12 +136,15 @@ def test_interleave_and_lds_limits_agree(ctx, inter, lds):
              opts={sc.SC_OPT_INTERLEAVE: inter, sc.SC_OPT_LDS_MAX: lds})
 
 
-@pytest.mark.parametrize("wave_rows", [0, 40960])
-def test_row_per_workgroup_or_per_wavefront_agree(ctx, wave_rows):
+@pytest.mark.parametrize("wave_rows,scale,inter", [(0, 16, 0), (40960, 16, 0), (40960, 13, 1)])
+def test_row_per_workgroup_or_per_wavefront_agree(ctx, wave_rows, scale, inter):
     """Every step built with one row per workgroup (0), or with one row per
-    wavefront wherever the row fits (40960 bytes)."""
-    g = I.rmat(11, 16, seed=13)
-    run_both(ctx, g, 10, I.prufer_tree(10, 13), 10, 14, 0, 8, opts={sc.SC_OPT_WAVE_ROW_MAX: wave_rows})
+    wavefront wherever the row fits (40960 bytes).  Rows per wavefront need
+    enough (plane, row) items to fill the chip: RMAT-16 with 8 interleaved
+    colourings, or RMAT-13 with 8 planes of one."""
+    g = I.rmat(scale, 16, seed=13)
+    run_both(ctx, g, 10, I.prufer_tree(10, 13), 10, 14, 0, 8,
+             opts={sc.SC_OPT_WAVE_ROW_MAX: wave_rows, sc.SC_OPT_INTERLEAVE: inter})
 
 
 # ------------------------------------------------------------------ overflow and edge cases
