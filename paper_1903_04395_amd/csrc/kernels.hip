@@ -40,6 +40,8 @@ constexpr int kMaxBlocksPerCU = 8;    // 32 wavefronts of 4-wave workgroups
 constexpr int kLdsPerCU = 160 * 1024;
 constexpr int kSplitLdsMax = 4096;    // split-table entries staged in LDS (16 KB)
 constexpr int kGroupRows = 3;         // chunk-count tag of the lane-group scatter
+// (plane, row) items a step needs before it builds rows one per wavefront:
+// four per wavefront slot of the chip
 constexpr int64_t kWaveRowsMin = (int64_t)kCUs * kMaxBlocksPerCU * kWaves * 4;
 constexpr int kMad3Pairs = 32;        // split pairs per entry from which the three-multiply
                                       // product is used (vector-ALU-bound multiply-adds)
@@ -191,10 +193,10 @@ __device__ __forceinline__ void lane_masks(const DpArgs &a, const uint16_t *unr,
 }
 
 // p >= 2: scatters the passive rows of neighbours [e0, e1) of row v (plane pl)
-// into the LDS neighbour sum Nl.  Wavefront w takes neighbours e0 + w, e0 +
-// w + 4, ...; it loads NB neighbours' rows at a time, CH chunks of 64
-// contiguous uint64 each (NB * CH = 16 loads in flight per lane), and rows
-// wider than CH chunks (BIG) are walked in groups of CH chunks.  Lane `ri` of
+// into the LDS neighbour sum Nl.  Wavefront w of a team of W wavefronts takes
+// neighbours e0 + w, e0 + w + W, ...; it loads NB neighbours' rows at a time,
+// CH chunks of 64 contiguous uint64 each (NB * CH = 16 loads in flight per
+// lane), and rows wider than CH chunks (BIG) are walked in groups of CH chunks.  Lane `ri` of
 // every group of Bi lanes serves colouring pl*Bi + ri.  Each entry {col(u)} +
 // T of a neighbour u lands on v's entry for the same set, re-ranked among the
 // colours other than col(v); sets holding col(v) are skipped.  Distinct
@@ -261,7 +263,10 @@ __device__ __forceinline__ void scatter_wide(const Team &tm, const DpArgs &a, in
     if (carry) m |= 1ull << r;
 }
 
-// The same scatter for rounds of many narrow rows (NB >= 4).
+// The same scatter for rounds of many narrow rows (NB >= 4): the round's
+// neighbour ids come in one load, every colour and row load of the round is
+// issued before any is used, and the carries of up to eight adds are read
+// together.
 template <int CH, int NB, bool BIG>
 __device__ __forceinline__ void scatter_narrow(const Team &tm, const DpArgs &a, int64_t v, int pl, int64_t e0,
                                              int64_t e1, uint64_t *Nl, const uint16_t *unr,
@@ -414,7 +419,7 @@ __device__ __forceinline__ void scatter_rows(const Team &tm, const DpArgs &a, in
 
 // p = 1: counts the colours of neighbours [e0, e1) of row v (plane pl): the
 // neighbour sum of single-vertex tables is N'[v][{x}] = #{u : col(u) = x}, x
-// renumbered among the colours other than col(v).  The block's threads are
+// renumbered among the colours other than col(v).  The team's threads are
 // (neighbour slot, colouring) pairs.
 __device__ __forceinline__ void count_colours(const Team &tm, const DpArgs &a, int64_t v, int pl,
                                               int64_t e0, int64_t e1, uint64_t *Nl) {
