@@ -40,6 +40,12 @@
  * an input: the residue X mod 2^64 does not depend on it, but the flag does,
  * because the intermediate tables do.
  *
+ * The same DP also runs modulo an odd modulus m < 2^63 (products through
+ * 128-bit integers): the map from integers to residues mod m is a ring
+ * homomorphism and the DP uses only + and *, so this gives X mod m.  Residues
+ * modulo 2^64 and modulo pairwise coprime primes determine X by the Chinese
+ * remainder theorem whenever X is below the product of the moduli.
+ *
  * Plan format: `child_ptr[t+1]`, `child_idx[t-1]` list, for each template
  * vertex u, its children in attach order (CSR); `root` is the root vertex.
  */
@@ -120,7 +126,19 @@ typedef struct {
     int flag;               /* sticky overflow flag */
     int unpruned;           /* 1: Algorithm-1 order (neighbour loop inside) */
     int oom;
+    uint64_t mod;           /* 0: arithmetic mod 2^64 with the flag; else mod this odd m < 2^63 */
 } octx;
+
+static uint64_t addm(const octx *c, uint64_t a, uint64_t b)
+{
+    uint64_t s = a + b;                         /* a, b < m < 2^63: no wrap */
+    return s >= c->mod ? s - c->mod : s;
+}
+
+static uint64_t mulm(const octx *c, uint64_t a, uint64_t b)
+{
+    return (uint64_t)(((u128)a * (u128)b) % (u128)c->mod);
+}
 
 static int popc(uint32_t x) { return __builtin_popcount(x); }
 
@@ -180,6 +198,10 @@ static uint64_t *neighbour_sum(octx *c, const uint64_t *P, int p)
         for (int64_t q = 0; q < Wp; ++q) row[q] = 0;
         for (int64_t e = c->rp[v]; e < c->rp[v + 1]; ++e) {
             const uint64_t *src = P + (int64_t)c->ci[e] * Wp;
+            if (c->mod) {
+                for (int64_t q = 0; q < Wp; ++q) row[q] = addm(c, row[q], src[q]);
+                continue;
+            }
             for (int64_t q = 0; q < Wp; ++q)
                 if (__builtin_add_overflow(row[q], src[q], &row[q]) && !(sets[q] & own)) flag = 1;
         }
@@ -207,6 +229,10 @@ static uint64_t *combine(octx *c, const uint64_t *Ma, int a, const uint64_t *N, 
         const uint64_t *rn = N + v * Wp;
         uint64_t *rs = S + v * Ws;
         for (int64_t q = 0; q < cnt; ++q) {
+            if (c->mod) {
+                rs[L[q].s] = addm(c, rs[L[q].s], mulm(c, ra[L[q].a], rn[L[q].p]));
+                continue;
+            }
             uint64_t prod;
             flag |= __builtin_mul_overflow(ra[L[q].a], rn[L[q].p], &prod);
             flag |= __builtin_add_overflow(rs[L[q].s], prod, &rs[L[q].s]);
@@ -283,7 +309,7 @@ static int setup(octx *c, int64_t n, const int64_t *rp, const int32_t *ci, int k
     if (k < 1 || k > OR_MAXK) return -1;
     c->n = n; c->rp = rp; c->ci = ci; c->k = k; c->col = col;
     c->child_ptr = child_ptr; c->child_idx = child_idx;
-    c->flag = 0; c->unpruned = 0; c->oom = 0;
+    c->flag = 0; c->unpruned = 0; c->oom = 0; c->mod = 0;
     c->rank = malloc(sizeof(int32_t) << k);
     if (!c->rank) return -2;
     for (uint32_t m = 0; m < (1u << k); ++m) c->rank[m] = (int32_t)oracle_rank(m);
@@ -313,16 +339,19 @@ int oracle_root_table(int64_t n, const int64_t *rp, const int32_t *ci, int t, in
     return 0;
 }
 
-/* X = sum_v sum_{|C|=t} M_root[v][C] for one explicit colouring. */
-int oracle_count_colored(int64_t n, const int64_t *rp, const int32_t *ci, int t, int root,
+/* X = sum_v sum_{|C|=t} M_root[v][C] for one explicit colouring, modulo 2^64
+ * (mod = 0, with the flag) or modulo the odd modulus `mod` < 2^63. */
+static int count_colored(int64_t n, const int64_t *rp, const int32_t *ci, int t, int root,
                          const int32_t *child_ptr, const int32_t *child_idx, int k,
-                         const uint8_t *col, int unpruned, uint64_t *count, int *flag)
+                         const uint8_t *col, int unpruned, uint64_t mod, uint64_t *count, int *flag)
 {
     octx c;
     if (t < 1 || t > k) return -1;
+    if (mod && (mod % 2 == 0 || mod >= (1ULL << 63))) return -1;
     int rc = setup(&c, n, rp, ci, k, col, child_ptr, child_idx);
     if (rc) return rc;
     c.unpruned = unpruned;
+    c.mod = mod;
     int size;
     uint64_t *M = subtree_table(&c, root, &size);
     free(c.rank);
@@ -331,28 +360,61 @@ int oracle_count_colored(int64_t n, const int64_t *rp, const int32_t *ci, int t,
     int64_t W = (int64_t)binom(k, t);
     uint64_t X = 0;
     int f = c.flag;
-    for (int64_t q = 0; q < n * W; ++q) f |= __builtin_add_overflow(X, M[q], &X);
+    for (int64_t q = 0; q < n * W; ++q) {
+        if (mod) X = addm(&c, X, M[q]);
+        else f |= __builtin_add_overflow(X, M[q], &X);
+    }
     free(M);
     *count = X;
-    *flag = f;
+    *flag = mod ? 0 : f;
     return 0;
 }
 
-/* Colourings first .. first+R-1 from the SplitMix64 colouring rule above. */
-int oracle_count(int64_t n, const int64_t *rp, const int32_t *ci, int t, int root,
-                 const int32_t *child_ptr, const int32_t *child_idx, int k, uint64_t seed,
-                 uint64_t first, int32_t R, uint64_t *counts, uint8_t *flags)
+int oracle_count_colored(int64_t n, const int64_t *rp, const int32_t *ci, int t, int root,
+                         const int32_t *child_ptr, const int32_t *child_idx, int k,
+                         const uint8_t *col, int unpruned, uint64_t *count, int *flag)
+{
+    return count_colored(n, rp, ci, t, root, child_ptr, child_idx, k, col, unpruned, 0, count, flag);
+}
+
+/* X mod `mod` (odd, < 2^63) for one explicit colouring. */
+int oracle_count_colored_mod(int64_t n, const int64_t *rp, const int32_t *ci, int t, int root,
+                             const int32_t *child_ptr, const int32_t *child_idx, int k,
+                             const uint8_t *col, uint64_t mod, uint64_t *count)
+{
+    int flag;
+    return count_colored(n, rp, ci, t, root, child_ptr, child_idx, k, col, 0, mod, count, &flag);
+}
+
+/* Colourings first .. first+R-1 from the SplitMix64 colouring rule above;
+ * mod = 0: residues mod 2^64 and flags, else residues mod `mod` (flags 0). */
+static int count_range(int64_t n, const int64_t *rp, const int32_t *ci, int t, int root,
+                       const int32_t *child_ptr, const int32_t *child_idx, int k, uint64_t seed,
+                       uint64_t first, int32_t R, uint64_t mod, uint64_t *counts, uint8_t *flags)
 {
     uint8_t *col = malloc((size_t)(n ? n : 1));
     if (!col) return -2;
     for (int32_t r = 0; r < R; ++r) {
         oracle_colors(seed, first + (uint64_t)r, n, k, col);
         int f;
-        int rc = oracle_count_colored(n, rp, ci, t, root, child_ptr, child_idx, k, col, 0,
-                                      &counts[r], &f);
+        int rc = count_colored(n, rp, ci, t, root, child_ptr, child_idx, k, col, 0, mod, &counts[r], &f);
         if (rc) { free(col); return rc; }
-        flags[r] = (uint8_t)f;
+        if (flags) flags[r] = (uint8_t)f;
     }
     free(col);
     return 0;
+}
+
+int oracle_count(int64_t n, const int64_t *rp, const int32_t *ci, int t, int root,
+                 const int32_t *child_ptr, const int32_t *child_idx, int k, uint64_t seed,
+                 uint64_t first, int32_t R, uint64_t *counts, uint8_t *flags)
+{
+    return count_range(n, rp, ci, t, root, child_ptr, child_idx, k, seed, first, R, 0, counts, flags);
+}
+
+int oracle_count_mod(int64_t n, const int64_t *rp, const int32_t *ci, int t, int root,
+                     const int32_t *child_ptr, const int32_t *child_idx, int k, uint64_t seed,
+                     uint64_t first, int32_t R, uint64_t mod, uint64_t *counts)
+{
+    return count_range(n, rp, ci, t, root, child_ptr, child_idx, k, seed, first, R, mod, counts, NULL);
 }

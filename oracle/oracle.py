@@ -28,7 +28,8 @@ import numpy as np
 __all__ = [
     "lib", "splitmix64", "color", "colors", "rank", "plan_arrays", "root_plan",
     "count", "count_colored", "root_table", "aut", "colorful_probability",
-    "estimate", "binom", "threads",
+    "estimate", "binom", "threads", "count_colored_mod", "count_mod", "PRIMES", "crt",
+    "count_exact",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -65,6 +66,11 @@ def lib():
         L.oracle_count_colored.argtypes = common + [_u8p, ctypes.c_int, _u64p, ctypes.POINTER(ctypes.c_int)]
         L.oracle_count.restype = ctypes.c_int
         L.oracle_count.argtypes = common + [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int32, _u64p, _u8p]
+        L.oracle_count_colored_mod.restype = ctypes.c_int
+        L.oracle_count_colored_mod.argtypes = common + [_u8p, ctypes.c_uint64, _u64p]
+        L.oracle_count_mod.restype = ctypes.c_int
+        L.oracle_count_mod.argtypes = common + [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int32,
+                                                ctypes.c_uint64, _u64p]
         _lib = L
     return _lib
 
@@ -204,6 +210,61 @@ def count(g, t: int, plan, k: int, seed: int, first: int, R: int):
     if rc:
         raise RuntimeError(f"oracle_count failed ({rc})")
     return counts[:R], flags[:R]
+
+
+def count_colored_mod(g, t: int, plan, k: int, col, mod: int) -> int:
+    """X mod `mod` (odd, < 2^63) for one explicit colouring."""
+    root, children = plan
+    root, ptr, idx = plan_arrays(t, root, children)
+    rp, ci = _csr_args(g)
+    col = np.ascontiguousarray(col, dtype=np.uint8)
+    if col.size == 0:
+        col = np.zeros(1, np.uint8)
+    X = ctypes.c_uint64(0)
+    rc = lib().oracle_count_colored_mod(g.n, _ptr(rp, _i64p), _ptr(ci, _i32p), t, root,
+                                        _ptr(ptr, _i32p), _ptr(idx, _i32p), k, _ptr(col, _u8p),
+                                        mod, ctypes.byref(X))
+    if rc:
+        raise RuntimeError(f"oracle_count_colored_mod failed ({rc})")
+    return int(X.value)
+
+
+def count_mod(g, t: int, plan, k: int, seed: int, first: int, R: int, mod: int):
+    """Per-colouring residues mod `mod` (odd, < 2^63) for colourings first..first+R-1."""
+    root, children = plan
+    root, ptr, idx = plan_arrays(t, root, children)
+    rp, ci = _csr_args(g)
+    counts = np.zeros(max(R, 1), dtype=np.uint64)
+    rc = lib().oracle_count_mod(g.n, _ptr(rp, _i64p), _ptr(ci, _i32p), t, root,
+                                _ptr(ptr, _i32p), _ptr(idx, _i32p), k,
+                                seed & (2**64 - 1), first, R, mod, _ptr(counts, _u64p))
+    if rc:
+        raise RuntimeError(f"oracle_count_mod failed ({rc})")
+    return counts[:R]
+
+
+# Odd primes below 2^63 that serve as extra moduli beside 2^64.
+PRIMES = (2**61 - 1, 2**62 - 57, 2**63 - 25)
+
+
+def crt(residues, moduli):
+    """The unique x in [0, prod(moduli)) with x = residues[i] mod moduli[i]
+    (pairwise coprime moduli), by incremental Chinese remaindering."""
+    x, m = 0, 1
+    for a, mi in zip(residues, moduli):
+        t = ((int(a) - x) * pow(m, -1, mi)) % mi
+        x += m * t
+        m *= mi
+    return x
+
+
+def count_exact(g, t: int, plan, k: int, seed: int, first: int, R: int, n_primes: int = 3):
+    """Per-colouring X mod 2^64 * PRIMES[0] * ... * PRIMES[n_primes-1] (Python
+    ints), from the residue DPs; X itself whenever it is below that product."""
+    moduli = [2**64] + list(PRIMES[:n_primes])
+    res = [count(g, t, plan, k, seed, first, R)[0]]
+    res += [count_mod(g, t, plan, k, seed, first, R, p) for p in PRIMES[:n_primes]]
+    return [crt([int(r[i]) for r in res], moduli) for i in range(R)]
 
 
 # ------------------------------------------------------------ template-only math

@@ -315,6 +315,68 @@ def test_overflow_ignores_neighbour_sums_that_hold_the_own_colour():
     assert X == exact % M64 and f == 1
 
 
+def exact_colored(g, t, plan, k, col, n_primes=3):
+    """X from its residues mod 2^64 and mod the first n_primes of O.PRIMES."""
+    res = [O.count_colored(g, t, plan, k, col)[0]]
+    res += [O.count_colored_mod(g, t, plan, k, col, p) for p in O.PRIMES[:n_primes]]
+    return O.crt(res, [2**64] + list(O.PRIMES[:n_primes]))
+
+
+def test_residues_mod_primes_match_the_u64_dp_below_2_64():
+    """Without overflow, X mod p from the modular DP equals the uint64 count mod p."""
+    rng = np.random.default_rng(11)
+    for trial in range(12):
+        g = I.erdos_renyi(int(rng.integers(20, 200)), int(rng.integers(40, 800)), 100 + trial)
+        t = int(rng.integers(2, 8))
+        k = t + int(rng.integers(0, 2))
+        plan = O.root_plan(t, I.prufer_tree(t, trial), int(rng.integers(0, t)), "small")
+        col = O.colors(trial, 0, g.n, k)
+        X, f = O.count_colored(g, t, plan, k, col)
+        assert f == 0
+        for p in O.PRIMES:
+            assert O.count_colored_mod(g, t, plan, k, col, p) == X % p
+
+
+def test_exact_counts_past_2_64_on_k1d():
+    """K_{1,d} with chosen colour multiplicities: the residues mod 2^64 and mod
+    three primes recover X = (t-1)! * prod n_c exactly, past 2^64, for the
+    centre-rooted and a leaf-rooted plan."""
+    t = k = 12
+    for bump in (0, 6, 11):
+        ns = [11 + (i < bump) for i in range(11)]
+        ns = [n * 3 for n in ns]                   # counts well past 2^64
+        d = sum(ns)
+        g = I.csr_from_edges(d + 1, np.zeros(d, np.int64), np.arange(1, d + 1))
+        col = np.zeros(d + 1, np.uint8)
+        pos = 1
+        for c, m in enumerate(ns, start=1):
+            col[pos:pos + m] = c
+            pos += m
+        exact = math.factorial(t - 1) * math.prod(ns)
+        assert exact >= 2**64
+        for root in (0, 1):
+            assert exact_colored(g, t, O.root_plan(t, I.star(t), root), k, col) == exact
+
+
+def test_exact_star_counts_on_a_hub_graph():
+    """The per-colouring star closed form (t-1)! * sum_v e_{t-1}(n_c(v)) in exact
+    integers, far past 2^64 on hub vertices, against the CRT of the residues."""
+    rng = np.random.default_rng(5)
+    n, hubs = 900, 4
+    src, dst = [], []
+    for h in range(hubs):
+        nb = rng.choice(np.arange(hubs, n), size=700, replace=False)
+        src.append(np.full(700, h)); dst.append(nb)
+    g0 = I.erdos_renyi(n, 1500, 5).edges()
+    src.append(g0[:, 0]); dst.append(g0[:, 1])
+    g = I.csr_from_edges(n, np.concatenate(src), np.concatenate(dst))
+    t = k = 12
+    col = O.colors(3, 0, g.n, k)
+    truth = star_closed_form(g, col, k, t)
+    assert truth >= 2**64
+    assert exact_colored(g, t, O.root_plan(t, I.star(t), 0), k, col) == truth
+
+
 def hubby_graph(seed, n=1500, m=4000, hubs=3, hub_deg=900):
     """Sparse random graph plus a few high-degree hubs, so counts pass 2^64."""
     rng = np.random.default_rng(seed)
@@ -338,6 +400,8 @@ def test_residue_is_plan_independent_under_overflow():
     results = {O.count_colored(g, t, plan, k, col) for plan in plans_for(t, edges)}
     residues = {x for x, _ in results}
     flags = {f for _, f in results}
+    for p in O.PRIMES[:1]:
+        assert len({O.count_colored_mod(g, t, plan, k, col, p) for plan in plans_for(t, edges)}) == 1
     assert len(residues) == 1
     assert 1 in flags   # this instance does overflow
 
