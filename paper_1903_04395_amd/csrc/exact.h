@@ -46,5 +46,38 @@ __host__ __device__ __forceinline__ uint64_t mad_ovf3(uint64_t acc, uint64_t a, 
     return s;
 }
 
+// ---------------------------------------------------------- residues mod p
+
+// An odd prime p = 2^w - c below 2^63; wrap = 2^64 mod p.  The DP commutes with
+// reduction modulo p (it uses only + and *), so running it on residues gives
+// X mod p; with X mod 2^64 the residues determine X below their product.
+struct Modulus {
+    uint64_t p, c, wrap;
+    int w;
+};
+
+// x mod p for any x < 2^128, by folding x = hi * 2^w + lo into hi * c + lo.
+__host__ __device__ __forceinline__ uint64_t mod_fold(unsigned __int128 x, const Modulus &m) {
+    const uint64_t mask = (1ull << m.w) - 1;
+    x = (x >> m.w) * m.c + (uint64_t)(x & mask);        // < 2^(128-w) * c + 2^w
+    x = (x >> m.w) * m.c + (uint64_t)(x & mask);        // < 2^w + small
+    uint64_t r = (uint64_t)((x >> m.w) * m.c + (uint64_t)(x & mask));
+    if (r >= m.p) r -= m.p;
+    if (r >= m.p) r -= m.p;
+    return r;
+}
+
+// a + b mod p for a, b < p (< 2^63, so the sum does not wrap).
+__host__ __device__ __forceinline__ uint64_t mod_add(uint64_t a, uint64_t b, const Modulus &m) {
+    const uint64_t s = a + b;
+    return s >= m.p ? s - m.p : s;
+}
+
+// acc + a*b mod p for acc, a, b < p.
+__host__ __device__ __forceinline__ uint64_t mod_mad(uint64_t acc, uint64_t a, uint64_t b,
+                                                     const Modulus &m) {
+    return mod_fold((unsigned __int128)a * b + acc, m);
+}
+
 }  // namespace kern
 }  // namespace sc

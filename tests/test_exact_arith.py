@@ -1,6 +1,7 @@
-"""The device's exact uint64 multiply-adds (both forms in csrc/exact.h), compiled for the
-host with g++, against unsigned 128-bit arithmetic: residue and overflow flag
-on edge values around every 32-bit and 64-bit boundary and on random pairs."""
+"""The device's exact arithmetic (csrc/exact.h), compiled for the host with
+g++, against unsigned 128-bit arithmetic: both uint64 multiply-adds (residue
+and overflow flag) on edge values around every 32-bit and 64-bit boundary and
+on random pairs, and the residue operations modulo the three primes."""
 import os
 import subprocess
 import textwrap
@@ -52,6 +53,24 @@ HARNESS = textwrap.dedent(r"""
             uint64_t b = ~0ull / a;
             bad += check(0, a, b) + check(0, a, b + 1) + check(~0ull - a * b, a, b) + check(~0ull - a * b + 1, a, b);
             n += 4;
+        }
+        // residues modulo the primes 2^61 - 1, 2^62 - 57, 2^63 - 25
+        const sc::kern::Modulus mods[3] = {{(1ull << 61) - 1, 1, 8, 61},
+                                           {(1ull << 62) - 57, 57, 228, 62},
+                                           {(1ull << 63) - 25, 25, 50, 63}};
+        for (const auto &md : mods) {
+            if (((u128)1 << 64) % md.p != md.wrap) { printf("BAD wrap\n"); return 1; }
+            std::mt19937_64 h(md.p);
+            for (long i = 0; i < 1000000; ++i) {
+                u128 x = ((u128)h() << 64) | h();
+                if (i % 3 == 0) x >>= (h() % 128);
+                if (sc::kern::mod_fold(x, md) != (uint64_t)(x % md.p)) { printf("FAIL fold\n"); bad++; }
+                uint64_t a = h() % md.p, b = h() % md.p, c = h() % md.p;
+                if (i % 5 == 0) { a = md.p - 1 - (h() % 3); b = md.p - 1 - (h() % 3); c = md.p - 1; }
+                if (sc::kern::mod_add(a, b, md) != (uint64_t)(((u128)a + b) % md.p)) { printf("FAIL add\n"); bad++; }
+                if (sc::kern::mod_mad(c, a, b, md) != (uint64_t)(((u128)a * b + c) % md.p)) { printf("FAIL mad\n"); bad++; }
+                n += 3;
+            }
         }
         printf("%s %ld\n", bad ? "BAD" : "OK", n);
         return bad != 0;
