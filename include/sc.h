@@ -181,6 +181,38 @@ int sc_run(sc_ctx *ctx, int32_t graph_id, int32_t tmpl_id, uint64_t first_colori
            int32_t n_colorings, void *stream, uint64_t *counts, uint8_t *overflow,
            double *est_maps, double *est_copies);
 
+/* Exact wide counts.  The DP uses only additions and multiplications, so it
+ * commutes with reduction modulo any m (Eq. 2 and the counting recursion of
+ * Sec. 3.1 with every entry taken mod m).  sc_run gives each count mod 2^64 and
+ * flags the colourings whose count reached 2^64; for those, sc_run_exact adds
+ * passes modulo three primes (2^61-1, 2^62-57, 2^63-25) and recovers the count
+ * by the Chinese remainder theorem below 2^64 p1 p2 p3 (about 2^250).  The
+ * result is certified when the homomorphism count of the template into the
+ * graph (an upper bound on every colouring's colourful count) lies below 2^249.
+ * Synchronous.  Host outputs: counts[n_colorings][4] (the count as four uint64
+ * limbs, least significant first), exact[n_colorings] (1: the count is exact;
+ * 0: only its residue mod 2^64 p1 p2 p3 is), hom_bound (may be NULL: the
+ * homomorphism count, computed when a colouring overflowed or when asked for,
+ * else NaN), est_maps / est_copies (may be NULL; from the exact counts, NaN if
+ * any is not exact).
+ * Errors: as sc_run. */
+int sc_run_exact(sc_ctx *ctx, int32_t graph_id, int32_t tmpl_id, uint64_t first_coloring,
+                 int32_t n_colorings, void *stream, uint64_t *counts, uint8_t *exact,
+                 double *hom_bound, double *est_maps, double *est_copies);
+
+/* Residues: residues[r] = (colourful count of colouring first_coloring + r) mod p,
+ * for p = 2^w - c with 61 <= w <= 63 and odd c <= 2^16 (p need not be prime).
+ * Synchronous.  Errors: SC_EINVAL (unsupported p, NULL output), else as sc_run. */
+int sc_run_mod(sc_ctx *ctx, int32_t graph_id, int32_t tmpl_id, uint64_t first_coloring,
+               int32_t n_colorings, void *stream, uint64_t p, uint64_t *residues);
+
+/* Homomorphisms of the template into the graph (maps of the template's
+ * vertices to the graph's that send edges to edges, not necessarily
+ * injective), in double precision (relative error below 2^-40), by the same
+ * steps as the counting DP on one value per vertex.  Synchronous.
+ * Errors: SC_EINVAL (NULL output), SC_ENOTFOUND, SC_ENOMEM, SC_EDEVICE. */
+int sc_hom_count(sc_ctx *ctx, int32_t graph_id, int32_t tmpl_id, void *stream, double *out);
+
 /* Batched form: many jobs -- each a (graph, template, k, seed, colouring range)
  * -- planned together and run back to back on one stream with a single host
  * wait at the end (colourings folded into the table columns, up to the

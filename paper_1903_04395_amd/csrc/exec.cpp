@@ -63,7 +63,8 @@ size_t npre_bytes(const Graph &g, const Plan &P) {
 
 // Kernel shape and device index tables of one step (tables are uploaded on
 // first use, so prepare_pass calls this before any capture).
-int step_args(sc_ctx *c, const Plan &P, const Step &s, kern::StepShape &sh, kern::StepTables &tb) {
+int step_args(sc_ctx *c, const Plan &P, const Step &s, uint64_t mod, kern::StepShape &sh,
+              kern::StepTables &tb) {
     const int k = P.k;
     sh.k = k; sh.a = s.a; sh.p = s.p;
     sh.B = P.batch; sh.Bi = P.interleave;
@@ -74,6 +75,7 @@ int step_args(sc_ctx *c, const Plan &P, const Step &s, kern::StepShape &sh, kern
     sh.nsplit = (int)binom(s.h - 1, s.a - 1);
     sh.amode = s.amode;
     sh.wave_row_max = P.opts.wave_row_max;
+    sh.mod = mod;
     int rc;
     if (s.a > 1 && (rc = get_split(c, k - 1, s.h - 1, s.a - 1, &tb.split))) return rc;
     if (s.p > 1) {
@@ -100,7 +102,7 @@ int prepare_pass(sc_ctx *c, const PassSpec &s, PassBuffers &b, hipStream_t st) {
     for (const Step &st_ : P.steps) {
         kern::StepShape sh;
         kern::StepTables tb;
-        if ((rc = step_args(c, P, st_, sh, tb))) return rc;
+        if ((rc = step_args(c, P, st_, s.mod, sh, tb))) return rc;
     }
     return SC_OK;
 }
@@ -130,7 +132,7 @@ int enqueue_pass(sc_ctx *c, const PassSpec &sp, PassBuffers &pb, hipStream_t st,
     for (const Step &s : P.steps) {
         kern::StepShape sh;
         kern::StepTables tb;
-        if ((rc = step_args(c, P, s, sh, tb))) return rc;
+        if ((rc = step_args(c, P, s, sp.mod, sh, tb))) return rc;
         uint64_t *S = buf(s.buf_s);
         const uint64_t *Pp = buf(s.buf_p), *A = buf(s.buf_a);
         // updates in the paper's units (Lemma 1): nnz*C(k,p) neighbour-sum
@@ -153,7 +155,7 @@ int enqueue_pass(sc_ctx *c, const PassSpec &sp, PassBuffers &pb, hipStream_t st,
     }
     const int W = (int)binom(k - 1, last->h - 1);
     ProfScope ps(c, prof, st, "reduce", 8.0 * dn * W * B, 0);
-    HIPCHK(c, kern::launch_reduce(n, buf(last->buf_s), W, B, P.interleave, X, flags, st));
+    HIPCHK(c, kern::launch_reduce(n, buf(last->buf_s), W, B, P.interleave, sp.mod, X, flags, st));
     return SC_OK;
 }
 
@@ -179,7 +181,7 @@ int launch_pass(sc_ctx *c, int gid, int tid, const PassSpec &s, PassBuffers &b, 
     HIPCHK(c, hipMemcpyAsync(b.desc.p, host_desc, 2 * sizeof(uint64_t), hipMemcpyHostToDevice, st));
     if (allow_graph && c->use_graph && !c->prof) {
         GraphExecKey key{gid, tid, P.k, P.batch, P.interleave, P.opts.lds_max, P.opts.wave_row_max,
-                         s.g->seg, b.gen};
+                         s.g->seg, s.mod, b.gen};
         auto it = c->graph_cache.find(key);
         if (it == c->graph_cache.end()) {
             hipGraph_t graph = nullptr;
@@ -215,6 +217,7 @@ struct PassJob {
     int job, gid, tid, k;
     uint64_t seed, first;
     int offset;                // first colouring of this pass within its job
+    uint64_t mod = 0;          // 0: uint64 counts with overflow flags; else residues mod this prime
     Plan P;
 };
 
@@ -243,6 +246,7 @@ int run_passes(sc_ctx *c, std::vector<PassJob> &passes, hipStream_t st,
         s.k = p.k;
         s.seed = p.seed;
         s.first = p.first;
+        s.mod = p.mod;
         uint64_t *stage = c->host_out + i * kStageWords;
         if ((rc = launch_pass(c, p.gid, p.tid, s, b, st, stage, stage + 2, true))) return rc;
     }
@@ -282,6 +286,113 @@ void estimates(const uint64_t *counts, const uint8_t *ovf, int n, int k, int t, 
     if (copies) *copies = cp;
 }
 
+// ---------------------------------------------------------------- exact counts
+
+// The three primes of the residue passes; with the uint64 pass they fix a count
+// below their product times 2^64 (about 2^250).
+constexpr uint64_t kPrimes[3] = {(1ull << 61) - 1, (1ull << 62) - 57, (1ull << 63) - 25};
+
+uint64_t mulmod(uint64_t a, uint64_t b, uint64_t p) { return (uint64_t)((unsigned __int128)a * b % p); }
+
+uint64_t powmod(uint64_t a, uint64_t e, uint64_t p) {
+    uint64_t r = 1 % p;
+    for (a %= p; e; e >>= 1, a = mulmod(a, a, p))
+        if (e & 1) r = mulmod(r, a, p);
+    return r;
+}
+
+// x = x * m + add over nl little-endian limbs.
+void big_muladd(uint64_t *x, int nl, uint64_t m, uint64_t add) {
+    unsigned __int128 carry = add;
+    for (int i = 0; i < nl; ++i) {
+        const unsigned __int128 t = (unsigned __int128)x[i] * m + carry;
+        x[i] = (uint64_t)t;
+        carry = t >> 64;
+    }
+}
+
+// The integer below 2^64 * p1 * p2 * p3 with residue r64 mod 2^64 and res[i]
+// mod kPrimes[i] (Garner's mixed-radix form: x = v0 + 2^64 (v1 + p1 (v2 + p2 v3))).
+void crt_combine(uint64_t r64, const uint64_t res[3], uint64_t out[4]) {
+    uint64_t v[4] = {r64, 0, 0, 0};
+    for (int i = 0; i < 3; ++i) {
+        const uint64_t p = kPrimes[i];
+        // value of the digits so far mod p, and the radix (2^64 p1 .. p_{i-1}) mod p
+        uint64_t acc = 0, radix = 1;
+        for (int j = 0; j <= i; ++j) {
+            acc = (acc + mulmod(v[j] % p, radix, p)) % p;
+            radix = mulmod(radix, j == 0 ? (uint64_t)(((unsigned __int128)1 << 64) % p) : kPrimes[j - 1] % p, p);
+        }
+        const uint64_t diff = (res[i] % p + p - acc) % p;
+        v[i + 1] = mulmod(diff, powmod(radix, p - 2, p), p);
+    }
+    uint64_t z[3] = {v[3], 0, 0};
+    big_muladd(z, 3, kPrimes[1], v[2]);
+    big_muladd(z, 3, kPrimes[0], v[1]);
+    out[0] = v[0]; out[1] = z[0]; out[2] = z[1]; out[3] = z[2];
+}
+
+// Residues mod `mod` of colourings first..first+n-1.
+int run_mod(sc_ctx *c, int gid, int tid, uint64_t first, int n, uint64_t mod, hipStream_t st, uint64_t *res) {
+    std::vector<PassJob> passes;
+    int rc = plan_job(c, 0, gid, tid, c->k, c->seed, first, n, passes);
+    if (rc) return rc;
+    for (auto &p : passes) p.mod = mod;
+    return run_passes(c, passes, st, [&](const PassJob &p, const uint64_t *r) {
+        for (int i = 0; i < p.P.batch; ++i) res[p.offset + i] = r[i] % mod;
+    });
+}
+
+// Homomorphisms of the template into the graph, in double, by the plan's
+// steps on one value per vertex (an upper bound on the colourful maps of any
+// colouring).
+int hom_count(sc_ctx *c, int gid, int tid, hipStream_t st, double *out) {
+    Plan P;
+    int rc = pick_batch(c, gid, tid, c->k, 1, 0, P);
+    if (rc) return rc;
+    Graph &g = *c->graphs[gid];
+    if (P.steps.empty()) { *out = (double)g.n; return SC_OK; }
+    if (g.n_rows == 0) { *out = 0; return SC_OK; }
+    if ((rc = rebin(c, g, default_segment(c)))) return rc;
+    const int64_t n = g.n_rows;
+    DevMem tmp;
+    if ((rc = dev_alloc(c, tmp, (P.bufs.size() * (size_t)n + 1) * sizeof(double)))) return rc;
+    double *base = (double *)tmp.p;
+    auto hb = [&](int id) { return id < 0 ? (double *)nullptr : base + 1 + (size_t)id * n; };
+    const kern::GraphBins bins = bins_of(g);
+    hipError_t e = kern::launch_zero_u64((uint64_t *)base, 1, st);
+    const Step *last = nullptr;
+    for (const Step &s : P.steps) {
+        if (e != hipSuccess) break;
+        e = kern::launch_hom_step(bins, hb(s.buf_a), hb(s.buf_p), hb(s.buf_s), st);
+        last = &s;
+    }
+    if (e == hipSuccess) e = kern::launch_hom_sum(n, hb(last->buf_s), base, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, base, sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    dev_free(c, tmp);
+    if (e != hipSuccess) return fail(c, SC_EDEVICE, "homomorphism count failed: %s", hipGetErrorString(e));
+    return SC_OK;
+}
+
+// A count below this (2^249 < 2^64 * p1 * p2 * p3) is fixed by its residues.
+constexpr double kCrtRange = 0x1p249;
+
+// Relative error of hom_count's double sums and products (t <= 32 rounded
+// steps over at most 2^31 terms each, and the root sum) is far below this.
+constexpr double kHomSlack = 1.0 + 0x1p-10;
+
+int check_run_args(sc_ctx *c, int gid, int tid, int ncol) {
+    if (ncol < 0) return fail(c, SC_EINVAL, "n_colorings < 0");
+    auto gi = c->graphs.find(gid);
+    if (gi == c->graphs.end()) return fail(c, SC_ENOTFOUND, "unknown graph %d", gid);
+    auto ti = c->tmpls.find(tid);
+    if (ti == c->tmpls.end()) return fail(c, SC_ENOTFOUND, "unknown template %d", tid);
+    if (c->k < ti->second->t) return fail(c, SC_EINVAL, "k=%d < t=%d (call sc_set_colors)", c->k, ti->second->t);
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, SC_EDEVICE, "hipSetDevice failed");
+    return SC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -307,6 +418,107 @@ int sc_run(sc_ctx *c, int32_t gid, int32_t tid, uint64_t first, int32_t ncol, vo
     });
     if (rc) return rc;
     estimates(counts, overflow, ncol, c->k, ti->second->t, ti->second->aut, est_maps, est_copies);
+    return SC_OK;
+}
+
+int sc_run_mod(sc_ctx *c, int32_t gid, int32_t tid, uint64_t first, int32_t ncol, void *stream, uint64_t p,
+               uint64_t *residues) {
+    if (!c) return SC_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    int rc = check_run_args(c, gid, tid, ncol);
+    if (rc) return rc;
+    if (!kern::mod_supported(p)) return fail(c, SC_EINVAL, "modulus %llu is not 2^w - c (61 <= w <= 63, odd c <= 2^16)",
+                                             (unsigned long long)p);
+    if (ncol > 0 && !residues) return fail(c, SC_EINVAL, "NULL output");
+    return run_mod(c, gid, tid, first, ncol, p, stream ? (hipStream_t)stream : c->stream, residues);
+}
+
+int sc_hom_count(sc_ctx *c, int32_t gid, int32_t tid, void *stream, double *out) {
+    if (!c) return SC_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    int rc = check_run_args(c, gid, tid, 0);
+    if (rc) return rc;
+    if (!out) return fail(c, SC_EINVAL, "NULL output");
+    return hom_count(c, gid, tid, stream ? (hipStream_t)stream : c->stream, out);
+}
+
+int sc_run_exact(sc_ctx *c, int32_t gid, int32_t tid, uint64_t first, int32_t ncol, void *stream,
+                 uint64_t *counts, uint8_t *exact, double *hom_bound, double *est_maps, double *est_copies) {
+    if (!c) return SC_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    int rc = check_run_args(c, gid, tid, ncol);
+    if (rc) return rc;
+    if (ncol > 0 && (!counts || !exact)) return fail(c, SC_EINVAL, "NULL output");
+    hipStream_t st = stream ? (hipStream_t)stream : c->stream;
+    // the uint64 pass: exact wherever no sum reached 2^64
+    std::vector<uint64_t> c64((size_t)ncol);
+    std::vector<uint8_t> ovf((size_t)ncol);
+    {
+        std::vector<PassJob> passes;
+        if ((rc = plan_job(c, 0, gid, tid, c->k, c->seed, first, ncol, passes))) return rc;
+        rc = run_passes(c, passes, st, [&](const PassJob &p, const uint64_t *res) {
+            unpack_pass(res, p.P.batch, c64.data() + p.offset, ovf.data() + p.offset);
+        });
+        if (rc) return rc;
+    }
+    // the colourings that overflowed, in runs of consecutive ones, get residue
+    // passes modulo each prime
+    std::vector<std::pair<int, int>> runs;
+    for (int r = 0; r < ncol; ++r) {
+        if (!ovf[r]) continue;
+        if (!runs.empty() && runs.back().first + runs.back().second == r) ++runs.back().second;
+        else runs.push_back({r, 1});
+    }
+    std::vector<uint64_t> res((size_t)3 * ncol);
+    if (!runs.empty()) {
+        std::vector<PassJob> passes;
+        for (int i = 0; i < 3; ++i)
+            for (auto &ru : runs) {
+                std::vector<PassJob> mine;
+                if ((rc = plan_job(c, i, gid, tid, c->k, c->seed, first + (uint64_t)ru.first, ru.second, mine)))
+                    return rc;
+                for (auto &p : mine) {
+                    p.mod = kPrimes[i];
+                    p.offset += ru.first;
+                    passes.push_back(std::move(p));
+                }
+            }
+        rc = run_passes(c, passes, st, [&](const PassJob &p, const uint64_t *r) {
+            for (int j = 0; j < p.P.batch; ++j) res[(size_t)p.job * ncol + p.offset + j] = r[j] % p.mod;
+        });
+        if (rc) return rc;
+    }
+    // certificate: every count is at most the homomorphism count
+    double H = NAN;
+    if (!runs.empty() || hom_bound) {
+        if ((rc = hom_count(c, gid, tid, st, &H))) return rc;
+    }
+    const bool certified = !runs.empty() && H * kHomSlack < kCrtRange;
+    long double sum = 0;
+    bool all = true;
+    for (int r = 0; r < ncol; ++r) {
+        uint64_t *out = counts + 4 * (size_t)r;
+        if (!ovf[r]) {
+            out[0] = c64[r]; out[1] = out[2] = out[3] = 0;
+            exact[r] = 1;
+        } else {
+            const uint64_t rr[3] = {res[r], res[(size_t)ncol + r], res[2 * (size_t)ncol + r]};
+            crt_combine(c64[r], rr, out);
+            exact[r] = certified ? 1 : 0;
+        }
+        all &= exact[r] != 0;
+        sum += (long double)out[0] + std::ldexp((long double)out[1], 64) + std::ldexp((long double)out[2], 128) +
+               std::ldexp((long double)out[3], 192);
+    }
+    if (hom_bound) *hom_bound = H;
+    const Template &T = *c->tmpls[tid];
+    double m = NAN, cp = NAN;
+    if (ncol > 0 && all) {
+        m = (double)(sum / ncol) / colorful_probability(c->k, T.t);
+        cp = m / T.aut;
+    }
+    if (est_maps) *est_maps = m;
+    if (est_copies) *est_copies = cp;
     return SC_OK;
 }
 

@@ -50,6 +50,8 @@ struct StepShape {
     int amode = kActiveLeaf;
     int wave_row_max = 8192;           // per-row LDS bytes up to which each wavefront
                                        // builds a row of its own (0: never)
+    uint64_t mod = 0;                  // 0: exact uint64 entries with carry flags; else the
+                                       // entries are residues mod this prime (mod_supported)
 };
 
 // Host-built index tables of a step (device pointers).
@@ -94,9 +96,19 @@ hipError_t launch_dp_row(const GraphBins &g, const StepShape &s, const StepTable
                          hipStream_t st);
 
 // X[r] = sum over rows and the W entries of colouring r of table S (with carry
-// flags); X must be zeroed first.
-hipError_t launch_reduce(int64_t n, const uint64_t *S, int W, int B, int Bi,
+// flags); X must be zeroed first.  mod != 0: S holds residues and X[r] ends
+// congruent to the sum mod `mod` (not reduced; no flags).
+hipError_t launch_reduce(int64_t n, const uint64_t *S, int W, int B, int Bi, uint64_t mod,
                          unsigned long long *X, unsigned long long *flags, hipStream_t st);
+
+// Residue passes accept primes p = 2^w - c with 61 <= w <= 63 and odd c <= 2^16.
+bool mod_supported(uint64_t p);
+
+// Homomorphism counts (double): S[v] = A[v] * sum over the neighbours u of v
+// of P[u], with A or P NULL standing for the single-vertex sub-template (all
+// ones).  launch_hom_sum adds the sum of S[0..n) into *out.
+hipError_t launch_hom_step(const GraphBins &g, const double *A, const double *P, double *S, hipStream_t st);
+hipError_t launch_hom_sum(int64_t n, const double *S, double *out, hipStream_t st);
 
 hipError_t launch_zero_u64(uint64_t *p, int64_t count, hipStream_t st);
 

@@ -111,6 +111,7 @@ struct DpArgs {
     int64_t n_items;
     int seg;
     int tab_off;                  // LDS byte offset of the index tables
+    Modulus md;                   // residue mode: the prime, its fold constants, 2^64 mod p
     unsigned long long *flags;
 };
 
@@ -138,6 +139,16 @@ __device__ __forceinline__ void team_sync() {
         __builtin_amdgcn_wave_barrier();
     } else {
         __syncthreads();
+    }
+}
+
+// Residue mode: a 64-bit word accumulates a value known only modulo p, so an
+// add that wraps past 2^64 loses 2^64, which is put back as 2^64 mod p (an add
+// that wraps again puts back once more).
+__device__ __forceinline__ void put_back_wrap(unsigned long long *ptr, uint64_t wrap) {
+    for (;;) {
+        const unsigned long long o = atomicAdd(ptr, (unsigned long long)wrap);
+        if ((uint64_t)o + wrap >= wrap) break;
     }
 }
 
@@ -203,7 +214,7 @@ __device__ __forceinline__ void lane_masks(const DpArgs &a, const uint16_t *unr,
 // entries of one row land on distinct sets, so a wavefront's adds never
 // collide; adds of different wavefronts meet in LDS atomics, whose returned
 // old value gives the carry.
-template <int CH, int NB, bool BIG>
+template <int CH, int NB, bool BIG, bool MOD>
 __device__ __forceinline__ void scatter_wide(const Team &tm, const DpArgs &a, int64_t v, int pl, int64_t e0,
                                              int64_t e1, uint64_t *Nl, const uint16_t *unr,
                                              const uint16_t *rk, const uint32_t (&rmsk)[CH],
@@ -253,9 +264,12 @@ __device__ __forceinline__ void scatter_wide(const Team &tm, const DpArgs &a, in
                     const uint32_t E = widen_at(msk[i], cu[b]) | own;
                     if (E & vbit) continue;
                     const int idx = rank_of(a, rk, narrow_at(E, cv));
-                    const unsigned long long old =
-                        atomicAdd((unsigned long long *)&Nl[(idx << a.sh) + ri], (unsigned long long)xv);
-                    carry |= (uint32_t)((uint64_t)old + xv < xv);
+                    unsigned long long *dst = (unsigned long long *)&Nl[(idx << a.sh) + ri];
+                    const unsigned long long old = atomicAdd(dst, (unsigned long long)xv);
+                    if ((uint64_t)old + xv < xv) {
+                        if constexpr (MOD) put_back_wrap(dst, a.md.wrap);
+                        else carry = 1;
+                    }
                 }
             }
         }
@@ -267,7 +281,7 @@ __device__ __forceinline__ void scatter_wide(const Team &tm, const DpArgs &a, in
 // neighbour ids come in one load, every colour and row load of the round is
 // issued before any is used, and the carries of up to eight adds are read
 // together.
-template <int CH, int NB, bool BIG>
+template <int CH, int NB, bool BIG, bool MOD>
 __device__ __forceinline__ void scatter_narrow(const Team &tm, const DpArgs &a, int64_t v, int pl, int64_t e0,
                                              int64_t e1, uint64_t *Nl, const uint16_t *unr,
                                              const uint16_t *rk, const uint32_t (&rmsk)[CH],
@@ -311,15 +325,17 @@ __device__ __forceinline__ void scatter_narrow(const Team &tm, const DpArgs &a, 
 #pragma unroll
             for (int f0 = 0; f0 < NB * CH; f0 += G) {
                 uint64_t old[G];
+                int tgt[G];
 #pragma unroll
                 for (int f = 0; f < G; ++f) {
                     const int b = (f0 + f) / CH, i = (f0 + f) % CH;
                     const uint32_t E = widen_at(msk[i], cu[b]) | (1u << cu[b]);
                     old[f] = 0;
+                    tgt[f] = 0;
                     if (x[b][i] != 0 && cu[b] != cv && !(E & vbit)) {
                         const int idx = rank_of(a, rk, narrow_at(E, cv));
-                        old[f] = atomicAdd((unsigned long long *)&Nl[(idx << a.sh) + ri],
-                                           (unsigned long long)x[b][i]);
+                        tgt[f] = (idx << a.sh) + ri;
+                        old[f] = atomicAdd((unsigned long long *)&Nl[tgt[f]], (unsigned long long)x[b][i]);
                     } else {
                         x[b][i] = 0;
                     }
@@ -327,7 +343,10 @@ __device__ __forceinline__ void scatter_narrow(const Team &tm, const DpArgs &a, 
 #pragma unroll
                 for (int f = 0; f < G; ++f) {
                     const uint64_t xv = x[(f0 + f) / CH][(f0 + f) % CH];
-                    carry |= (uint32_t)(old[f] + xv < xv);
+                    if (old[f] + xv < xv) {
+                        if constexpr (MOD) put_back_wrap((unsigned long long *)&Nl[tgt[f]], a.md.wrap);
+                        else carry = 1;
+                    }
                 }
             }
         }
@@ -341,7 +360,7 @@ __device__ __forceinline__ void scatter_narrow(const Team &tm, const DpArgs &a, 
 // neighbours' entries for one set; U rounds of neighbours are in flight.
 // Groups of one wavefront may add to the same entry, so adds are LDS atomics
 // (carry from the returned old value).
-template <int U>
+template <int U, bool MOD>
 __device__ __forceinline__ void scatter_groups(const Team &tm, const DpArgs &a, int64_t v, int pl, int64_t e0,
                                                int64_t e1, uint64_t *Nl, const uint16_t *unr,
                                                const uint16_t *rk, uint64_t &m) {
@@ -382,21 +401,27 @@ __device__ __forceinline__ void scatter_groups(const Team &tm, const DpArgs &a, 
 #pragma unroll
             for (int j0 = 0; j0 < kMaxW; j0 += 8) {
                 uint64_t old[8];
+                int tgt[8];
 #pragma unroll
                 for (int f = 0; f < 8; ++f) {
                     const int j = j0 + f;
                     old[f] = 0;
+                    tgt[f] = 0;
                     const uint32_t E = widen_at(unr[j < a.Wq ? j : 0], cu[t]) | own;
                     if (x[t][j] != 0 && cu[t] != cv && !(E & vbit)) {
                         const int idx = rank_of(a, rk, narrow_at(E, cv));
-                        old[f] = atomicAdd((unsigned long long *)&Nl[(idx << a.sh) + ri],
-                                           (unsigned long long)x[t][j]);
+                        tgt[f] = (idx << a.sh) + ri;
+                        old[f] = atomicAdd((unsigned long long *)&Nl[tgt[f]], (unsigned long long)x[t][j]);
                     } else {
                         x[t][j] = 0;
                     }
                 }
 #pragma unroll
-                for (int f = 0; f < 8; ++f) carry |= (uint32_t)(old[f] + x[t][j0 + f] < x[t][j0 + f]);
+                for (int f = 0; f < 8; ++f)
+                    if (old[f] + x[t][j0 + f] < x[t][j0 + f]) {
+                        if constexpr (MOD) put_back_wrap((unsigned long long *)&Nl[tgt[f]], a.md.wrap);
+                        else carry = 1;
+                    }
             }
         }
     }
@@ -407,14 +432,14 @@ __device__ __forceinline__ void scatter_groups(const Team &tm, const DpArgs &a, 
 // and read the carries of a group of adds at once; rounds of one or two wide
 // rows keep fewer registers live instead.
 // CH == kGroupRows selects the lane-group scatter for rows of at most 16 sets.
-template <int CH, int NB, bool BIG>
+template <int CH, int NB, bool BIG, bool MOD>
 __device__ __forceinline__ void scatter_rows(const Team &tm, const DpArgs &a, int64_t v, int pl, int64_t e0,
                                              int64_t e1, uint64_t *Nl, const uint16_t *unr,
                                              const uint16_t *rk, const uint32_t (&rmsk)[CH],
                                              uint64_t &m) {
-    if constexpr (CH == kGroupRows) scatter_groups<2>(tm, a, v, pl, e0, e1, Nl, unr, rk, m);
-    else if constexpr (NB >= 4) scatter_narrow<CH, NB, BIG>(tm, a, v, pl, e0, e1, Nl, unr, rk, rmsk, m);
-    else scatter_wide<CH, NB, BIG>(tm, a, v, pl, e0, e1, Nl, unr, rk, rmsk, m);
+    if constexpr (CH == kGroupRows) scatter_groups<2, MOD>(tm, a, v, pl, e0, e1, Nl, unr, rk, m);
+    else if constexpr (NB >= 4) scatter_narrow<CH, NB, BIG, MOD>(tm, a, v, pl, e0, e1, Nl, unr, rk, rmsk, m);
+    else scatter_wide<CH, NB, BIG, MOD>(tm, a, v, pl, e0, e1, Nl, unr, rk, rmsk, m);
 }
 
 // p = 1: counts the colours of neighbours [e0, e1) of row v (plane pl): the
@@ -447,7 +472,7 @@ __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t x, int mask) {
 // pair), whose partial sums meet through cross-lane shuffles; all terms are
 // non-negative, so a carry in any partial sum or in their combination means
 // the exact sum reaches 2^64.
-template <int AM>
+template <int AM, bool MOD>
 __device__ __forceinline__ void emit_row(const Team &tm, const DpArgs &a, int64_t v, int pl,
                                          const uint64_t *Nl, const uint64_t *Al, const uint32_t *split,
                                          uint64_t &m) {
@@ -480,7 +505,10 @@ __device__ __forceinline__ void emit_row(const Team &tm, const DpArgs &a, int64_
                     x[i] = Ar[((pr[i] & 0xffffu) << a.sh) + ri];
                     y[i] = Nl[((pr[i] >> 16) << a.sh) + ri];
                 }
-                if (lean) {
+                if constexpr (MOD) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) acc = mod_mad(acc, x[i], y[i], a.md);
+                } else if (lean) {
 #pragma unroll
                     for (int i = 0; i < 4; ++i) acc = mad_ovf3(acc, x[i], y[i], ovf);
                 } else {
@@ -490,15 +518,21 @@ __device__ __forceinline__ void emit_row(const Team &tm, const DpArgs &a, int64_
             }
             for (; j < a.nsplit; j += step) {
                 const uint32_t pr = sp[j];
-                acc = mad_ovf(acc, Ar[((pr & 0xffffu) << a.sh) + ri], Nl[((pr >> 16) << a.sh) + ri], ovf);
+                const uint64_t xa = Ar[((pr & 0xffffu) << a.sh) + ri], yn = Nl[((pr >> 16) << a.sh) + ri];
+                if constexpr (MOD) acc = mod_mad(acc, xa, yn, a.md);
+                else acc = mad_ovf(acc, xa, yn, ovf);
             }
         }
         for (int o = 1; o < a.eg; o <<= 1) {
             const uint64_t y = shfl_xor_u64(acc, o);
-            ovf |= (uint32_t)__shfl_xor((int)ovf, o, kWave);
-            const uint64_t t = acc + y;
-            ovf |= (uint32_t)(t < y);
-            acc = t;
+            if constexpr (MOD) {
+                acc = mod_add(acc, y, a.md);
+            } else {
+                ovf |= (uint32_t)__shfl_xor((int)ovf, o, kWave);
+                const uint64_t t = acc + y;
+                ovf |= (uint32_t)(t < y);
+                acc = t;
+            }
         }
         if (q < Ls && g == 0) {
             out[q] = acc;
@@ -514,7 +548,7 @@ __device__ __forceinline__ void emit_row(const Team &tm, const DpArgs &a, int64_
 // four times as many rows are in flight.  LDS per team: the neighbour-sum row
 // N' (Wn * Bi) and the staged active row (Wa * Bi, AM == kActiveLds); then the
 // index tables, shared by the workgroup.  CH = 0: p = 1.
-template <int CH, int NB, bool BIG, int AM, bool WAVE>
+template <int CH, int NB, bool BIG, int AM, bool WAVE, bool MOD>
 __global__ __launch_bounds__(kBlock) void dp_row_kernel(DpArgs a) {
     constexpr bool HIST = CH == 0;
     constexpr int C = HIST ? 1 : CH;
@@ -551,10 +585,14 @@ __global__ __launch_bounds__(kBlock) void dp_row_kernel(DpArgs a) {
         team_sync<WAVE>();
         if (sv < 0) {
             if constexpr (HIST) count_colours(tm, a, v, pl, a.rp[v], a.rp[v + 1], Nl);
-            else scatter_rows<C, NB, BIG>(tm, a, v, pl, a.rp[v], a.rp[v + 1], Nl, tab, tab + a.Wq, msk, m);
+            else scatter_rows<C, NB, BIG, MOD>(tm, a, v, pl, a.rp[v], a.rp[v + 1], Nl, tab, tab + a.Wq, msk, m);
         }
         team_sync<WAVE>();
-        emit_row<AM>(tm, a, v, pl, Nl, Al, split, m);
+        if constexpr (MOD) {                     // the sums, known modulo p, into [0, p)
+            for (int q = tm.tid; q < Ln; q += tm.size) Nl[q] = mod_fold(Nl[q], a.md);
+            team_sync<WAVE>();
+        }
+        emit_row<AM, MOD>(tm, a, v, pl, Nl, Al, split, m);
         team_sync<WAVE>();                       // LDS is reused by the next item
     }
     flush_flags(m, a.flags);
@@ -563,7 +601,7 @@ __global__ __launch_bounds__(kBlock) void dp_row_kernel(DpArgs a) {
 // Split rows: one workgroup per (plane, row, segment of `seg` neighbours)
 // item; the segment's sum is built in LDS as in the row kernel and added into
 // Npre with global atomics (carry from the returned old value).
-template <int CH, int NB, bool BIG>
+template <int CH, int NB, bool BIG, bool MOD>
 __global__ __launch_bounds__(kBlock) void dp_split_kernel(DpArgs a) {
     constexpr bool HIST = CH == 0;
     constexpr int C = HIST ? 1 : CH;
@@ -589,7 +627,7 @@ __global__ __launch_bounds__(kBlock) void dp_split_kernel(DpArgs a) {
         for (int q = threadIdx.x; q < Ln; q += kBlock) Nl[q] = 0;
         __syncthreads();
         if constexpr (HIST) count_colours(block_team(), a, v, pl, e0, e1, Nl);
-        else scatter_rows<C, NB, BIG>(block_team(), a, v, pl, e0, e1, Nl, tab, tab + a.Wq, msk, m);
+        else scatter_rows<C, NB, BIG, MOD>(block_team(), a, v, pl, e0, e1, Nl, tab, tab + a.Wq, msk, m);
         __syncthreads();
         unsigned long long *dst =
             (unsigned long long *)a.Npre + ((int64_t)pl * a.n_split + a.slot[v]) * Ln;
@@ -597,7 +635,10 @@ __global__ __launch_bounds__(kBlock) void dp_split_kernel(DpArgs a) {
             const uint64_t x = Nl[q];
             if (x == 0) continue;
             const unsigned long long old = atomicAdd(dst + q, (unsigned long long)x);
-            if ((uint64_t)old + x < x) m |= 1ull << (pl * a.Bi + (q & (a.Bi - 1)));
+            if ((uint64_t)old + x < x) {
+                if constexpr (MOD) put_back_wrap(dst + q, a.md.wrap);
+                else m |= 1ull << (pl * a.Bi + (q & (a.Bi - 1)));
+            }
         }
         __syncthreads();
     }
@@ -607,9 +648,11 @@ __global__ __launch_bounds__(kBlock) void dp_split_kernel(DpArgs a) {
 // ------------------------------------------------------------------ root reduction
 
 // grid: (blocks, B); block y = colouring r = pl*Bi + ri sums the n*W entries of
-// that colouring (stride Bi inside plane pl).
+// that colouring (stride Bi inside plane pl).  MOD: the entries are residues
+// mod md.p and X[r] ends congruent to their sum.
+template <bool MOD>
 __global__ __launch_bounds__(kBlock) void reduce_kernel(int64_t n, const uint64_t *__restrict__ S,
-                                                       int W, int Bi,
+                                                       int W, int Bi, Modulus md,
                                                        unsigned long long *__restrict__ X,
                                                        unsigned long long *__restrict__ flags) {
     __shared__ uint64_t part[kBlock];
@@ -622,9 +665,13 @@ __global__ __launch_bounds__(kBlock) void reduce_kernel(int64_t n, const uint64_
     uint32_t carry = 0;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < total; i += (int64_t)gridDim.x * kBlock) {
         const uint64_t x = base[i * Bi];
-        const uint64_t s = acc + x;
-        carry |= s < x;
-        acc = s;
+        if constexpr (MOD) {
+            acc = mod_add(acc, x, md);
+        } else {
+            const uint64_t s = acc + x;
+            carry |= s < x;
+            acc = s;
+        }
     }
     part[threadIdx.x] = acc;
     cpart[threadIdx.x] = carry;
@@ -632,16 +679,66 @@ __global__ __launch_bounds__(kBlock) void reduce_kernel(int64_t n, const uint64_
     for (int w = kBlock / 2; w > 0; w >>= 1) {
         if (threadIdx.x < w) {
             const uint64_t x = part[threadIdx.x + w];
-            const uint64_t s = part[threadIdx.x] + x;
-            cpart[threadIdx.x] |= cpart[threadIdx.x + w] | (s < x);
-            part[threadIdx.x] = s;
+            if constexpr (MOD) {
+                part[threadIdx.x] = mod_add(part[threadIdx.x], x, md);
+            } else {
+                const uint64_t s = part[threadIdx.x] + x;
+                cpart[threadIdx.x] |= cpart[threadIdx.x + w] | (s < x);
+                part[threadIdx.x] = s;
+            }
         }
         __syncthreads();
     }
     if (threadIdx.x == 0) {
         const unsigned long long old = atomicAdd(&X[r], (unsigned long long)part[0]);
-        if (cpart[0] || (uint64_t)old + part[0] < (uint64_t)old) atomicOr(flags, 1ull << r);
+        const bool wrapped = (uint64_t)old + part[0] < (uint64_t)old;
+        if constexpr (MOD) {
+            if (wrapped) put_back_wrap(&X[r], md.wrap);
+        } else if (cpart[0] || wrapped) {
+            atomicOr(flags, 1ull << r);
+        }
     }
+}
+
+// ------------------------------------------------------------------ homomorphism bound
+
+// Homomorphisms of the sub-template into the graph rooted at each row, in
+// double: S[v] = A[v] * sum over neighbours u of P[u] (A or P NULL: the
+// single-vertex sub-template, 1 at every row).  One wavefront per row.
+__global__ __launch_bounds__(kBlock) void hom_step_kernel(int64_t n, const int64_t *__restrict__ rp,
+                                                         const int32_t *__restrict__ ci,
+                                                         const double *__restrict__ A,
+                                                         const double *__restrict__ P,
+                                                         double *__restrict__ S) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t waves = (int64_t)gridDim.x * kWaves;
+    for (int64_t v = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); v < n; v += waves) {
+        const int64_t e0 = rp[v], e1 = rp[v + 1];
+        double acc = 0;
+        if (P) {
+            for (int64_t e = e0 + lane; e < e1; e += kWave) acc += P[ci[e]];
+            for (int o = kWave / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
+        } else {
+            acc = (double)(e1 - e0);
+        }
+        if (lane == 0) S[v] = A ? A[v] * acc : acc;
+    }
+}
+
+// out[0] += sum of S[0..n).
+__global__ __launch_bounds__(kBlock) void hom_sum_kernel(int64_t n, const double *__restrict__ S,
+                                                        double *__restrict__ out) {
+    __shared__ double part[kBlock];
+    double acc = 0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        acc += S[i];
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicAdd(out, part[0]);
 }
 
 __global__ __launch_bounds__(kBlock) void zero_kernel(uint64_t *p, int64_t count) {
@@ -674,6 +771,21 @@ int split_lds_words(const StepShape &s) {
     return s.amode != kActiveLeaf && s.a >= 2 && w <= kSplitLdsMax ? (int)w : 0;
 }
 
+// p = 2^w - c with 61 <= w <= 63 and c odd, c <= 2^16: the forms mod_fold
+// reduces in three folds.
+bool make_modulus(uint64_t p, Modulus &m) {
+    m = Modulus{};
+    if (p == 0) return true;
+    int w = 64;
+    while (w > 0 && !((p >> (w - 1)) & 1)) --w;      // p < 2^w
+    if (w < 61 || w > 63) return false;
+    const uint64_t c = (1ull << w) - p;
+    if (c == 0 || c > (1ull << 16) || !(c & 1)) return false;
+    m.p = p; m.c = c; m.w = w;
+    m.wrap = (uint64_t)(((unsigned __int128)1 << 64) % p);
+    return true;
+}
+
 DpArgs make_args(const GraphBins &g, const StepShape &s, const StepTables &t, const uint8_t *col,
                  const uint64_t *P, const uint64_t *A, const uint64_t *Npre, uint64_t *S,
                  unsigned long long *flags, int teams) {
@@ -703,25 +815,26 @@ DpArgs make_args(const GraphBins &g, const StepShape &s, const StepTables &t, co
     a.tab_off = 8 * teams * (s.Wn * s.Bi + (s.amode == kActiveLds ? s.Wa * s.Bi : 0));
     a.split_lds = s.amode != kActiveLeaf && split_lds_words(s) > 0;
     a.flags = flags;
+    make_modulus(s.mod, a.md);
     return a;
 }
 
-template <int CH, int NB, bool BIG, int AM, bool WAVE>
+template <int CH, int NB, bool BIG, int AM, bool WAVE, bool MOD>
 hipError_t row_launch(const DpArgs &a, int lds, hipStream_t st) {
-    hipError_t e = allow_lds(dp_row_kernel<CH, NB, BIG, AM, WAVE>, lds);
+    hipError_t e = allow_lds(dp_row_kernel<CH, NB, BIG, AM, WAVE, MOD>, lds);
     if (e != hipSuccess) return e;
     const int64_t teams = WAVE ? kWaves : 1;
     const int64_t blocks = std::min<int64_t>((a.n * a.planes + teams - 1) / teams, 2 * resident_blocks(lds));
-    dp_row_kernel<CH, NB, BIG, AM, WAVE><<<dim3((unsigned)blocks), dim3(kBlock), lds, st>>>(a);
+    dp_row_kernel<CH, NB, BIG, AM, WAVE, MOD><<<dim3((unsigned)blocks), dim3(kBlock), lds, st>>>(a);
     return hipGetLastError();
 }
 
-template <int CH, int NB, bool BIG>
+template <int CH, int NB, bool BIG, bool MOD>
 hipError_t split_launch(const DpArgs &a, int lds, hipStream_t st) {
-    hipError_t e = allow_lds(dp_split_kernel<CH, NB, BIG>, lds);
+    hipError_t e = allow_lds(dp_split_kernel<CH, NB, BIG, MOD>, lds);
     if (e != hipSuccess) return e;
     const int64_t blocks = std::min<int64_t>(a.n_items * a.planes, 2 * resident_blocks(lds));
-    dp_split_kernel<CH, NB, BIG><<<dim3((unsigned)blocks), dim3(kBlock), lds, st>>>(a);
+    dp_split_kernel<CH, NB, BIG, MOD><<<dim3((unsigned)blocks), dim3(kBlock), lds, st>>>(a);
     return hipGetLastError();
 }
 
@@ -740,38 +853,45 @@ int row_chunks(const StepShape &s, bool groups) {
 
 // The row kernels keep the chunked scatter for narrow rows too: a light row's
 // few neighbours spread over more lanes that way.
-template <int AM, bool WAVE>
+template <int AM, bool WAVE, bool MOD>
 hipError_t row_dispatch(const StepShape &s, const DpArgs &a, int lds, hipStream_t st) {
     switch (row_chunks(s, false)) {
-    case 0: return row_launch<0, 1, false, AM, WAVE>(a, lds, st);
-    case 1: return row_launch<1, 8, false, AM, WAVE>(a, lds, st);
-    case 2: return row_launch<2, 8, false, AM, WAVE>(a, lds, st);
-    case 4: return row_launch<4, 4, false, AM, WAVE>(a, lds, st);
-    case 8: return row_launch<8, 2, false, AM, WAVE>(a, lds, st);
-    case 16: return row_launch<16, 1, false, AM, WAVE>(a, lds, st);
-    default: return row_launch<16, 1, true, AM, WAVE>(a, lds, st);
+    case 0: return row_launch<0, 1, false, AM, WAVE, MOD>(a, lds, st);
+    case 1: return row_launch<1, 8, false, AM, WAVE, MOD>(a, lds, st);
+    case 2: return row_launch<2, 8, false, AM, WAVE, MOD>(a, lds, st);
+    case 4: return row_launch<4, 4, false, AM, WAVE, MOD>(a, lds, st);
+    case 8: return row_launch<8, 2, false, AM, WAVE, MOD>(a, lds, st);
+    case 16: return row_launch<16, 1, false, AM, WAVE, MOD>(a, lds, st);
+    default: return row_launch<16, 1, true, AM, WAVE, MOD>(a, lds, st);
     }
 }
 
+template <bool MOD>
 hipError_t split_dispatch(const StepShape &s, const DpArgs &a, int lds, hipStream_t st) {
     switch (row_chunks(s, true)) {
-    case 0: return split_launch<0, 1, false>(a, lds, st);
-    case kGroupRows: return split_launch<kGroupRows, 1, false>(a, lds, st);
-    case 1: return split_launch<1, 8, false>(a, lds, st);
-    case 2: return split_launch<2, 8, false>(a, lds, st);
-    case 4: return split_launch<4, 4, false>(a, lds, st);
-    case 8: return split_launch<8, 2, false>(a, lds, st);
-    case 16: return split_launch<16, 1, false>(a, lds, st);
-    default: return split_launch<16, 1, true>(a, lds, st);
+    case 0: return split_launch<0, 1, false, MOD>(a, lds, st);
+    case kGroupRows: return split_launch<kGroupRows, 1, false, MOD>(a, lds, st);
+    case 1: return split_launch<1, 8, false, MOD>(a, lds, st);
+    case 2: return split_launch<2, 8, false, MOD>(a, lds, st);
+    case 4: return split_launch<4, 4, false, MOD>(a, lds, st);
+    case 8: return split_launch<8, 2, false, MOD>(a, lds, st);
+    case 16: return split_launch<16, 1, false, MOD>(a, lds, st);
+    default: return split_launch<16, 1, true, MOD>(a, lds, st);
     }
 }
 
 bool shape_ok(const StepShape &s) {
+    Modulus m;
     return s.Bi >= 1 && s.Bi <= kWave && (s.Bi & (s.Bi - 1)) == 0 && s.B % s.Bi == 0 &&
-           s.Wn >= 1 && s.Wh >= 1 && (s.p < 2 || s.Wq >= 1);
+           s.Wn >= 1 && s.Wh >= 1 && (s.p < 2 || s.Wq >= 1) && make_modulus(s.mod, m);
 }
 
 }  // namespace
+
+bool mod_supported(uint64_t p) {
+    Modulus m;
+    return p != 0 && make_modulus(p, m);
+}
 
 int rank_entries(int k1) { return k1 <= kDirectRankBits ? 1 << k1 : 256 + 9 * (1 << (k1 - 8)); }
 
@@ -815,7 +935,7 @@ hipError_t launch_dp_split(const GraphBins &g, const StepShape &s, const StepTab
     s1.amode = kActiveLeaf;                            // the pre-pass stages no active row or split table
     const DpArgs a = make_args(g, s1, t, col, P, nullptr, Npre, nullptr, flags, 1);
     const int lds = dp_lds_bytes(s1, kActiveLeaf, t.n_rank, 1);
-    return split_dispatch(s1, a, lds, st);
+    return s.mod ? split_dispatch<true>(s1, a, lds, st) : split_dispatch<false>(s1, a, lds, st);
 }
 
 hipError_t launch_dp_row(const GraphBins &g, const StepShape &s, const StepTables &t,
@@ -830,27 +950,50 @@ hipError_t launch_dp_row(const GraphBins &g, const StepShape &s, const StepTable
     // are enough rows to keep every wavefront slot of the chip busy (on a
     // small graph a row's latency matters more than the rows in flight)
     const int region = 8 * (s.Wn * s.Bi + (s.amode == kActiveLds ? s.Wa * s.Bi : 0));
-    const bool wave = region <= s.wave_row_max && g.n * (s.B / s.Bi) >= kWaveRowsMin;
+    // (residue passes always build a row per workgroup)
+    const bool wave = !s.mod && region <= s.wave_row_max && g.n * (s.B / s.Bi) >= kWaveRowsMin;
     const int teams = wave ? kWaves : 1;
     const DpArgs a = make_args(g, s, t, col, P, A, Npre, S, flags, teams);
     const int lds = dp_lds_bytes(s, s.amode, t.n_rank, teams);
-    if (wave) {
-        if (s.amode == kActiveLeaf) return row_dispatch<kActiveLeaf, true>(s, a, lds, st);
-        if (s.amode == kActiveLds) return row_dispatch<kActiveLds, true>(s, a, lds, st);
-        return row_dispatch<kActiveGlobal, true>(s, a, lds, st);
+    if (s.mod) {
+        if (s.amode == kActiveLeaf) return row_dispatch<kActiveLeaf, false, true>(s, a, lds, st);
+        if (s.amode == kActiveLds) return row_dispatch<kActiveLds, false, true>(s, a, lds, st);
+        return row_dispatch<kActiveGlobal, false, true>(s, a, lds, st);
     }
-    if (s.amode == kActiveLeaf) return row_dispatch<kActiveLeaf, false>(s, a, lds, st);
-    if (s.amode == kActiveLds) return row_dispatch<kActiveLds, false>(s, a, lds, st);
-    return row_dispatch<kActiveGlobal, false>(s, a, lds, st);
+    if (wave) {
+        if (s.amode == kActiveLeaf) return row_dispatch<kActiveLeaf, true, false>(s, a, lds, st);
+        if (s.amode == kActiveLds) return row_dispatch<kActiveLds, true, false>(s, a, lds, st);
+        return row_dispatch<kActiveGlobal, true, false>(s, a, lds, st);
+    }
+    if (s.amode == kActiveLeaf) return row_dispatch<kActiveLeaf, false, false>(s, a, lds, st);
+    if (s.amode == kActiveLds) return row_dispatch<kActiveLds, false, false>(s, a, lds, st);
+    return row_dispatch<kActiveGlobal, false, false>(s, a, lds, st);
 }
 
-hipError_t launch_reduce(int64_t n, const uint64_t *S, int W, int B, int Bi,
+hipError_t launch_reduce(int64_t n, const uint64_t *S, int W, int B, int Bi, uint64_t mod,
                          unsigned long long *X, unsigned long long *flags, hipStream_t st) {
     if (n <= 0 || B <= 0) return hipSuccess;
-    if (Bi < 1 || B % Bi) return hipErrorInvalidValue;
+    Modulus md;
+    if (Bi < 1 || B % Bi || !make_modulus(mod, md)) return hipErrorInvalidValue;
     const int64_t total = n * W;
     const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((total + kBlock - 1) / kBlock, 1024));
-    reduce_kernel<<<dim3(blocks, (unsigned)B), dim3(kBlock), 0, st>>>(n, S, W, Bi, X, flags);
+    if (mod) reduce_kernel<true><<<dim3(blocks, (unsigned)B), dim3(kBlock), 0, st>>>(n, S, W, Bi, md, X, flags);
+    else reduce_kernel<false><<<dim3(blocks, (unsigned)B), dim3(kBlock), 0, st>>>(n, S, W, Bi, md, X, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_hom_step(const GraphBins &g, const double *A, const double *P, double *S, hipStream_t st) {
+    if (g.n <= 0) return hipSuccess;
+    if (!S) return hipErrorInvalidValue;
+    const int64_t blocks = std::min<int64_t>((g.n + kWaves - 1) / kWaves, kMaxStrideBlocks);
+    hom_step_kernel<<<dim3((unsigned)blocks), dim3(kBlock), 0, st>>>(g.n, g.row_ptr, g.col_idx, A, P, S);
+    return hipGetLastError();
+}
+
+hipError_t launch_hom_sum(int64_t n, const double *S, double *out, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((n + kBlock - 1) / kBlock, 1024);
+    hom_sum_kernel<<<dim3((unsigned)blocks), dim3(kBlock), 0, st>>>(n, S, out);
     return hipGetLastError();
 }
 

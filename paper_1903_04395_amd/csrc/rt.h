@@ -67,6 +67,7 @@ struct PassSpec {
     const Plan *P = nullptr;
     int k = 0;
     uint64_t seed = 0, first = 0;
+    uint64_t mod = 0;              // 0: exact uint64 counts; else counts mod this prime
 };
 
 // Device buffers one in-flight pass uses besides the resident graph and the
@@ -79,11 +80,11 @@ struct PassBuffers {
 
 struct GraphExecKey {
     int graph_id, tmpl_id, k, batch, interleave, lds_max, wave_row_max, seg;
-    uint64_t bufgen;
+    uint64_t mod, bufgen;
     bool operator<(const GraphExecKey &o) const {
-        return std::tie(graph_id, tmpl_id, k, batch, interleave, lds_max, wave_row_max, seg, bufgen) <
+        return std::tie(graph_id, tmpl_id, k, batch, interleave, lds_max, wave_row_max, seg, mod, bufgen) <
                std::tie(o.graph_id, o.tmpl_id, o.k, o.batch, o.interleave, o.lds_max, o.wave_row_max, o.seg,
-                        o.bufgen);
+                        o.mod, o.bufgen);
     }
 };
 

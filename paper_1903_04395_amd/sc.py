@@ -164,6 +164,11 @@ def lib():
             "sc_color_of": (ctypes.c_int32, [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int32]),
             "sc_run": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int32,
                                       _vp, _u64p, _u8p, _dblp, _dblp]),
+            "sc_run_exact": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int32,
+                                            _vp, _u64p, _u8p, _dblp, _dblp, _dblp]),
+            "sc_run_mod": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int32,
+                                          _vp, ctypes.c_uint64, _u64p]),
+            "sc_hom_count": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _dblp]),
             "sc_set_option": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int64]),
             "sc_get_option": (ctypes.c_int, [_vp, ctypes.c_int32, _i64p]),
             "sc_run_batch": (ctypes.c_int, [_vp, ctypes.POINTER(Job), ctypes.c_int32, _vp]),
@@ -422,3 +427,28 @@ class Context:
         self._check(self._L.sc_run(self._h, gid, tid, first, R, stream, _p(counts, _u64p), _p(ovf, _u8p),
                                    ctypes.byref(em), ctypes.byref(ec)))
         return counts[:R], ovf[:R], em.value, ec.value
+
+    def run_exact(self, gid, tid, first, n_colorings, stream=None):
+        """Returns (counts [int], exact uint8[R], hom_bound, est_maps, est_copies): the
+        counts as Python integers, combined from four uint64 limbs."""
+        R = int(n_colorings)
+        limbs = np.zeros((max(R, 1), 4), np.uint64)
+        exact = np.zeros(max(R, 1), np.uint8)
+        hb, em, ec = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        self._check(self._L.sc_run_exact(self._h, gid, tid, first, R, stream, _p(limbs, _u64p), _p(exact, _u8p),
+                                         ctypes.byref(hb), ctypes.byref(em), ctypes.byref(ec)))
+        counts = [sum(int(limbs[r, i]) << (64 * i) for i in range(4)) for r in range(R)]
+        return counts, exact[:R], hb.value, em.value, ec.value
+
+    def run_mod(self, gid, tid, first, n_colorings, p, stream=None):
+        """Returns uint64[R]: each colouring's count mod p."""
+        R = int(n_colorings)
+        res = np.zeros(max(R, 1), np.uint64)
+        self._check(self._L.sc_run_mod(self._h, gid, tid, first, R, stream, int(p), _p(res, _u64p)))
+        return res[:R]
+
+    def hom_count(self, gid, tid, stream=None):
+        """Homomorphisms of the template into the graph (double)."""
+        out = ctypes.c_double()
+        self._check(self._L.sc_hom_count(self._h, gid, tid, stream, ctypes.byref(out)))
+        return out.value

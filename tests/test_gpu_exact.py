@@ -1,0 +1,162 @@
+"""GPU parity of the exact wide counts.  The residue passes (the counting DP
+with every entry taken mod p) against the oracle's modular DP, bit-exact; the
+CRT-combined counts of sc_run_exact against the oracle's exact counts (Python
+integers); the homomorphism bound against closed forms.  Calls go through the
+C ABI."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1903_04395_amd import inputs as I
+from paper_1903_04395_amd import sc
+
+pytestmark = pytest.mark.gpu
+
+# a supported modulus that is not prime: residues need no primality
+COMPOSITE = 2**62 - 1
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available()
+    c = sc.Context(0)
+    yield c
+    c.close()
+
+
+def hubby_graph(seed, n=1500, m=4000, hubs=3, hub_deg=900):
+    """Sparse random graph plus a few high-degree hubs, so counts pass 2^64."""
+    rng = np.random.default_rng(seed)
+    e = I.erdos_renyi(n, m, seed).edges()
+    src, dst = [e[:, 0]], [e[:, 1]]
+    for h in range(hubs):
+        nb = rng.choice(np.arange(hubs, n), size=hub_deg, replace=False)
+        src.append(np.full(hub_deg, h))
+        dst.append(nb)
+    return I.csr_from_edges(n, np.concatenate(src), np.concatenate(dst))
+
+
+def setup(ctx, g, t, edges, k, seed, R, root=-1):
+    gid = ctx.load_graph(g)
+    tid = ctx.load_template(t, edges, root)
+    ctx.set_colors(k, seed)
+    info = ctx.plan_info(gid, tid, R)
+    return gid, tid, info
+
+
+RESIDUE_CASES = [
+    # (name, graph, t, edges, k, seed, first, R, options)
+    ("er_path5", lambda: I.erdos_renyi(2000, 10000, 1), 5, I.path(5), 5, 2024, 0, 8, {}),
+    ("rmat12_tree10", lambda: I.rmat(12, 16, seed=2), 10, I.prufer_tree(10, 0), 10, 5, 3, 8,
+     {sc.SC_OPT_SEGMENT: 128}),
+    ("chunglu_tree12", lambda: I.chung_lu(3000, 20, 2.1, seed=3), 12, I.prufer_tree(12, 3), 12, 7, 0, 4, {}),
+    ("hubby_star9", lambda: hubby_graph(4), 9, I.star(9), 9, 11, 1, 6, {sc.SC_OPT_SEGMENT: 256}),
+    ("hubby_tree11_bi2", lambda: hubby_graph(6), 11, I.prufer_tree(11, 6), 12, 13, 0, 6,
+     {sc.SC_OPT_INTERLEAVE: 2}),
+]
+
+
+@pytest.mark.parametrize("case", RESIDUE_CASES, ids=[c[0] for c in RESIDUE_CASES])
+def test_residues_match_the_oracle(ctx, case):
+    name, mk, t, edges, k, seed, first, R, opts = case
+    g = mk()
+    for o, v in opts.items():
+        ctx.set_option(o, v)
+    try:
+        gid, tid, info = setup(ctx, g, t, edges, k, seed, R)
+        plan = (info.root, info.children())
+        for p in O.PRIMES + (COMPOSITE,):
+            say(f"{name}: n={g.n} nnz={g.nnz} t={t} k={k} R={R} batch={info.batch} p={p}")
+            got = ctx.run_mod(gid, tid, first, R, p)
+            want = O.count_mod(g, t, plan, k, seed, first, R, p)
+            assert np.array_equal(got, want), (p, got, want)
+        ctx.unload_graph(gid)
+    finally:
+        for o in opts:
+            ctx.set_option(o, sc.OPTION_DEFAULTS[o])
+
+
+# a 12-vertex spider: nine legs of length 1 and one of length 2
+SPIDER = np.array([(0, i) for i in range(1, 10)] + [(0, 10), (10, 11)], np.int32)
+
+
+@pytest.mark.parametrize("t,edges,root", [(12, I.star(12), 0), (12, I.star(12), 1),
+                                          (12, SPIDER, -1), (12, SPIDER, 11)])
+def test_exact_counts_past_2_64(ctx, t, edges, root):
+    """Hub vertices push counts past 2^64; sc_run_exact recovers them exactly."""
+    g = hubby_graph(9)
+    k, seed, first, R = 12, 21, 2, 5
+    gid, tid, info = setup(ctx, g, t, edges, k, seed, R, root)
+    say(f"exact: n={g.n} nnz={g.nnz} t={t} root={info.root} R={R} batch={info.batch}")
+    counts, exact, hom, maps, copies = ctx.run_exact(gid, tid, first, R)
+    want = O.count_exact(g, t, (info.root, info.children()), k, seed, first, R)
+    assert counts == want
+    assert exact.all()
+    assert max(want) >= 2**64                      # the case the residues are for
+    assert hom >= max(want)
+    # the uint64 pass agrees mod 2^64 and flags exactly the wide counts
+    c64, ovf, _, _ = ctx.run(gid, tid, first, R)
+    assert [int(x) for x in c64] == [x % 2**64 for x in want]
+    assert [bool(f) for f in ovf] == [x >= 2**64 for x in want]
+    P = O.colorful_probability(k, t)
+    assert maps == pytest.approx(sum(want) / R / P, rel=1e-12)
+    assert copies == pytest.approx(maps / O.aut(t, edges), rel=1e-12)
+    ctx.unload_graph(gid)
+
+
+def test_exact_without_overflow_is_the_uint64_count(ctx):
+    g = I.erdos_renyi(3000, 12000, 4)
+    t, k, seed, R = 7, 7, 3, 12
+    gid, tid, info = setup(ctx, g, t, I.prufer_tree(7, 4), k, seed, R)
+    c64, ovf, maps64, _ = ctx.run(gid, tid, 0, R)
+    assert not ovf.any()
+    counts, exact, hom, maps, _ = ctx.run_exact(gid, tid, 0, R)
+    assert counts == [int(x) for x in c64] and exact.all()
+    assert maps == pytest.approx(maps64, rel=1e-12)
+    assert hom >= max(counts)
+    ctx.unload_graph(gid)
+
+
+def walks(g, t):
+    """1^T A^(t-1) 1 in exact integers: homomorphisms of the t-vertex path."""
+    x = [1] * g.n
+    rp, ci = g.row_ptr, g.col_idx
+    for _ in range(t - 1):
+        x = [sum(x[int(u)] for u in ci[rp[v]:rp[v + 1]]) for v in range(g.n)]
+    return sum(x)
+
+
+@pytest.mark.parametrize("root", [0, 3])
+def test_hom_count_closed_forms(ctx, root):
+    """Stars: sum over v of deg(v)^(t-1); paths: 1^T A^(t-1) 1."""
+    g = hubby_graph(2, n=600, m=1500, hubs=2, hub_deg=400)
+    deg = [int(d) for d in g.degrees()]
+    gid = ctx.load_graph(g)
+    ctx.set_colors(12, 1)
+    for t in (2, 5, 12):
+        tid = ctx.load_template(t, I.star(t), min(root, t - 1))
+        want = sum(d ** (t - 1) for d in deg)
+        assert ctx.hom_count(gid, tid) == pytest.approx(want, rel=1e-12)
+        tid = ctx.load_template(t, I.path(t), min(root, t - 1))
+        assert ctx.hom_count(gid, tid) == pytest.approx(walks(g, t), rel=1e-12)
+    ctx.unload_graph(gid)
+
+
+def test_run_mod_rejects_unsupported_moduli(ctx):
+    g = I.erdos_renyi(100, 300, 1)
+    gid = ctx.load_graph(g)
+    tid = ctx.load_template(3, I.path(3), -1)
+    ctx.set_colors(3, 1)
+    for p in (2**62, 2**61 - 2, 1000003, 2**64 - 59, 0):
+        with pytest.raises(sc.ScError):
+            ctx.run_mod(gid, tid, 0, 4, p)
+    assert np.array_equal(ctx.run_mod(gid, tid, 0, 4, O.PRIMES[0]),
+                          O.count_mod(g, 3, O.root_plan(3, I.path(3), 0), 3, 1, 0, 4, O.PRIMES[0]))
+    ctx.unload_graph(gid)
