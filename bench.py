@@ -54,6 +54,9 @@ def parse():
                     help="only copy 1 GiB three times (calibrates rocprofv3 FETCH_SIZE/WRITE_SIZE)")
     ap.add_argument("--forms", action="store_true",
                     help="plain per-colouring launch loop vs batched form (config 1 and the headline workload)")
+    ap.add_argument("--exact", action="store_true",
+                    help="time exact wide counts (uint64 pass + residue passes + CRT) beside the uint64 "
+                         "pass, on the RMAT scale-20 and Chung-Lu k=12 workloads")
     ap.add_argument("--serve", action="store_true",
                     help="serving mix: RMAT 18/20/22 resident, Poisson query stream, p50/p99 latency")
     ap.add_argument("--queries", type=int, default=40, help="stream length for --serve")
@@ -256,6 +259,45 @@ def configs_bench():
     print(json.dumps({"configs": out}), flush=True)
 
 
+def exact_bench():
+    """Exact wide counts beside the uint64 pass, per call after a warm-up:
+    RMAT scale 20 / 10-vertex tree / k=10 / 8 colourings, and Chung-Lu
+    n=4,194,304 / 12-star / k=12 / 16 colourings.  Every colouring of these
+    workloads overflows 2^64, so sc_run_exact adds three residue passes."""
+    from paper_1903_04395_amd import inputs as I
+    from paper_1903_04395_amd import sc
+    ctx = sc.Context(0)
+    out = {}
+    cases = [("rmat20-tree10-k10", lambda: I.rmat(20, 16, seed=0), 10, I.prufer_tree(10, 0), 0, 10, 1, 8),
+             ("chunglu4m-star12-k12", lambda: I.chung_lu(4194304, 30, 2.1, seed=3), 12, I.star(12), 0, 12, 7, 16)]
+    for name, gen, t, edges, root, k, seed, R in cases:
+        g = gen()
+        gid = ctx.load_graph(g)
+        tid = ctx.load_template(t, edges, root)
+        ctx.set_colors(k, seed)
+        ctx.run(gid, tid, 0, R)
+        ctx.run_exact(gid, tid, 0, R)
+        t0 = time.perf_counter()
+        c64, ovf, _, _ = ctx.run(gid, tid, R, R)
+        t1 = time.perf_counter()
+        counts, exact, hom, maps, copies = ctx.run_exact(gid, tid, R, R)
+        t2 = time.perf_counter()
+        t3 = time.perf_counter()
+        hom2 = ctx.hom_count(gid, tid)
+        t4 = time.perf_counter()
+        out[name] = {"colorings": R, "overflowed": int(ovf.sum()), "exact": int(exact.sum()),
+                     "s_uint64": round(t1 - t0, 4), "s_exact": round(t2 - t1, 4),
+                     "exact_over_uint64": round((t2 - t1) / (t1 - t0), 2), "s_hom_count": round(t4 - t3, 4),
+                     "hom_bound_log2": round(math.log2(hom2), 1) if hom2 > 0 else None,
+                     "max_count_log2": round(math.log2(max(counts)), 1) if max(counts) > 0 else None,
+                     "est_maps": maps, "est_copies": copies}
+        print(f"[bench] exact {name}: {out[name]}", file=sys.stderr, flush=True)
+        ctx.unload_graph(gid)
+        del g
+    ctx.close()
+    print(json.dumps({"exact": out}), flush=True)
+
+
 def copy_probe():
     import torch
     a = torch.empty(1 << 27, dtype=torch.int64, device="cuda")   # 1 GiB
@@ -299,7 +341,7 @@ def main():
     if args.gather_probe:
         gather_probe()
         return
-    if args.forms or args.serve or args.configs:
+    if args.forms or args.serve or args.configs or args.exact:
         import torch
         if not torch.cuda.is_available():
             print("bench.py needs a GPU", file=sys.stderr)
@@ -308,6 +350,8 @@ def main():
             forms_bench()
         elif args.serve:
             serve_bench(args.queries, args.qps, args.streams)
+        elif args.exact:
+            exact_bench()
         else:
             configs_bench()
         return

@@ -79,5 +79,21 @@ __host__ __device__ __forceinline__ uint64_t mod_mad(uint64_t acc, uint64_t a, u
     return mod_fold((unsigned __int128)a * b + acc, m);
 }
 
+// Lazy sums of products: (top * 2^128 + lo) mod p.  A sum of products of
+// residues (each below 2^126) is kept exactly as a 128-bit word plus a count
+// of its carries, and reduced once.  2^128 mod p = wrap^2 (wrap = 2^(64-w) c
+// < 2^19, so wrap^2 < p).
+__host__ __device__ __forceinline__ void wide_add_product(unsigned __int128 &lo, uint64_t &top, uint64_t a,
+                                                          uint64_t b) {
+    const unsigned __int128 pr = (unsigned __int128)a * b;
+    lo += pr;
+    top += (uint64_t)(lo < pr);
+}
+
+__host__ __device__ __forceinline__ uint64_t mod_wide_fold(unsigned __int128 lo, uint64_t top,
+                                                           const Modulus &m) {
+    return mod_fold((unsigned __int128)top * (m.wrap * m.wrap) + mod_fold(lo, m), m);
+}
+
 }  // namespace kern
 }  // namespace sc

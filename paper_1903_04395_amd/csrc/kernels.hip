@@ -471,7 +471,9 @@ __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t x, int mask) {
 // Each output entry is summed by a group of eg adjacent lanes (every eg-th
 // pair), whose partial sums meet through cross-lane shuffles; all terms are
 // non-negative, so a carry in any partial sum or in their combination means
-// the exact sum reaches 2^64.
+// the exact sum reaches 2^64.  MOD: each lane keeps its sum of products
+// exactly (a 128-bit word and a count of its carries) and reduces it mod p
+// once; the lanes then meet by modular adds.
 template <int AM, bool MOD>
 __device__ __forceinline__ void emit_row(const Team &tm, const DpArgs &a, int64_t v, int pl,
                                          const uint64_t *Nl, const uint64_t *Al, const uint32_t *split,
@@ -492,6 +494,8 @@ __device__ __forceinline__ void emit_row(const Team &tm, const DpArgs &a, int64_
         const int D = q >> a.sh, ri = q & (a.Bi - 1);
         uint64_t acc = 0;
         uint32_t ovf = 0;
+        unsigned __int128 wlo = 0;                  // MOD: the lane's exact sum of products,
+        uint64_t wtop = 0;                          // reduced once below
         if (q < Ls) {
             const uint32_t *sp = split + (int64_t)D * a.nsplit;
             int j = g;
@@ -507,7 +511,7 @@ __device__ __forceinline__ void emit_row(const Team &tm, const DpArgs &a, int64_
                 }
                 if constexpr (MOD) {
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) acc = mod_mad(acc, x[i], y[i], a.md);
+                    for (int i = 0; i < 4; ++i) wide_add_product(wlo, wtop, x[i], y[i]);
                 } else if (lean) {
 #pragma unroll
                     for (int i = 0; i < 4; ++i) acc = mad_ovf3(acc, x[i], y[i], ovf);
@@ -519,10 +523,11 @@ __device__ __forceinline__ void emit_row(const Team &tm, const DpArgs &a, int64_
             for (; j < a.nsplit; j += step) {
                 const uint32_t pr = sp[j];
                 const uint64_t xa = Ar[((pr & 0xffffu) << a.sh) + ri], yn = Nl[((pr >> 16) << a.sh) + ri];
-                if constexpr (MOD) acc = mod_mad(acc, xa, yn, a.md);
+                if constexpr (MOD) wide_add_product(wlo, wtop, xa, yn);
                 else acc = mad_ovf(acc, xa, yn, ovf);
             }
         }
+        if constexpr (MOD) acc = mod_wide_fold(wlo, wtop, a.md);
         for (int o = 1; o < a.eg; o <<= 1) {
             const uint64_t y = shfl_xor_u64(acc, o);
             if constexpr (MOD) {
@@ -950,11 +955,15 @@ hipError_t launch_dp_row(const GraphBins &g, const StepShape &s, const StepTable
     // are enough rows to keep every wavefront slot of the chip busy (on a
     // small graph a row's latency matters more than the rows in flight)
     const int region = 8 * (s.Wn * s.Bi + (s.amode == kActiveLds ? s.Wa * s.Bi : 0));
-    // (residue passes always build a row per workgroup)
-    const bool wave = !s.mod && region <= s.wave_row_max && g.n * (s.B / s.Bi) >= kWaveRowsMin;
+    const bool wave = region <= s.wave_row_max && g.n * (s.B / s.Bi) >= kWaveRowsMin;
     const int teams = wave ? kWaves : 1;
     const DpArgs a = make_args(g, s, t, col, P, A, Npre, S, flags, teams);
     const int lds = dp_lds_bytes(s, s.amode, t.n_rank, teams);
+    if (s.mod && wave) {
+        if (s.amode == kActiveLeaf) return row_dispatch<kActiveLeaf, true, true>(s, a, lds, st);
+        if (s.amode == kActiveLds) return row_dispatch<kActiveLds, true, true>(s, a, lds, st);
+        return row_dispatch<kActiveGlobal, true, true>(s, a, lds, st);
+    }
     if (s.mod) {
         if (s.amode == kActiveLeaf) return row_dispatch<kActiveLeaf, false, true>(s, a, lds, st);
         if (s.amode == kActiveLds) return row_dispatch<kActiveLds, false, true>(s, a, lds, st);

@@ -1,5 +1,7 @@
 """Writes tests/golden/full_size.json: oracle residues and overflow flags for
-sampled colourings of the full-size workloads.
+sampled colourings of the full-size workloads, and, with --exact, the exact
+counts of the sampled colourings that overflowed (Chinese remaindering of the
+oracle's residues mod 2^64 and mod three primes).
 
 Calls only the CPU oracle (oracle/) and the seeded input generators; nothing
 here touches the HIP library.  Each entry names its generator call, template,
@@ -7,7 +9,7 @@ explicit plan (root and ordered children, so the flag is comparable), k,
 seed and the colourings computed.  Run on a host with enough memory (the
 k = 12 entries hold up to ~80 GB of tables at once):
 
-    python tests/golden/make_full_size.py [--out PATH] [names...]
+    python tests/golden/make_full_size.py [--out PATH] [--exact] [names...]
 
 Entries already present are kept; results are written after each colouring.
 """
@@ -48,7 +50,7 @@ def make_tree(spec):
     return spec[1], I.prufer_tree(spec[1], spec[2])
 
 
-def main(names, out=OUT):
+def main(names, out=OUT, exact=False):
     data = json.load(open(out)) if os.path.exists(out) else {}
     graphs = {}
     for name in names:
@@ -77,6 +79,21 @@ def main(names, out=OUT):
             os.replace(out + ".tmp", out)
             print(f"[golden] {name} colouring {r}: {int(c[0])} flag {int(f[0])} "
                   f"({time.time() - t0:.0f}s, {O.threads()} threads)", flush=True)
+        if not exact:
+            continue
+        ex = entry.setdefault("exact", {})
+        for r in cols:
+            if str(r) in ex or not entry["results"][str(r)][1]:
+                continue
+            t0 = time.time()
+            res = [int(entry["results"][str(r)][0])]
+            res += [int(O.count_mod(g, t, (rt, children), k, seed, r, 1, p)[0]) for p in O.PRIMES]
+            ex[str(r)] = str(O.crt(res, [2**64] + list(O.PRIMES)))
+            data[name] = entry
+            with open(out + ".tmp", "w") as fh:
+                json.dump(data, fh, indent=1)
+            os.replace(out + ".tmp", out)
+            print(f"[golden] {name} colouring {r}: exact {ex[str(r)]} ({time.time() - t0:.0f}s)", flush=True)
 
 
 if __name__ == "__main__":
@@ -84,4 +101,6 @@ if __name__ == "__main__":
     out = OUT
     if argv[:1] == ["--out"]:
         out, argv = argv[1], argv[2:]
-    main(argv or list(ENTRIES), out)
+    exact = "--exact" in argv
+    argv = [a for a in argv if a != "--exact"]
+    main(argv or list(ENTRIES), out, exact)

@@ -71,6 +71,26 @@ HARNESS = textwrap.dedent(r"""
                 if (sc::kern::mod_mad(c, a, b, md) != (uint64_t)(((u128)a * b + c) % md.p)) { printf("FAIL mad\n"); bad++; }
                 n += 3;
             }
+            // lazy sums of up to 40 products of residues against term-by-term reduction
+            const uint64_t w2 = (uint64_t)((((u128)1 << 64) % md.p) * (((u128)1 << 64) % md.p) % md.p);
+            for (long i = 0; i < 200000; ++i) {
+                u128 lo = 0;
+                uint64_t top = 0, want = 0;
+                const int terms = 1 + (int)(h() % 40);
+                for (int j = 0; j < terms; ++j) {
+                    uint64_t a = h() % md.p, b = h() % md.p;
+                    if (i % 4 == 0) { a = md.p - 1; b = md.p - 1 - (h() % 2); }
+                    sc::kern::wide_add_product(lo, top, a, b);
+                    want = (uint64_t)(((u128)a * b % md.p + want) % md.p);
+                }
+                if (sc::kern::mod_wide_fold(lo, top, md) != want) { printf("FAIL wide\n"); bad++; }
+                // arbitrary (top, lo), against (top * (2^128 mod p) + lo) mod p
+                const u128 x = ((u128)h() << 64) | h();
+                const uint64_t t2 = h() >> (h() % 64);
+                const uint64_t ref = (uint64_t)(((u128)(t2 % md.p) * w2 % md.p + x % md.p) % md.p);
+                if (sc::kern::mod_wide_fold(x, t2, md) != ref) { printf("FAIL widefold\n"); bad++; }
+                n += 2;
+            }
         }
         printf("%s %ld\n", bad ? "BAD" : "OK", n);
         return bad != 0;

@@ -60,6 +60,9 @@ RESIDUE_CASES = [
     ("hubby_star9", lambda: hubby_graph(4), 9, I.star(9), 9, 11, 1, 6, {sc.SC_OPT_SEGMENT: 256}),
     ("hubby_tree11_bi2", lambda: hubby_graph(6), 11, I.prufer_tree(11, 6), 12, 13, 0, 6,
      {sc.SC_OPT_INTERLEAVE: 2}),
+    # enough rows that light steps build one row per wavefront
+    ("chunglu40k_tree7_rows_per_wavefront", lambda: I.chung_lu(40000, 10, 2.2, seed=8), 7, I.prufer_tree(7, 8),
+     7, 17, 0, 8, {}),
 ]
 
 

@@ -68,3 +68,28 @@ def test_full_size_matches_oracle(ctx, name):
     for r, (cnt, flag) in e["results"].items():
         assert int(counts[int(r)]) == int(cnt), (name, r)
         assert int(ovf[int(r)]) == flag, (name, r)
+
+
+@pytest.mark.parametrize("name", list(RUN_COLOURINGS))
+def test_full_size_exact_counts(ctx, name):
+    """sc_run_exact at full size: the sampled colourings' exact counts (past
+    2^64) against the oracle's, every count certified exact."""
+    data = load()
+    if name not in data or not data[name].get("exact"):
+        pytest.skip(f"no exact golden values for {name}")
+    e = data[name]
+    print(f"[case] {name} exact: generating and loading the graph", flush=True)
+    gid = graph_for(ctx, e["graph"])
+    tid = ctx.load_template_plan(e["t"], e["root"], e["children"])
+    ctx.set_colors(e["k"], e["seed"])
+    R = RUN_COLOURINGS[name]
+    t0 = time.perf_counter()
+    counts, exact, hom, _, _ = ctx.run_exact(gid, tid, 0, R)
+    print(f"[case] {name} exact: {R} colourings in {time.perf_counter() - t0:.3f} s, "
+          f"homomorphism bound 2^{np.log2(hom):.1f}", flush=True)
+    assert exact.all()
+    for r, (cnt, _) in e["results"].items():
+        assert counts[int(r)] % 2**64 == int(cnt), (name, r)
+    for r, x in e["exact"].items():
+        assert counts[int(r)] == int(x), (name, r)
+        assert hom >= int(x)
