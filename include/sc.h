@@ -200,6 +200,41 @@ int sc_run_exact(sc_ctx *ctx, int32_t graph_id, int32_t tmpl_id, uint64_t first_
                  int32_t n_colorings, void *stream, uint64_t *counts, uint8_t *exact,
                  double *hom_bound, double *est_maps, double *est_copies);
 
+/* Estimates to relative error eps with probability at least 1 - delta.  The
+ * paper bounds the colourings an (eps, delta)-approximation takes by
+ * O(e^k log(1/delta) / eps^2) (Lemma 3 and its proof); here the constants come
+ * from the median of means: the count estimate X/P of one colouring (P the
+ * colourful probability, Sec. 2.1 phase 1) is unbiased with relative variance
+ * at most 1/P - 1, so a mean of g >= 4 (1/P - 1) / eps^2 colourings misses by
+ * more than eps with probability at most 1/4 (Chebyshev), and the median of
+ * m >= 8 ln(1/delta) such means (m odd) misses with probability at most delta
+ * (Hoeffding).
+ * sc_colorings_for: m (groups) and g (per_group) of that bound, pure host.
+ *   Errors: SC_EINVAL (eps <= 0, delta outside (0, 1), k < t, k > SC_MAX_K).
+ * sc_estimate: runs colourings first_coloring, first_coloring + 1, ... with
+ *   exact counts (as sc_run_exact) and returns the median of the means of m
+ *   groups of consecutive colourings.  mode SC_EST_BOUND runs m * g colourings
+ *   of the bound (SC_EINVAL if that exceeds max_colorings > 0); mode
+ *   SC_EST_SAMPLE uses the sample relative variance in place of 1/P - 1,
+ *   re-evaluated after each round (the first round 4m colourings, each round at
+ *   most doubling the total), and stops when enough colourings ran or at
+ *   max_colorings (> 0) -- a heuristic: the variance is estimated, not bounded.
+ *   Synchronous.  Errors: as sc_run_exact, SC_EINVAL for bad eps/delta/mode. */
+enum { SC_EST_BOUND = 0, SC_EST_SAMPLE = 1 };
+typedef struct {
+    double est_maps, est_copies;   /* median of group means; NaN if a count is not exact */
+    double mean_maps;              /* mean over every colouring run */
+    double rel_stderr;             /* sample standard error of mean_maps, relative */
+    int64_t colorings;             /* colourings run */
+    int64_t per_group;             /* colourings per group used by the median */
+    int64_t needed;                /* colourings the rule asked for at the end */
+    int32_t groups;
+    int32_t exact;                 /* 1: every count exact */
+} sc_estimate_t;
+int sc_colorings_for(int32_t k, int32_t t, double eps, double delta, int32_t *groups, int64_t *per_group);
+int sc_estimate(sc_ctx *ctx, int32_t graph_id, int32_t tmpl_id, uint64_t first_coloring, double eps,
+                double delta, int32_t mode, int64_t max_colorings, void *stream, sc_estimate_t *out);
+
 /* Residues: residues[r] = (colourful count of colouring first_coloring + r) mod p,
  * for p = 2^w - c with 61 <= w <= 63 and odd c <= 2^16 (p need not be prime).
  * Synchronous.  Errors: SC_EINVAL (unsupported p, NULL output), else as sc_run. */

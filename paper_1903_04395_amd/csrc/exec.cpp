@@ -4,6 +4,7 @@
 // sc_run_batch does the same for many (graph, template, k, seed) jobs at
 // once; sc_autotune picks the interleave and LDS limit by timing real passes.
 #include <algorithm>
+#include <climits>
 #include <atomic>
 #include <cmath>
 #include <cstdio>
@@ -393,6 +394,95 @@ int check_run_args(sc_ctx *c, int gid, int tid, int ncol) {
     return SC_OK;
 }
 
+// Count of four little-endian limbs as a long double.
+long double limbs_value(const uint64_t *l) {
+    return (long double)l[0] + std::ldexp((long double)l[1], 64) + std::ldexp((long double)l[2], 128) +
+           std::ldexp((long double)l[3], 192);
+}
+
+// Exact counts of colourings first..first+n-1 as four limbs each: the uint64
+// pass, then residue passes for the colourings that overflowed, combined by
+// CRT and certified by the homomorphism count (computed when a colouring
+// overflowed or `want_hom`, into *H if that is still NaN).
+int exact_counts(sc_ctx *c, int gid, int tid, uint64_t first, int ncol, hipStream_t st, uint64_t *counts,
+                 uint8_t *exact, bool want_hom, double *H) {
+    int rc;
+    std::vector<uint64_t> c64((size_t)ncol);
+    std::vector<uint8_t> ovf((size_t)ncol);
+    {
+        std::vector<PassJob> passes;
+        if ((rc = plan_job(c, 0, gid, tid, c->k, c->seed, first, ncol, passes))) return rc;
+        rc = run_passes(c, passes, st, [&](const PassJob &p, const uint64_t *res) {
+            unpack_pass(res, p.P.batch, c64.data() + p.offset, ovf.data() + p.offset);
+        });
+        if (rc) return rc;
+    }
+    // the colourings that overflowed, in runs of consecutive ones, get residue
+    // passes modulo each prime
+    std::vector<std::pair<int, int>> runs;
+    for (int r = 0; r < ncol; ++r) {
+        if (!ovf[r]) continue;
+        if (!runs.empty() && runs.back().first + runs.back().second == r) ++runs.back().second;
+        else runs.push_back({r, 1});
+    }
+    std::vector<uint64_t> res((size_t)3 * ncol);
+    if (!runs.empty()) {
+        std::vector<PassJob> passes;
+        for (int i = 0; i < 3; ++i)
+            for (auto &ru : runs) {
+                std::vector<PassJob> mine;
+                if ((rc = plan_job(c, i, gid, tid, c->k, c->seed, first + (uint64_t)ru.first, ru.second, mine)))
+                    return rc;
+                for (auto &p : mine) {
+                    p.mod = kPrimes[i];
+                    p.offset += ru.first;
+                    passes.push_back(std::move(p));
+                }
+            }
+        rc = run_passes(c, passes, st, [&](const PassJob &p, const uint64_t *r) {
+            for (int j = 0; j < p.P.batch; ++j) res[(size_t)p.job * ncol + p.offset + j] = r[j] % p.mod;
+        });
+        if (rc) return rc;
+    }
+    // certificate: every count is at most the homomorphism count
+    if ((!runs.empty() || want_hom) && std::isnan(*H)) {
+        if ((rc = hom_count(c, gid, tid, st, H))) return rc;
+    }
+    const bool certified = !runs.empty() && *H * kHomSlack < kCrtRange;
+    for (int r = 0; r < ncol; ++r) {
+        uint64_t *out = counts + 4 * (size_t)r;
+        if (!ovf[r]) {
+            out[0] = c64[r]; out[1] = out[2] = out[3] = 0;
+            exact[r] = 1;
+        } else {
+            const uint64_t rr[3] = {res[r], res[(size_t)ncol + r], res[2 * (size_t)ncol + r]};
+            crt_combine(c64[r], rr, out);
+            exact[r] = certified ? 1 : 0;
+        }
+    }
+    return SC_OK;
+}
+
+// Colourings for an (eps, delta)-approximation of the count from i.i.d.
+// colourings whose estimates have relative variance at most `relvar`: groups
+// of g colourings make the group mean fail (miss by more than eps) with
+// probability at most relvar / (g eps^2) <= 1/4 (Chebyshev), and the median of
+// m groups fails only if half of them do, with probability at most
+// exp(-m/8) <= delta (Hoeffding).  m is odd.
+int colorings_for(int k, int t, double eps, double delta, double relvar, int32_t *m, int64_t *g) {
+    if (!(eps > 0) || !(delta > 0) || !(delta < 1) || k < 1 || t < 1 || k < t || k > SC_MAX_K ||
+        !(relvar >= 0))
+        return SC_EINVAL;
+    long double mm = std::ceil(8.0L * std::log(1.0L / (long double)delta));
+    if (mm < 1) mm = 1;
+    int32_t mi = (int32_t)std::min<long double>(mm, 1 << 30);
+    if (mi % 2 == 0) ++mi;
+    const long double gg = std::ceil(4.0L * (long double)relvar / ((long double)eps * eps));
+    *m = mi;
+    *g = (int64_t)std::max<long double>(1, std::min<long double>(gg, (long double)(INT64_MAX / 4) / mi));
+    return SC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -450,67 +540,15 @@ int sc_run_exact(sc_ctx *c, int32_t gid, int32_t tid, uint64_t first, int32_t nc
     if (rc) return rc;
     if (ncol > 0 && (!counts || !exact)) return fail(c, SC_EINVAL, "NULL output");
     hipStream_t st = stream ? (hipStream_t)stream : c->stream;
-    // the uint64 pass: exact wherever no sum reached 2^64
-    std::vector<uint64_t> c64((size_t)ncol);
-    std::vector<uint8_t> ovf((size_t)ncol);
-    {
-        std::vector<PassJob> passes;
-        if ((rc = plan_job(c, 0, gid, tid, c->k, c->seed, first, ncol, passes))) return rc;
-        rc = run_passes(c, passes, st, [&](const PassJob &p, const uint64_t *res) {
-            unpack_pass(res, p.P.batch, c64.data() + p.offset, ovf.data() + p.offset);
-        });
-        if (rc) return rc;
-    }
-    // the colourings that overflowed, in runs of consecutive ones, get residue
-    // passes modulo each prime
-    std::vector<std::pair<int, int>> runs;
-    for (int r = 0; r < ncol; ++r) {
-        if (!ovf[r]) continue;
-        if (!runs.empty() && runs.back().first + runs.back().second == r) ++runs.back().second;
-        else runs.push_back({r, 1});
-    }
-    std::vector<uint64_t> res((size_t)3 * ncol);
-    if (!runs.empty()) {
-        std::vector<PassJob> passes;
-        for (int i = 0; i < 3; ++i)
-            for (auto &ru : runs) {
-                std::vector<PassJob> mine;
-                if ((rc = plan_job(c, i, gid, tid, c->k, c->seed, first + (uint64_t)ru.first, ru.second, mine)))
-                    return rc;
-                for (auto &p : mine) {
-                    p.mod = kPrimes[i];
-                    p.offset += ru.first;
-                    passes.push_back(std::move(p));
-                }
-            }
-        rc = run_passes(c, passes, st, [&](const PassJob &p, const uint64_t *r) {
-            for (int j = 0; j < p.P.batch; ++j) res[(size_t)p.job * ncol + p.offset + j] = r[j] % p.mod;
-        });
-        if (rc) return rc;
-    }
-    // certificate: every count is at most the homomorphism count
     double H = NAN;
-    if (!runs.empty() || hom_bound) {
-        if ((rc = hom_count(c, gid, tid, st, &H))) return rc;
-    }
-    const bool certified = !runs.empty() && H * kHomSlack < kCrtRange;
+    if ((rc = exact_counts(c, gid, tid, first, ncol, st, counts, exact, hom_bound != nullptr, &H))) return rc;
+    if (hom_bound) *hom_bound = H;
     long double sum = 0;
     bool all = true;
     for (int r = 0; r < ncol; ++r) {
-        uint64_t *out = counts + 4 * (size_t)r;
-        if (!ovf[r]) {
-            out[0] = c64[r]; out[1] = out[2] = out[3] = 0;
-            exact[r] = 1;
-        } else {
-            const uint64_t rr[3] = {res[r], res[(size_t)ncol + r], res[2 * (size_t)ncol + r]};
-            crt_combine(c64[r], rr, out);
-            exact[r] = certified ? 1 : 0;
-        }
         all &= exact[r] != 0;
-        sum += (long double)out[0] + std::ldexp((long double)out[1], 64) + std::ldexp((long double)out[2], 128) +
-               std::ldexp((long double)out[3], 192);
+        sum += limbs_value(counts + 4 * (size_t)r);
     }
-    if (hom_bound) *hom_bound = H;
     const Template &T = *c->tmpls[tid];
     double m = NAN, cp = NAN;
     if (ncol > 0 && all) {
@@ -519,6 +557,99 @@ int sc_run_exact(sc_ctx *c, int32_t gid, int32_t tid, uint64_t first, int32_t nc
     }
     if (est_maps) *est_maps = m;
     if (est_copies) *est_copies = cp;
+    return SC_OK;
+}
+
+int sc_colorings_for(int32_t k, int32_t t, double eps, double delta, int32_t *groups, int64_t *per_group) {
+    if (!groups || !per_group) return SC_EINVAL;
+    return colorings_for(k, t, eps, delta, 1.0 / colorful_probability(k, t) - 1.0, groups, per_group);
+}
+
+int sc_estimate(sc_ctx *c, int32_t gid, int32_t tid, uint64_t first, double eps, double delta, int32_t mode,
+                int64_t max_colorings, void *stream, sc_estimate_t *out) {
+    if (!c) return SC_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    if (!out) return fail(c, SC_EINVAL, "NULL output");
+    int rc = check_run_args(c, gid, tid, 0);
+    if (rc) return rc;
+    if (mode != SC_EST_BOUND && mode != SC_EST_SAMPLE) return fail(c, SC_EINVAL, "unknown mode %d", mode);
+    const Template &T = *c->tmpls[tid];
+    const double P = colorful_probability(c->k, T.t);
+    int32_t m = 0;
+    int64_t g = 0;
+    if (colorings_for(c->k, T.t, eps, delta, 1.0 / P - 1.0, &m, &g))
+        return fail(c, SC_EINVAL, "need 0 < eps and 0 < delta < 1 (eps=%g, delta=%g)", eps, delta);
+    const int64_t cap = max_colorings > 0 ? max_colorings : INT64_MAX;
+    hipStream_t st = stream ? (hipStream_t)stream : c->stream;
+    std::vector<long double> y;                    // per colouring: count / P
+    bool all = true;
+    double H = NAN;
+    auto run = [&](int64_t n) -> int {
+        std::vector<uint64_t> limbs;
+        std::vector<uint8_t> ex;
+        while (n > 0) {
+            const int chunk = (int)std::min<int64_t>(n, 1 << 20);
+            limbs.assign(4 * (size_t)chunk, 0);
+            ex.assign((size_t)chunk, 0);
+            int r = exact_counts(c, gid, tid, first + (uint64_t)y.size(), chunk, st, limbs.data(), ex.data(), false, &H);
+            if (r) return r;
+            for (int i = 0; i < chunk; ++i) {
+                all &= ex[i] != 0;
+                y.push_back(limbs_value(limbs.data() + 4 * (size_t)i) / P);
+            }
+            n -= chunk;
+        }
+        return SC_OK;
+    };
+    int64_t need = (int64_t)m * g;                 // SC_EST_BOUND: the variance bound 1/P - 1
+    if (mode == SC_EST_BOUND) {
+        if (need > cap)
+            return fail(c, SC_EINVAL, "the bound needs %lld colourings (%d groups of %lld), above max_colorings=%lld",
+                        (long long)need, m, (long long)g, (long long)cap);
+        if ((rc = run(need))) return rc;
+    } else {
+        // SC_EST_SAMPLE: the same rule with the sample relative variance, re-evaluated
+        // after each round; rounds at most double the colourings run so far
+        int64_t next = std::min<int64_t>(cap, 4 * (int64_t)m);
+        for (;;) {
+            if ((rc = run(next - (int64_t)y.size()))) return rc;
+            long double mean = 0, var = 0;
+            for (long double v : y) mean += v;
+            mean /= (long double)y.size();
+            for (long double v : y) var += (v - mean) * (v - mean);
+            var /= (long double)(y.size() > 1 ? y.size() - 1 : 1);
+            const double rel = mean > 0 ? (double)(var / (mean * mean)) : 0.0;
+            int32_t m2 = 0;
+            int64_t g2 = 0;
+            colorings_for(c->k, T.t, eps, delta, rel, &m2, &g2);
+            need = (int64_t)m2 * g2;
+            if ((int64_t)y.size() >= need || (int64_t)y.size() >= cap) break;
+            next = std::min<int64_t>({cap, need, 2 * (int64_t)y.size()});
+        }
+    }
+    // median of the means of m groups of consecutive colourings
+    const int64_t per = (int64_t)y.size() / m;
+    std::vector<long double> means;
+    for (int32_t i = 0; i < m && per > 0; ++i) {
+        long double s = 0;
+        for (int64_t j = 0; j < per; ++j) s += y[(size_t)(i * per + j)];
+        means.push_back(s / per);
+    }
+    std::sort(means.begin(), means.end());
+    long double mean_all = 0, var = 0;
+    for (long double v : y) mean_all += v;
+    mean_all /= (long double)std::max<size_t>(1, y.size());
+    for (long double v : y) var += (v - mean_all) * (v - mean_all);
+    var /= (long double)(y.size() > 1 ? y.size() - 1 : 1);
+    out->colorings = (int64_t)y.size();
+    out->groups = m;
+    out->per_group = per;
+    out->needed = need;
+    out->exact = all ? 1 : 0;
+    out->est_maps = means.empty() || !all ? NAN : (double)means[means.size() / 2];
+    out->est_copies = out->est_maps / T.aut;
+    out->mean_maps = all && !y.empty() ? (double)mean_all : NAN;
+    out->rel_stderr = all && mean_all > 0 ? std::sqrt((double)(var / y.size())) / (double)mean_all : NAN;
     return SC_OK;
 }
 

@@ -108,6 +108,16 @@ class Tune(ctypes.Structure):
                 ("batch", ctypes.c_int32), ("trials", ctypes.c_int32), ("ms", ctypes.c_double)]
 
 
+class Estimate(ctypes.Structure):
+    _fields_ = [("est_maps", ctypes.c_double), ("est_copies", ctypes.c_double),
+                ("mean_maps", ctypes.c_double), ("rel_stderr", ctypes.c_double),
+                ("colorings", ctypes.c_int64), ("per_group", ctypes.c_int64), ("needed", ctypes.c_int64),
+                ("groups", ctypes.c_int32), ("exact", ctypes.c_int32)]
+
+
+SC_EST_BOUND, SC_EST_SAMPLE = 0, 1
+
+
 class ServeCfg(ctypes.Structure):
     _fields_ = [("mem_budget_bytes", ctypes.c_uint64), ("max_inflight", ctypes.c_int32),
                 ("max_batch", ctypes.c_int32)]
@@ -169,6 +179,11 @@ def lib():
             "sc_run_mod": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int32,
                                           _vp, ctypes.c_uint64, _u64p]),
             "sc_hom_count": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _dblp]),
+            "sc_colorings_for": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                                _i32p, _i64p]),
+            "sc_estimate": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_double,
+                                           ctypes.c_double, ctypes.c_int32, ctypes.c_int64, _vp,
+                                           ctypes.POINTER(Estimate)]),
             "sc_set_option": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int64]),
             "sc_get_option": (ctypes.c_int, [_vp, ctypes.c_int32, _i64p]),
             "sc_run_batch": (ctypes.c_int, [_vp, ctypes.POINTER(Job), ctypes.c_int32, _vp]),
@@ -199,6 +214,15 @@ def _p(a, t):
 
 def sc_version() -> str:
     return lib().sc_version().decode()
+
+
+def colorings_for(k, t, eps, delta):
+    """(groups, per_group) of the (eps, delta) median-of-means bound; pure host."""
+    m, g = ctypes.c_int32(), ctypes.c_int64()
+    rc = lib().sc_colorings_for(k, t, eps, delta, ctypes.byref(m), ctypes.byref(g))
+    if rc:
+        raise ScError(rc, f"sc_colorings_for(k={k}, t={t}, eps={eps}, delta={delta}) rejected")
+    return m.value, g.value
 
 
 def _edges_array(t, edges):
@@ -446,6 +470,13 @@ class Context:
         res = np.zeros(max(R, 1), np.uint64)
         self._check(self._L.sc_run_mod(self._h, gid, tid, first, R, stream, int(p), _p(res, _u64p)))
         return res[:R]
+
+    def estimate(self, gid, tid, eps, delta, mode=SC_EST_BOUND, max_colorings=0, first=0, stream=None):
+        """(eps, delta) estimate by the median of means; returns an Estimate."""
+        out = Estimate()
+        self._check(self._L.sc_estimate(self._h, gid, tid, first, eps, delta, mode, max_colorings, stream,
+                                        ctypes.byref(out)))
+        return out
 
     def hom_count(self, gid, tid, stream=None):
         """Homomorphisms of the template into the graph (double)."""

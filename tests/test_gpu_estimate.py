@@ -1,0 +1,136 @@
+"""GPU: the (eps, delta) estimator.  Its median of means and its sample-variance
+stopping rule recomputed from the oracle's counts of the same colourings
+(exactly the colourings the library ran), and the estimate against the true
+number of maps by brute force.  Calls go through the C ABI."""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1903_04395_amd import inputs as I
+from paper_1903_04395_amd import sc
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available()
+    c = sc.Context(0)
+    yield c
+    c.close()
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def path_maps(g, t):
+    """Maps of the t-vertex path: ordered simple paths on t vertices (DFS)."""
+    adj = [g.col_idx[g.row_ptr[v]:g.row_ptr[v + 1]].tolist() for v in range(g.n)]
+
+    def walk(v, left, seen):
+        if left == 0:
+            return 1
+        total = 0
+        for u in adj[v]:
+            if u not in seen:
+                seen.add(u)
+                total += walk(u, left - 1, seen)
+                seen.discard(u)
+        return total
+    return sum(walk(v, t - 1, {v}) for v in range(g.n))
+
+
+def median_of_means(y, m):
+    per = len(y) // m
+    means = sorted(sum(y[i * per:(i + 1) * per], Fraction(0)) / per for i in range(m))
+    return means[m // 2], per
+
+
+def run_case(ctx, g, t, edges, k, seed):
+    gid = ctx.load_graph(g)
+    tid = ctx.load_template(t, edges)
+    ctx.set_colors(k, seed)
+    info = ctx.plan_info(gid, tid, 1)
+    return gid, tid, (info.root, info.children())
+
+
+def test_bound_mode_median_of_means(ctx):
+    g = I.erdos_renyi(60, 150, 3)
+    t, k, seed, eps, delta = 3, 3, 5, 0.5, 0.1
+    gid, tid, plan = run_case(ctx, g, t, I.path(t), k, seed)
+    m, per = sc.colorings_for(k, t, eps, delta)
+    say(f"bound mode: n={g.n} t={t} k={k} m={m} g={per}")
+    est = ctx.estimate(gid, tid, eps, delta, sc.SC_EST_BOUND)
+    assert (est.groups, est.per_group, est.colorings, est.exact) == (m, per, m * per, 1)
+    counts, flags = O.count(g, t, plan, k, seed, 0, m * per)
+    assert not flags.any()
+    P = Fraction(math.factorial(k), math.factorial(k - t) * k**t)
+    y = [Fraction(int(x)) / P for x in counts]
+    want, _ = median_of_means(y, m)
+    assert est.est_maps == pytest.approx(float(want), rel=1e-12)
+    assert est.mean_maps == pytest.approx(float(sum(y) / len(y)), rel=1e-12)
+    truth = path_maps(g, t)
+    assert abs(est.est_maps - truth) <= eps * truth
+    assert est.est_copies == pytest.approx(est.est_maps / 2, rel=1e-15)
+    # the bound's colourings above the cap: refused
+    with pytest.raises(sc.ScError):
+        ctx.estimate(gid, tid, eps, delta, sc.SC_EST_BOUND, max_colorings=m * per - 1)
+    ctx.unload_graph(gid)
+
+
+def test_sample_mode_stopping_rule(ctx):
+    g = I.erdos_renyi(300, 1200, 7)
+    t, k, seed, eps, delta = 5, 5, 9, 0.1, 0.1
+    gid, tid, plan = run_case(ctx, g, t, I.path(t), k, seed)
+    est = ctx.estimate(gid, tid, eps, delta, sc.SC_EST_SAMPLE, max_colorings=20000)
+    say(f"sample mode: ran {est.colorings}, needed {est.needed}, est {est.est_maps:.6g}, "
+        f"rel stderr {est.rel_stderr:.3g}")
+    m = est.groups
+    assert m == sc.colorings_for(k, t, eps, delta)[0]
+    counts, flags = O.count(g, t, plan, k, seed, 0, est.colorings)
+    assert not flags.any()
+    P = float(Fraction(math.factorial(k), math.factorial(k - t) * k**t))
+    y_all = [int(x) / P for x in counts]
+    # replay the rule: rounds of 4m, then at most doubling, until the sample
+    # relative variance asks for no more colourings
+    n, nxt = 0, 4 * m
+    while True:
+        n = nxt
+        y = y_all[:n]
+        mean = sum(y) / n
+        var = sum((v - mean) ** 2 for v in y) / (n - 1)
+        need = m * max(1, math.ceil(4 * (var / mean**2) / eps**2))
+        if n >= need:
+            break
+        nxt = min(need, 2 * n)
+    assert est.colorings == n and est.needed == need
+    want, per = median_of_means([Fraction(v) for v in y_all], m)
+    assert est.per_group == per
+    assert est.est_maps == pytest.approx(float(want), rel=1e-12)
+    truth = path_maps(g, t)
+    assert abs(est.est_maps - truth) <= eps * truth
+    ctx.unload_graph(gid)
+
+
+def test_estimate_with_counts_past_2_64(ctx):
+    """Star counts on hub vertices pass 2^64: the estimator runs on exact counts."""
+    rng = np.random.default_rng(4)
+    n, hub_deg = 1200, 900
+    e = I.erdos_renyi(n, 3000, 4).edges()
+    nb = rng.choice(np.arange(2, n), size=hub_deg, replace=False)
+    g = I.csr_from_edges(n, np.concatenate([e[:, 0], np.zeros(hub_deg, np.int64)]),
+                         np.concatenate([e[:, 1], nb]))
+    t, k, seed = 12, 12, 3
+    gid, tid, plan = run_case(ctx, g, t, I.star(t), k, seed)
+    est = ctx.estimate(gid, tid, 0.5, 0.5, sc.SC_EST_SAMPLE, max_colorings=64)
+    assert est.exact == 1 and est.colorings >= 1
+    exact = O.count_exact(g, t, plan, k, seed, 0, est.colorings)
+    assert max(exact) >= 2**64
+    P = Fraction(math.factorial(k), math.factorial(k - t) * k**t)
+    assert est.mean_maps == pytest.approx(float(Fraction(sum(exact), len(exact)) / P), rel=1e-12)
+    ctx.unload_graph(gid)
