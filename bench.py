@@ -57,6 +57,9 @@ def parse():
     ap.add_argument("--exact", action="store_true",
                     help="time exact wide counts (uint64 pass + residue passes + CRT) beside the uint64 "
                          "pass, on the RMAT scale-20 and Chung-Lu k=12 workloads")
+    ap.add_argument("--ablation", action="store_true",
+                    help="pruning ablation: FASCIA and PFASCIA baseline kernels beside the library's path, "
+                         "RMAT scale 16, Pruefer trees of 6..10 vertices, k = t, one colouring")
     ap.add_argument("--serve", action="store_true",
                     help="serving mix: RMAT 18/20/22 resident, Poisson query stream, p50/p99 latency")
     ap.add_argument("--queries", type=int, default=40, help="stream length for --serve")
@@ -298,6 +301,47 @@ def exact_bench():
     print(json.dumps({"exact": out}), flush=True)
 
 
+def ablation_bench():
+    """The paper's pruning ablation (Sec. 6.3), on MI355X: per colouring, the
+    FASCIA baseline (Algorithm 1: every split re-sums the passive column over
+    the neighbours), PFASCIA (pruned: neighbour sums once), and the library's
+    path (one colouring per pass, and 8 folded into a pass), on RMAT scale 16
+    with seeded Pruefer trees of 6..10 vertices, k = t.  All four give the same
+    counts (checked here)."""
+    import numpy as np
+    import torch
+    from paper_1903_04395_amd import inputs as I
+    from paper_1903_04395_amd import sc
+    ctx = sc.Context(0)
+    g = I.rmat(16, 16, seed=6)
+    gid = ctx.load_graph(g)
+    print(f"[bench] ablation graph n={g.n} nnz={g.nnz}", file=sys.stderr, flush=True)
+    out = {}
+
+    def clock(fn):
+        fn()                                          # warm (allocation, tables)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, r
+
+    for t in range(6, 11):
+        tid = ctx.load_template(t, I.prufer_tree(t, t))
+        ctx.set_colors(t, 11)
+        tf, (cf, _) = clock(lambda: ctx.run_ablation(gid, tid, sc.SC_ABL_FASCIA, 0, 1))
+        tp, (cp, _) = clock(lambda: ctx.run_ablation(gid, tid, sc.SC_ABL_PFASCIA, 0, 1))
+        t1, (c1, _, _, _) = clock(lambda: ctx.run(gid, tid, 0, 1))
+        t8, (c8, _, _, _) = clock(lambda: ctx.run(gid, tid, 0, 8))
+        assert int(cf[0]) == int(cp[0]) == int(c1[0]) == int(c8[0])
+        out[f"tree{t}"] = {"fascia_ms": round(tf * 1e3, 2), "pfascia_ms": round(tp * 1e3, 2),
+                           "libsc_1_ms": round(t1 * 1e3, 3), "libsc_8_ms_per_colouring": round(t8 * 1e3 / 8, 3),
+                           "pruning_speedup": round(tf / tp, 2), "libsc_over_pfascia": round(tp / t1, 1)}
+        print(f"[bench] ablation tree{t}: {out[f'tree{t}']}", file=sys.stderr, flush=True)
+    ctx.close()
+    print(json.dumps({"ablation": out}), flush=True)
+
+
 def copy_probe():
     import torch
     a = torch.empty(1 << 27, dtype=torch.int64, device="cuda")   # 1 GiB
@@ -341,7 +385,7 @@ def main():
     if args.gather_probe:
         gather_probe()
         return
-    if args.forms or args.serve or args.configs or args.exact:
+    if args.forms or args.serve or args.configs or args.exact or args.ablation:
         import torch
         if not torch.cuda.is_available():
             print("bench.py needs a GPU", file=sys.stderr)
@@ -352,6 +396,8 @@ def main():
             serve_bench(args.queries, args.qps, args.streams)
         elif args.exact:
             exact_bench()
+        elif args.ablation:
+            ablation_bench()
         else:
             configs_bench()
         return

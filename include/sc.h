@@ -235,6 +235,20 @@ int sc_colorings_for(int32_t k, int32_t t, double eps, double delta, int32_t *gr
 int sc_estimate(sc_ctx *ctx, int32_t graph_id, int32_t tmpl_id, uint64_t first_coloring, double eps,
                 double delta, int32_t mode, int64_t max_colorings, void *stream, sc_estimate_t *out);
 
+/* Baselines for the pruning ablation (Sec. 3.2, Sec. 4.1, Sec. 6.3): the same
+ * counts as sc_run, one colouring at a time, by plain kernels over tables in
+ * the paper's layout (all binom(k, s) colour sets per row):
+ *   SC_ABL_FASCIA  -- Algorithm 1: every split sums the passive column over
+ *                     the row's neighbours again;
+ *   SC_ABL_PFASCIA -- pruned: each passive column's neighbour sum once per row,
+ *                     then the split multiply-add.
+ * Allocates every table of the plan for the call (no reuse).  Synchronous.
+ * Host outputs as sc_run (counts, overflow).  Errors: as sc_run, SC_EINVAL for
+ * an unknown variant. */
+enum { SC_ABL_FASCIA = 1, SC_ABL_PFASCIA = 2 };
+int sc_run_ablation(sc_ctx *ctx, int32_t graph_id, int32_t tmpl_id, int32_t variant, uint64_t first_coloring,
+                    int32_t n_colorings, void *stream, uint64_t *counts, uint8_t *overflow);
+
 /* Residues: residues[r] = (colourful count of colouring first_coloring + r) mod p,
  * for p = 2^w - c with 61 <= w <= 63 and odd c <= 2^16 (p need not be prime).
  * Synchronous.  Errors: SC_EINVAL (unsupported p, NULL output), else as sc_run. */

@@ -112,5 +112,18 @@ hipError_t launch_hom_sum(int64_t n, const double *S, double *out, hipStream_t s
 
 hipError_t launch_zero_u64(uint64_t *p, int64_t count, hipStream_t st);
 
+// Baselines for the pruning ablation (ablation.hip): one DP step of one
+// colouring with tables in the paper's layout ([n][binom(k, s)], column =
+// Eq. 1 rank), either FASCIA's (the passive column summed over the neighbours
+// once per split) or PFASCIA's (neighbour sums N[n][binom(k, p)] once, then
+// the split multiply-add).  A / P NULL: single-vertex child (from `col`, one
+// colour per row).  split: (k, h, a) split table; pmask: masks of the
+// p-subsets of k colours.  Overflow sets bit 0 of *flag.
+enum { kAblFascia = 1, kAblPfascia = 2 };
+hipError_t launch_ablation_step(int variant, const GraphBins &g, int k, int a, int p, const uint8_t *col,
+                                const uint32_t *split, const uint16_t *pmask, const uint64_t *A,
+                                const uint64_t *P, uint64_t *N, uint64_t *S, unsigned long long *flag,
+                                hipStream_t st);
+
 }  // namespace kern
 }  // namespace sc

@@ -116,6 +116,7 @@ class Estimate(ctypes.Structure):
 
 
 SC_EST_BOUND, SC_EST_SAMPLE = 0, 1
+SC_ABL_FASCIA, SC_ABL_PFASCIA = 1, 2
 
 
 class ServeCfg(ctypes.Structure):
@@ -179,6 +180,8 @@ def lib():
             "sc_run_mod": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int32,
                                           _vp, ctypes.c_uint64, _u64p]),
             "sc_hom_count": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _dblp]),
+            "sc_run_ablation": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64,
+                                               ctypes.c_int32, _vp, _u64p, _u8p]),
             "sc_colorings_for": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                                                 _i32p, _i64p]),
             "sc_estimate": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_double,
@@ -470,6 +473,15 @@ class Context:
         res = np.zeros(max(R, 1), np.uint64)
         self._check(self._L.sc_run_mod(self._h, gid, tid, first, R, stream, int(p), _p(res, _u64p)))
         return res[:R]
+
+    def run_ablation(self, gid, tid, variant, first, n_colorings, stream=None):
+        """Counts by the FASCIA or PFASCIA baseline kernels: (counts uint64[R], overflow uint8[R])."""
+        R = int(n_colorings)
+        counts = np.zeros(max(R, 1), np.uint64)
+        ovf = np.zeros(max(R, 1), np.uint8)
+        self._check(self._L.sc_run_ablation(self._h, gid, tid, variant, first, R, stream, _p(counts, _u64p),
+                                            _p(ovf, _u8p)))
+        return counts[:R], ovf[:R]
 
     def estimate(self, gid, tid, eps, delta, mode=SC_EST_BOUND, max_colorings=0, first=0, stream=None):
         """(eps, delta) estimate by the median of means; returns an Estimate."""
