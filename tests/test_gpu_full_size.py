@@ -6,6 +6,7 @@ stored in tests/golden/full_size.json (written by
 tests/golden/make_full_size.py, which calls only the oracle).  The GPU runs
 every colouring of the configured batch; the sampled ones are compared."""
 import json
+import math
 import os
 import time
 
@@ -36,6 +37,7 @@ def ctx():
 
 
 _graphs = {}
+_host = {}
 
 
 def graph_for(ctx, spec):
@@ -43,9 +45,15 @@ def graph_for(ctx, spec):
     if key not in _graphs:
         for k in list(_graphs):
             ctx.unload_graph(_graphs.pop(k))
+            _host.pop(k, None)
         g = getattr(I, spec["fn"])(*spec["args"], **spec["kwargs"])
         _graphs[key] = ctx.load_graph(g)
+        _host[key] = g
     return _graphs[key]
+
+
+def host_graph(spec):
+    return _host[json.dumps(spec, sort_keys=True)]
 
 
 @pytest.mark.parametrize("name", list(RUN_COLOURINGS))
@@ -93,3 +101,39 @@ def test_full_size_exact_counts(ctx, name):
     for r, x in e["exact"].items():
         assert counts[int(r)] == int(x), (name, r)
         assert hom >= int(x)
+
+
+def star_closed_form(g, col, k):
+    """Colourful maps of the k-vertex star (k colours) into g for one colouring:
+    (k-1)! * sum over centres v of the product, over the k-1 colours other than
+    col(v), of the number of v's neighbours with that colour (exact integer)."""
+    src = np.repeat(np.arange(g.n, dtype=np.int64), np.diff(g.row_ptr))
+    cnt = np.bincount(src * k + col[g.col_idx].astype(np.int64), minlength=g.n * k).reshape(g.n, k)
+    del src
+    cnt[np.arange(g.n), col] = 1                       # the centre's own colour is not a leaf colour
+    rows = cnt[cnt.min(axis=1) > 0]
+    return math.factorial(k - 1) * sum(math.prod(r) for r in rows.tolist())
+
+
+def test_full_size_exact_star_against_closed_form(ctx):
+    """Chung-Lu n=4,194,304, the 12-star, k = 12: sc_run_exact's counts (past
+    2^64) against the star closed form evaluated exactly on the host."""
+    import oracle as O
+    data = load()
+    name = "chunglu4m_star12_k12"
+    if name not in data:
+        pytest.skip("no golden entry for the Chung-Lu workload")
+    e = data[name]
+    print(f"[case] {name} closed form: generating and loading the graph", flush=True)
+    gid = graph_for(ctx, e["graph"])
+    g = host_graph(e["graph"])
+    tid = ctx.load_template_plan(e["t"], e["root"], e["children"])
+    k = e["k"]
+    ctx.set_colors(k, e["seed"])
+    cols = [0, 5, 15]
+    for r in cols:
+        counts, exact, hom, _, _ = ctx.run_exact(gid, tid, r, 1)
+        want = star_closed_form(g, O.colors(e["seed"], r, g.n, k), k)
+        print(f"[case] {name} colouring {r}: 2^{math.log2(want):.1f}", flush=True)
+        assert want >= 2**64
+        assert exact[0] == 1 and counts[0] == want
