@@ -46,6 +46,21 @@ __host__ __device__ __forceinline__ uint64_t mad_ovf3(uint64_t acc, uint64_t a, 
     return s;
 }
 
+// acc + a*b for b < 2^32 (a neighbour count: steps whose passive child is a
+// single vertex), with the same overflow rule, from two 32-bit products:
+// a*b = (ah*b)*2^32 + al*b reaches 2^64 exactly when ah*b >= 2^32 or
+// lo32(ah*b) + hi32(al*b) >= 2^32.
+__host__ __device__ __forceinline__ uint64_t mad_ovf_n32(uint64_t acc, uint64_t a, uint32_t b, uint32_t &ovf) {
+    const uint64_t ll = (uint64_t)(uint32_t)a * b;
+    const uint64_t c = (a >> 32) * (uint64_t)b;
+    const uint64_t mid = (ll >> 32) + (uint32_t)c;
+    ovf |= (uint32_t)((c >> 32) != 0) | (uint32_t)(mid >> 32);
+    const uint64_t lo = ll + (c << 32);
+    const uint64_t s = acc + lo;
+    ovf |= (uint32_t)(s < lo);
+    return s;
+}
+
 // ---------------------------------------------------------- residues mod p
 
 // An odd prime p = 2^w - c below 2^63; wrap = 2^64 mod p.  The DP commutes with
@@ -86,6 +101,15 @@ __host__ __device__ __forceinline__ uint64_t mod_mad(uint64_t acc, uint64_t a, u
 __host__ __device__ __forceinline__ void wide_add_product(unsigned __int128 &lo, uint64_t &top, uint64_t a,
                                                           uint64_t b) {
     const unsigned __int128 pr = (unsigned __int128)a * b;
+    lo += pr;
+    top += (uint64_t)(lo < pr);
+}
+
+// The same for b < 2^32, from two 32-bit products.
+__host__ __device__ __forceinline__ void wide_add_product_n32(unsigned __int128 &lo, uint64_t &top, uint64_t a,
+                                                              uint32_t b) {
+    const unsigned __int128 pr =
+        ((unsigned __int128)((a >> 32) * (uint64_t)b) << 32) + (uint64_t)(uint32_t)a * b;
     lo += pr;
     top += (uint64_t)(lo < pr);
 }

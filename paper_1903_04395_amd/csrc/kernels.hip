@@ -473,8 +473,10 @@ __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t x, int mask) {
 // non-negative, so a carry in any partial sum or in their combination means
 // the exact sum reaches 2^64.  MOD: each lane keeps its sum of products
 // exactly (a 128-bit word and a count of its carries) and reduces it mod p
-// once; the lanes then meet by modular adds.
-template <int AM, bool MOD>
+// once; the lanes then meet by modular adds.  N32: the neighbour sums are
+// colour counts (p = 1), below 2^32, so each product takes two 32-bit
+// multiplies.
+template <int AM, bool MOD, bool N32>
 __device__ __forceinline__ void emit_row(const Team &tm, const DpArgs &a, int64_t v, int pl,
                                          const uint64_t *Nl, const uint64_t *Al, const uint32_t *split,
                                          uint64_t &m) {
@@ -509,9 +511,15 @@ __device__ __forceinline__ void emit_row(const Team &tm, const DpArgs &a, int64_
                     x[i] = Ar[((pr[i] & 0xffffu) << a.sh) + ri];
                     y[i] = Nl[((pr[i] >> 16) << a.sh) + ri];
                 }
-                if constexpr (MOD) {
+                if constexpr (MOD && N32) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) wide_add_product_n32(wlo, wtop, x[i], (uint32_t)y[i]);
+                } else if constexpr (MOD) {
 #pragma unroll
                     for (int i = 0; i < 4; ++i) wide_add_product(wlo, wtop, x[i], y[i]);
+                } else if constexpr (N32) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) acc = mad_ovf_n32(acc, x[i], (uint32_t)y[i], ovf);
                 } else if (lean) {
 #pragma unroll
                     for (int i = 0; i < 4; ++i) acc = mad_ovf3(acc, x[i], y[i], ovf);
@@ -523,7 +531,9 @@ __device__ __forceinline__ void emit_row(const Team &tm, const DpArgs &a, int64_
             for (; j < a.nsplit; j += step) {
                 const uint32_t pr = sp[j];
                 const uint64_t xa = Ar[((pr & 0xffffu) << a.sh) + ri], yn = Nl[((pr >> 16) << a.sh) + ri];
-                if constexpr (MOD) wide_add_product(wlo, wtop, xa, yn);
+                if constexpr (MOD && N32) wide_add_product_n32(wlo, wtop, xa, (uint32_t)yn);
+                else if constexpr (MOD) wide_add_product(wlo, wtop, xa, yn);
+                else if constexpr (N32) acc = mad_ovf_n32(acc, xa, (uint32_t)yn, ovf);
                 else acc = mad_ovf(acc, xa, yn, ovf);
             }
         }
@@ -597,7 +607,7 @@ __global__ __launch_bounds__(kBlock) void dp_row_kernel(DpArgs a) {
             for (int q = tm.tid; q < Ln; q += tm.size) Nl[q] = mod_fold(Nl[q], a.md);
             team_sync<WAVE>();
         }
-        emit_row<AM, MOD>(tm, a, v, pl, Nl, Al, split, m);
+        emit_row<AM, MOD, HIST>(tm, a, v, pl, Nl, Al, split, m);
         team_sync<WAVE>();                       // LDS is reused by the next item
     }
     flush_flags(m, a.flags);

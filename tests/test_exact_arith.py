@@ -54,6 +54,26 @@ HARNESS = textwrap.dedent(r"""
             bad += check(0, a, b) + check(0, a, b + 1) + check(~0ull - a * b, a, b) + check(~0ull - a * b + 1, a, b);
             n += 4;
         }
+        // second operand below 2^32 (neighbour counts)
+        for (long i = 0; i < 2000000; ++i) {
+            uint64_t a = g(), c = g();
+            uint32_t b = (uint32_t)g();
+            const int m = i % 8;
+            a >>= (g() % 64) * (m & 1);
+            b >>= (g() % 32) * ((m >> 1) & 1);
+            c >>= (g() % 64) * ((m >> 2) & 1);
+            if (i % 97 == 0) { a = ~0ull / (b ? b : 1); c = ~0ull - a * b + (g() & 1); }
+            uint32_t o1 = 0, o2 = 0;
+            const uint64_t r1 = sc::kern::mad_ovf_n32(c, a, b, o1);
+            const uint64_t r2 = sc::kern::mad_ovf(c, a, b, o2);
+            if (r1 != r2 || o1 != o2) { printf("FAIL n32 %llu %u %llu\n", (unsigned long long)a, b, (unsigned long long)c); bad++; }
+            u128 lo1 = ((u128)g() << 64) | g(), lo2 = lo1;
+            uint64_t t1 = g() >> 8, t2 = t1;
+            sc::kern::wide_add_product_n32(lo1, t1, a, b);
+            sc::kern::wide_add_product(lo2, t2, a, b);
+            if (lo1 != lo2 || t1 != t2) { printf("FAIL wide n32\n"); bad++; }
+            n += 2;
+        }
         // residues modulo the primes 2^61 - 1, 2^62 - 57, 2^63 - 25
         const sc::kern::Modulus mods[3] = {{(1ull << 61) - 1, 1, 8, 61},
                                            {(1ull << 62) - 57, 57, 228, 62},
