@@ -219,7 +219,8 @@ int sc_run_exact(sc_ctx *ctx, int32_t graph_id, int32_t tmpl_id, uint64_t first_
  *   re-evaluated after each round (the first round 4m colourings, each round at
  *   most doubling the total), and stops when enough colourings ran or at
  *   max_colorings (> 0) -- a heuristic: the variance is estimated, not bounded.
- *   Synchronous.  Errors: as sc_run_exact, SC_EINVAL for bad eps/delta/mode. */
+ *   Synchronous.  Errors: as sc_run_exact, SC_EINVAL for bad eps/delta/mode or
+ *   0 < max_colorings < m. */
 enum { SC_EST_BOUND = 0, SC_EST_SAMPLE = 1 };
 typedef struct {
     double est_maps, est_copies;   /* median of group means; NaN if a count is not exact */

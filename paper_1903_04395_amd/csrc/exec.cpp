@@ -652,6 +652,8 @@ int sc_estimate(sc_ctx *c, int32_t gid, int32_t tid, uint64_t first, double eps,
     if (colorings_for(c->k, T.t, eps, delta, 1.0 / P - 1.0, &m, &g))
         return fail(c, SC_EINVAL, "need 0 < eps and 0 < delta < 1 (eps=%g, delta=%g)", eps, delta);
     const int64_t cap = max_colorings > 0 ? max_colorings : INT64_MAX;
+    if (cap < m) return fail(c, SC_EINVAL, "max_colorings=%lld is below the %d groups the median needs",
+                             (long long)cap, m);
     hipStream_t st = stream ? (hipStream_t)stream : c->stream;
     std::vector<long double> y;                    // per colouring: count / P
     bool all = true;

@@ -77,9 +77,11 @@ def test_bound_mode_median_of_means(ctx):
     truth = path_maps(g, t)
     assert abs(est.est_maps - truth) <= eps * truth
     assert est.est_copies == pytest.approx(est.est_maps / 2, rel=1e-15)
-    # the bound's colourings above the cap: refused
+    # the bound's colourings above the cap, or a cap below the groups: refused
     with pytest.raises(sc.ScError):
         ctx.estimate(gid, tid, eps, delta, sc.SC_EST_BOUND, max_colorings=m * per - 1)
+    with pytest.raises(sc.ScError):
+        ctx.estimate(gid, tid, eps, delta, sc.SC_EST_SAMPLE, max_colorings=m - 1)
     ctx.unload_graph(gid)
 
 
