@@ -32,6 +32,11 @@ namespace {
 constexpr int kWave = 64;
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / kWave;
+// Steps whose rows need more than kWideLds bytes of LDS fit at most three
+// workgroups per CU; they run 512-thread workgroups, so that twice as many
+// wavefronts share each row's LDS.
+constexpr int kBlockWide = 512;
+constexpr int kWideLds = 48 * 1024;
 // A launch may hold at most 2^32 - 1 work-items per grid dimension; kernels
 // that stride over their items are launched with at most this many workgroups.
 constexpr int64_t kMaxStrideBlocks = 1 << 16;
@@ -122,9 +127,11 @@ struct Team {
     int tid, size;        // this thread within the team, threads in the team
 };
 
+template <int TPB>
 __device__ __forceinline__ Team block_team() {
-    return Team{(int)(threadIdx.x >> 6), kWaves, (int)threadIdx.x, kBlock};
+    return Team{(int)(threadIdx.x >> 6), TPB / kWave, (int)threadIdx.x, TPB};
 }
+
 __device__ __forceinline__ Team wave_team() {
     return Team{0, 1, (int)(threadIdx.x & (kWave - 1)), kWave};
 }
@@ -165,15 +172,16 @@ __device__ __forceinline__ uint32_t narrow_at(uint32_t m, int c) {
 
 // Copies the index tables a step needs into LDS (called by the whole block):
 // unrank and rank tables (p >= 2), then the split table when it fits.
+template <int TPB>
 __device__ __forceinline__ void stage_tables(const DpArgs &a, uint16_t *tab) {
     const int nt = a.p >= 2 ? a.Wq + a.n_rank : 0;
     if (a.p >= 2) {
-        for (int i = threadIdx.x; i < a.Wq; i += kBlock) tab[i] = a.unrank[i];
-        for (int i = threadIdx.x; i < a.n_rank; i += kBlock) tab[a.Wq + i] = a.rank[i];
+        for (int i = threadIdx.x; i < a.Wq; i += TPB) tab[i] = a.unrank[i];
+        for (int i = threadIdx.x; i < a.n_rank; i += TPB) tab[a.Wq + i] = a.rank[i];
     }
     if (a.split_lds) {
         uint32_t *sp = (uint32_t *)(tab + ((nt + 1) & ~1));
-        for (int i = threadIdx.x; i < a.Wh * a.nsplit; i += kBlock) sp[i] = a.split[i];
+        for (int i = threadIdx.x; i < a.Wh * a.nsplit; i += TPB) sp[i] = a.split[i];
     }
 }
 
@@ -563,20 +571,20 @@ __device__ __forceinline__ void emit_row(const Team &tm, const DpArgs &a, int64_
 // four times as many rows are in flight.  LDS per team: the neighbour-sum row
 // N' (Wn * Bi) and the staged active row (Wa * Bi, AM == kActiveLds); then the
 // index tables, shared by the workgroup.  CH = 0: p = 1.
-template <int CH, int NB, bool BIG, int AM, bool WAVE, bool MOD>
-__global__ __launch_bounds__(kBlock) void dp_row_kernel(DpArgs a) {
+template <int CH, int NB, bool BIG, int AM, bool WAVE, bool MOD, int TPB>
+__global__ __launch_bounds__(TPB) void dp_row_kernel(DpArgs a) {
     constexpr bool HIST = CH == 0;
     constexpr int C = HIST ? 1 : CH;
     constexpr int kTeams = WAVE ? kWaves : 1;
     extern __shared__ uint64_t lds[];
-    const Team tm = WAVE ? wave_team() : block_team();
+    const Team tm = WAVE ? wave_team() : block_team<TPB>();
     const int Ln = a.Wn * a.Bi, La = a.Wa * a.Bi;
     const int region = Ln + (AM == kActiveLds ? La : 0);
     uint64_t *Nl = lds + (WAVE ? (int)(threadIdx.x >> 6) * region : 0);
     uint64_t *Al = Nl + Ln;
     uint16_t *tab = (uint16_t *)((char *)lds + a.tab_off);
     uint32_t msk[C];
-    stage_tables(a, tab);
+    stage_tables<TPB>(a, tab);
     __syncthreads();
     if constexpr (!HIST && !BIG && CH != kGroupRows) lane_masks<C>(a, tab, 0, msk);
     const uint32_t *split = split_of(a, tab);
@@ -616,8 +624,8 @@ __global__ __launch_bounds__(kBlock) void dp_row_kernel(DpArgs a) {
 // Split rows: one workgroup per (plane, row, segment of `seg` neighbours)
 // item; the segment's sum is built in LDS as in the row kernel and added into
 // Npre with global atomics (carry from the returned old value).
-template <int CH, int NB, bool BIG, bool MOD>
-__global__ __launch_bounds__(kBlock) void dp_split_kernel(DpArgs a) {
+template <int CH, int NB, bool BIG, bool MOD, int TPB>
+__global__ __launch_bounds__(TPB) void dp_split_kernel(DpArgs a) {
     constexpr bool HIST = CH == 0;
     constexpr int C = HIST ? 1 : CH;
     extern __shared__ uint64_t lds[];
@@ -625,7 +633,7 @@ __global__ __launch_bounds__(kBlock) void dp_split_kernel(DpArgs a) {
     uint16_t *tab = (uint16_t *)((char *)lds + a.tab_off);
     uint32_t msk[C];
     if constexpr (!HIST) {
-        stage_tables(a, tab);
+        stage_tables<TPB>(a, tab);
         __syncthreads();
         if constexpr (!BIG && CH != kGroupRows) lane_masks<C>(a, tab, 0, msk);
     }
@@ -639,14 +647,14 @@ __global__ __launch_bounds__(kBlock) void dp_split_kernel(DpArgs a) {
         const int64_t r1 = a.rp[v + 1];
         const int64_t e0 = a.rp[v] + (int64_t)item.y * a.seg;
         const int64_t e1 = e0 + a.seg < r1 ? e0 + a.seg : r1;
-        for (int q = threadIdx.x; q < Ln; q += kBlock) Nl[q] = 0;
+        for (int q = threadIdx.x; q < Ln; q += TPB) Nl[q] = 0;
         __syncthreads();
-        if constexpr (HIST) count_colours(block_team(), a, v, pl, e0, e1, Nl);
-        else scatter_rows<C, NB, BIG, MOD>(block_team(), a, v, pl, e0, e1, Nl, tab, tab + a.Wq, msk, m);
+        if constexpr (HIST) count_colours(block_team<TPB>(), a, v, pl, e0, e1, Nl);
+        else scatter_rows<C, NB, BIG, MOD>(block_team<TPB>(), a, v, pl, e0, e1, Nl, tab, tab + a.Wq, msk, m);
         __syncthreads();
         unsigned long long *dst =
             (unsigned long long *)a.Npre + ((int64_t)pl * a.n_split + a.slot[v]) * Ln;
-        for (int q = threadIdx.x; q < Ln; q += kBlock) {
+        for (int q = threadIdx.x; q < Ln; q += TPB) {
             const uint64_t x = Nl[q];
             if (x == 0) continue;
             const unsigned long long old = atomicAdd(dst + q, (unsigned long long)x);
@@ -768,8 +776,8 @@ int log2_exact(int x) {
 }
 
 // Workgroups that stay resident on the chip for a given dynamic LDS size.
-int64_t resident_blocks(int lds_bytes) {
-    const int per_cu = std::max(1, std::min(kMaxBlocksPerCU, kLdsPerCU / std::max(lds_bytes, 1)));
+int64_t resident_blocks(int lds_bytes, int tpb = kBlock) {
+    const int per_cu = std::max(1, std::min(kMaxBlocksPerCU * kBlock / tpb, kLdsPerCU / std::max(lds_bytes, 1)));
     return (int64_t)per_cu * kCUs;
 }
 
@@ -803,7 +811,7 @@ bool make_modulus(uint64_t p, Modulus &m) {
 
 DpArgs make_args(const GraphBins &g, const StepShape &s, const StepTables &t, const uint8_t *col,
                  const uint64_t *P, const uint64_t *A, const uint64_t *Npre, uint64_t *S,
-                 unsigned long long *flags, int teams) {
+                 unsigned long long *flags, int teams, int tpb = kBlock) {
     DpArgs a{};
     a.rp = g.row_ptr; a.ci = g.col_idx; a.col = col; a.n = g.n;
     a.B = s.B; a.Bi = s.Bi; a.sh = log2_exact(s.Bi); a.planes = s.B / s.Bi;
@@ -813,7 +821,7 @@ DpArgs make_args(const GraphBins &g, const StepShape &s, const StepTables &t, co
     a.eg = 1; a.lg_eg = 0;
     {
         const int Ls = s.Wh * s.Bi;
-        const int threads = kBlock / teams;              // threads building one row
+        const int threads = tpb / teams;                 // threads building one row
         int64_t best = -1;
         for (int lg = 0, G = 1; G <= kWave; ++lg, G *= 2) {
             if (G > 1 && G / 2 >= s.nsplit) break;
@@ -834,24 +842,27 @@ DpArgs make_args(const GraphBins &g, const StepShape &s, const StepTables &t, co
     return a;
 }
 
-template <int CH, int NB, bool BIG, int AM, bool WAVE, bool MOD>
+template <int CH, int NB, bool BIG, int AM, bool WAVE, bool MOD, int TPB = kBlock>
 hipError_t row_launch(const DpArgs &a, int lds, hipStream_t st) {
-    hipError_t e = allow_lds(dp_row_kernel<CH, NB, BIG, AM, WAVE, MOD>, lds);
+    hipError_t e = allow_lds(dp_row_kernel<CH, NB, BIG, AM, WAVE, MOD, TPB>, lds);
     if (e != hipSuccess) return e;
     const int64_t teams = WAVE ? kWaves : 1;
-    const int64_t blocks = std::min<int64_t>((a.n * a.planes + teams - 1) / teams, 2 * resident_blocks(lds));
-    dp_row_kernel<CH, NB, BIG, AM, WAVE, MOD><<<dim3((unsigned)blocks), dim3(kBlock), lds, st>>>(a);
+    const int64_t blocks = std::min<int64_t>((a.n * a.planes + teams - 1) / teams, 2 * resident_blocks(lds, TPB));
+    dp_row_kernel<CH, NB, BIG, AM, WAVE, MOD, TPB><<<dim3((unsigned)blocks), dim3(TPB), lds, st>>>(a);
     return hipGetLastError();
 }
 
-template <int CH, int NB, bool BIG, bool MOD>
+template <int CH, int NB, bool BIG, bool MOD, int TPB = kBlock>
 hipError_t split_launch(const DpArgs &a, int lds, hipStream_t st) {
-    hipError_t e = allow_lds(dp_split_kernel<CH, NB, BIG, MOD>, lds);
+    hipError_t e = allow_lds(dp_split_kernel<CH, NB, BIG, MOD, TPB>, lds);
     if (e != hipSuccess) return e;
-    const int64_t blocks = std::min<int64_t>(a.n_items * a.planes, 2 * resident_blocks(lds));
-    dp_split_kernel<CH, NB, BIG, MOD><<<dim3((unsigned)blocks), dim3(kBlock), lds, st>>>(a);
+    const int64_t blocks = std::min<int64_t>(a.n_items * a.planes, 2 * resident_blocks(lds, TPB));
+    dp_split_kernel<CH, NB, BIG, MOD, TPB><<<dim3((unsigned)blocks), dim3(TPB), lds, st>>>(a);
     return hipGetLastError();
 }
+
+// Rows walked in groups of chunks whose LDS leaves few workgroups per CU.
+bool wide_workgroup(const StepShape &s, int lds, bool wave);
 
 // Chunks of 64 uint64 per passive row, rounded up to a power of two (0 for
 // p = 1, 32 for rows wider than 16 chunks, walked in groups of 16), or
@@ -877,7 +888,10 @@ hipError_t row_dispatch(const StepShape &s, const DpArgs &a, int lds, hipStream_
     case 4: return row_launch<4, 4, false, AM, WAVE, MOD>(a, lds, st);
     case 8: return row_launch<8, 2, false, AM, WAVE, MOD>(a, lds, st);
     case 16: return row_launch<16, 1, false, AM, WAVE, MOD>(a, lds, st);
-    default: return row_launch<16, 1, true, AM, WAVE, MOD>(a, lds, st);
+    default:
+        if constexpr (!WAVE)
+            if (lds > kWideLds) return row_launch<16, 1, true, AM, WAVE, MOD, kBlockWide>(a, lds, st);
+        return row_launch<16, 1, true, AM, WAVE, MOD>(a, lds, st);
     }
 }
 
@@ -891,8 +905,14 @@ hipError_t split_dispatch(const StepShape &s, const DpArgs &a, int lds, hipStrea
     case 4: return split_launch<4, 4, false, MOD>(a, lds, st);
     case 8: return split_launch<8, 2, false, MOD>(a, lds, st);
     case 16: return split_launch<16, 1, false, MOD>(a, lds, st);
-    default: return split_launch<16, 1, true, MOD>(a, lds, st);
+    default:
+        if (lds > kWideLds) return split_launch<16, 1, true, MOD, kBlockWide>(a, lds, st);
+        return split_launch<16, 1, true, MOD>(a, lds, st);
     }
+}
+
+bool wide_workgroup(const StepShape &s, int lds, bool wave) {
+    return !wave && row_chunks(s, false) > 16 && lds > kWideLds;
 }
 
 bool shape_ok(const StepShape &s) {
@@ -967,8 +987,8 @@ hipError_t launch_dp_row(const GraphBins &g, const StepShape &s, const StepTable
     const int region = 8 * (s.Wn * s.Bi + (s.amode == kActiveLds ? s.Wa * s.Bi : 0));
     const bool wave = region <= s.wave_row_max && g.n * (s.B / s.Bi) >= kWaveRowsMin;
     const int teams = wave ? kWaves : 1;
-    const DpArgs a = make_args(g, s, t, col, P, A, Npre, S, flags, teams);
     const int lds = dp_lds_bytes(s, s.amode, t.n_rank, teams);
+    const DpArgs a = make_args(g, s, t, col, P, A, Npre, S, flags, teams, wide_workgroup(s, lds, wave) ? kBlockWide : kBlock);
     if (s.mod && wave) {
         if (s.amode == kActiveLeaf) return row_dispatch<kActiveLeaf, true, true>(s, a, lds, st);
         if (s.amode == kActiveLds) return row_dispatch<kActiveLds, true, true>(s, a, lds, st);
