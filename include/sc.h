@@ -185,10 +185,11 @@ int sc_run(sc_ctx *ctx, int32_t graph_id, int32_t tmpl_id, uint64_t first_colori
  * commutes with reduction modulo any m (Eq. 2 and the counting recursion of
  * Sec. 3.1 with every entry taken mod m).  sc_run gives each count mod 2^64 and
  * flags the colourings whose count reached 2^64; for those, sc_run_exact adds
- * passes modulo three primes (2^61-1, 2^62-57, 2^63-25) and recovers the count
- * by the Chinese remainder theorem below 2^64 p1 p2 p3 (about 2^250).  The
- * result is certified when the homomorphism count of the template into the
- * graph (an upper bound on every colouring's colourful count) lies below 2^249.
+ * passes modulo the primes 2^61-1, 2^62-57, 2^63-25 and recovers the count by
+ * the Chinese remainder theorem.  The homomorphism count of the template into
+ * the graph bounds every colouring's colourful count; the first one, two or
+ * three primes run, as that bound (with a 2^-10 margin) lies below 2^124,
+ * 2^185 or 2^247, and the result is certified exact when it does.
  * Synchronous.  Host outputs: counts[n_colorings][4] (the count as four uint64
  * limbs, least significant first), exact[n_colorings] (1: the count is exact;
  * 0: only its residue mod 2^64 p1 p2 p3 is), hom_bound (may be NULL: the

@@ -312,11 +312,12 @@ void big_muladd(uint64_t *x, int nl, uint64_t m, uint64_t add) {
     }
 }
 
-// The integer below 2^64 * p1 * p2 * p3 with residue r64 mod 2^64 and res[i]
-// mod kPrimes[i] (Garner's mixed-radix form: x = v0 + 2^64 (v1 + p1 (v2 + p2 v3))).
-void crt_combine(uint64_t r64, const uint64_t res[3], uint64_t out[4]) {
+// The integer below 2^64 * p1 * ... * pm with residue r64 mod 2^64 and res[i]
+// mod kPrimes[i], i < m <= 3 (Garner's mixed-radix form:
+// x = v0 + 2^64 (v1 + p1 (v2 + p2 v3)), the digits of unused primes zero).
+void crt_combine(uint64_t r64, const uint64_t res[3], int m, uint64_t out[4]) {
     uint64_t v[4] = {r64, 0, 0, 0};
-    for (int i = 0; i < 3; ++i) {
+    for (int i = 0; i < m; ++i) {
         const uint64_t p = kPrimes[i];
         // value of the digits so far mod p, and the radix (2^64 p1 .. p_{i-1}) mod p
         uint64_t acc = 0, radix = 1;
@@ -376,12 +377,21 @@ int hom_count(sc_ctx *c, int gid, int tid, hipStream_t st, double *out) {
     return SC_OK;
 }
 
-// A count below this (2^249 < 2^64 * p1 * p2 * p3) is fixed by its residues.
-constexpr double kCrtRange = 0x1p249;
+// Counts below 2^kCrtBits[m-1] are fixed by their residues mod 2^64 and the
+// first m primes (2^64 p1 > 2^124, 2^64 p1 p2 > 2^185, 2^64 p1 p2 p3 > 2^247).
+constexpr int kCrtBits[3] = {124, 185, 247};
 
 // Relative error of hom_count's double sums and products (t <= 32 rounded
 // steps over at most 2^31 terms each, and the root sum) is far below this.
 constexpr double kHomSlack = 1.0 + 0x1p-10;
+
+// Residue primes a count bounded by H needs: the fewest that certify it, or
+// all three (then only the residue mod their product is known).
+int primes_for(double H) {
+    for (int m = 1; m <= 3; ++m)
+        if (H * kHomSlack < std::ldexp(1.0, kCrtBits[m - 1])) return m;
+    return 3;
+}
 
 int check_run_args(sc_ctx *c, int gid, int tid, int ncol) {
     if (ncol < 0) return fail(c, SC_EINVAL, "n_colorings < 0");
@@ -418,17 +428,22 @@ int exact_counts(sc_ctx *c, int gid, int tid, uint64_t first, int ncol, hipStrea
         if (rc) return rc;
     }
     // the colourings that overflowed, in runs of consecutive ones, get residue
-    // passes modulo each prime
+    // passes modulo as many primes as the homomorphism bound (every count is
+    // at most the homomorphism count) asks for
     std::vector<std::pair<int, int>> runs;
     for (int r = 0; r < ncol; ++r) {
         if (!ovf[r]) continue;
         if (!runs.empty() && runs.back().first + runs.back().second == r) ++runs.back().second;
         else runs.push_back({r, 1});
     }
+    if ((!runs.empty() || want_hom) && std::isnan(*H)) {
+        if ((rc = hom_count(c, gid, tid, st, H))) return rc;
+    }
+    const int m = primes_for(*H);
     std::vector<uint64_t> res((size_t)3 * ncol);
     if (!runs.empty()) {
         std::vector<PassJob> passes;
-        for (int i = 0; i < 3; ++i)
+        for (int i = 0; i < m; ++i)
             for (auto &ru : runs) {
                 std::vector<PassJob> mine;
                 if ((rc = plan_job(c, i, gid, tid, c->k, c->seed, first + (uint64_t)ru.first, ru.second, mine)))
@@ -444,11 +459,7 @@ int exact_counts(sc_ctx *c, int gid, int tid, uint64_t first, int ncol, hipStrea
         });
         if (rc) return rc;
     }
-    // certificate: every count is at most the homomorphism count
-    if ((!runs.empty() || want_hom) && std::isnan(*H)) {
-        if ((rc = hom_count(c, gid, tid, st, H))) return rc;
-    }
-    const bool certified = !runs.empty() && *H * kHomSlack < kCrtRange;
+    const bool certified = !runs.empty() && *H * kHomSlack < std::ldexp(1.0, kCrtBits[m - 1]);
     for (int r = 0; r < ncol; ++r) {
         uint64_t *out = counts + 4 * (size_t)r;
         if (!ovf[r]) {
@@ -456,7 +467,7 @@ int exact_counts(sc_ctx *c, int gid, int tid, uint64_t first, int ncol, hipStrea
             exact[r] = 1;
         } else {
             const uint64_t rr[3] = {res[r], res[(size_t)ncol + r], res[2 * (size_t)ncol + r]};
-            crt_combine(c64[r], rr, out);
+            crt_combine(c64[r], rr, m, out);
             exact[r] = certified ? 1 : 0;
         }
     }

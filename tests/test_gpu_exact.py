@@ -163,3 +163,22 @@ def test_run_mod_rejects_unsupported_moduli(ctx):
     assert np.array_equal(ctx.run_mod(gid, tid, 0, 4, O.PRIMES[0]),
                           O.count_mod(g, 3, O.root_plan(3, I.path(3), 0), 3, 1, 0, 4, O.PRIMES[0]))
     ctx.unload_graph(gid)
+
+
+def test_exact_counts_needing_three_primes(ctx):
+    """A 6100-neighbour hub and the 16-star: the homomorphism bound (about
+    2^188.6) exceeds what 2^64 and two primes certify, so all three residue
+    passes run; the count (about 2^169) against the oracle's."""
+    rng = np.random.default_rng(12)
+    n, hub = 6200, 6100
+    e = I.erdos_renyi(n, 9000, 12).edges()
+    nb = rng.choice(np.arange(1, n), size=hub, replace=False)
+    g = I.csr_from_edges(n, np.concatenate([e[:, 0], np.zeros(hub, np.int64)]), np.concatenate([e[:, 1], nb]))
+    t = k = 16
+    gid, tid, info = setup(ctx, g, t, I.star(t), k, 5, 1, root=0)
+    say(f"three primes: n={g.n} nnz={g.nnz} max degree {hub}")
+    counts, exact, hom, _, _ = ctx.run_exact(gid, tid, 0, 1)
+    assert hom > 2.0**185
+    want = O.count_exact(g, t, (info.root, info.children()), k, 5, 0, 1)
+    assert counts == want and exact.all() and want[0] >= 2**124
+    ctx.unload_graph(gid)
