@@ -220,18 +220,30 @@ def configs_bench():
     """Per-configuration timings after a warm-up pass (allocation excluded):
     ER 2000 / P5 / k=5 (one colouring per call: launch latency); Chung-Lu
     n=4,194,304 (mean degree 30, exponent 2.1) / 12-vertex tree and 12-star /
-    k=12 / 16 colourings; RMAT scale 19 / 15-vertex tree / k=15 / 4 colourings
-    with the interleave and LDS limit picked by the autotuner."""
+    k=12 / 16 colourings; RMAT scale 19 / 15-vertex tree / k=15 / 4 colourings.
+    The multi-colouring cases are timed with the planner's default knobs, then
+    again after the autotuner picks the interleave and LDS limit."""
     from paper_1903_04395_amd import inputs as I
     from paper_1903_04395_amd import sc
     ctx = sc.Context(0)
     out = {}
-    # (name, graph, templates, k, colourings per call, timed calls, autotune first)
+    # (name, graph, templates, k, colourings per call, timed calls, autotune)
     cases = [("er2000-p5-k5", lambda: I.erdos_renyi(2000, 10000, seed=1), [("p5", 5, I.path(5), 0)], 5, 1, 200, False),
              ("chunglu4m-k12", lambda: I.chung_lu(4194304, 30, 2.1, seed=3),
-              [("tree12", 12, I.prufer_tree(12, 3), -1), ("star12", 12, I.star(12), 0)], 12, 16, 1, False),
+              [("tree12", 12, I.prufer_tree(12, 3), -1), ("star12", 12, I.star(12), 0)], 12, 16, 1, True),
              ("rmat19-tree15-k15", lambda: I.rmat(19, 16, seed=4), [("tree15", 15, I.prufer_tree(15, 4), -1)],
               15, 4, 1, True)]
+
+    def timed_calls(gid, tid, R, reps):
+        ctx.run(gid, tid, 0, R)                           # warm (allocation, tables)
+        ctx.profile(True)
+        t0 = time.perf_counter()
+        for i in range(reps):
+            ctx.run(gid, tid, R * (i + 1), R)
+        dt = (time.perf_counter() - t0) / reps
+        ctx.profile(False)
+        return dt, ctx.profile_read()
+
     for gname, gen, tmpls, k, R, reps, tune in cases:
         tg = time.time()
         g = gen()
@@ -240,20 +252,19 @@ def configs_bench():
         for tname, t, edges, root in tmpls:
             tid = ctx.load_template(t, edges, root)
             ctx.set_colors(k, 7)
-            tuned = ctx.autotune(gid, tid, R) if tune else None
-            info = ctx.plan_info(gid, tid, R)
-            ctx.run(gid, tid, 0, R)
-            ctx.profile(True)
-            t0 = time.perf_counter()
-            for i in range(reps):
-                ctx.run(gid, tid, R * (i + 1), R)
-            dt = (time.perf_counter() - t0) / reps
-            ctx.profile(False)
-            fams = ctx.profile_read()
+            info0 = ctx.plan_info(gid, tid, R)
+            dt0, fams = timed_calls(gid, tid, R, reps)
+            tuned, dt, info = None, dt0, info0
+            if tune:
+                tuned = ctx.autotune(gid, tid, R)
+                info = ctx.plan_info(gid, tid, R)
+                dt, fams = timed_calls(gid, tid, R, reps)
             key = f"{gname}/{tname}"
             out[key] = {"colorings": R, "batch": info.batch, "interleave": info.interleave,
                         "passes": -(-R // info.batch), "tables_GB_per_pass": round(info.arena_bytes / 1e9, 1),
-                        "s_per_call": round(dt, 4), "colorings_per_s": round(R / dt, 2), "autotuned": tuned,
+                        "s_per_call": round(dt, 4), "colorings_per_s": round(R / dt, 2),
+                        "default_s_per_call": round(dt0, 4), "default_interleave": info0.interleave,
+                        "autotuned": tuned,
                         "families_ms_per_call": {f: round(v["total_ms"] / reps, 2) for f, v in fams.items()}}
             print(f"[bench] configs {key}: {out[key]}", file=sys.stderr, flush=True)
         ctx.unload_graph(gid)
