@@ -7,7 +7,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsc.so")
 
-SOURCES = ["plan.cpp", "runtime.cpp", "exec.cpp", "serve.cpp", "kernels.hip", "ablation.hip"]
+SOURCES = ["plan.cpp", "runtime.cpp", "exec.cpp", "counts.cpp", "ablation_run.cpp", "serve.cpp", "kernels.hip",
+           "ablation.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

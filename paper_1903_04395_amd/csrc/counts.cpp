@@ -1,0 +1,363 @@
+// libsc exact wide counts and the (eps, delta) estimator: residue passes
+// modulo primes of the form 2^w - c, their combination with the uint64 pass by
+// the Chinese remainder theorem, the homomorphism-count bound that picks the
+// primes and certifies the result, and the median-of-means estimate over
+// exact counts.
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "rt.h"
+
+using namespace sc;
+
+namespace {
+
+// ---------------------------------------------------------------- exact counts
+
+// The three primes of the residue passes; with the uint64 pass they fix a count
+// below their product times 2^64 (about 2^250).
+constexpr uint64_t kPrimes[3] = {(1ull << 61) - 1, (1ull << 62) - 57, (1ull << 63) - 25};
+
+uint64_t mulmod(uint64_t a, uint64_t b, uint64_t p) { return (uint64_t)((unsigned __int128)a * b % p); }
+
+uint64_t powmod(uint64_t a, uint64_t e, uint64_t p) {
+    uint64_t r = 1 % p;
+    for (a %= p; e; e >>= 1, a = mulmod(a, a, p))
+        if (e & 1) r = mulmod(r, a, p);
+    return r;
+}
+
+// x = x * m + add over nl little-endian limbs.
+void big_muladd(uint64_t *x, int nl, uint64_t m, uint64_t add) {
+    unsigned __int128 carry = add;
+    for (int i = 0; i < nl; ++i) {
+        const unsigned __int128 t = (unsigned __int128)x[i] * m + carry;
+        x[i] = (uint64_t)t;
+        carry = t >> 64;
+    }
+}
+
+// The integer below 2^64 * p1 * ... * pm with residue r64 mod 2^64 and res[i]
+// mod kPrimes[i], i < m <= 3 (Garner's mixed-radix form:
+// x = v0 + 2^64 (v1 + p1 (v2 + p2 v3)), the digits of unused primes zero).
+void crt_combine(uint64_t r64, const uint64_t res[3], int m, uint64_t out[4]) {
+    uint64_t v[4] = {r64, 0, 0, 0};
+    for (int i = 0; i < m; ++i) {
+        const uint64_t p = kPrimes[i];
+        // value of the digits so far mod p, and the radix (2^64 p1 .. p_{i-1}) mod p
+        uint64_t acc = 0, radix = 1;
+        for (int j = 0; j <= i; ++j) {
+            acc = (acc + mulmod(v[j] % p, radix, p)) % p;
+            radix = mulmod(radix, j == 0 ? (uint64_t)(((unsigned __int128)1 << 64) % p) : kPrimes[j - 1] % p, p);
+        }
+        const uint64_t diff = (res[i] % p + p - acc) % p;
+        v[i + 1] = mulmod(diff, powmod(radix, p - 2, p), p);
+    }
+    uint64_t z[3] = {v[3], 0, 0};
+    big_muladd(z, 3, kPrimes[1], v[2]);
+    big_muladd(z, 3, kPrimes[0], v[1]);
+    out[0] = v[0]; out[1] = z[0]; out[2] = z[1]; out[3] = z[2];
+}
+
+// Residues mod `mod` of colourings first..first+n-1.
+int run_mod(sc_ctx *c, int gid, int tid, uint64_t first, int n, uint64_t mod, hipStream_t st, uint64_t *res) {
+    std::vector<PassJob> passes;
+    int rc = plan_job(c, 0, gid, tid, c->k, c->seed, first, n, passes);
+    if (rc) return rc;
+    for (auto &p : passes) p.mod = mod;
+    return run_passes(c, passes, st, [&](const PassJob &p, const uint64_t *r) {
+        for (int i = 0; i < p.P.batch; ++i) res[p.offset + i] = r[i] % mod;
+    });
+}
+
+// Homomorphisms of the template into the graph, in double, by the plan's
+// steps on one value per vertex (an upper bound on the colourful maps of any
+// colouring).
+int hom_count(sc_ctx *c, int gid, int tid, hipStream_t st, double *out) {
+    Plan P;
+    int rc = pick_batch(c, gid, tid, c->k, 1, 0, P);
+    if (rc) return rc;
+    Graph &g = *c->graphs[gid];
+    if (P.steps.empty()) { *out = (double)g.n; return SC_OK; }
+    if (g.n_rows == 0) { *out = 0; return SC_OK; }
+    if ((rc = rebin(c, g, default_segment(c)))) return rc;
+    const int64_t n = g.n_rows;
+    DevMem tmp;
+    if ((rc = dev_alloc(c, tmp, (P.bufs.size() * (size_t)n + 1) * sizeof(double)))) return rc;
+    double *base = (double *)tmp.p;
+    auto hb = [&](int id) { return id < 0 ? (double *)nullptr : base + 1 + (size_t)id * n; };
+    const kern::GraphBins bins = bins_of(g);
+    hipError_t e = kern::launch_zero_u64((uint64_t *)base, 1, st);
+    const Step *last = nullptr;
+    for (const Step &s : P.steps) {
+        if (e != hipSuccess) break;
+        e = kern::launch_hom_step(bins, hb(s.buf_a), hb(s.buf_p), hb(s.buf_s), st);
+        last = &s;
+    }
+    if (e == hipSuccess) e = kern::launch_hom_sum(n, hb(last->buf_s), base, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, base, sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    dev_free(c, tmp);
+    if (e != hipSuccess) return fail(c, SC_EDEVICE, "homomorphism count failed: %s", hipGetErrorString(e));
+    return SC_OK;
+}
+
+// Counts below 2^kCrtBits[m-1] are fixed by their residues mod 2^64 and the
+// first m primes (2^64 p1 > 2^124, 2^64 p1 p2 > 2^185, 2^64 p1 p2 p3 > 2^247).
+constexpr int kCrtBits[3] = {124, 185, 247};
+
+// Relative error of hom_count's double sums and products (t <= 32 rounded
+// steps over at most 2^31 terms each, and the root sum) is far below this.
+constexpr double kHomSlack = 1.0 + 0x1p-10;
+
+// Residue primes a count bounded by H needs: the fewest that certify it, or
+// all three (then only the residue mod their product is known).
+int primes_for(double H) {
+    for (int m = 1; m <= 3; ++m)
+        if (H * kHomSlack < std::ldexp(1.0, kCrtBits[m - 1])) return m;
+    return 3;
+}
+
+
+// Count of four little-endian limbs as a long double.
+long double limbs_value(const uint64_t *l) {
+    return (long double)l[0] + std::ldexp((long double)l[1], 64) + std::ldexp((long double)l[2], 128) +
+           std::ldexp((long double)l[3], 192);
+}
+
+// Exact counts of colourings first..first+n-1 as four limbs each: the uint64
+// pass, then residue passes for the colourings that overflowed, combined by
+// CRT and certified by the homomorphism count (computed when a colouring
+// overflowed or `want_hom`, into *H if that is still NaN).
+int exact_counts(sc_ctx *c, int gid, int tid, uint64_t first, int ncol, hipStream_t st, uint64_t *counts,
+                 uint8_t *exact, bool want_hom, double *H) {
+    int rc;
+    std::vector<uint64_t> c64((size_t)ncol);
+    std::vector<uint8_t> ovf((size_t)ncol);
+    {
+        std::vector<PassJob> passes;
+        if ((rc = plan_job(c, 0, gid, tid, c->k, c->seed, first, ncol, passes))) return rc;
+        rc = run_passes(c, passes, st, [&](const PassJob &p, const uint64_t *res) {
+            unpack_pass(res, p.P.batch, c64.data() + p.offset, ovf.data() + p.offset);
+        });
+        if (rc) return rc;
+    }
+    // the colourings that overflowed, in runs of consecutive ones, get residue
+    // passes modulo as many primes as the homomorphism bound (every count is
+    // at most the homomorphism count) asks for
+    std::vector<std::pair<int, int>> runs;
+    for (int r = 0; r < ncol; ++r) {
+        if (!ovf[r]) continue;
+        if (!runs.empty() && runs.back().first + runs.back().second == r) ++runs.back().second;
+        else runs.push_back({r, 1});
+    }
+    if ((!runs.empty() || want_hom) && std::isnan(*H)) {
+        if ((rc = hom_count(c, gid, tid, st, H))) return rc;
+    }
+    const int m = primes_for(*H);
+    std::vector<uint64_t> res((size_t)3 * ncol);
+    if (!runs.empty()) {
+        std::vector<PassJob> passes;
+        for (int i = 0; i < m; ++i)
+            for (auto &ru : runs) {
+                std::vector<PassJob> mine;
+                if ((rc = plan_job(c, i, gid, tid, c->k, c->seed, first + (uint64_t)ru.first, ru.second, mine)))
+                    return rc;
+                for (auto &p : mine) {
+                    p.mod = kPrimes[i];
+                    p.offset += ru.first;
+                    passes.push_back(std::move(p));
+                }
+            }
+        rc = run_passes(c, passes, st, [&](const PassJob &p, const uint64_t *r) {
+            for (int j = 0; j < p.P.batch; ++j) res[(size_t)p.job * ncol + p.offset + j] = r[j] % p.mod;
+        });
+        if (rc) return rc;
+    }
+    const bool certified = !runs.empty() && *H * kHomSlack < std::ldexp(1.0, kCrtBits[m - 1]);
+    for (int r = 0; r < ncol; ++r) {
+        uint64_t *out = counts + 4 * (size_t)r;
+        if (!ovf[r]) {
+            out[0] = c64[r]; out[1] = out[2] = out[3] = 0;
+            exact[r] = 1;
+        } else {
+            const uint64_t rr[3] = {res[r], res[(size_t)ncol + r], res[2 * (size_t)ncol + r]};
+            crt_combine(c64[r], rr, m, out);
+            exact[r] = certified ? 1 : 0;
+        }
+    }
+    return SC_OK;
+}
+
+// Colourings for an (eps, delta)-approximation of the count from i.i.d.
+// colourings whose estimates have relative variance at most `relvar`: groups
+// of g colourings make the group mean fail (miss by more than eps) with
+// probability at most relvar / (g eps^2) <= 1/4 (Chebyshev), and the median of
+// m groups fails only if half of them do, with probability at most
+// exp(-m/8) <= delta (Hoeffding).  m is odd.
+int colorings_for(int k, int t, double eps, double delta, double relvar, int32_t *m, int64_t *g) {
+    if (!(eps > 0) || !(delta > 0) || !(delta < 1) || k < 1 || t < 1 || k < t || k > SC_MAX_K ||
+        !(relvar >= 0))
+        return SC_EINVAL;
+    long double mm = std::ceil(8.0L * std::log(1.0L / (long double)delta));
+    if (mm < 1) mm = 1;
+    int32_t mi = (int32_t)std::min<long double>(mm, 1 << 30);
+    if (mi % 2 == 0) ++mi;
+    const long double gg = std::ceil(4.0L * (long double)relvar / ((long double)eps * eps));
+    *m = mi;
+    *g = (int64_t)std::max<long double>(1, std::min<long double>(gg, (long double)(INT64_MAX / 4) / mi));
+    return SC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sc_run_mod(sc_ctx *c, int32_t gid, int32_t tid, uint64_t first, int32_t ncol, void *stream, uint64_t p,
+               uint64_t *residues) {
+    if (!c) return SC_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    int rc = check_run_args(c, gid, tid, ncol);
+    if (rc) return rc;
+    if (!kern::mod_supported(p)) return fail(c, SC_EINVAL, "modulus %llu is not 2^w - c (61 <= w <= 63, odd c <= 2^16)",
+                                             (unsigned long long)p);
+    if (ncol > 0 && !residues) return fail(c, SC_EINVAL, "NULL output");
+    return run_mod(c, gid, tid, first, ncol, p, stream ? (hipStream_t)stream : c->stream, residues);
+}
+
+int sc_hom_count(sc_ctx *c, int32_t gid, int32_t tid, void *stream, double *out) {
+    if (!c) return SC_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    int rc = check_run_args(c, gid, tid, 0);
+    if (rc) return rc;
+    if (!out) return fail(c, SC_EINVAL, "NULL output");
+    return hom_count(c, gid, tid, stream ? (hipStream_t)stream : c->stream, out);
+}
+
+int sc_run_exact(sc_ctx *c, int32_t gid, int32_t tid, uint64_t first, int32_t ncol, void *stream,
+                 uint64_t *counts, uint8_t *exact, double *hom_bound, double *est_maps, double *est_copies) {
+    if (!c) return SC_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    int rc = check_run_args(c, gid, tid, ncol);
+    if (rc) return rc;
+    if (ncol > 0 && (!counts || !exact)) return fail(c, SC_EINVAL, "NULL output");
+    hipStream_t st = stream ? (hipStream_t)stream : c->stream;
+    double H = NAN;
+    if ((rc = exact_counts(c, gid, tid, first, ncol, st, counts, exact, hom_bound != nullptr, &H))) return rc;
+    if (hom_bound) *hom_bound = H;
+    long double sum = 0;
+    bool all = true;
+    for (int r = 0; r < ncol; ++r) {
+        all &= exact[r] != 0;
+        sum += limbs_value(counts + 4 * (size_t)r);
+    }
+    const Template &T = *c->tmpls[tid];
+    double m = NAN, cp = NAN;
+    if (ncol > 0 && all) {
+        m = (double)(sum / ncol) / colorful_probability(c->k, T.t);
+        cp = m / T.aut;
+    }
+    if (est_maps) *est_maps = m;
+    if (est_copies) *est_copies = cp;
+    return SC_OK;
+}
+
+int sc_colorings_for(int32_t k, int32_t t, double eps, double delta, int32_t *groups, int64_t *per_group) {
+    if (!groups || !per_group) return SC_EINVAL;
+    return colorings_for(k, t, eps, delta, 1.0 / colorful_probability(k, t) - 1.0, groups, per_group);
+}
+
+int sc_estimate(sc_ctx *c, int32_t gid, int32_t tid, uint64_t first, double eps, double delta, int32_t mode,
+                int64_t max_colorings, void *stream, sc_estimate_t *out) {
+    if (!c) return SC_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    if (!out) return fail(c, SC_EINVAL, "NULL output");
+    int rc = check_run_args(c, gid, tid, 0);
+    if (rc) return rc;
+    if (mode != SC_EST_BOUND && mode != SC_EST_SAMPLE) return fail(c, SC_EINVAL, "unknown mode %d", mode);
+    const Template &T = *c->tmpls[tid];
+    const double P = colorful_probability(c->k, T.t);
+    int32_t m = 0;
+    int64_t g = 0;
+    if (colorings_for(c->k, T.t, eps, delta, 1.0 / P - 1.0, &m, &g))
+        return fail(c, SC_EINVAL, "need 0 < eps and 0 < delta < 1 (eps=%g, delta=%g)", eps, delta);
+    const int64_t cap = max_colorings > 0 ? max_colorings : INT64_MAX;
+    if (cap < m) return fail(c, SC_EINVAL, "max_colorings=%lld is below the %d groups the median needs",
+                             (long long)cap, m);
+    hipStream_t st = stream ? (hipStream_t)stream : c->stream;
+    std::vector<long double> y;                    // per colouring: count / P
+    bool all = true;
+    double H = NAN;
+    auto run = [&](int64_t n) -> int {
+        std::vector<uint64_t> limbs;
+        std::vector<uint8_t> ex;
+        while (n > 0) {
+            const int chunk = (int)std::min<int64_t>(n, 1 << 20);
+            limbs.assign(4 * (size_t)chunk, 0);
+            ex.assign((size_t)chunk, 0);
+            int r = exact_counts(c, gid, tid, first + (uint64_t)y.size(), chunk, st, limbs.data(), ex.data(), false, &H);
+            if (r) return r;
+            for (int i = 0; i < chunk; ++i) {
+                all &= ex[i] != 0;
+                y.push_back(limbs_value(limbs.data() + 4 * (size_t)i) / P);
+            }
+            n -= chunk;
+        }
+        return SC_OK;
+    };
+    int64_t need = (int64_t)m * g;                 // SC_EST_BOUND: the variance bound 1/P - 1
+    if (mode == SC_EST_BOUND) {
+        if (need > cap)
+            return fail(c, SC_EINVAL, "the bound needs %lld colourings (%d groups of %lld), above max_colorings=%lld",
+                        (long long)need, m, (long long)g, (long long)cap);
+        if ((rc = run(need))) return rc;
+    } else {
+        // SC_EST_SAMPLE: the same rule with the sample relative variance, re-evaluated
+        // after each round; rounds at most double the colourings run so far
+        int64_t next = std::min<int64_t>(cap, 4 * (int64_t)m);
+        for (;;) {
+            if ((rc = run(next - (int64_t)y.size()))) return rc;
+            long double mean = 0, var = 0;
+            for (long double v : y) mean += v;
+            mean /= (long double)y.size();
+            for (long double v : y) var += (v - mean) * (v - mean);
+            var /= (long double)(y.size() > 1 ? y.size() - 1 : 1);
+            const double rel = mean > 0 ? (double)(var / (mean * mean)) : 0.0;
+            int32_t m2 = 0;
+            int64_t g2 = 0;
+            colorings_for(c->k, T.t, eps, delta, rel, &m2, &g2);
+            need = (int64_t)m2 * g2;
+            if ((int64_t)y.size() >= need || (int64_t)y.size() >= cap) break;
+            next = std::min<int64_t>({cap, need, 2 * (int64_t)y.size()});
+        }
+    }
+    // median of the means of m groups of consecutive colourings
+    const int64_t per = (int64_t)y.size() / m;
+    std::vector<long double> means;
+    for (int32_t i = 0; i < m && per > 0; ++i) {
+        long double s = 0;
+        for (int64_t j = 0; j < per; ++j) s += y[(size_t)(i * per + j)];
+        means.push_back(s / per);
+    }
+    std::sort(means.begin(), means.end());
+    long double mean_all = 0, var = 0;
+    for (long double v : y) mean_all += v;
+    mean_all /= (long double)std::max<size_t>(1, y.size());
+    for (long double v : y) var += (v - mean_all) * (v - mean_all);
+    var /= (long double)(y.size() > 1 ? y.size() - 1 : 1);
+    out->colorings = (int64_t)y.size();
+    out->groups = m;
+    out->per_group = per;
+    out->needed = need;
+    out->exact = all ? 1 : 0;
+    out->est_maps = means.empty() || !all ? NAN : (double)means[means.size() / 2];
+    out->est_copies = out->est_maps / T.aut;
+    out->mean_maps = all && !y.empty() ? (double)mean_all : NAN;
+    out->rel_stderr = all && mean_all > 0 ? std::sqrt((double)(var / y.size())) / (double)mean_all : NAN;
+    return SC_OK;
+}
+
+}  // extern "C"

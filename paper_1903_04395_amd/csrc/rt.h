@@ -1,11 +1,14 @@
 // Internal runtime state of libsc shared by runtime.cpp (contexts, graphs,
 // templates, options, tracing), exec.cpp (passes, batches, hipGraph replay,
-// autotuning) and serve.cpp (the serving loop).  Not part of the public ABI.
+// autotuning), counts.cpp (exact counts, residues, the estimator),
+// ablation_run.cpp (the pruning-ablation baselines) and serve.cpp (the
+// serving loop).  Not part of the public ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -172,6 +175,24 @@ int enqueue_pass(sc_ctx *c, const PassSpec &s, PassBuffers &b, hipStream_t st, b
 int launch_pass(sc_ctx *c, int gid, int tid, const PassSpec &s, PassBuffers &b, hipStream_t st,
                 uint64_t *host_desc, uint64_t *host_res, bool allow_graph);
 void unpack_pass(const uint64_t *host_res, int B, uint64_t *counts, uint8_t *flags);
+
+// One pass of a planned job: colourings first..first+P.batch-1 of job `job`.
+struct PassJob {
+    int job, gid, tid, k;
+    uint64_t seed, first;
+    int offset;                // first colouring of this pass within its job
+    uint64_t mod = 0;          // 0: uint64 counts with overflow flags; else residues mod this prime
+    Plan P;
+};
+// Runs the passes back to back on `st` and waits once; then done(pass, its
+// SC_MAX_BATCH + 1 result words) for each.
+int run_passes(sc_ctx *c, std::vector<PassJob> &passes, hipStream_t st,
+               const std::function<void(const PassJob &, const uint64_t *)> &done);
+// Splits n colourings of one job into passes of the planned batch.
+int plan_job(sc_ctx *c, int job, int gid, int tid, int k, uint64_t seed, uint64_t first, int n,
+             std::vector<PassJob> &out);
+// Checks a run's graph, template, k >= t and colouring count; selects the device.
+int check_run_args(sc_ctx *c, int gid, int tid, int ncol);
 
 void serve_shutdown(sc_ctx *c);
 
