@@ -355,9 +355,10 @@ enum {
     SC_OPT_GRAPH = 3,         /* 1: replay each pass from a captured hipGraph   */
     SC_OPT_SEGMENT = 5,       /* neighbours per work item of heavy rows, > 64
                                  (0 = default, 512)                            */
-    SC_OPT_REORDER = 8,       /* 1 (default): graphs loaded afterwards are kept
-                                 relabelled by descending degree (colours still
-                                 follow the caller's vertex ids)               */
+    SC_OPT_REORDER = 8,       /* graphs loaded afterwards are kept relabelled:
+                                 1 (default) by descending degree, 2 in reverse
+                                 Cuthill-McKee order, 0 not at all (colours
+                                 always follow the caller's vertex ids)        */
     SC_OPT_INTERLEAVE = 9,    /* cap on colourings interleaved per table plane:
                                  1, 2, 4, ..., 64 (0 = default, no cap)        */
     SC_OPT_LDS_MAX = 10,      /* LDS bytes per row-kernel workgroup,

@@ -326,15 +326,41 @@ int sc_load_graph_csr(sc_ctx *c, int64_t n, int64_t nnz, const int64_t *rp, cons
     g->deg_host.resize(n);
     int rc;
     if (c->reorder) {
-        // Relabel by descending degree: the rows that neighbour sums gather most
-        // often become one contiguous region and the isolated vertices the tail.
+        // Relabel by descending degree (1): the rows that neighbour sums gather
+        // most often become one contiguous region and the isolated vertices the
+        // tail; or in reverse Cuthill-McKee order (2), isolated vertices last.
         // Colours are still drawn from the caller's ids (perm), so every count
         // is unchanged.
         std::vector<int32_t> perm(n), inv(n);
+        auto deg = [&](int32_t x) { return rp[x + 1] - rp[x]; };
         for (int64_t v = 0; v < n; ++v) perm[v] = (int32_t)v;
-        std::stable_sort(perm.begin(), perm.end(), [&](int32_t x, int32_t y) {
-            return rp[x + 1] - rp[x] > rp[y + 1] - rp[y];
-        });
+        std::stable_sort(perm.begin(), perm.end(), [&](int32_t x, int32_t y) { return deg(x) > deg(y); });
+        if (c->reorder == 2) {
+            // breadth-first from each component's lowest-degree vertex,
+            // neighbours in ascending degree, then reversed
+            std::vector<int32_t> order;
+            order.reserve(n);
+            std::vector<uint8_t> seen(n, 0);
+            std::vector<int32_t> nb;
+            for (int64_t i = n - 1; i >= 0; --i) {
+                const int32_t s0 = perm[i];
+                if (seen[s0] || deg(s0) == 0) continue;
+                size_t head = order.size();
+                order.push_back(s0);
+                seen[s0] = 1;
+                while (head < order.size()) {
+                    const int32_t u = order[head++];
+                    nb.assign(ci + rp[u], ci + rp[u + 1]);
+                    std::stable_sort(nb.begin(), nb.end(), [&](int32_t x, int32_t y) { return deg(x) < deg(y); });
+                    for (int32_t w : nb)
+                        if (!seen[w]) { seen[w] = 1; order.push_back(w); }
+                }
+            }
+            std::reverse(order.begin(), order.end());
+            for (int64_t v = 0; v < n; ++v)
+                if (deg((int32_t)v) == 0) order.push_back((int32_t)v);
+            perm.swap(order);
+        }
         for (int64_t v = 0; v < n; ++v) inv[perm[v]] = (int32_t)v;
         std::vector<int64_t> nrp(n + 1, 0);
         for (int64_t v = 0; v < n; ++v) nrp[v + 1] = nrp[v] + (rp[perm[v] + 1] - rp[perm[v]]);
@@ -456,7 +482,10 @@ int sc_set_option(sc_ctx *c, int32_t opt, int64_t v) {
     case SC_OPT_WAVE_ROW_MAX:
         if (v < -1 || v > 40960) return fail(c, SC_EINVAL, "wave row limit must be -1 (default) or in [0, 40960]");
         c->wave_row_max = v; return SC_OK;
-    case SC_OPT_REORDER: c->reorder = v != 0; return SC_OK;
+    case SC_OPT_REORDER:
+        if (v < 0 || v > 2) return fail(c, SC_EINVAL, "SC_OPT_REORDER must be 0, 1 or 2");
+        c->reorder = v;
+        return SC_OK;
     default: return fail(c, SC_EINVAL, "unknown option %d", opt);
     }
 }

@@ -235,14 +235,18 @@ def test_full_config2_batch_and_plan_invariance(ctx):
 
 
 def test_relabelling_does_not_change_results(ctx):
-    """Graphs are kept relabelled by descending degree unless SC_OPT_REORDER is
-    0; colours follow the caller's ids, so residues and flags agree."""
+    """Graphs are kept relabelled by descending degree (SC_OPT_REORDER 1), in
+    reverse Cuthill-McKee order (2) or as given (0); colours follow the caller's
+    ids, so residues and flags agree."""
     g = I.rmat(12, 16, seed=21)
     out = []
-    for reorder in (0, 1):
+    for reorder in (0, 1, 2):
         ctx.set_option(sc.SC_OPT_REORDER, reorder)
         gid = ctx.load_graph(g)
         out.append(run_both(ctx, g, 9, I.prufer_tree(9, 21), 9, 3, 0, 6, gid=gid)[:2])
         ctx.unload_graph(gid)
+    with pytest.raises(sc.ScError):
+        ctx.set_option(sc.SC_OPT_REORDER, 3)
     ctx.set_option(sc.SC_OPT_REORDER, 1)
-    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+    for o in out[1:]:
+        assert np.array_equal(out[0][0], o[0]) and np.array_equal(out[0][1], o[1])
