@@ -182,3 +182,32 @@ def test_exact_counts_needing_three_primes(ctx):
     want = O.count_exact(g, t, (info.root, info.children()), k, 5, 0, 1)
     assert counts == want and exact.all() and want[0] >= 2**124
     ctx.unload_graph(gid)
+
+
+def test_degenerate_templates_and_graphs(ctx):
+    """t = 1 (every vertex is a map), a graph without edges, k > t: exact counts,
+    residues, the bound, the estimate and the ablation baselines agree with the
+    closed forms."""
+    g = I.erdos_renyi(300, 900, 2)
+    empty = I.csr_from_edges(50, np.zeros(0, np.int64), np.zeros(0, np.int64))
+    gid, gid0 = ctx.load_graph(g), ctx.load_graph(empty)
+    t1 = ctx.load_template(1, np.zeros((0, 2), np.int32))
+    t3 = ctx.load_template(3, I.path(3))
+    ctx.set_colors(4, 9)
+    counts, exact, hom, maps, _ = ctx.run_exact(gid, t1, 0, 3)
+    assert counts == [g.n] * 3 and exact.all() and hom == g.n and maps == pytest.approx(g.n)
+    assert list(ctx.run_mod(gid, t1, 0, 2, O.PRIMES[0])) == [g.n] * 2
+    assert ctx.run_ablation(gid, t1, sc.SC_ABL_FASCIA, 0, 2)[0].tolist() == [g.n] * 2
+    est = ctx.estimate(gid, t1, 0.1, 0.1, sc.SC_EST_SAMPLE, max_colorings=200)
+    assert est.est_maps == pytest.approx(g.n) and est.exact == 1
+    counts, exact, hom, _, _ = ctx.run_exact(gid0, t3, 0, 2)
+    assert counts == [0, 0] and exact.all() and hom == 0
+    assert ctx.run_ablation(gid0, t3, sc.SC_ABL_PFASCIA, 0, 2)[0].tolist() == [0, 0]
+    # k > t: the estimate divides by k!/((k-t)! k^t)
+    est = ctx.estimate(gid, t3, 0.3, 0.2, sc.SC_EST_BOUND)
+    counts, _ = O.count(g, 3, O.root_plan(3, I.path(3), 0), 4, 9, 0, est.colorings)
+    P = 4 * 3 * 2 / 4**3
+    y = sorted(np.mean((counts.astype(float) / P).reshape(est.groups, -1)[:, :est.per_group], axis=1))
+    assert est.est_maps == pytest.approx(y[est.groups // 2], rel=1e-12)
+    ctx.unload_graph(gid)
+    ctx.unload_graph(gid0)
