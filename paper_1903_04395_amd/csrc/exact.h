@@ -1,8 +1,9 @@
 // Exact uint64 arithmetic of the DP with the overflow rule: every result is
 // the residue mod 2^64, and a flag records whether the exact value reached
-// 2^64.  Written for the device; plain C++ otherwise, so a host compiler can
-// check it against 128-bit arithmetic (include it after the HIP runtime
-// header on the device side).
+// 2^64; and the arithmetic modulo p = 2^w - c of the residue passes.  Written
+// for the device; plain C++ otherwise, so a host compiler can check it against
+// 128-bit arithmetic (include it after the HIP runtime header on the device
+// side).
 #pragma once
 
 #include <cstdint>
@@ -63,7 +64,8 @@ __host__ __device__ __forceinline__ uint64_t mad_ovf_n32(uint64_t acc, uint64_t 
 
 // ---------------------------------------------------------- residues mod p
 
-// An odd prime p = 2^w - c below 2^63; wrap = 2^64 mod p.  The DP commutes with
+// An odd modulus p = 2^w - c below 2^63 (61 <= w <= 63, c <= 2^16; a prime
+// when the residues feed the Chinese remainder theorem); wrap = 2^64 mod p.  The DP commutes with
 // reduction modulo p (it uses only + and *), so running it on residues gives
 // X mod p; with X mod 2^64 the residues determine X below their product.
 struct Modulus {

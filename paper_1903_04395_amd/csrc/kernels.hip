@@ -10,9 +10,13 @@
 //                    described in kernels.h
 //  * split pre-pass -- the neighbour sums of rows with very many neighbours
 //  * root reduction -- colourful count per colouring
+//  * homomorphism bound -- the same steps on one double per vertex (an upper
+//                    bound on every colouring's count)
 //
 // All arithmetic is exact uint64 modulo 2^64; every carry out of 64 bits sets
 // the colouring's bit in a 64-bit flag mask (bit r = colouring r of the pass).
+// In residue mode (MOD) the same kernels keep every entry modulo a prime
+// instead, which with the uint64 pass recovers counts past 2^64.
 //
 // In the rooted-colour layout a neighbour u of v contributes its entry for the
 // set {col(u)} + T (T a subset of the colours other than col(u)) to v's
