@@ -78,14 +78,17 @@ def test_full_size_matches_oracle(ctx, name):
         assert int(ovf[int(r)]) == flag, (name, r)
 
 
-@pytest.mark.parametrize("name", list(RUN_COLOURINGS))
+# entries whose golden file holds oracle exact counts (the oracle's full-width
+# k = 12 and k = 15 tables do not fit the host that wrote them; the Chung-Lu
+# star is checked against its closed form below instead)
+EXACT_ENTRIES = [n for n in RUN_COLOURINGS if load().get(n, {}).get("exact")]
+
+
+@pytest.mark.parametrize("name", EXACT_ENTRIES)
 def test_full_size_exact_counts(ctx, name):
     """sc_run_exact at full size: the sampled colourings' exact counts (past
     2^64) against the oracle's, every count certified exact."""
-    data = load()
-    if name not in data or not data[name].get("exact"):
-        pytest.skip(f"no exact golden values for {name}")
-    e = data[name]
+    e = load()[name]
     print(f"[case] {name} exact: generating and loading the graph", flush=True)
     gid = graph_for(ctx, e["graph"])
     tid = ctx.load_template_plan(e["t"], e["root"], e["children"])
