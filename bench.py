@@ -413,8 +413,8 @@ def main():
             configs_bench()
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the method's multi-GPU "
-              "split (colourings across GPUs) is described in DESIGN.md but not built.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); splitting the colourings "
+              "across GPUs is not built.", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
