@@ -211,3 +211,25 @@ def test_degenerate_templates_and_graphs(ctx):
     assert est.est_maps == pytest.approx(y[est.groups // 2], rel=1e-12)
     ctx.unload_graph(gid)
     ctx.unload_graph(gid0)
+
+
+def test_exact_counts_replayed_from_captured_graphs(ctx):
+    """With SC_OPT_GRAPH the uint64 and residue passes replay captured hipGraphs
+    (one per modulus); every replay, with eager work in between, matches the
+    eager result."""
+    g = hubby_graph(9)
+    gid, tid, info = setup(ctx, g, 12, SPIDER, 12, 21, 4)
+    eager = [ctx.run_exact(gid, tid, first, 4)[0] for first in (0, 4, 8)]
+    ctx.set_option(sc.SC_OPT_GRAPH, 1)
+    try:
+        for rep in range(2):
+            for i, first in enumerate((0, 4, 8)):
+                got = ctx.run_exact(gid, tid, first, 4)[0]
+                assert got == eager[i], (rep, first)
+                ctx.set_option(sc.SC_OPT_GRAPH, 0)           # eager work between replays
+                ctx.run(gid, tid, 100, 2)
+                ctx.set_option(sc.SC_OPT_GRAPH, 1)
+    finally:
+        ctx.set_option(sc.SC_OPT_GRAPH, sc.OPTION_DEFAULTS[sc.SC_OPT_GRAPH])
+    assert max(eager[0]) >= 2**64
+    ctx.unload_graph(gid)
