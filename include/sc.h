@@ -260,7 +260,9 @@ int sc_run_mod(sc_ctx *ctx, int32_t graph_id, int32_t tmpl_id, uint64_t first_co
 /* Homomorphisms of the template into the graph (maps of the template's
  * vertices to the graph's that send edges to edges, not necessarily
  * injective), in double precision (relative error below 2^-40), by the same
- * steps as the counting DP on one value per vertex.  Synchronous.
+ * steps as the counting DP (Sec. 2.1 phase 3) on one value per vertex with the
+ * colour condition dropped.  Not a quantity of the paper: it bounds every
+ * colouring's colourful count, which certifies sc_run_exact.  Synchronous.
  * Errors: SC_EINVAL (NULL output), SC_ENOTFOUND, SC_ENOMEM, SC_EDEVICE. */
 int sc_hom_count(sc_ctx *ctx, int32_t graph_id, int32_t tmpl_id, void *stream, double *out);
 
