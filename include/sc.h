@@ -20,7 +20,10 @@
  * table entry or final count, evaluated exactly from the stored 64-bit
  * operands, reached 2^64.  The flag depends on the plan (root and child order)
  * but not on summation order, batching or fusion; the residue depends on
- * nothing but (graph, template, k, seed, colouring index).
+ * nothing but (graph, template, k, seed, colouring index).  sc_run_exact
+ * recovers the counts that pass 2^64 exactly (residue passes modulo primes and
+ * the Chinese remainder theorem), and sc_estimate turns exact counts into an
+ * (eps, delta) estimate.
  *
  * Colouring rule (the paper only says "randomly selected"): colouring r of
  * vertex v is floor(x * k / 2^64) where x is output number r*2^40 + v of
