@@ -144,3 +144,37 @@ def test_plan_rejects_bad_templates():
         sc.sc_plan_template(4, I.path(4), -1, 3, 10, 10, 1)     # k < t
     with pytest.raises(sc.ScError):
         sc.sc_plan_template(17, [(i, i + 1) for i in range(16)], -1, 16, 10, 10, 1)
+
+
+def test_binding_constants_match_the_header():
+    """Every SC_* enumerator the binding defines has the header's value."""
+    import re
+    hdr = open(os.path.join(ROOT, "include", "sc.h")).read()
+    vals = {m.group(1): int(m.group(2)) for m in re.finditer(r"\b(SC_[A-Z0-9_]+)\s*=\s*(-?\d+)", hdr)}
+    defs = {m.group(1): int(m.group(2)) for m in re.finditer(r"#define\s+(SC_[A-Z0-9_]+)\s+(\d+)", hdr)}
+    vals.update(defs)
+    checked = 0
+    for name in dir(sc):
+        if name.startswith("SC_") and isinstance(getattr(sc, name), int) and name in vals:
+            assert getattr(sc, name) == vals[name], name
+            checked += 1
+    assert checked >= 15
+    for opt in sc.OPTION_DEFAULTS:
+        assert opt in vals.values()
+
+
+def test_bench_traffic_follows_the_kernel_sources(tmp_path, monkeypatch):
+    """bench.py reports the committed HBM traffic only for the kernel sources
+    it was measured on."""
+    import json
+    import bench
+    h = bench.source_hash()
+    assert len(h) == 16
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    (prof / "traffic.json").write_text(json.dumps({"source_hash": h, "hbm_bytes_per_step": 123.0}))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "source_hash", lambda: h)
+    assert bench.traffic_per_step() == 123.0
+    monkeypatch.setattr(bench, "source_hash", lambda: "0" * 16)
+    assert bench.traffic_per_step() is None
