@@ -19,6 +19,8 @@ __all__ = [
     "Job", "Tune", "ServeCfg", "Query", "Result", "ServeStats", "lib", "lib_path", "sc_version",
     "sc_plan_template",
     "sc_colorset_rank", "sc_color_of", "Context",
+    "Estimate", "SC_EST_BOUND", "SC_EST_SAMPLE", "SC_ABL_FASCIA", "SC_ABL_PFASCIA", "colorings_for",
+    "SC_MAX_T",
 ]
 
 SC_OK, SC_EINVAL, SC_ENOMEM, SC_EDEVICE, SC_ENOTFOUND, SC_EBUSY, SC_ESTATE = 0, -1, -2, -3, -4, -5, -6
