@@ -16,9 +16,13 @@
  *    multiply-add ("eMA") M_s[v,C] = sum_{C1 (+) C2 = C} M_a[v,C1] * N[v,C2].
  *
  * Counts are exact unsigned 64-bit residues.  Overflow is not an error: each
- * colouring carries a flag that is 1 iff some neighbour-sum entry, product,
- * table entry or final count, evaluated exactly from the stored 64-bit
- * operands, reached 2^64.  The flag depends on the plan (root and child order)
+ * colouring carries a flag that is 1 iff some usable neighbour-sum entry, some
+ * product, some table entry or the final count, evaluated exactly from the
+ * stored 64-bit operands, reached 2^64.  A neighbour-sum entry N[v][C2] is
+ * usable iff C2 leaves out the colour of v: every other entry only ever meets
+ * zero active entries (the active child's root maps to v, so its colour set
+ * holds col(v), and the split sets are disjoint).  The flag depends on the
+ * plan (root and child order)
  * but not on summation order, batching or fusion; the residue depends on
  * nothing but (graph, template, k, seed, colouring index).  sc_run_exact
  * recovers the counts that pass 2^64 exactly (residue passes modulo primes and
@@ -28,6 +32,11 @@
  * Colouring rule (the paper only says "randomly selected"): colouring r of
  * vertex v is floor(x * k / 2^64) where x is output number r*2^40 + v of
  * SplitMix64 (Steele, Lea & Flood, OOPSLA 2014) seeded with the context seed.
+ * Vertex ids are below 2^31, so the rule gives distinct outputs for colouring
+ * indices below SC_MAX_COLORING = 2^24; every call that runs colourings
+ * rejects a range that reaches past it (SC_EINVAL), because colouring
+ * r + 2^24 would repeat colouring r and the colourings would no longer be
+ * independent draws.
  *
  * Conventions for every call:
  *  - return value: SC_OK (0) or a negative SC_E* code; nothing throws or aborts;
@@ -52,6 +61,7 @@ extern "C" {
 #define SC_MAX_T 16          /* template vertices */
 #define SC_MAX_K 16          /* colours */
 #define SC_MAX_BATCH 64      /* colourings folded into one pass */
+#define SC_MAX_COLORING (1ull << 24)   /* colouring indices run below this */
 
 enum {
     SC_OK = 0,
@@ -65,15 +75,24 @@ enum {
 
 typedef struct sc_ctx sc_ctx;
 
-/* Optional device allocator hook.  `alloc` returns device memory of at least
- * `bytes` bytes usable on `stream` (NULL on failure); `free_fn` releases it.
- * When both are NULL the library uses hipMalloc / hipFree. */
+/* Device allocator hook, required: every device buffer the library holds
+ * (resident graphs, index tables, count tables, colours, results) comes from
+ * `alloc` and goes back through `free_fn`; the library never allocates device
+ * memory any other way.  `alloc` returns device memory of at least `bytes`
+ * bytes for use on `stream` (a hipStream_t), or NULL on failure (the call
+ * that needed it then returns SC_ENOMEM); `free_fn` receives the pointer, its
+ * size and the stream it was allocated for, once the library's work on it has
+ * completed.  The hooks may be called from the serving loop's worker thread.
+ * The Python binding passes PyTorch's caching allocator. */
 typedef void *(*sc_alloc_fn)(size_t bytes, void *stream, void *user);
 typedef void (*sc_free_fn)(void *ptr, size_t bytes, void *stream, void *user);
 
-/* Creates a context on HIP device `device`.  `mem_budget_bytes` caps the count
- * tables of one run (0 = 90% of the device's free memory at creation).
- * Errors: SC_EINVAL (bad device or only one of alloc/free given), SC_EDEVICE. */
+/* Creates a context on HIP device `device` with the allocator hooks `alloc` /
+ * `free_fn` (both required; `user` is passed to them).  `mem_budget_bytes`
+ * caps the count tables of one run (0 = 90% of the device's free memory at
+ * creation).  The context owns a non-blocking stream of its own, which every
+ * call given a NULL stream uses.
+ * Errors: SC_EINVAL (bad device, NULL alloc or free_fn), SC_EDEVICE. */
 int sc_create(int device, sc_alloc_fn alloc, sc_free_fn free_fn, void *user,
               uint64_t mem_budget_bytes, sc_ctx **out);
 
@@ -174,7 +193,9 @@ int32_t sc_color_of(uint64_t seed, uint64_t coloring, uint64_t vertex, int32_t k
  * first_coloring .. first_coloring+n_colorings-1 (colourings are folded into
  * the table columns, up to the planned batch per pass).  Synchronous: on return
  * the host outputs are written.  `stream` is a hipStream_t (NULL = the
- * context's own stream).
+ * context's own stream; the legacy null stream is not used because it cannot
+ * be captured into a hipGraph).  Buffers the run allocates are requested
+ * for this stream.
  * Host outputs: counts[n_colorings] (residues mod 2^64), overflow[n_colorings]
  * (0/1), and optionally (may be NULL) est_maps / est_copies: the mean count
  * divided by k!/((k-t)! k^t), and that divided by |Aut(T)|; NaN if any
@@ -186,7 +207,7 @@ int sc_run(sc_ctx *ctx, int32_t graph_id, int32_t tmpl_id, uint64_t first_colori
 
 /* Exact wide counts.  The DP uses only additions and multiplications, so it
  * commutes with reduction modulo any m (Eq. 2 and the counting recursion of
- * Sec. 3.1 with every entry taken mod m).  sc_run gives each count mod 2^64 and
+ * Sec. 2.1 with every entry taken mod m).  sc_run gives each count mod 2^64 and
  * flags the colourings whose count reached 2^64; for those, sc_run_exact adds
  * passes modulo the primes 2^61-1, 2^62-57, 2^63-25 and recovers the count by
  * the Chinese remainder theorem.  The homomorphism count of the template into
@@ -240,7 +261,7 @@ int sc_colorings_for(int32_t k, int32_t t, double eps, double delta, int32_t *gr
 int sc_estimate(sc_ctx *ctx, int32_t graph_id, int32_t tmpl_id, uint64_t first_coloring, double eps,
                 double delta, int32_t mode, int64_t max_colorings, void *stream, sc_estimate_t *out);
 
-/* Baselines for the pruning ablation (Sec. 3.2, Sec. 4.1, Sec. 6.3): the same
+/* Baselines for the pruning ablation (Sec. 3.1, Sec. 4.1, Sec. 7.1): the same
  * counts as sc_run, one colouring at a time, by plain kernels over tables in
  * the paper's layout (all binom(k, s) colour sets per row):
  *   SC_ABL_FASCIA  -- Algorithm 1: every split sums the passive column over
@@ -320,7 +341,9 @@ int sc_tune_load(sc_ctx *ctx, const char *path, int32_t *n_applied);
  * cannot change and graphs with passes in flight cannot be unloaded. */
 typedef struct {
     uint64_t mem_budget_bytes;
-    int32_t max_inflight;           /* streams, 1..16 */
+    int32_t max_inflight;           /* streams, 1..4 (HIP's default hardware
+                                       queues per process; more streams would
+                                       only share them) */
     int32_t max_batch;              /* colourings per pass, 1..SC_MAX_BATCH */
 } sc_serve_cfg_t;
 
@@ -379,16 +402,46 @@ int sc_get_option(sc_ctx *ctx, int32_t option, int64_t *value);
 /* ------------------------------------------------------------------ tracing */
 
 /* Per-kernel-family statistics gathered with HIP events recorded around every
- * launch on the run's stream while profiling is on.  `alg_bytes` is the
- * algorithmic (compulsory) HBM traffic of those launches and `updates` their
- * update count (neighbour-sum updates nnz*C(k,p) and multiply-adds), summed. */
+ * launch on the run's stream while profiling is on (families: zero, color,
+ * split, row_hist, row_gather, reduce).  Summed over those launches:
+ *  - alg_bytes: the algorithmic (compulsory) bytes of the method in the
+ *    paper's table layout (binom(k, s) colour sets per row, every vertex of
+ *    the graph; Sec. 4.3): per DP step (h, a, p) with B colourings,
+ *    4 nnz + 8 (n+1) (the adjacency once), + 8 n B binom(k, p) (the passive
+ *    table read once; n B colour bytes for p = 1), + 8 n B binom(k, a) (the
+ *    active table; n B colour bytes for a = 1), + 8 n B binom(k, h) (the output
+ *    written once).  The neighbour sum N of a fused step is never stored, so
+ *    its write and read are not counted.  A step's bytes are attributed to
+ *    its row kernel; the split pre-pass (rows with more neighbours than the
+ *    segment size) carries none.
+ *  - layout_bytes: the same in this library's rooted-colour layout
+ *    (binom(k-1, s-1) sets per table row, non-isolated rows only), plus the
+ *    split pre-pass's partial sums written and read back.
+ *  - updates: Lemma 1's counts, nnz binom(k, p) neighbour-sum updates plus
+ *    n binom(k, h) binom(h, a) multiply-adds (n binom(k, h) for a = 1), times B. */
 typedef struct {
     char name[32];
     int32_t launches;
     double total_ms;
     double alg_bytes;
     double updates;
+    double layout_bytes;
 } sc_kernel_stat_t;
+
+/* One traced launch: the kernel instantiation as profilers name it (e.g.
+ * "dp_row_kernel<16, 1, false, 0, true, false, 256>"), its family, the DP step
+ * it belongs to (index in the plan and its sizes h, a, p; step -1 outside the
+ * steps), the colourings of its pass, its duration between HIP events on the
+ * run's stream, and its bytes and updates as in sc_kernel_stat_t. */
+typedef struct {
+    char kernel[96];
+    char family[16];
+    int32_t step, h, a, p, colorings;
+    double ms;
+    double alg_bytes;
+    double layout_bytes;
+    double updates;
+} sc_launch_t;
 
 /* enable = 1 starts recording (and clears earlier records), 0 stops. */
 int sc_profile(sc_ctx *ctx, int32_t enable);
@@ -396,6 +449,9 @@ int sc_profile(sc_ctx *ctx, int32_t enable);
  * and sets *n_out to the number of families.  Records are kept until the next
  * sc_profile(ctx, 1). */
 int sc_profile_read(sc_ctx *ctx, sc_kernel_stat_t *out, int32_t cap, int32_t *n_out);
+/* Waits for the recorded launches and copies the first `cap` of them, in
+ * launch order, into out; *n_out = the number recorded. */
+int sc_profile_launches(sc_ctx *ctx, sc_launch_t *out, int32_t cap, int32_t *n_out);
 
 #ifdef __cplusplus
 }

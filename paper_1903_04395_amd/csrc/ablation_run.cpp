@@ -15,6 +15,7 @@ int sc_run_ablation(sc_ctx *c, int32_t gid, int32_t tid, int32_t variant, uint64
     if (!c) return SC_EINVAL;
     std::lock_guard<std::recursive_mutex> lk(c->mu);
     int rc = check_run_args(c, gid, tid, ncol);
+    if (!rc) rc = check_coloring_range(c, first, ncol);
     if (rc) return rc;
     if (variant != SC_ABL_FASCIA && variant != SC_ABL_PFASCIA) return fail(c, SC_EINVAL, "unknown variant %d", variant);
     if (ncol > 0 && (!counts || !overflow)) return fail(c, SC_EINVAL, "NULL output");
@@ -41,10 +42,10 @@ int sc_run_ablation(sc_ctx *c, int32_t gid, int32_t tid, int32_t variant, uint64
     int64_t wp_max = 0;
     for (const Step &s : P.steps) wp_max = std::max<int64_t>(wp_max, (int64_t)binom(k, s.p));
     for (size_t i = 0; i < P.bufs.size() && !rc; ++i)
-        rc = dev_alloc(c, tabs[i], (size_t)n * binom(k, P.bufs[i].size) * 8);
-    if (!rc && variant == SC_ABL_PFASCIA) rc = dev_alloc(c, nbuf, (size_t)n * wp_max * 8);
-    if (!rc) rc = dev_alloc(c, colb, (size_t)n);
-    if (!rc) rc = dev_alloc(c, misc, 4 * sizeof(uint64_t));
+        rc = dev_alloc(c, tabs[i], (size_t)n * binom(k, P.bufs[i].size) * 8, st);
+    if (!rc && variant == SC_ABL_PFASCIA) rc = dev_alloc(c, nbuf, (size_t)n * wp_max * 8, st);
+    if (!rc) rc = dev_alloc(c, colb, (size_t)n, st);
+    if (!rc) rc = dev_alloc(c, misc, 4 * sizeof(uint64_t), st);
     if (rc) { release(); return rc; }
     auto tab = [&](int id) { return id < 0 ? (uint64_t *)nullptr : (uint64_t *)tabs[id].p; };
     auto *words = (uint64_t *)misc.p;            // desc[2], X, flag

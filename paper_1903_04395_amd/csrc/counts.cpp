@@ -86,7 +86,7 @@ int hom_count(sc_ctx *c, int gid, int tid, hipStream_t st, double *out) {
     if ((rc = rebin(c, g, default_segment(c)))) return rc;
     const int64_t n = g.n_rows;
     DevMem tmp;
-    if ((rc = dev_alloc(c, tmp, (P.bufs.size() * (size_t)n + 1) * sizeof(double)))) return rc;
+    if ((rc = dev_alloc(c, tmp, (P.bufs.size() * (size_t)n + 1) * sizeof(double), st))) return rc;
     double *base = (double *)tmp.p;
     auto hb = [&](int id) { return id < 0 ? (double *)nullptr : base + 1 + (size_t)id * n; };
     const kern::GraphBins bins = bins_of(g);
@@ -310,6 +310,7 @@ int sc_estimate(sc_ctx *c, int32_t gid, int32_t tid, uint64_t first, double eps,
     };
     int64_t need = (int64_t)m * g;                 // SC_EST_BOUND: the variance bound 1/P - 1
     if (mode == SC_EST_BOUND) {
+        if ((rc = check_coloring_range(c, first, need))) return rc;
         if (need > cap)
             return fail(c, SC_EINVAL, "the bound needs %lld colourings (%d groups of %lld), above max_colorings=%lld",
                         (long long)need, m, (long long)g, (long long)cap);
@@ -319,6 +320,7 @@ int sc_estimate(sc_ctx *c, int32_t gid, int32_t tid, uint64_t first, double eps,
         // after each round; rounds at most double the colourings run so far
         int64_t next = std::min<int64_t>(cap, 4 * (int64_t)m);
         for (;;) {
+            if ((rc = check_coloring_range(c, first, next))) return rc;
             if ((rc = run(next - (int64_t)y.size()))) return rc;
             long double mean = 0, var = 0;
             for (long double v : y) mean += v;

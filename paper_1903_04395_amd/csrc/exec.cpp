@@ -28,15 +28,24 @@ hipEvent_t next_event(sc_ctx *c) {
     return c->event_pool[c->events_used++];
 }
 
-// Brackets one launch with HIP events on its stream while profiling is on.
+// What a traced launch belongs to: its family, the DP step (index and sizes;
+// step -1 for launches outside the steps), the colourings of the pass, the
+// compulsory bytes of the paper's layout and of the rooted-colour layout, and
+// its updates in the paper's units.
+struct LaunchInfo {
+    const char *family;
+    int step = -1, h = 0, a = 0, p = 0, colorings = 0;
+    double bytes = 0, layout_bytes = 0, updates = 0;
+};
+
+// Brackets one launch with HIP events on its stream while profiling is on and
+// records the kernel instantiation the launcher enqueued.
 struct ProfScope {
     sc_ctx *c;
     hipStream_t st;
-    const char *name;
-    double bytes, updates;
+    LaunchInfo li;
     hipEvent_t a = nullptr;
-    ProfScope(sc_ctx *c_, bool on, hipStream_t st_, const char *n, double by, double up)
-        : c(c_), st(st_), name(n), bytes(by), updates(up) {
+    ProfScope(sc_ctx *c_, bool on, hipStream_t st_, const LaunchInfo &l) : c(c_), st(st_), li(l) {
         if (on && (a = next_event(c))) (void)hipEventRecord(a, st);
     }
     ~ProfScope() {
@@ -44,7 +53,8 @@ struct ProfScope {
         hipEvent_t b = next_event(c);
         if (!b) return;
         (void)hipEventRecord(b, st);
-        c->recs.push_back({name, a, b, bytes, updates});
+        c->recs.push_back({li.family, kern::last_kernel_name(), li.step, li.h, li.a, li.p, li.colorings, a, b,
+                           li.bytes, li.layout_bytes, li.updates});
     }
 };
 
@@ -89,6 +99,13 @@ int step_args(sc_ctx *c, const Plan &P, const Step &s, uint64_t mod, kern::StepS
 
 }  // namespace
 
+uint64_t buffers_after(const Graph &g, const Plan &P, const PassBuffers &b) {
+    auto grown = [](const DevMem &m, uint64_t need) { return std::max<uint64_t>(m.bytes, need); };
+    return grown(b.arena, P.arena_bytes) + grown(b.colbuf, (uint64_t)g.n_rows * P.batch) +
+           grown(b.npre, npre_bytes(g, P)) + grown(b.xbuf, (SC_MAX_BATCH + 1) * sizeof(uint64_t)) +
+           grown(b.desc, 2 * sizeof(uint64_t));
+}
+
 int prepare_pass(sc_ctx *c, const PassSpec &s, PassBuffers &b, hipStream_t st) {
     Graph &g = *s.g;
     const Plan &P = *s.P;
@@ -122,40 +139,67 @@ int enqueue_pass(sc_ctx *c, const PassSpec &sp, PassBuffers &pb, hipStream_t st,
     auto *Npre = (uint64_t *)pb.npre.p;
     auto buf = [&](int id) { return id < 0 ? (uint64_t *)nullptr : (uint64_t *)(base + P.bufs[id].offset); };
     const kern::GraphBins bins = bins_of(g);
-    const double split_nnz = g.split_nnz, row_nnz = (double)g.nnz - split_nnz;
+    // the paper's units count every vertex of the graph (isolated ones included)
+    const double nall = (double)g.n, nnz = (double)g.nnz;
 
-    HIPCHK(c, kern::launch_zero_u64((uint64_t *)X, SC_MAX_BATCH + 1, st));
     {
-        ProfScope ps(c, prof, st, "color", dn * B, 0);
+        LaunchInfo li{"zero"};
+        li.colorings = B;
+        ProfScope ps(c, prof, st, li);
+        HIPCHK(c, kern::launch_zero_u64((uint64_t *)X, SC_MAX_BATCH + 1, st));
+    }
+    {
+        LaunchInfo li{"color"};
+        li.colorings = B;
+        li.bytes = li.layout_bytes = dn * B;
+        ProfScope ps(c, prof, st, li);
         HIPCHK(c, kern::launch_color((const uint64_t *)pb.desc.p, n, B, k, (const int32_t *)g.perm.p, col, st));
     }
     const Step *last = nullptr;
+    int si = 0;
     for (const Step &s : P.steps) {
         kern::StepShape sh;
         kern::StepTables tb;
         if ((rc = step_args(c, P, s, sp.mod, sh, tb))) return rc;
         uint64_t *S = buf(s.buf_s);
         const uint64_t *Pp = buf(s.buf_p), *A = buf(s.buf_a);
+        LaunchInfo li{s.p == 1 ? "row_hist" : "row_gather", si, s.h, s.a, s.p, B};
         // updates in the paper's units (Lemma 1): nnz*C(k,p) neighbour-sum
         // updates, n*C(k,h)*C(h,a) multiply-adds (n*C(k,h) selects for a = 1)
-        const double Wp = (double)binom(k, s.p), Wh = (double)binom(k, s.h);
-        const double ema_upd = dn * Wh * (s.a > 1 ? (double)binom(s.h, s.a) : 1.0) * dB;
+        const double Wp = (double)binom(k, s.p), Wa = (double)binom(k, s.a), Wh = (double)binom(k, s.h);
+        li.updates = (nnz * Wp + nall * Wh * (s.a > 1 ? (double)binom(s.h, s.a) : 1.0)) * dB;
+        // compulsory bytes of the fused step in the paper's layout (every
+        // vertex, binom(k, s) colour sets per row): the adjacency once, the
+        // passive table read once (colours for p = 1), the active table read
+        // once (colours for a = 1), the output written once; N never stored
+        li.bytes = 4.0 * nnz + 8.0 * (nall + 1) + (s.p > 1 ? 8.0 * nall * dB * Wp : nall * dB) +
+                   (s.a > 1 ? 8.0 * nall * dB * Wa : nall * dB) + 8.0 * nall * dB * Wh;
+        // the same in the rooted-colour layout over the table rows, plus the
+        // split rows' sums written and read back
+        li.layout_bytes = 4.0 * nnz + 8.0 * (dn + 1) + dn * dB +
+                          8.0 * dn * dB * ((s.p > 1 ? sh.Wq : 0) + (s.a > 1 ? sh.Wa : 0) + sh.Wh) +
+                          8.0 * (double)g.n_split * sh.Wn * dB;
         if (g.n_split) {
-            ProfScope ps(c, prof, st, "split", 4.0 * split_nnz + 16.0 * g.n_split * sh.Wn * dB,
-                         split_nnz * Wp * dB);
+            // the heavy rows' share of the step's neighbour sums; its bytes
+            // and updates are counted with the row kernel, which completes them
+            LaunchInfo ls{"split", si, s.h, s.a, s.p, B};
+            ls.layout_bytes = 4.0 * g.split_nnz + 16.0 * g.n_split * sh.Wn * dB;
+            ProfScope ps(c, prof, st, ls);
             HIPCHK(c, kern::launch_dp_split(bins, sh, tb, col, Pp, Npre, flags, st));
         }
-        // compulsory bytes: adjacency, colours, the passive and active tables
-        // read once, the output written once, split rows' sums read back
-        const double bytes = 4.0 * (double)g.nnz + 8.0 * (dn + 1) + dn * dB +
-                             8.0 * dn * dB * ((s.p > 1 ? sh.Wq : 0) + (s.a > 1 ? sh.Wa : 0) + sh.Wh) +
-                             8.0 * (double)g.n_split * sh.Wn * dB;
-        ProfScope ps(c, prof, st, s.p == 1 ? "row_hist" : "row_gather", bytes, row_nnz * Wp * dB + ema_upd);
-        HIPCHK(c, kern::launch_dp_row(bins, sh, tb, col, Pp, A, Npre, S, flags, st));
+        {
+            ProfScope ps(c, prof, st, li);
+            HIPCHK(c, kern::launch_dp_row(bins, sh, tb, col, Pp, A, Npre, S, flags, st));
+        }
         last = &s;
+        ++si;
     }
     const int W = (int)binom(k - 1, last->h - 1);
-    ProfScope ps(c, prof, st, "reduce", 8.0 * dn * W * B, 0);
+    LaunchInfo li{"reduce"};
+    li.colorings = B;
+    li.layout_bytes = 8.0 * dn * W * B;
+    li.bytes = 8.0 * nall * (double)binom(k, last->h) * B;
+    ProfScope ps(c, prof, st, li);
     HIPCHK(c, kern::launch_reduce(n, buf(last->buf_s), W, B, P.interleave, sp.mod, X, flags, st));
     return SC_OK;
 }
@@ -248,9 +292,17 @@ int run_passes(sc_ctx *c, std::vector<PassJob> &passes, hipStream_t st,
     return SC_OK;
 }
 
+int check_coloring_range(sc_ctx *c, uint64_t first, int64_t n) {
+    if (n < 0 || first > SC_MAX_COLORING || (uint64_t)n > SC_MAX_COLORING - first)
+        return fail(c, SC_EINVAL, "colourings %llu..%llu+%lld reach past 2^24, where the colouring rule repeats",
+                    (unsigned long long)first, (unsigned long long)first, (long long)n);
+    return SC_OK;
+}
+
 // Splits n colourings of one job into passes of the planned batch.
 int plan_job(sc_ctx *c, int job, int gid, int tid, int k, uint64_t seed, uint64_t first, int n,
              std::vector<PassJob> &out) {
+    if (int rc = check_coloring_range(c, first, n)) return rc;
     int off = 0;
     while (off < n) {
         PassJob p;

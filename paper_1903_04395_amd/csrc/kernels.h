@@ -112,6 +112,11 @@ hipError_t launch_hom_sum(int64_t n, const double *S, double *out, hipStream_t s
 
 hipError_t launch_zero_u64(uint64_t *p, int64_t count, hipStream_t st);
 
+// Name of the kernel instantiation the calling thread's last launcher call
+// enqueued (as profilers print it, e.g. "dp_row_kernel<16, 1, false, 0, true,
+// false, 256>"), or "" if that call launched nothing.
+const char *last_kernel_name();
+
 // Baselines for the pruning ablation (ablation.hip): one DP step of one
 // colouring with tables in the paper's layout ([n][binom(k, s)], column =
 // Eq. 1 rank), either FASCIA's (the passive column summed over the neighbours

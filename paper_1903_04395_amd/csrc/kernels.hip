@@ -25,6 +25,8 @@
 // col(v).  Sets that hold col(v) only ever meet zero active entries and are
 // skipped, and neighbours that share v's colour contribute nothing.
 #include <algorithm>
+#include <cstdarg>
+#include <cstdio>
 
 #include "kernels.h"
 #include "exact.h"      // after the HIP runtime header (it uses __device__)
@@ -773,6 +775,19 @@ __global__ __launch_bounds__(kBlock) void zero_kernel(uint64_t *p, int64_t count
         p[i] = 0;
 }
 
+// Instantiation launched last by this thread (for launch tracing).
+thread_local char t_last_kernel[96];
+
+void name_kernel(const char *fmt, ...) __attribute__((format(printf, 1, 2)));
+void name_kernel(const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(t_last_kernel, sizeof t_last_kernel, fmt, ap);
+    va_end(ap);
+}
+
+const char *tf(bool b) { return b ? "true" : "false"; }
+
 int log2_exact(int x) {
     int s = 0;
     while ((1 << s) < x) ++s;
@@ -852,6 +867,7 @@ hipError_t row_launch(const DpArgs &a, int lds, hipStream_t st) {
     if (e != hipSuccess) return e;
     const int64_t teams = WAVE ? kWaves : 1;
     const int64_t blocks = std::min<int64_t>((a.n * a.planes + teams - 1) / teams, 2 * resident_blocks(lds, TPB));
+    name_kernel("dp_row_kernel<%d, %d, %s, %d, %s, %s, %d>", CH, NB, tf(BIG), AM, tf(WAVE), tf(MOD), TPB);
     dp_row_kernel<CH, NB, BIG, AM, WAVE, MOD, TPB><<<dim3((unsigned)blocks), dim3(TPB), lds, st>>>(a);
     return hipGetLastError();
 }
@@ -861,6 +877,7 @@ hipError_t split_launch(const DpArgs &a, int lds, hipStream_t st) {
     hipError_t e = allow_lds(dp_split_kernel<CH, NB, BIG, MOD, TPB>, lds);
     if (e != hipSuccess) return e;
     const int64_t blocks = std::min<int64_t>(a.n_items * a.planes, 2 * resident_blocks(lds, TPB));
+    name_kernel("dp_split_kernel<%d, %d, %s, %s, %d>", CH, NB, tf(BIG), tf(MOD), TPB);
     dp_split_kernel<CH, NB, BIG, MOD, TPB><<<dim3((unsigned)blocks), dim3(TPB), lds, st>>>(a);
     return hipGetLastError();
 }
@@ -932,6 +949,8 @@ bool mod_supported(uint64_t p) {
     return p != 0 && make_modulus(p, m);
 }
 
+const char *last_kernel_name() { return t_last_kernel; }
+
 int rank_entries(int k1) { return k1 <= kDirectRankBits ? 1 << k1 : 256 + 9 * (1 << (k1 - 8)); }
 
 int dp_lds_bytes(const StepShape &s, int amode, int n_rank, int teams) {
@@ -948,7 +967,9 @@ int dp_lds_bytes(const StepShape &s, int amode, int n_rank, int teams) {
 }
 
 hipError_t launch_zero_u64(uint64_t *p, int64_t count, hipStream_t st) {
+    t_last_kernel[0] = 0;
     if (count <= 0) return hipSuccess;
+    name_kernel("zero_kernel");
     int64_t blocks = std::min<int64_t>((count + kBlock - 1) / kBlock, 8192);
     zero_kernel<<<dim3((unsigned)blocks), dim3(kBlock), 0, st>>>(p, count);
     return hipGetLastError();
@@ -957,8 +978,10 @@ hipError_t launch_zero_u64(uint64_t *p, int64_t count, hipStream_t st) {
 hipError_t launch_color(const uint64_t *desc, int64_t n, int B, int k, const int32_t *perm,
                         uint8_t *col, hipStream_t st) {
     const int64_t total = n * B;
+    t_last_kernel[0] = 0;
     if (total <= 0) return hipSuccess;
     const int64_t blocks = std::min<int64_t>((total + kBlock - 1) / kBlock, kMaxStrideBlocks);
+    name_kernel("color_kernel");
     color_kernel<<<dim3((unsigned)blocks), dim3(kBlock), 0, st>>>(desc, n, B, k, perm, col);
     return hipGetLastError();
 }
@@ -966,6 +989,7 @@ hipError_t launch_color(const uint64_t *desc, int64_t n, int B, int k, const int
 hipError_t launch_dp_split(const GraphBins &g, const StepShape &s, const StepTables &t,
                            const uint8_t *col, const uint64_t *P, uint64_t *Npre,
                            unsigned long long *flags, hipStream_t st) {
+    t_last_kernel[0] = 0;
     if (g.n_split == 0 || g.n_split_items == 0) return hipSuccess;
     if (!shape_ok(s) || (s.p >= 2 && (!P || !t.unrank || !t.rank))) return hipErrorInvalidValue;
     hipError_t e = launch_zero_u64(Npre, g.n_split * (int64_t)s.Wn * s.B, st);
@@ -981,6 +1005,7 @@ hipError_t launch_dp_row(const GraphBins &g, const StepShape &s, const StepTable
                          const uint8_t *col, const uint64_t *P, const uint64_t *A,
                          const uint64_t *Npre, uint64_t *S, unsigned long long *flags,
                          hipStream_t st) {
+    t_last_kernel[0] = 0;
     if (g.n <= 0) return hipSuccess;
     if (!shape_ok(s) || !S || (s.p >= 2 && (!P || !t.unrank || !t.rank)) ||
         (s.amode != kActiveLeaf && (!A || !t.split)) || (g.n_split && !Npre))
@@ -1015,11 +1040,13 @@ hipError_t launch_dp_row(const GraphBins &g, const StepShape &s, const StepTable
 
 hipError_t launch_reduce(int64_t n, const uint64_t *S, int W, int B, int Bi, uint64_t mod,
                          unsigned long long *X, unsigned long long *flags, hipStream_t st) {
+    t_last_kernel[0] = 0;
     if (n <= 0 || B <= 0) return hipSuccess;
     Modulus md;
     if (Bi < 1 || B % Bi || !make_modulus(mod, md)) return hipErrorInvalidValue;
     const int64_t total = n * W;
     const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((total + kBlock - 1) / kBlock, 1024));
+    name_kernel("reduce_kernel<%s>", tf(mod != 0));
     if (mod) reduce_kernel<true><<<dim3(blocks, (unsigned)B), dim3(kBlock), 0, st>>>(n, S, W, Bi, md, X, flags);
     else reduce_kernel<false><<<dim3(blocks, (unsigned)B), dim3(kBlock), 0, st>>>(n, S, W, Bi, md, X, flags);
     return hipGetLastError();

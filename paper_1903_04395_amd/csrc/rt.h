@@ -21,9 +21,12 @@
 
 namespace sc {
 
+// Device memory from the context's allocator hook, with the stream it was
+// allocated for (handed back to the hook when it is freed).
 struct DevMem {
     void *p = nullptr;
     size_t bytes = 0;
+    hipStream_t stream = nullptr;
 };
 
 struct Graph {
@@ -119,7 +122,13 @@ struct sc_ctx {
     int64_t interleave = 0, lds_max = 0, wave_row_max = -1, reorder = 1;
     // tracing
     bool prof = false;
-    struct Rec { const char *name; hipEvent_t a, b; double bytes, updates; };
+    struct Rec {
+        const char *name;          // family
+        std::string kernel;        // instantiation
+        int step, h, a, p, colorings;
+        hipEvent_t a_ev, b_ev;
+        double bytes, layout_bytes, updates;
+    };
     std::vector<Rec> recs;
     std::vector<hipEvent_t> event_pool;
     size_t events_used = 0;
@@ -139,7 +148,8 @@ int fail(sc_ctx *c, int code, const char *fmt, ...);
             return ::sc::fail(ctx, SC_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
     } while (0)
 
-int dev_alloc(sc_ctx *c, DevMem &m, size_t bytes);
+// Memory from the allocator hook for use on `st` (NULL: the context's stream).
+int dev_alloc(sc_ctx *c, DevMem &m, size_t bytes, hipStream_t st = nullptr);
 void dev_free(sc_ctx *c, DevMem &m);
 // Grows m to at least `bytes` (contents not kept); waits for `st` before freeing.
 int ensure(sc_ctx *c, DevMem &m, size_t bytes, hipStream_t st, uint64_t *gen = nullptr);
@@ -164,6 +174,9 @@ int pick_batch(sc_ctx *c, int gid, int tid, int k, int want, uint64_t budget, Pl
 uint64_t pass_bytes(const Graph &g, const Plan &P);
 double colorful_probability(int k, int t);
 
+// Bytes `b` holds once a pass of plan P on graph g has run in it: buffers only
+// grow, so each one ends at the larger of what it held and what P needs.
+uint64_t buffers_after(const Graph &g, const Plan &P, const PassBuffers &b);
 // Allocations and uploads a pass needs (not capturable).
 int prepare_pass(sc_ctx *c, const PassSpec &s, PassBuffers &b, hipStream_t st);
 // The pass's kernels on `st`, reading seed and first colouring from b.desc
@@ -188,6 +201,8 @@ struct PassJob {
 // SC_MAX_BATCH + 1 result words) for each.
 int run_passes(sc_ctx *c, std::vector<PassJob> &passes, hipStream_t st,
                const std::function<void(const PassJob &, const uint64_t *)> &done);
+// SC_EINVAL unless colourings first..first+n-1 all lie below SC_MAX_COLORING.
+int check_coloring_range(sc_ctx *c, uint64_t first, int64_t n);
 // Splits n colourings of one job into passes of the planned batch.
 int plan_job(sc_ctx *c, int job, int gid, int tid, int k, uint64_t seed, uint64_t first, int n,
              std::vector<PassJob> &out);

@@ -20,30 +20,23 @@ int fail(sc_ctx *c, int code, const char *fmt, ...) {
     return code;
 }
 
-int dev_alloc(sc_ctx *c, DevMem &m, size_t bytes) {
+int dev_alloc(sc_ctx *c, DevMem &m, size_t bytes, hipStream_t st) {
     if (bytes == 0) bytes = 256;
-    void *p = nullptr;
-    if (c->alloc) {
-        p = c->alloc(bytes, (void *)c->stream, c->user);
-        if (!p) return fail(c, SC_ENOMEM, "allocator hook returned NULL for %zu bytes", bytes);
-    } else {
-        hipError_t e = hipMalloc(&p, bytes);
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
-            return fail(c, SC_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
-        }
-    }
+    if (!st) st = c->stream;
+    void *p = c->alloc(bytes, (void *)st, c->user);
+    if (!p) return fail(c, SC_ENOMEM, "the allocator hook returned NULL for %zu bytes", bytes);
     m.p = p;
     m.bytes = bytes;
+    m.stream = st;
     return SC_OK;
 }
 
 void dev_free(sc_ctx *c, DevMem &m) {
     if (!m.p) return;
-    if (c->free_fn) c->free_fn(m.p, m.bytes, (void *)c->stream, c->user);
-    else (void)hipFree(m.p);
+    c->free_fn(m.p, m.bytes, (void *)m.stream, c->user);
     m.p = nullptr;
     m.bytes = 0;
+    m.stream = nullptr;
 }
 
 int ensure(sc_ctx *c, DevMem &m, size_t bytes, hipStream_t st, uint64_t *gen) {
@@ -53,7 +46,7 @@ int ensure(sc_ctx *c, DevMem &m, size_t bytes, hipStream_t st, uint64_t *gen) {
         dev_free(c, m);
     }
     if (gen) ++*gen;
-    return dev_alloc(c, m, bytes);
+    return dev_alloc(c, m, bytes, st);
 }
 
 int upload(sc_ctx *c, DevMem &m, const void *host, size_t bytes) {
@@ -259,7 +252,7 @@ int sc_create(int device, sc_alloc_fn alloc, sc_free_fn free_fn, void *user, uin
               sc_ctx **out) {
     if (!out) return SC_EINVAL;
     *out = nullptr;
-    if ((alloc == nullptr) != (free_fn == nullptr)) return SC_EINVAL;
+    if (!alloc || !free_fn) return SC_EINVAL;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) { (void)hipGetLastError(); return SC_EDEVICE; }
     if (device < 0 || device >= ndev) return SC_EINVAL;
@@ -557,9 +550,9 @@ int sc_profile_read(sc_ctx *c, sc_kernel_stat_t *out, int32_t cap, int32_t *n_ou
     if (!n_out || (cap > 0 && !out)) return fail(c, SC_EINVAL, "NULL argument");
     std::vector<sc_kernel_stat_t> agg;
     for (auto &r : c->recs) {
-        HIPCHK(c, hipEventSynchronize(r.b));
+        HIPCHK(c, hipEventSynchronize(r.b_ev));
         float ms = 0.f;
-        HIPCHK(c, hipEventElapsedTime(&ms, r.a, r.b));
+        HIPCHK(c, hipEventElapsedTime(&ms, r.a_ev, r.b_ev));
         sc_kernel_stat_t *hit = nullptr;
         for (auto &a : agg) if (!strcmp(a.name, r.name)) hit = &a;
         if (!hit) {
@@ -571,10 +564,34 @@ int sc_profile_read(sc_ctx *c, sc_kernel_stat_t *out, int32_t cap, int32_t *n_ou
         hit->launches += 1;
         hit->total_ms += ms;
         hit->alg_bytes += r.bytes;
+        hit->layout_bytes += r.layout_bytes;
         hit->updates += r.updates;
     }
     *n_out = (int32_t)agg.size();
     for (int32_t i = 0; i < cap && i < (int32_t)agg.size(); ++i) out[i] = agg[i];
+    return SC_OK;
+}
+
+int sc_profile_launches(sc_ctx *c, sc_launch_t *out, int32_t cap, int32_t *n_out) {
+    if (!c) return SC_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    if (!n_out || (cap > 0 && !out)) return fail(c, SC_EINVAL, "NULL argument");
+    *n_out = (int32_t)c->recs.size();
+    for (int32_t i = 0; i < cap && i < (int32_t)c->recs.size(); ++i) {
+        const auto &r = c->recs[i];
+        HIPCHK(c, hipEventSynchronize(r.b_ev));
+        float ms = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&ms, r.a_ev, r.b_ev));
+        sc_launch_t &o = out[i];
+        std::memset(&o, 0, sizeof o);
+        std::snprintf(o.kernel, sizeof o.kernel, "%s", r.kernel.c_str());
+        std::snprintf(o.family, sizeof o.family, "%s", r.name);
+        o.step = r.step; o.h = r.h; o.a = r.a; o.p = r.p; o.colorings = r.colorings;
+        o.ms = ms;
+        o.alg_bytes = r.bytes;
+        o.layout_bytes = r.layout_bytes;
+        o.updates = r.updates;
+    }
     return SC_OK;
 }
 

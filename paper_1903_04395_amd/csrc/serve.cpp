@@ -22,6 +22,11 @@ namespace sc {
 
 namespace {
 
+// Streams of the serving loop: HIP maps a process's streams onto 4 hardware
+// queues by default, so more streams only share them (and compete for the
+// table budget).
+constexpr int kMaxInflight = 4;
+
 double now_s() {
     using namespace std::chrono;
     return duration<double>(steady_clock::now().time_since_epoch()).count();
@@ -177,6 +182,19 @@ bool admit(sc_ctx *c, ServeState &S) {
             continue;
         }
         Graph *g = c->graphs[Q->q.graph_id].get();
+        {
+            // the plan fits what is left beside the other slots; this slot's
+            // buffers only grow, so if keeping them would take the total past
+            // the budget, release them first (the slot is idle)
+            uint64_t mem = 0;
+            for (const Slot &o : S.slots) mem += slot_bytes(o);
+            const uint64_t others3 = mem - slot_bytes(sl);
+            if (others3 + buffers_after(*g, P, sl.buf) > S.cfg.mem_budget_bytes) {
+                (void)hipStreamSynchronize(sl.st);
+                dev_free(c, sl.buf.arena); dev_free(c, sl.buf.colbuf); dev_free(c, sl.buf.npre);
+                sl.buf.gen = 0;
+            }
+        }
         PassSpec spec;
         spec.g = g;
         spec.P = &sl.P;
@@ -267,7 +285,8 @@ int sc_serve_start(sc_ctx *c, const sc_serve_cfg_t *cfg) {
     std::lock_guard<std::recursive_mutex> lk(c->mu);
     if (!cfg) return fail(c, SC_EINVAL, "NULL config");
     if (c->serve) return fail(c, SC_ESTATE, "the serving loop already runs");
-    if (cfg->max_inflight < 1 || cfg->max_inflight > 16) return fail(c, SC_EINVAL, "max_inflight must be in [1, 16]");
+    if (cfg->max_inflight < 1 || cfg->max_inflight > kMaxInflight)
+        return fail(c, SC_EINVAL, "max_inflight must be in [1, %d]", kMaxInflight);
     if (cfg->max_batch < 1 || cfg->max_batch > SC_MAX_BATCH) return fail(c, SC_EINVAL, "max_batch must be in [1, %d]", SC_MAX_BATCH);
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, SC_EDEVICE, "hipSetDevice failed");
     auto S = std::make_unique<ServeState>();
@@ -303,6 +322,7 @@ int sc_submit(sc_ctx *c, const sc_query_t *q, uint64_t *ticket) {
         if (ti == c->tmpls.end()) return fail(c, SC_ENOTFOUND, "unknown template %d", q->tmpl_id);
         if (q->k < ti->second->t || q->k > SC_MAX_K) return fail(c, SC_EINVAL, "need t <= k <= 16");
         if (q->n_colorings < 1) return fail(c, SC_EINVAL, "n_colorings must be >= 1");
+        if (int rc = check_coloring_range(c, q->first_coloring, q->n_colorings)) return rc;
     }
     ServeState &S = *c->serve;
     auto Q = std::make_unique<Query>();

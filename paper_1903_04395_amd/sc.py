@@ -15,7 +15,7 @@ import numpy as np
 __all__ = [
     "SC_OK", "SC_EINVAL", "SC_ENOMEM", "SC_EDEVICE", "SC_ENOTFOUND", "SC_EBUSY", "SC_ESTATE",
     "SC_OPT_MAX_BATCH", "SC_OPT_GRAPH", "SC_OPT_SEGMENT", "SC_OPT_REORDER", "SC_OPT_INTERLEAVE",
-    "SC_OPT_LDS_MAX", "SC_OPT_WAVE_ROW_MAX", "OPTION_DEFAULTS", "ScError", "PlanInfo", "KernelStat",
+    "SC_OPT_LDS_MAX", "SC_OPT_WAVE_ROW_MAX", "OPTION_DEFAULTS", "ScError", "PlanInfo", "KernelStat", "Launch",
     "Job", "Tune", "ServeCfg", "Query", "Result", "ServeStats", "lib", "lib_path", "sc_version",
     "sc_plan_template",
     "sc_colorset_rank", "sc_color_of", "Context",
@@ -88,7 +88,16 @@ class PlanInfo(ctypes.Structure):
 class KernelStat(ctypes.Structure):
     _fields_ = [
         ("name", ctypes.c_char * 32), ("launches", ctypes.c_int32), ("total_ms", ctypes.c_double),
-        ("alg_bytes", ctypes.c_double), ("updates", ctypes.c_double),
+        ("alg_bytes", ctypes.c_double), ("updates", ctypes.c_double), ("layout_bytes", ctypes.c_double),
+    ]
+
+
+class Launch(ctypes.Structure):
+    _fields_ = [
+        ("kernel", ctypes.c_char * 96), ("family", ctypes.c_char * 16), ("step", ctypes.c_int32),
+        ("h", ctypes.c_int32), ("a", ctypes.c_int32), ("p", ctypes.c_int32), ("colorings", ctypes.c_int32),
+        ("ms", ctypes.c_double), ("alg_bytes", ctypes.c_double), ("layout_bytes", ctypes.c_double),
+        ("updates", ctypes.c_double),
     ]
 
 
@@ -152,11 +161,18 @@ class ScError(RuntimeError):
 
 
 def lib():
-    """Load libsc.so; raises if it has not been built."""
+    """Load libsc.so; raises if it has not been built.
+
+    PyTorch is imported first: its wheel carries its own HIP runtime
+    (libamdhip64.so.7, libhsa-runtime64.so.1), and loading it first lets
+    libsc's dependencies resolve to those same, already loaded, libraries, so
+    the process has one HIP runtime and the memory PyTorch's allocator hands
+    the library belongs to the runtime that launches its kernels."""
     global _lib
     if _lib is None:
         if not os.path.exists(lib_path):
             raise RuntimeError(f"{lib_path} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+        import torch  # noqa: F401  (see above: one HIP runtime per process)
         L = ctypes.CDLL(lib_path)
         sig = {
             "sc_create": (ctypes.c_int, [ctypes.c_int, ALLOC_FN, FREE_FN, _vp, ctypes.c_uint64, ctypes.POINTER(_vp)]),
@@ -204,6 +220,7 @@ def lib():
             "sc_profile": (ctypes.c_int, [_vp, ctypes.c_int32]),
             "sc_profile_read": (ctypes.c_int, [_vp, ctypes.POINTER(KernelStat), ctypes.c_int32,
                                                _i32p]),
+            "sc_profile_launches": (ctypes.c_int, [_vp, ctypes.POINTER(Launch), ctypes.c_int32, _i32p]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -258,34 +275,47 @@ def sc_color_of(seed: int, coloring: int, vertex: int, k: int) -> int:
 class Context:
     """One libsc context on a HIP device.
 
-    ``torch_allocator=True`` routes the library's device allocations through
-    PyTorch's caching allocator (and PyTorch's current stream)."""
+    Device memory comes from PyTorch's caching allocator (the library's
+    required allocator hook), so the library's tables show in
+    ``torch.cuda.memory_allocated()``; every call that takes a stream runs on
+    PyTorch's current stream unless given another (a ``torch.cuda.Stream`` or
+    a raw hipStream_t as an int).  PyTorch's default stream is the null
+    stream, for which the library uses its own non-blocking stream."""
 
-    def __init__(self, device: int = 0, budget: int = 0, torch_allocator: bool = False):
+    def __init__(self, device: int = 0, budget: int = 0):
+        import torch
         L = lib()
-        self._cbs = None
-        alloc = ALLOC_FN()
-        free = FREE_FN()
-        if torch_allocator:
-            import torch
+        dev = int(device)
 
-            def _alloc(nbytes, stream, user):
-                try:
-                    return int(torch.cuda.caching_allocator_alloc(int(nbytes), device, stream))
-                except Exception:
-                    return None
+        def _alloc(nbytes, stream, user):
+            try:
+                return int(torch.cuda.caching_allocator_alloc(int(nbytes), dev, stream or 0))
+            except Exception:
+                return None
 
-            def _free(ptr, nbytes, stream, user):
+        def _free(ptr, nbytes, stream, user):
+            try:
                 torch.cuda.caching_allocator_delete(ptr)
+            except Exception:
+                pass
 
-            alloc, free = ALLOC_FN(_alloc), FREE_FN(_free)
-            self._cbs = (alloc, free)
+        self._cbs = (ALLOC_FN(_alloc), FREE_FN(_free))
+        self._device = dev
+        self._torch = torch
         h = _vp()
-        rc = L.sc_create(device, alloc, free, None, budget, ctypes.byref(h))
+        rc = L.sc_create(dev, self._cbs[0], self._cbs[1], None, budget, ctypes.byref(h))
         if rc:
             raise ScError(rc, "sc_create failed (no usable HIP device?)")
         self._h = h
         self._L = L
+
+    def _stream(self, stream):
+        """hipStream_t for a call: PyTorch's current stream unless given."""
+        if stream is None:
+            return self._torch.cuda.current_stream(self._device).cuda_stream or None
+        if isinstance(stream, int):
+            return stream or None
+        return stream.cuda_stream or None
 
     # -- plumbing
     def _check(self, rc):
@@ -367,8 +397,23 @@ class Context:
         n = ctypes.c_int32()
         self._check(self._L.sc_profile_read(self._h, arr, cap, ctypes.byref(n)))
         return {arr[i].name.decode(): {"launches": arr[i].launches, "total_ms": arr[i].total_ms,
-                                       "alg_bytes": arr[i].alg_bytes, "updates": arr[i].updates}
+                                       "alg_bytes": arr[i].alg_bytes, "layout_bytes": arr[i].layout_bytes,
+                                       "updates": arr[i].updates}
                 for i in range(min(n.value, cap))}
+
+    def profile_launches(self):
+        """Every recorded launch in order, as dicts (kernel, family, step, h, a, p,
+        colorings, ms, alg_bytes, layout_bytes, updates)."""
+        n = ctypes.c_int32()
+        self._check(self._L.sc_profile_launches(self._h, None, 0, ctypes.byref(n)))
+        arr = (Launch * max(1, n.value))()
+        self._check(self._L.sc_profile_launches(self._h, arr, n.value, ctypes.byref(n)))
+        out = []
+        for r in arr[:n.value]:
+            d = {f: getattr(r, f) for f, _ in Launch._fields_}
+            d["kernel"], d["family"] = r.kernel.decode(), r.family.decode()
+            out.append(d)
+        return out
 
     def plan_info(self, gid, tid, n_colorings=1) -> PlanInfo:
         out = PlanInfo()
@@ -391,7 +436,7 @@ class Context:
             arr[i].n_colorings = n
             arr[i].counts = _p(cnt, _u64p)
             arr[i].overflow = _p(ovf, _u8p)
-        rc = self._L.sc_run_batch(self._h, arr, len(jobs), stream)
+        rc = self._L.sc_run_batch(self._h, arr, len(jobs), self._stream(stream))
         out = [(bufs[i][0][:bufs[i][2]], bufs[i][1][:bufs[i][2]], arr[i].est_maps, arr[i].est_copies,
                 arr[i].status) for i in range(len(jobs))]
         if rc and all(o[4] == 0 for o in out):
@@ -453,7 +498,7 @@ class Context:
         counts = np.zeros(max(R, 1), np.uint64)
         ovf = np.zeros(max(R, 1), np.uint8)
         em, ec = ctypes.c_double(), ctypes.c_double()
-        self._check(self._L.sc_run(self._h, gid, tid, first, R, stream, _p(counts, _u64p), _p(ovf, _u8p),
+        self._check(self._L.sc_run(self._h, gid, tid, first, R, self._stream(stream), _p(counts, _u64p), _p(ovf, _u8p),
                                    ctypes.byref(em), ctypes.byref(ec)))
         return counts[:R], ovf[:R], em.value, ec.value
 
@@ -464,7 +509,7 @@ class Context:
         limbs = np.zeros((max(R, 1), 4), np.uint64)
         exact = np.zeros(max(R, 1), np.uint8)
         hb, em, ec = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
-        self._check(self._L.sc_run_exact(self._h, gid, tid, first, R, stream, _p(limbs, _u64p), _p(exact, _u8p),
+        self._check(self._L.sc_run_exact(self._h, gid, tid, first, R, self._stream(stream), _p(limbs, _u64p), _p(exact, _u8p),
                                          ctypes.byref(hb), ctypes.byref(em), ctypes.byref(ec)))
         counts = [sum(int(limbs[r, i]) << (64 * i) for i in range(4)) for r in range(R)]
         return counts, exact[:R], hb.value, em.value, ec.value
@@ -473,7 +518,7 @@ class Context:
         """Returns uint64[R]: each colouring's count mod p."""
         R = int(n_colorings)
         res = np.zeros(max(R, 1), np.uint64)
-        self._check(self._L.sc_run_mod(self._h, gid, tid, first, R, stream, int(p), _p(res, _u64p)))
+        self._check(self._L.sc_run_mod(self._h, gid, tid, first, R, self._stream(stream), int(p), _p(res, _u64p)))
         return res[:R]
 
     def run_ablation(self, gid, tid, variant, first, n_colorings, stream=None):
@@ -481,19 +526,19 @@ class Context:
         R = int(n_colorings)
         counts = np.zeros(max(R, 1), np.uint64)
         ovf = np.zeros(max(R, 1), np.uint8)
-        self._check(self._L.sc_run_ablation(self._h, gid, tid, variant, first, R, stream, _p(counts, _u64p),
+        self._check(self._L.sc_run_ablation(self._h, gid, tid, variant, first, R, self._stream(stream), _p(counts, _u64p),
                                             _p(ovf, _u8p)))
         return counts[:R], ovf[:R]
 
     def estimate(self, gid, tid, eps, delta, mode=SC_EST_BOUND, max_colorings=0, first=0, stream=None):
         """(eps, delta) estimate by the median of means; returns an Estimate."""
         out = Estimate()
-        self._check(self._L.sc_estimate(self._h, gid, tid, first, eps, delta, mode, max_colorings, stream,
+        self._check(self._L.sc_estimate(self._h, gid, tid, first, eps, delta, mode, max_colorings, self._stream(stream),
                                         ctypes.byref(out)))
         return out
 
     def hom_count(self, gid, tid, stream=None):
         """Homomorphisms of the template into the graph (double)."""
         out = ctypes.c_double()
-        self._check(self._L.sc_hom_count(self._h, gid, tid, stream, ctypes.byref(out)))
+        self._check(self._L.sc_hom_count(self._h, gid, tid, self._stream(stream), ctypes.byref(out)))
         return out.value

@@ -24,6 +24,7 @@ def declared_functions():
 
 
 def test_library_exports_every_declared_symbol():
+    sc.lib()                                  # loads PyTorch's HIP runtime first
     L = ctypes.CDLL(sc.lib_path)
     names = declared_functions()
     assert "sc_run" in names and "sc_create" in names
@@ -33,6 +34,30 @@ def test_library_exports_every_declared_symbol():
 
 def test_version_string():
     assert "libsc" in sc.sc_version()
+
+
+def test_create_requires_the_allocator_hook():
+    """The allocator hook is the library's only source of device memory:
+    sc_create rejects NULL hooks before it looks for a device."""
+    L = sc.lib()
+    h = ctypes.c_void_p()
+    assert L.sc_create(0, sc.ALLOC_FN(), sc.FREE_FN(), None, 0, ctypes.byref(h)) == sc.SC_EINVAL
+    assert not h.value
+    keep = sc.ALLOC_FN(lambda n, s, u: None)
+    assert L.sc_create(0, keep, sc.FREE_FN(), None, 0, ctypes.byref(h)) == sc.SC_EINVAL
+
+
+def test_library_shares_pytorchs_hip_runtime():
+    """In a fresh process, loading the library through the binding leaves one
+    HIP runtime (PyTorch's) mapped."""
+    import subprocess
+    import sys
+    code = ("from paper_1903_04395_amd import sc; sc.lib(); "
+            "m = open('/proc/self/maps').read().splitlines(); "
+            "print(len({l.split()[-1] for l in m if 'libamdhip64' in l}), "
+            "len({l.split()[-1] for l in m if 'libhsa-runtime64' in l}))")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, check=True)
+    assert out.stdout.split() == ["1", "1"], out.stdout + out.stderr
 
 
 def test_no_device_create_fails_cleanly():

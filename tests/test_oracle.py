@@ -210,6 +210,36 @@ def test_sum_over_all_colourings_identity(t, edges, k):
     assert total == M * math.factorial(k) // math.factorial(k - t) * k ** (g.n - t)
 
 
+@pytest.mark.parametrize("t,edges,k", [
+    (3, [(0, 1), (1, 2)], 4),
+    (3, [(0, 1), (1, 2)], 5),
+    (4, [(0, 1), (0, 2), (0, 3)], 5),
+    (2, [(0, 1)], 4),
+])
+def test_colorful_probability_and_estimate_for_k_above_t(t, edges, k):
+    """k > t (Section 2.1, phase 1): over all k^n colourings the mean colourful
+    count is M(T,G) * P exactly, so O.colorful_probability(k, t) must equal
+    (sum X) / (k^n M), and O.estimate over all colourings must return M (maps)
+    and M / |Aut T| (copies).  M comes from brute-force enumeration; a dropped
+    (k-t)! or a k^k in place of k^t fails both checks."""
+    from fractions import Fraction
+    g = I.random_small_graph(6, 0.6, 7)
+    plan = O.root_plan(t, edges, 0, "given")
+    counts = []
+    for col in itertools.product(range(k), repeat=g.n):
+        X, f = O.count_colored(g, t, plan, k, np.array(col, np.uint8))
+        assert f == 0
+        counts.append(X)
+    M = brute_maps(g, t, edges, 0)
+    assert M > 0
+    ratio = Fraction(sum(counts), k ** g.n * M)
+    assert O.colorful_probability(k, t) == pytest.approx(float(ratio), rel=1e-12)
+    maps, copies = O.estimate(np.array(counts, np.uint64), np.zeros(len(counts), np.uint8), k, t,
+                              O.aut(t, edges))
+    assert maps == pytest.approx(M, rel=1e-9)
+    assert copies == pytest.approx(M / O.aut(t, edges), rel=1e-9)
+
+
 def _neighbour_colour_counts(g, col, k):
     cnt = np.zeros((g.n, k), dtype=object)
     for v in range(g.n):
@@ -447,6 +477,16 @@ def test_estimator_converges_star():
     deg = g.degrees()
     copies = sum(math.comb(int(d), t - 1) for d in deg)
     est_copies = _convergence(g, t, I.star(t), k, copies * math.factorial(t - 1), 1500, 3)
+    assert est_copies == pytest.approx(copies, rel=0.1)
+
+
+def test_estimator_converges_star_k_above_t():
+    """k = t + 1: colourful maps use t of the k colours, P = k!/((k-t)! k^t)."""
+    g = I.erdos_renyi(80, 400, 24)
+    t, k = 4, 5
+    deg = g.degrees()
+    copies = sum(math.comb(int(d), t - 1) for d in deg)
+    est_copies = _convergence(g, t, I.star(t), k, copies * math.factorial(t - 1), 1500, 8)
     assert est_copies == pytest.approx(copies, rel=0.1)
 
 
