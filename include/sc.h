@@ -205,6 +205,26 @@ int sc_run(sc_ctx *ctx, int32_t graph_id, int32_t tmpl_id, uint64_t first_colori
            int32_t n_colorings, void *stream, uint64_t *counts, uint8_t *overflow,
            double *est_maps, double *est_copies);
 
+/* For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid allocation between set-up and tear-down): sc_run with
+ * every buffer of the run -- colours, count tables, the split rows' neighbour
+ * sums, index tables, descriptor and results -- placed in one device array of
+ * SC_STATIC_SCRATCH_BYTES that the library holds per device (and per process)
+ * from its first sc_create on that device until the process ends.  The call
+ * allocates nothing (no hipMalloc, no allocator hook, no pinned host memory);
+ * the graph and template must already be loaded.  Same arguments, outputs,
+ * counts and flags as sc_run; colourings are folded into passes whose
+ * buffers fit the array.  Calls on one device are serialised inside the
+ * process (the array keeps the last call's contents; everything a run reads
+ * is written by that run first).  Synchronous.
+ * Errors: as sc_run; SC_ENOMEM when even one colouring's buffers exceed
+ * SC_STATIC_SCRATCH_BYTES; SC_ESTATE when the graph's heavy-row bins are
+ * stale (SC_OPT_SEGMENT changed since the graph was last run or loaded). */
+#define SC_STATIC_SCRATCH_BYTES 67108864ull   /* 64 MiB */
+int sc_run_static(sc_ctx *ctx, int32_t graph_id, int32_t tmpl_id, uint64_t first_coloring,
+                  int32_t n_colorings, void *stream, uint64_t *counts, uint8_t *overflow,
+                  double *est_maps, double *est_copies);
+
 /* Exact wide counts.  The DP uses only additions and multiplications, so it
  * commutes with reduction modulo any m (Eq. 2 and the counting recursion of
  * Sec. 2.1 with every entry taken mod m).  sc_run gives each count mod 2^64 and

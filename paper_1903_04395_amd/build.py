@@ -14,7 +14,7 @@ LIB = os.path.join(HERE, "libsc.so")
 OBJ = os.path.join(HERE, "_build")
 
 SOURCES = ["plan.cpp", "runtime.cpp", "exec.cpp", "counts.cpp", "ablation_run.cpp", "serve.cpp", "kernels.hip",
-           "ablation.hip"]
+           "ablation.hip", "static_run.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -66,16 +66,11 @@ int ensure_gen(sc_ctx *c, DevMem &m, size_t bytes, hipStream_t st, PassBuffers &
     return rc;
 }
 
-size_t npre_bytes(const Graph &g, const Plan &P) {
-    size_t w = 0;
-    for (const Step &s : P.steps) w = std::max(w, (size_t)g.n_split * binom(P.k - 1, s.p) * P.batch);
-    return w * 8;
-}
-
-// Kernel shape and device index tables of one step (tables are uploaded on
-// first use, so prepare_pass calls this before any capture).
+// Kernel shape and device index tables of one step: the tables are the staged
+// copies when `staged` is given, else the context's (uploaded on first use, so
+// prepare_pass calls this before any capture).
 int step_args(sc_ctx *c, const Plan &P, const Step &s, uint64_t mod, kern::StepShape &sh,
-              kern::StepTables &tb) {
+              kern::StepTables &tb, const StagedTables *staged = nullptr) {
     const int k = P.k;
     sh.k = k; sh.a = s.a; sh.p = s.p;
     sh.B = P.batch; sh.Bi = P.interleave;
@@ -87,6 +82,23 @@ int step_args(sc_ctx *c, const Plan &P, const Step &s, uint64_t mod, kern::StepS
     sh.amode = s.amode;
     sh.wave_row_max = P.opts.wave_row_max;
     sh.mod = mod;
+    if (staged) {
+        auto find = [](const auto &m, const TableKey &key, auto *&out) {
+            auto it = m.find(key);
+            if (it == m.end()) return false;
+            out = it->second;
+            return true;
+        };
+        if (s.a > 1 && !find(staged->split, TableKey{k - 1, s.h - 1, s.a - 1}, tb.split))
+            return fail(c, SC_EINVAL, "split table (%d,%d,%d) not staged", k - 1, s.h - 1, s.a - 1);
+        if (s.p > 1) {
+            if (!find(staged->unrank, TableKey{k - 1, s.p - 1, 0}, tb.unrank) ||
+                !find(staged->rank, TableKey{k - 1, 0, 0}, tb.rank))
+                return fail(c, SC_EINVAL, "rank tables for k-1=%d, size %d not staged", k - 1, s.p - 1);
+            tb.n_rank = kern::rank_entries(k - 1);
+        }
+        return SC_OK;
+    }
     int rc;
     if (s.a > 1 && (rc = get_split(c, k - 1, s.h - 1, s.a - 1, &tb.split))) return rc;
     if (s.p > 1) {
@@ -98,6 +110,12 @@ int step_args(sc_ctx *c, const Plan &P, const Step &s, uint64_t mod, kern::StepS
 }
 
 }  // namespace
+
+size_t npre_bytes(const Graph &g, const Plan &P) {
+    size_t w = 0;
+    for (const Step &s : P.steps) w = std::max(w, (size_t)g.n_split * binom(P.k - 1, s.p) * P.batch);
+    return w * 8;
+}
 
 uint64_t buffers_after(const Graph &g, const Plan &P, const PassBuffers &b) {
     auto grown = [](const DevMem &m, uint64_t need) { return std::max<uint64_t>(m.bytes, need); };
@@ -160,7 +178,7 @@ int enqueue_pass(sc_ctx *c, const PassSpec &sp, PassBuffers &pb, hipStream_t st,
     for (const Step &s : P.steps) {
         kern::StepShape sh;
         kern::StepTables tb;
-        if ((rc = step_args(c, P, s, sp.mod, sh, tb))) return rc;
+        if ((rc = step_args(c, P, s, sp.mod, sh, tb, pb.staged))) return rc;
         uint64_t *S = buf(s.buf_s);
         const uint64_t *Pp = buf(s.buf_p), *A = buf(s.buf_a);
         LaunchInfo li{s.p == 1 ? "row_hist" : "row_gather", si, s.h, s.a, s.p, B};
@@ -330,7 +348,7 @@ int check_run_args(sc_ctx *c, int gid, int tid, int ncol) {
 
 }  // namespace sc
 
-namespace {
+namespace sc {
 
 void estimates(const uint64_t *counts, const uint8_t *ovf, int n, int k, int t, double aut,
                double *maps, double *copies) {
@@ -346,7 +364,7 @@ void estimates(const uint64_t *counts, const uint8_t *ovf, int n, int k, int t, 
     if (copies) *copies = cp;
 }
 
-}  // namespace
+}  // namespace sc
 
 extern "C" {
 

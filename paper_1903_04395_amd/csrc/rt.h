@@ -76,12 +76,21 @@ struct PassSpec {
     uint64_t mod = 0;              // 0: exact uint64 counts; else counts mod this prime
 };
 
+// Index tables of one pass copied into memory the caller provides (the
+// allocation-free entry point); keyed as the context's table caches are.
+struct StagedTables {
+    std::map<TableKey, const uint32_t *> split;
+    std::map<TableKey, const uint16_t *> unrank, rank;
+};
+
 // Device buffers one in-flight pass uses besides the resident graph and the
 // index tables.  `gen` changes whenever one of them is reallocated (captured
-// graphs that baked the old addresses are then discarded).
+// graphs that baked the old addresses are then discarded).  `staged`, when
+// set, supplies every index table the pass reads (nothing is uploaded).
 struct PassBuffers {
     DevMem arena, colbuf, xbuf, npre, desc;
     uint64_t gen = 0;
+    const StagedTables *staged = nullptr;
 };
 
 struct GraphExecKey {
@@ -188,6 +197,14 @@ int enqueue_pass(sc_ctx *c, const PassSpec &s, PassBuffers &b, hipStream_t st, b
 int launch_pass(sc_ctx *c, int gid, int tid, const PassSpec &s, PassBuffers &b, hipStream_t st,
                 uint64_t *host_desc, uint64_t *host_res, bool allow_graph);
 void unpack_pass(const uint64_t *host_res, int B, uint64_t *counts, uint8_t *flags);
+// Mean-count estimates of maps and copies (NaN if any colouring overflowed).
+void estimates(const uint64_t *counts, const uint8_t *ovf, int n, int k, int t, double aut,
+               double *maps, double *copies);
+// Bytes of the pre-pass neighbour sums of split rows for plan P on graph g.
+size_t npre_bytes(const Graph &g, const Plan &P);
+// Sets up the allocation-free entry point's device scratch on `device` (the
+// device must be current); called once per context creation.
+int static_scratch_init(int device);
 
 // One pass of a planned job: colourings first..first+P.batch-1 of job `job`.
 struct PassJob {

@@ -257,6 +257,7 @@ int sc_create(int device, sc_alloc_fn alloc, sc_free_fn free_fn, void *user, uin
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) { (void)hipGetLastError(); return SC_EDEVICE; }
     if (device < 0 || device >= ndev) return SC_EINVAL;
     if (hipSetDevice(device) != hipSuccess) return SC_EDEVICE;
+    if (static_scratch_init(device) != SC_OK) return SC_EDEVICE;
     auto *c = new sc_ctx();
     c->device = device;
     c->alloc = alloc;

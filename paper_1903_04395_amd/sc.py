@@ -20,13 +20,14 @@ __all__ = [
     "sc_plan_template",
     "sc_colorset_rank", "sc_color_of", "Context",
     "Estimate", "SC_EST_BOUND", "SC_EST_SAMPLE", "SC_ABL_FASCIA", "SC_ABL_PFASCIA", "colorings_for",
-    "SC_MAX_T",
+    "SC_MAX_T", "SC_STATIC_SCRATCH_BYTES",
 ]
 
 SC_OK, SC_EINVAL, SC_ENOMEM, SC_EDEVICE, SC_ENOTFOUND, SC_EBUSY, SC_ESTATE = 0, -1, -2, -3, -4, -5, -6
 SC_OPT_MAX_BATCH, SC_OPT_GRAPH, SC_OPT_SEGMENT, SC_OPT_REORDER = 1, 3, 5, 8
 SC_OPT_INTERLEAVE, SC_OPT_LDS_MAX, SC_OPT_WAVE_ROW_MAX = 9, 10, 11
 SC_MAX_T = 16
+SC_STATIC_SCRATCH_BYTES = 64 << 20     # the allocation-free entry point's device array
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 lib_path = os.path.join(_HERE, "libsc.so")
@@ -193,6 +194,8 @@ def lib():
             "sc_color_of": (ctypes.c_int32, [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int32]),
             "sc_run": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int32,
                                       _vp, _u64p, _u8p, _dblp, _dblp]),
+            "sc_run_static": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int32,
+                                             _vp, _u64p, _u8p, _dblp, _dblp]),
             "sc_run_exact": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int32,
                                             _vp, _u64p, _u8p, _dblp, _dblp, _dblp]),
             "sc_run_mod": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int32,
@@ -500,6 +503,17 @@ class Context:
         em, ec = ctypes.c_double(), ctypes.c_double()
         self._check(self._L.sc_run(self._h, gid, tid, first, R, self._stream(stream), _p(counts, _u64p), _p(ovf, _u8p),
                                    ctypes.byref(em), ctypes.byref(ec)))
+        return counts[:R], ovf[:R], em.value, ec.value
+
+    def run_static(self, gid, tid, first, n_colorings, stream=None):
+        """As run(), through the allocation-free entry point (every buffer in the
+        library's per-device static array of SC_STATIC_SCRATCH_BYTES)."""
+        R = int(n_colorings)
+        counts = np.zeros(max(R, 1), np.uint64)
+        ovf = np.zeros(max(R, 1), np.uint8)
+        em, ec = ctypes.c_double(), ctypes.c_double()
+        self._check(self._L.sc_run_static(self._h, gid, tid, first, R, self._stream(stream), _p(counts, _u64p),
+                                          _p(ovf, _u8p), ctypes.byref(em), ctypes.byref(ec)))
         return counts[:R], ovf[:R], em.value, ec.value
 
     def run_exact(self, gid, tid, first, n_colorings, stream=None):

@@ -1,0 +1,89 @@
+"""GPU tests of sc_run_static, the allocation-free entry point: through the
+C ABI it gives the same (residue, overflow flag) per colouring and the same
+estimates as sc_run, on two calls in a row (the second on a smaller input),
+without a single allocation through the allocator hook; and it rejects a run
+whose buffers exceed its static array before launching anything."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1903_04395_amd import inputs as I
+from paper_1903_04395_amd import sc
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available()
+    c = sc.Context(0)
+    yield c
+    c.close()
+
+
+def hook_allocations():
+    import torch
+    torch.cuda.synchronize()
+    return torch.cuda.memory_stats().get("allocation.all.allocated", 0), torch.cuda.memory_allocated()
+
+
+def same(a, b):
+    return (math.isnan(a) and math.isnan(b)) or a == b
+
+
+def check_against_run(ctx, g, t, edges, k, seed, first, n):
+    gid = ctx.load_graph(g)
+    tid = ctx.load_template(t, edges)
+    ctx.set_colors(k, seed)
+    ref = ctx.run(gid, tid, first, n)
+    before = hook_allocations()
+    got = ctx.run_static(gid, tid, first, n)
+    after = hook_allocations()
+    assert after == before, (before, after)           # nothing allocated through the hook
+    assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
+    assert same(got[2], ref[2]) and same(got[3], ref[3])
+    info = ctx.plan_info(gid, tid, n)
+    oc, of = O.count(g, t, (info.root, info.children()), k, seed, first, n)
+    assert np.array_equal(got[0], oc) and np.array_equal(got[1], of)
+    ctx.unload_graph(gid)
+    return got
+
+
+def test_static_run_matches_sc_run_on_two_calls(ctx):
+    say("static run 1: RMAT-12, 8-vertex tree, k=8, 40 colourings")
+    got = check_against_run(ctx, I.rmat(12, 16, seed=41), 8, I.prufer_tree(8, 2), 8, 5, 7, 40)
+    assert got[0].any()
+    say("static run 2 (smaller): ER(500, 2000), P5, k=6, 3 colourings")
+    check_against_run(ctx, I.erdos_renyi(500, 2000, 9), 5, I.path(5), 6, 11, 100, 3)
+
+
+def test_static_run_flags_overflow_like_sc_run(ctx):
+    """A star on K_{1,d} whose count passes 2^64: same residue and flag."""
+    d = 200
+    g = I.csr_from_edges(d + 1, np.zeros(d, np.int64), np.arange(1, d + 1))
+    say("static run: K_{1,200}, 12-star, k=12, 8 colourings")
+    got = check_against_run(ctx, g, 12, I.star(12), 12, 3, 0, 8)
+    assert got[1].any()
+
+
+def test_static_run_rejects_runs_beyond_its_array(ctx):
+    g = I.rmat(16, 16, seed=6)
+    gid = ctx.load_graph(g)
+    tid = ctx.load_template(12, I.star(12), 0)
+    ctx.set_colors(12, 1)
+    info = ctx.plan_info(gid, tid, 1)
+    assert info.arena_bytes > sc.SC_STATIC_SCRATCH_BYTES
+    say("static run beyond the array: RMAT-16, 12-star, k=12")
+    before = hook_allocations()
+    with pytest.raises(sc.ScError) as e:
+        ctx.run_static(gid, tid, 0, 1)
+    assert e.value.code == sc.SC_ENOMEM
+    assert hook_allocations() == before
+    ctx.unload_graph(gid)
