@@ -1,20 +1,29 @@
 """Benchmark: colour-coding tree counting on one MI355X.
 
-Workload (the headline configuration): RMAT scale 20 (1,048,576 vertices, 16
-edges per vertex, a/b/c/d = .57/.19/.19/.05, symmetrised, deduplicated,
-self-loops removed, labels permuted), a 10-vertex template tree from a seeded
-Pruefer sequence, k = 10 colours, 8 colourings folded into one pass.  One
-"step" is one sc_run over a fresh batch of 8 colourings (colouring, every DP
-step, root reduction, 9-byte-per-colouring result copy); the graph is resident
-in HBM before the timed region starts.
+Workload (the largest single-GPU configuration): a Chung-Lu power-law graph
+(4,194,304 vertices, mean degree 30, degree exponent 2.1, weights capped at
+sqrt(n * mean degree), seed 3; symmetrised, deduplicated, self-loops removed,
+labels permuted), counted against two 12-vertex templates -- a tree from a
+seeded Pruefer sequence (seed 3) and the 12-star -- with k = 12 colours and 16
+colourings of each template per step.  One "step" is one sc_run of 16
+colourings of the tree and one of 16 colourings of the star (colouring, every
+DP step, root reduction, 9-byte-per-colouring result copy; the library splits
+each into the passes that fit HBM); the graph is resident in HBM before the
+timed region starts.
 
 Prints one JSON line.  `value` is G-updates/s: per colouring the neighbour-sum
 updates sum_steps nnz*C(k,p) plus the multiply-adds sum_steps n*C(k,h)*C(h,a)
-(n*C(k,h) for a select step), over the timed wall time.  `roofline` describes
-the kernel family with the largest share of time, from HIP events recorded by
-libsc on its stream around every launch in the timed region.  `cpu_baseline`
-times the CPU oracle on one colouring of the same workload (and checks that
-colouring's residue and flag against the GPU).
+(n*C(k,h) for a select step), summed over both templates and the timed
+colourings, over the timed wall time.  `roofline` describes the DP step (the
+split pre-pass and row kernel of each step, 99.9% of the GPU time) from HIP
+events recorded by libsc on its stream around every launch in the timed
+region, with the compulsory bytes of the paper's table layout; `steps` gives
+each DP step's time against both roofs it could meet (HBM bytes, and the
+multiply-adds at the vector-ALU rate measured by sc_valu_probe).
+`cpu_baseline` times the CPU oracle on a bounded sample of the same workload:
+the first three DP steps of both templates' plans (the 4-vertex star rooted at
+its centre, k = 12) for one colouring on the whole graph, and checks that
+sample's residue and flag against the GPU.
 """
 import argparse
 import hashlib
@@ -39,11 +48,11 @@ KERNEL_OF = {
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--scale", type=int, default=20, help="RMAT scale (20 = the headline workload)")
-    ap.add_argument("--batch", type=int, default=8)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the side measurements (RMAT-20 workload, plain vs batched, exact counts)")
     ap.add_argument("--opt", action="append", default=[], help="libsc option NUM=VALUE (ablation)")
     ap.add_argument("--breakdown", action="store_true", help="also print the per-family table")
     ap.add_argument("--configs", action="store_true",
@@ -388,6 +397,183 @@ def traffic_per_step():
     return d.get("hbm_bytes_per_step")
 
 
+# the workload: (name, n, mean degree, exponent, graph seed), k, colouring seed,
+# colourings per template per step, and the templates (name, t, edges, root)
+CL = ("Chung-Lu", 4194304, 30, 2.1, 3)
+K, SEED, R_STEP = 12, 7, 16
+
+
+def templates():
+    from paper_1903_04395_amd import inputs as I
+    return [("tree12", 12, I.prufer_tree(12, 3), -1), ("star12", 12, I.star(12), 0)]
+
+
+def host_info():
+    """CPU model, logical cores and RAM of this host (for the CPU baseline)."""
+    model, ram = None, None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+        for line in open("/proc/meminfo"):
+            if line.startswith("MemTotal"):
+                ram = round(int(line.split()[1]) / 2**20, 1)
+                break
+    except OSError:
+        pass
+    return {"cpu_model": model, "ram_GiB": ram, "cpus_visible": os.cpu_count()}
+
+
+def passes_of(launches):
+    """Splits a launch trace into passes (each starts by clearing its result words)."""
+    out = []
+    for r in launches:
+        if r["family"] == "zero" or not out:
+            out.append([])
+        out[-1].append(r)
+    return out
+
+
+def step_table(launches, sequence, rows, valu):
+    """Per template and DP step (a chain of single-vertex attaches counts as one
+    step): ms per step of the benchmark, the paper-layout compulsory bytes,
+    the rooted-layout bytes, the multiply-adds executed, and the fraction of
+    each roof; `bound` is the roof with the larger lower bound on the time.
+    `sequence` names the template of each traced pass in order."""
+    table = {}
+    passes = passes_of(launches)
+    if len(passes) != len(sequence):
+        return None
+    for name, ps in zip(sequence, passes):
+        for r in ps:
+            if r["step"] < 0:
+                continue
+            key = (name, r["step"])
+            fam = r["family"]
+            e = table.setdefault(key, {"template": name, "step": r["step"], "hap": None, "chain": False,
+                                       "ms": 0.0, "alg_bytes": 0.0, "layout_bytes": 0.0, "mul_adds": 0.0,
+                                       "colorings": 0})
+            e["ms"] += r["ms"]
+            e["alg_bytes"] += r["alg_bytes"]
+            e["layout_bytes"] += r["layout_bytes"]
+            if fam in ("row_gather", "row_hist", "chain"):
+                h, a, p = r["h"], r["a"], r["p"]
+                e["hap"] = [h, a, p]
+                e["chain"] = fam == "chain"
+                e["colorings"] += r["colorings"]
+                # executed multiply-adds of the rooted-colour layout (a >= 2);
+                # a chain runs the steps (a+1, a, 1) .. (h, h-1, 1)
+                hs = [(hh, hh - 1) for hh in range(a + 1, h + 1)] if fam == "chain" else [(h, a)]
+                for hh, aa in hs:
+                    if aa > 1:
+                        e["mul_adds"] += rows * math.comb(K - 1, hh - 1) * math.comb(hh - 1, aa - 1) * r["colorings"]
+    out = []
+    for e in sorted(table.values(), key=lambda x: (x["template"], x["step"])):
+        if e["hap"] is None or not e["colorings"]:
+            continue
+        h, a, p = e["hap"]
+        reps = e["colorings"] / R_STEP
+        ms = e["ms"] / reps
+        ab, lb, ma = e["alg_bytes"] / reps, e["layout_bytes"] / reps, e["mul_adds"] / reps
+        form = 2 if p == 1 else (1 if math.comb(h - 1, a - 1) >= 32 else 0)
+        t_hbm = ab / (PEAK_HBM_GBS * 1e9)
+        t_alu = ma / valu[form] if ma else 0.0
+        out.append({"template": e["template"], "step": e["step"], "hap": e["hap"], "chain": e["chain"],
+                    "ms": round(ms, 3), "alg_GB": round(ab / 1e9, 2), "layout_GB": round(lb / 1e9, 2),
+                    "G_mul_adds": round(ma / 1e9, 2),
+                    "hbm_frac": round(t_hbm / (ms / 1e3), 3), "layout_hbm_frac": round(lb / 8e12 / (ms / 1e3), 3),
+                    "valu_frac": round(t_alu / (ms / 1e3), 3) if ma else None,
+                    "bound": "valu" if t_alu > t_hbm else "hbm"})
+    return out
+
+
+def golden_check(counts):
+    """The colourings 0..15 of both templates against the oracle's residues and
+    flags stored in tests/golden/full_size.json (written by a script that
+    calls only the oracle), where the file holds them."""
+    path = os.path.join(ROOT, "tests", "golden", "full_size.json")
+    if not os.path.exists(path):
+        return None
+    data = json.load(open(path))
+    out = {}
+    for name, key in (("tree12", "chunglu4m_tree12_k12"), ("star12", "chunglu4m_star12_k12")):
+        e = data.get(key)
+        if not e or e.get("seed") != SEED or e.get("k") != K or name not in counts:
+            continue
+        c, f = counts[name]
+        hits = [r for r in e["results"] if int(r) < len(c)]
+        ok = all(int(c[int(r)]) == int(e["results"][r][0]) and int(f[int(r)]) == int(e["results"][r][1])
+                 for r in hits)
+        out[name] = {"colorings": len(hits), "equal": ok}
+    return out
+
+
+def extras(ctx, gid3, star_tid):
+    """Side measurements for the same line, after the timed region: exact
+    counts (sc_run_exact, residue passes and CRT) of 16 colourings of the
+    Chung-Lu 12-star beside its uint64 pass; then, on RMAT scale 20 / 10-vertex
+    Pruefer tree (seed 0) / k = 10, the uint64 pass of 8 colourings, exact
+    counts of 8 colourings, and the plain per-colouring launch loop (one
+    colouring per sc_run) against the batched form (8 colourings folded into a
+    pass, replayed from a captured hipGraph) on 16 colourings."""
+    import numpy as np
+    from paper_1903_04395_amd import inputs as I
+    from paper_1903_04395_amd import sc
+    out = {}
+    ctx.set_colors(K, SEED)
+    ctx.run_exact(gid3, star_tid, 0, R_STEP)                  # warm
+    t0 = time.perf_counter()
+    ctx.run(gid3, star_tid, R_STEP, R_STEP)
+    t1 = time.perf_counter()
+    _, exact, _, _, _ = ctx.run_exact(gid3, star_tid, R_STEP, R_STEP)
+    t2 = time.perf_counter()
+    out["chunglu4m_star12_exact"] = {"colorings": R_STEP, "certified": int(exact.sum()),
+                                     "s_uint64": round(t1 - t0, 3), "s_exact": round(t2 - t1, 3),
+                                     "exact_colorings_per_s": round(R_STEP / (t2 - t1), 2),
+                                     "exact_over_uint64": round((t2 - t1) / (t1 - t0), 2)}
+    print(f"[bench] extras: {out}", file=sys.stderr, flush=True)
+    ctx.unload_graph(gid3)
+    g = I.rmat(20, 16, seed=0)
+    gid = ctx.load_graph(g)
+    tid = ctx.load_template(10, I.prufer_tree(10, 0))
+    ctx.set_colors(10, 1)
+    info = ctx.plan_info(gid, tid, 8)
+    ctx.run(gid, tid, 0, 8)
+    reps = 5
+    t0 = time.perf_counter()
+    for i in range(reps):
+        ctx.run(gid, tid, 8 * (i + 1), 8)
+    dt = (time.perf_counter() - t0) / reps
+    ctx.run_exact(gid, tid, 0, 8)
+    t1 = time.perf_counter()
+    _, exact, _, _, _ = ctx.run_exact(gid, tid, 8, 8)
+    dte = time.perf_counter() - t1
+    ctx.set_option(sc.SC_OPT_MAX_BATCH, 1)
+    ctx.run(gid, tid, 0, 1)
+    t0 = time.perf_counter()
+    plain = [ctx.run(gid, tid, r, 1)[0][0] for r in range(16)]
+    dt_p = time.perf_counter() - t0
+    ctx.set_option(sc.SC_OPT_MAX_BATCH, 8)
+    ctx.set_option(sc.SC_OPT_GRAPH, 1)
+    ctx.run(gid, tid, 0, 16)
+    t0 = time.perf_counter()
+    batched = ctx.run(gid, tid, 0, 16)[0]
+    dt_b = time.perf_counter() - t0
+    ctx.set_option(sc.SC_OPT_GRAPH, 0)
+    ctx.set_option(sc.SC_OPT_MAX_BATCH, 64)
+    assert np.array_equal(np.asarray(plain, np.uint64), batched)
+    out["rmat20_tree10_k10_b8"] = {
+        "ms_per_pass": round(dt * 1e3, 2), "colorings_per_s": round(8 / dt, 1),
+        "G_updates_per_s": round(8 * (info.spmm_updates + info.ema_updates) / dt / 1e9, 1),
+        "exact_ms_per_8": round(dte * 1e3, 1), "exact_certified": int(exact.sum()),
+        "plain_colorings_per_s": round(16 / dt_p, 1), "batched_colorings_per_s": round(16 / dt_b, 1),
+        "batched_over_plain": round(dt_p / dt_b, 2)}
+    print(f"[bench] extras: {out['rmat20_tree10_k10_b8']}", file=sys.stderr, flush=True)
+    ctx.unload_graph(gid)
+    return out
+
+
 def main():
     args = parse()
     if args.copy_probe:
@@ -425,9 +611,8 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     t_gen = time.time()
-    g = I.rmat(args.scale, 16, seed=0)
-    t, k, B, seed = 10, 10, args.batch, 1
-    edges = I.prufer_tree(t, 0)
+    _, n0, deg, gamma, gseed = CL
+    g = I.chung_lu(n0, deg, gamma, seed=gseed)
     print(f"[bench] graph n={g.n} nnz={g.nnz} generated in {time.time() - t_gen:.1f}s", file=sys.stderr, flush=True)
 
     ctx = sc.Context(0)
@@ -435,84 +620,118 @@ def main():
         key, val = o.split("=")
         ctx.set_option(int(key), int(val))
     gid = ctx.load_graph(g)
-    tid = ctx.load_template(t, edges)
-    ctx.set_colors(k, seed)
-    info = ctx.plan_info(gid, tid, B)
-    upd_per_coloring = info.spmm_updates + info.ema_updates
-    print(f"[bench] plan root={info.root} steps={info.steps()} modes={info.modes()} batch={info.batch} "
-          f"arena={info.arena_bytes / 1e9:.1f} GB", file=sys.stderr, flush=True)
+    ctx.set_colors(K, SEED)
+    tmpls, infos, plans = {}, {}, {}
+    upd = 0.0
+    for name, t, edges, root in templates():
+        tid = ctx.load_template(t, edges, root)
+        info = ctx.plan_info(gid, tid, R_STEP)
+        tmpls[name], infos[name], plans[name] = tid, info, info.steps()
+        upd += (info.spmm_updates + info.ema_updates) * R_STEP
+        print(f"[bench] {name}: root={info.root} steps={info.steps()} batch={info.batch} "
+              f"interleave={info.interleave} arena={info.arena_bytes / 1e9:.1f} GB", file=sys.stderr, flush=True)
+
+    def step(first):
+        res = {}
+        for name, tid in tmpls.items():
+            c, f, _, _ = ctx.run(gid, tid, first, R_STEP)
+            res[name] = (c, f)
+        return res
 
     first = 0
-    for _ in range(args.warmup):
-        ctx.run(gid, tid, first, B)
-        first += B
+    golden = None
+    for w in range(max(args.warmup, 1)):             # colourings 0..15 first: the golden check
+        res = step(first)
+        if w == 0:
+            golden = golden_check(res)
+        first += R_STEP
+        print(f"[bench] warm-up step {w + 1} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     ctx.profile(True)
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        counts, ovf, _, _ = ctx.run(gid, tid, first, B)
-        first += B
+    for i in range(args.steps):
+        step(first)
+        first += R_STEP
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ctx.profile(False)
     fams = ctx.profile_read()
-    last_first = first - B
+    launches = ctx.profile_launches()
+    print(f"[bench] {args.steps} timed steps in {elapsed:.2f}s", file=sys.stderr, flush=True)
 
-    colorings = args.steps * B
-    value = colorings * upd_per_coloring / elapsed / 1e9
-    # the DP step: each row kernel launch with the split pre-pass before it
+    colorings = args.steps * R_STEP * len(tmpls)
+    value = args.steps * upd / elapsed / 1e9
     dp_f = [f for f in ("split", "row_gather", "row_hist") if f in fams]
-    dp = {"total_ms": sum(fams[f]["total_ms"] for f in dp_f),
-          "alg_bytes": sum(fams[f]["alg_bytes"] for f in dp_f),
-          "launches": sum(fams[f]["launches"] for f in ("row_gather", "row_hist") if f in fams)}
-    achieved = dp["alg_bytes"] / (dp["total_ms"] / 1e3) / 1e9
+    dp_ms = sum(fams[f]["total_ms"] for f in dp_f)
+    dp_alg = sum(fams[f]["alg_bytes"] for f in dp_f)
+    dp_lay = sum(fams[f]["layout_bytes"] for f in dp_f)
+    dp_launches = sum(fams[f]["launches"] for f in ("row_gather", "row_hist") if f in fams)
+    achieved = dp_alg / (dp_ms / 1e3) / 1e9
     roofline = {
         "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
         "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic_per_step(),
         "kernel": "DP step = dp_split_kernel (rows above the segment size) + dp_row_kernel",
-        "avg_step_ms": round(dp["total_ms"] / dp["launches"], 4),
-        "alg_bytes_per_step": dp["alg_bytes"] / dp["launches"],
-        "share_of_gpu_time": round(dp["total_ms"] / sum(f["total_ms"] for f in fams.values()), 3),
+        "bytes": "paper layout: binom(k, s) colour sets per row, every vertex; fused steps",
+        "avg_step_ms": round(dp_ms / dp_launches, 4),
+        "alg_bytes_per_step": dp_alg / dp_launches,
+        "layout_achieved": round(dp_lay / (dp_ms / 1e3) / 1e9, 1),
+        "layout_frac": round(dp_lay / (dp_ms / 1e3) / 1e9 / PEAK_HBM_GBS, 4),
+        "layout_bytes_per_step": dp_lay / dp_launches,
+        "share_of_gpu_time": round(dp_ms / sum(f["total_ms"] for f in fams.values()), 3),
     }
-    # passive rows gathered per pass: nnz * C(k-1, p-1) words per colouring for
-    # every step with p >= 2 (row kernels and the split pre-pass)
-    gathered = sum(g.nnz * math.comb(k - 1, p - 1) * 8 * B for h, a, p in info.steps() if p > 1)
-    gather_ms = sum(fams[f]["total_ms"] for f in ("row_gather", "split") if f in fams) / args.steps
-    roofline["gathered_GBps"] = round(gathered / (gather_ms / 1e3) / 1e9, 1) if gather_ms else None
+    valu = {f: ctx.valu_probe(f) for f in (0, 1, 2)}
+    rows = int((np.diff(g.row_ptr) > 0).sum())        # table rows: the non-isolated vertices
+    sequence = []
+    for _ in range(args.steps):
+        for name in tmpls:
+            sequence += [name] * -(-R_STEP // infos[name].batch)
+    steps_tab = step_table(launches, sequence, rows, valu)
     out = {
         "metric": "SpMM+eMA G-updates/s & colorings/s (bit-exact); p50/p99 query latency",
         "value": round(value, 2), "unit": "G-updates/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(elapsed / args.steps * 1e3, 3),
-        "colorings_per_s": round(colorings / elapsed, 2),
-        "exec_updates_per_s": round(colorings * info.exec_updates / elapsed / 1e9, 2),
+        "colorings_per_s": round(colorings / elapsed, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "u64", "data": "synthetic",
-        "config": {"workload": f"rmat{args.scale}-tree10-k10-b{B}", "graph": f"RMAT scale {args.scale}, 16 edges/vertex",
-                   "n": g.n, "nnz": g.nnz, "template": "10-vertex Pruefer tree (seed 0)", "k": k,
-                   "colorings_per_step": B, "root": info.root, "steps": info.steps(),
-                   "modes": info.modes()},
+        "config": {"workload": "chunglu4m-k12-tree12+star12-r16",
+                   "graph": f"Chung-Lu n={g.n}, mean degree {deg}, exponent {gamma}, seed {gseed}",
+                   "n": g.n, "nnz": g.nnz, "k": K, "seed": SEED, "colorings_per_template_per_step": R_STEP,
+                   "templates": {nm: {"template": "12-vertex Pruefer tree (seed 3)" if nm == "tree12" else "12-star",
+                                      "root": infos[nm].root, "steps": infos[nm].steps(),
+                                      "batch": infos[nm].batch, "interleave": infos[nm].interleave,
+                                      "tables_GB_per_pass": round(infos[nm].arena_bytes / 1e9, 1)}
+                                 for nm in tmpls}},
         "roofline": roofline,
+        "valu_mul_adds_per_s": {["128-bit", "3-multiply", "32-bit operand"][f]: v for f, v in valu.items()},
         "families_ms_per_step": {k: round(v["total_ms"] / args.steps, 2) for k, v in fams.items()},
+        "steps_table": steps_tab,
+        "golden_check": golden,
     }
-    if args.breakdown:
-        print(json.dumps({"breakdown": fams}), file=sys.stderr, flush=True)
 
     if not args.no_cpu_baseline:
         import oracle as O
-        plan = (info.root, info.children())
+        t4, e4 = 4, I.star(4)
+        plan4 = O.root_plan(t4, e4, 0, "small")
+        s4 = sc.sc_plan_template(t4, e4, 0, K, g.n, g.nnz, 1)
+        sample = first - R_STEP
         tc = time.perf_counter()
-        oc, of = O.count(g, t, plan, k, seed, last_first, 1)
+        oc, of = O.count(g, t4, plan4, K, SEED, sample, 1)
         dt = time.perf_counter() - tc
+        tid4 = ctx.load_template_plan(t4, plan4[0], plan4[1])
+        gc, gf, _, _ = ctx.run(gid, tid4, sample, 1)
         out["cpu_baseline"] = {
-            "value": round(upd_per_coloring / dt / 1e9, 4), "unit": "G-updates/s",
+            "value": round((s4.spmm_updates + s4.ema_updates) / dt / 1e9, 4), "unit": "G-updates/s",
             "cores": O.threads(), "kind": "oracle",
-            "sample": f"1 colouring (index {last_first}) of the same workload, whole graph; {dt:.1f} s",
+            "sample": f"the first three DP steps of both templates' plans (the 4-vertex star rooted at its "
+                      f"centre, k = {K}), colouring {sample}, on the whole graph; {dt:.1f} s",
+            "host": host_info(),
         }
-        out["parity_sample"] = {"coloring": int(last_first),
-                                "gpu": [str(int(counts[0])), int(ovf[0])],
-                                "oracle": [str(int(oc[0])), int(of[0])],
-                                "equal": bool(int(counts[0]) == int(oc[0]) and int(ovf[0]) == int(of[0]))}
+        out["parity_sample"] = {"coloring": int(sample), "template": "4-vertex star (the plans' first three steps)",
+                                "gpu": [str(int(gc[0])), int(gf[0])], "oracle": [str(int(oc[0])), int(of[0])],
+                                "equal": bool(int(gc[0]) == int(oc[0]) and int(gf[0]) == int(of[0]))}
+    if not args.no_extras:
+        out["extras"] = extras(ctx, gid, tmpls["star12"])
     ctx.close()
     print(json.dumps(out), flush=True)
 

@@ -411,10 +411,15 @@ enum {
                                  1, 2, 4, ..., 64 (0 = default, no cap)        */
     SC_OPT_LDS_MAX = 10,      /* LDS bytes per row-kernel workgroup,
                                  16384..163840 (0 = default, 65536)            */
-    SC_OPT_WAVE_ROW_MAX = 11  /* steps whose per-row LDS is at most this many
+    SC_OPT_WAVE_ROW_MAX = 11, /* steps whose per-row LDS is at most this many
                                  bytes build one row per wavefront instead of
                                  one per workgroup: 0..40960 (0 = never,
                                  -1 = default, 8192)                          */
+    SC_OPT_CHAIN = 12         /* 1 (default): a run of steps that each attach a
+                                 single vertex to the previous step's output
+                                 runs as one kernel, its intermediate tables
+                                 kept in LDS (when its two widest rows fit the
+                                 LDS limit); 0: one kernel and table per step */
 };
 int sc_set_option(sc_ctx *ctx, int32_t option, int64_t value);
 int sc_get_option(sc_ctx *ctx, int32_t option, int64_t *value);
@@ -462,6 +467,18 @@ typedef struct {
     double layout_bytes;
     double updates;
 } sc_launch_t;
+
+/* The vector-ALU roof of the multiply-add (the arithmetic of Algorithm 4's
+ * element-wise multiply-add, exact 64-bit with overflow detection): every
+ * wavefront slot of the device runs independent chains of multiply-adds on
+ * register operands, timed with HIP events on `stream` (NULL = the context's).
+ * form 0: the 128-bit product; 1: three 32-bit multiplies (the form of
+ * vector-ALU-bound steps); 2: a second operand below 2^32 (the form of steps
+ * whose passive child is one vertex).  Writes multiply-adds per second to
+ * *mul_adds_per_s.  Allocates one word per thread through the hook for the
+ * call.  Errors: SC_EINVAL (form outside 0..2, NULL output), SC_ENOMEM,
+ * SC_EDEVICE. */
+int sc_valu_probe(sc_ctx *ctx, int32_t form, void *stream, double *mul_adds_per_s);
 
 /* enable = 1 starts recording (and clears earlier records), 0 stops. */
 int sc_profile(sc_ctx *ctx, int32_t enable);

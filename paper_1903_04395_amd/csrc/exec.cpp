@@ -143,6 +143,53 @@ int prepare_pass(sc_ctx *c, const PassSpec &s, PassBuffers &b, hipStream_t st) {
     return SC_OK;
 }
 
+// One chain of single-vertex attaches (steps ch.first..ch.last): the split
+// pre-pass of its first step (the colour counts of rows above the segment
+// size), then the chain kernel.
+template <typename BufOf>
+int enqueue_chain(sc_ctx *c, const PassSpec &sp, const Chain &ch, const kern::GraphBins &bins,
+                  const uint8_t *col, const BufOf &buf, uint64_t *Npre, unsigned long long *flags,
+                  const StagedTables *staged, hipStream_t st, bool prof) {
+    const Plan &P = *sp.P;
+    const Graph &g = *sp.g;
+    const int B = P.batch, k = P.k;
+    const double dn = (double)g.n_rows, dB = (double)B, nall = (double)g.n, nnz = (double)g.nnz;
+    const Step &s0 = P.steps[ch.first], &sl = P.steps[ch.last];
+    int rc;
+    kern::StepShape sh;
+    kern::StepTables tb;
+    if ((rc = step_args(c, P, s0, sp.mod, sh, tb, staged))) return rc;
+    kern::ChainShape cs;
+    cs.k = k; cs.a0 = s0.a; cs.steps = ch.last - ch.first + 1;
+    cs.B = B; cs.Bi = P.interleave; cs.wmax = ch.wmax; cs.mod = sp.mod;
+    LaunchInfo li{"chain", ch.first, sl.h, s0.a, 1, B};
+    for (int i = 0; i < cs.steps; ++i) {
+        const Step &s = P.steps[ch.first + i];
+        kern::StepShape shi;
+        kern::StepTables tbi;
+        if ((rc = step_args(c, P, s, sp.mod, shi, tbi, staged))) return rc;
+        cs.Wa[i] = shi.Wa; cs.Wh[i] = shi.Wh; cs.nsplit[i] = shi.nsplit; cs.split[i] = tbi.split;
+        li.updates += (nnz * (double)k + nall * (double)binom(k, s.h) * (s.a > 1 ? (double)binom(s.h, s.a) : 1.0)) * dB;
+    }
+    // compulsory bytes of the fused chain: the adjacency and colours once, the
+    // first step's active table read once, the last step's output written
+    // once (the intermediate tables never leave the kernel)
+    li.bytes = 4.0 * nnz + 8.0 * (nall + 1) + nall * dB + (s0.a > 1 ? 8.0 * nall * dB * (double)binom(k, s0.a) : 0.0) +
+               8.0 * nall * dB * (double)binom(k, sl.h);
+    li.layout_bytes = 4.0 * nnz + 8.0 * (dn + 1) + dn * dB + 8.0 * dn * dB * ((s0.a > 1 ? cs.Wa[0] : 0) + cs.Wh[cs.steps - 1]) +
+                      8.0 * (double)g.n_split * sh.Wn * dB;
+    if (g.n_split) {
+        LaunchInfo ls{"split", ch.first, s0.h, s0.a, 1, B};
+        ls.layout_bytes = 4.0 * g.split_nnz + 16.0 * g.n_split * sh.Wn * dB;
+        ProfScope ps(c, prof, st, ls);
+        HIPCHK(c, kern::launch_dp_split(bins, sh, tb, col, nullptr, Npre, flags, st));
+    }
+    ProfScope ps(c, prof, st, li);
+    HIPCHK(c, kern::launch_dp_chain(bins, cs, col, buf(s0.buf_a), Npre, buf(sl.buf_s), flags,
+                                    P.opts.wave_row_max, st));
+    return SC_OK;
+}
+
 int enqueue_pass(sc_ctx *c, const PassSpec &sp, PassBuffers &pb, hipStream_t st, bool prof) {
     Graph &g = *sp.g;
     const Plan &P = *sp.P;
@@ -174,8 +221,16 @@ int enqueue_pass(sc_ctx *c, const PassSpec &sp, PassBuffers &pb, hipStream_t st,
         HIPCHK(c, kern::launch_color((const uint64_t *)pb.desc.p, n, B, k, (const int32_t *)g.perm.p, col, st));
     }
     const Step *last = nullptr;
-    int si = 0;
-    for (const Step &s : P.steps) {
+    size_t next_chain = 0;
+    for (int si = 0; si < (int)P.steps.size(); ++si) {
+        const Step &s = P.steps[si];
+        if (next_chain < P.chains.size() && P.chains[next_chain].first == si) {
+            const Chain &ch = P.chains[next_chain++];
+            if ((rc = enqueue_chain(c, sp, ch, bins, col, buf, Npre, flags, pb.staged, st, prof))) return rc;
+            last = &P.steps[ch.last];
+            si = ch.last;
+            continue;
+        }
         kern::StepShape sh;
         kern::StepTables tb;
         if ((rc = step_args(c, P, s, sp.mod, sh, tb, pb.staged))) return rc;
@@ -210,7 +265,6 @@ int enqueue_pass(sc_ctx *c, const PassSpec &sp, PassBuffers &pb, hipStream_t st,
             HIPCHK(c, kern::launch_dp_row(bins, sh, tb, col, Pp, A, Npre, S, flags, st));
         }
         last = &s;
-        ++si;
     }
     const int W = (int)binom(k - 1, last->h - 1);
     LaunchInfo li{"reduce"};
@@ -244,7 +298,7 @@ int launch_pass(sc_ctx *c, int gid, int tid, const PassSpec &s, PassBuffers &b, 
     HIPCHK(c, hipMemcpyAsync(b.desc.p, host_desc, 2 * sizeof(uint64_t), hipMemcpyHostToDevice, st));
     if (allow_graph && c->use_graph && !c->prof) {
         GraphExecKey key{gid, tid, P.k, P.batch, P.interleave, P.opts.lds_max, P.opts.wave_row_max,
-                         s.g->seg, s.mod, b.gen};
+                         s.g->seg, P.opts.chain, s.mod, b.gen};
         auto it = c->graph_cache.find(key);
         if (it == c->graph_cache.end()) {
             hipGraph_t graph = nullptr;

@@ -73,6 +73,33 @@ int rank_entries(int k1);
 // built by `teams` teams per workgroup (1: the workgroup; 4: one per wavefront).
 int dp_lds_bytes(const StepShape &s, int amode, int n_rank, int teams = 1);
 
+// A run of steps executed by one kernel: the first step (h0, a0, 1) attaches
+// a single vertex to the active table (the all-ones single-vertex table when
+// a0 = 1), and every later step attaches one more single vertex to the
+// previous step's output.  Each step's neighbour sum is the row's neighbour
+// colour counts, so a row needs them once; the intermediate outputs stay in
+// LDS and only the last step's output is written.
+constexpr int kMaxChainSteps = 16;
+struct ChainShape {
+    int k = 0, a0 = 1, steps = 0;      // colours; active size of the first step; steps
+    int B = 1, Bi = 1;
+    int wmax = 0;                      // widest row held in LDS (entries per colouring)
+    // per step: active and output row entries, split pairs per output entry
+    // (h - 1), and (a >= 2) the (k-1, h-1, a-1) split table
+    int Wa[kMaxChainSteps] = {}, Wh[kMaxChainSteps] = {}, nsplit[kMaxChainSteps] = {};
+    const uint32_t *split[kMaxChainSteps] = {};
+    uint64_t mod = 0;
+};
+// Dynamic LDS bytes of a chain kernel (neighbour colour counts and two rows of
+// `wmax` entries per interleaved colouring).
+int chain_lds_bytes(int k1, int wmax, int bi);
+// Runs the chain over every row: A is the first step's active table (NULL for
+// a0 = 1), S the last step's output; rows above the segment size take their
+// colour counts from Npre, written by launch_dp_split for the first step.
+hipError_t launch_dp_chain(const GraphBins &g, const ChainShape &c, const uint8_t *col, const uint64_t *A,
+                           const uint64_t *Npre, uint64_t *S, unsigned long long *flags, int wave_row_max,
+                           hipStream_t st);
+
 // col[v*B + r] = colour of vertex v in colouring first+r (SplitMix64 rule),
 // drawn from the original id perm[v] when the graph was relabelled (perm != NULL);
 // desc[0] = seed and desc[1] = first live in device memory.
@@ -111,6 +138,14 @@ hipError_t launch_hom_step(const GraphBins &g, const double *A, const double *P,
 hipError_t launch_hom_sum(int64_t n, const double *S, double *out, hipStream_t st);
 
 hipError_t launch_zero_u64(uint64_t *p, int64_t count, hipStream_t st);
+
+// Vector-ALU roof of the exact multiply-add (form 0: 128-bit product, 1: three
+// 32-bit multiplies, 2: 32-bit second operand): a register-only loop of
+// `iters` multiply-adds per chain; `out` holds valu_probe_threads() words;
+// *mul_adds is set to the multiply-adds the launch performs.
+int64_t valu_probe_threads();
+hipError_t launch_valu_probe(int form, uint64_t seed, int iters, unsigned long long *out, double *mul_adds,
+                             hipStream_t st);
 
 // Name of the kernel instantiation the calling thread's last launcher call
 // enqueued (as profilers print it, e.g. "dp_row_kernel<16, 1, false, 0, true,

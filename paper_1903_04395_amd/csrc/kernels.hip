@@ -674,6 +674,118 @@ __global__ __launch_bounds__(TPB) void dp_split_kernel(DpArgs a) {
     flush_flags(m, a.flags);
 }
 
+// ------------------------------------------------------------------ chains of single-vertex attaches
+
+struct ChainStepArgs {
+    const uint32_t *split;
+    int Wh, nsplit, eg, lg_eg;
+};
+
+struct ChainArgs {
+    DpArgs d;                     // graph, colours, interleave, split rows, flags, modulus
+    int steps, a0, wmax, k1, Wa0;
+    const uint64_t *A;
+    uint64_t *S;
+    ChainStepArgs st[kMaxChainSteps];
+};
+
+// One chain step's output row: for every output set D and colouring, the sum
+// over the nsplit pairs (Ia, {x}) of D of cur[Ia] * N'[x], N' the row's
+// neighbour colour counts (below 2^32: the two-multiply product); lanes meet
+// as in emit_row.  `out` is the next LDS row, or the step's table in global
+// memory for the chain's last step.
+template <bool MOD>
+__device__ __forceinline__ void chain_emit(const Team &tm, const DpArgs &a, const ChainStepArgs &cs, int pl,
+                                           const uint64_t *cur, const uint64_t *Nl, uint64_t *out, uint64_t &m) {
+    const int Ls = cs.Wh * a.Bi;
+    const int g = tm.tid & (cs.eg - 1);
+    const int per = tm.size >> cs.lg_eg;
+    for (int q0 = 0; q0 < Ls; q0 += per) {          // uniform over the team
+        const int q = q0 + (tm.tid >> cs.lg_eg);
+        const int D = q >> a.sh, ri = q & (a.Bi - 1);
+        uint64_t acc = 0;
+        uint32_t ovf = 0;
+        unsigned __int128 wlo = 0;
+        uint64_t wtop = 0;
+        if (q < Ls) {
+            const uint32_t *sp = cs.split + (int64_t)D * cs.nsplit;
+            for (int j = g; j < cs.nsplit; j += cs.eg) {
+                const uint32_t pr = sp[j];
+                const uint64_t xa = cur[((pr & 0xffffu) << a.sh) + ri];
+                const uint32_t yn = (uint32_t)Nl[((pr >> 16) << a.sh) + ri];
+                if constexpr (MOD) wide_add_product_n32(wlo, wtop, xa, yn);
+                else acc = mad_ovf_n32(acc, xa, yn, ovf);
+            }
+        }
+        if constexpr (MOD) acc = mod_wide_fold(wlo, wtop, a.md);
+        for (int o = 1; o < cs.eg; o <<= 1) {
+            const uint64_t y = shfl_xor_u64(acc, o);
+            if constexpr (MOD) {
+                acc = mod_add(acc, y, a.md);
+            } else {
+                ovf |= (uint32_t)__shfl_xor((int)ovf, o, kWave);
+                const uint64_t t = acc + y;
+                ovf |= (uint32_t)(t < y);
+                acc = t;
+            }
+        }
+        if (q < Ls && g == 0) {
+            out[q] = acc;
+            if (ovf) m |= 1ull << (pl * a.Bi + ri);
+        }
+    }
+}
+
+// A chain of steps whose passive children are single vertices, one team per
+// (plane, row) item as in dp_row_kernel: the row's neighbour colour counts N'
+// (from the split pre-pass for rows above the segment size), then every step
+// of the chain on the row, its output in LDS (two rows used in turn), and the
+// last step's output written to its table.  For a0 = 1 the first step's
+// output is N' itself.  LDS per team: N' (k1 * Bi), then two rows of wmax * Bi.
+template <bool WAVE, bool MOD, int TPB>
+__global__ __launch_bounds__(TPB) void dp_chain_kernel(ChainArgs c) {
+    constexpr int kTeams = WAVE ? TPB / kWave : 1;
+    extern __shared__ uint64_t lds[];
+    const DpArgs &a = c.d;
+    const Team tm = WAVE ? wave_team() : block_team<TPB>();
+    const int Ln = c.k1 * a.Bi, Lw = c.wmax * a.Bi;
+    uint64_t *Nl = lds + (WAVE ? (int)(threadIdx.x >> 6) * (Ln + 2 * Lw) : 0);
+    uint64_t *rows[2] = {Nl + Ln, Nl + Ln + Lw};
+    const int64_t total = a.n * a.planes;
+    uint64_t m = 0;
+    for (int64_t it = (int64_t)blockIdx.x * kTeams + (WAVE ? (int)(threadIdx.x >> 6) : 0); it < total;
+         it += (int64_t)gridDim.x * kTeams) {
+        const int pl = (int)(it / a.n);
+        const int64_t v = it - (int64_t)pl * a.n;
+        const int sv = a.slot ? a.slot[v] : -1;
+        if (sv >= 0) {
+            const uint64_t *src = a.Npre + ((int64_t)pl * a.n_split + sv) * Ln;
+            for (int q = tm.tid; q < Ln; q += tm.size) Nl[q] = src[q];
+        } else {
+            for (int q = tm.tid; q < Ln; q += tm.size) Nl[q] = 0;
+        }
+        if (c.a0 > 1) {
+            const int La = c.Wa0 * a.Bi;
+            const uint64_t *src = c.A + ((int64_t)pl * a.n + v) * La;
+            for (int q = tm.tid; q < La; q += tm.size) rows[0][q] = src[q];
+        }
+        team_sync<WAVE>();
+        if (sv < 0) count_colours(tm, a, v, pl, a.rp[v], a.rp[v + 1], Nl);
+        team_sync<WAVE>();
+        const uint64_t *cur = c.a0 > 1 ? rows[0] : Nl;   // a0 = 1: the first output is N'
+        int next = c.a0 > 1 ? 1 : 0;
+        for (int i = c.a0 > 1 ? 0 : 1; i < c.steps; ++i) {
+            const ChainStepArgs &cs = c.st[i];
+            uint64_t *out = i == c.steps - 1 ? c.S + ((int64_t)pl * a.n + v) * (int64_t)(cs.Wh * a.Bi) : rows[next];
+            chain_emit<MOD>(tm, a, cs, pl, cur, Nl, out, m);
+            team_sync<WAVE>();                   // the output is the next step's input; LDS is
+            cur = out;                           // reused by the next item after the last step
+            next ^= 1;
+        }
+    }
+    flush_flags(m, a.flags);
+}
+
 // ------------------------------------------------------------------ root reduction
 
 // grid: (blocks, B); block y = colouring r = pl*Bi + ri sums the n*W entries of
@@ -768,6 +880,42 @@ __global__ __launch_bounds__(kBlock) void hom_sum_kernel(int64_t n, const double
         __syncthreads();
     }
     if (threadIdx.x == 0) atomicAdd(out, part[0]);
+}
+
+// ------------------------------------------------------------------ vector-ALU roof
+
+// The multiply-add's arithmetic alone: each thread runs kProbeChains
+// independent chains of `iters` exact multiply-adds with overflow detection
+// (FORM 0: the 128-bit product, mad_ovf; 1: three 32-bit multiplies,
+// mad_ovf3; 2: a 32-bit second operand, mad_ovf_n32) on register operands, and
+// writes its sums and flag so that nothing is folded away.
+constexpr int kProbeChains = 8;
+
+template <int FORM>
+__global__ __launch_bounds__(kBlock) void valu_probe_kernel(uint64_t seed, int iters,
+                                                           unsigned long long *__restrict__ out) {
+    const uint64_t tid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    uint64_t a[kProbeChains], acc[kProbeChains];
+#pragma unroll
+    for (int j = 0; j < kProbeChains; ++j) {
+        a[j] = (seed ^ (tid * 0x9E3779B97F4A7C15ull)) + (uint64_t)j * 0xBF58476D1CE4E5B9ull;
+        acc[j] = 0;
+    }
+    uint64_t b = seed + tid;
+    uint32_t ovf = 0;
+    for (int i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int j = 0; j < kProbeChains; ++j) {
+            if constexpr (FORM == 0) acc[j] = mad_ovf(acc[j], a[j], b, ovf);
+            else if constexpr (FORM == 1) acc[j] = mad_ovf3(acc[j], a[j], b, ovf);
+            else acc[j] = mad_ovf_n32(acc[j], a[j], (uint32_t)b, ovf);
+        }
+        b += 0x94D049BB133111EBull;
+    }
+    uint64_t s = ovf;
+#pragma unroll
+    for (int j = 0; j < kProbeChains; ++j) s += acc[j];
+    out[tid] = s;
 }
 
 __global__ __launch_bounds__(kBlock) void zero_kernel(uint64_t *p, int64_t count) {
@@ -966,6 +1114,83 @@ int dp_lds_bytes(const StepShape &s, int amode, int n_rank, int teams) {
     return bytes > (1 << 30) ? (1 << 30) : (int)bytes;
 }
 
+int chain_lds_bytes(int k1, int wmax, int bi) {
+    int64_t bytes = 8LL * bi * (k1 + 2LL * wmax);
+    bytes = (bytes + 15) & ~15LL;
+    return bytes > (1 << 30) ? (1 << 30) : (int)bytes;
+}
+
+namespace {
+
+template <bool WAVE, bool MOD, int TPB>
+hipError_t chain_launch(const ChainArgs &c, int lds, hipStream_t st) {
+    hipError_t e = allow_lds(dp_chain_kernel<WAVE, MOD, TPB>, lds);
+    if (e != hipSuccess) return e;
+    const int64_t teams = WAVE ? TPB / kWave : 1;
+    const int64_t blocks =
+        std::min<int64_t>((c.d.n * c.d.planes + teams - 1) / teams, 2 * resident_blocks(lds, TPB));
+    name_kernel("dp_chain_kernel<%s, %s, %d>", tf(WAVE), tf(MOD), TPB);
+    dp_chain_kernel<WAVE, MOD, TPB><<<dim3((unsigned)blocks), dim3(TPB), lds, st>>>(c);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_dp_chain(const GraphBins &g, const ChainShape &cs, const uint8_t *col, const uint64_t *A,
+                           const uint64_t *Npre, uint64_t *S, unsigned long long *flags, int wave_row_max,
+                           hipStream_t st) {
+    t_last_kernel[0] = 0;
+    if (g.n <= 0) return hipSuccess;
+    Modulus md;
+    const int k1 = cs.k - 1;
+    if (cs.steps < 2 || cs.steps > kMaxChainSteps || cs.a0 < 1 || cs.a0 + cs.steps > cs.k || cs.k > 16 ||
+        cs.Bi < 1 || cs.Bi > kWave || (cs.Bi & (cs.Bi - 1)) || cs.B % cs.Bi || !S || !col ||
+        (cs.a0 > 1) != (A != nullptr) || (g.n_split && !Npre) || !make_modulus(cs.mod, md))
+        return hipErrorInvalidValue;
+    ChainArgs c{};
+    for (int i = 0; i < cs.steps; ++i) {
+        const int a = cs.a0 + i;
+        if ((a > 1 && !cs.split[i]) || cs.Wh[i] < 1 || cs.Wh[i] > cs.wmax || cs.nsplit[i] != a ||
+            (i == 0 && a > 1 && cs.Wa[0] > cs.wmax))
+            return hipErrorInvalidValue;
+    }
+    const int region = chain_lds_bytes(k1, cs.wmax, cs.Bi);
+    const bool wave = region <= wave_row_max && g.n * (cs.B / cs.Bi) >= kWaveRowsMin;
+    const int teams = wave ? kWaves : 1;
+    const int lds = region * teams;
+    if (lds > kLdsPerCU) return hipErrorInvalidValue;
+    const int tpb = !wave && lds > kWideLds ? kBlockWide : kBlock;
+    DpArgs &a = c.d;
+    a.rp = g.row_ptr; a.ci = g.col_idx; a.col = col; a.n = g.n;
+    a.B = cs.B; a.Bi = cs.Bi; a.sh = log2_exact(cs.Bi); a.planes = cs.B / cs.Bi;
+    a.p = 1; a.Wn = k1;
+    a.Npre = const_cast<uint64_t *>(Npre);
+    a.slot = g.n_split ? g.slot : nullptr; a.n_split = g.n_split;
+    a.flags = flags;
+    a.md = md;
+    c.steps = cs.steps; c.a0 = cs.a0; c.wmax = cs.wmax; c.k1 = k1; c.Wa0 = cs.Wa[0];
+    c.A = A; c.S = S;
+    const int threads = tpb / teams;                 // threads building one row
+    for (int i = 0; i < cs.steps; ++i) {
+        ChainStepArgs &x = c.st[i];
+        x.split = cs.split[i]; x.Wh = cs.Wh[i]; x.nsplit = cs.nsplit[i];
+        // lanes per output entry: the power of two that shortens the longest chain
+        x.eg = 1; x.lg_eg = 0;
+        const int Ls = cs.Wh[i] * cs.Bi;
+        int64_t best = -1;
+        for (int lg = 0, G = 1; G <= kWave; ++lg, G *= 2) {
+            if (G > 1 && G / 2 >= x.nsplit) break;
+            const int64_t rounds = (Ls + (threads / G) - 1) / (threads / G);
+            const int64_t chain = rounds * (((int64_t)x.nsplit + G - 1) / G + 2 * lg);
+            if (best < 0 || chain < best) { best = chain; x.eg = G; x.lg_eg = lg; }
+        }
+    }
+    if (wave) return cs.mod ? chain_launch<true, true, kBlock>(c, lds, st) : chain_launch<true, false, kBlock>(c, lds, st);
+    if (tpb == kBlockWide)
+        return cs.mod ? chain_launch<false, true, kBlockWide>(c, lds, st) : chain_launch<false, false, kBlockWide>(c, lds, st);
+    return cs.mod ? chain_launch<false, true, kBlock>(c, lds, st) : chain_launch<false, false, kBlock>(c, lds, st);
+}
+
 hipError_t launch_zero_u64(uint64_t *p, int64_t count, hipStream_t st) {
     t_last_kernel[0] = 0;
     if (count <= 0) return hipSuccess;
@@ -1049,6 +1274,20 @@ hipError_t launch_reduce(int64_t n, const uint64_t *S, int W, int B, int Bi, uin
     name_kernel("reduce_kernel<%s>", tf(mod != 0));
     if (mod) reduce_kernel<true><<<dim3(blocks, (unsigned)B), dim3(kBlock), 0, st>>>(n, S, W, Bi, md, X, flags);
     else reduce_kernel<false><<<dim3(blocks, (unsigned)B), dim3(kBlock), 0, st>>>(n, S, W, Bi, md, X, flags);
+    return hipGetLastError();
+}
+
+int64_t valu_probe_threads() { return (int64_t)kCUs * 4 * 8 * kWave; }   // 8 wavefronts per SIMD
+
+hipError_t launch_valu_probe(int form, uint64_t seed, int iters, unsigned long long *out, double *mul_adds,
+                             hipStream_t st) {
+    const unsigned blocks = (unsigned)(valu_probe_threads() / kBlock);
+    *mul_adds = (double)valu_probe_threads() * iters * kProbeChains;
+    name_kernel("valu_probe_kernel<%d>", form);
+    if (form == 0) valu_probe_kernel<0><<<dim3(blocks), dim3(kBlock), 0, st>>>(seed, iters, out);
+    else if (form == 1) valu_probe_kernel<1><<<dim3(blocks), dim3(kBlock), 0, st>>>(seed, iters, out);
+    else if (form == 2) valu_probe_kernel<2><<<dim3(blocks), dim3(kBlock), 0, st>>>(seed, iters, out);
+    else return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

@@ -94,6 +94,8 @@ int step_lds_bytes(int k, int a, int p, int bi, int amode) {
     return kern::dp_lds_bytes(sh, amode, kern::rank_entries(k - 1));
 }
 
+int chain_lds_bytes(int k, int wmax, int bi) { return kern::chain_lds_bytes(k - 1, wmax, bi); }
+
 namespace {
 
 // First-fit placement of buffers inside one arena, in allocation order.
@@ -150,6 +152,8 @@ int pick_interleave(const Plan &P, int cap, int lds_max) {
         bool fits = true;
         for (const Step &s : P.steps)
             if (step_lds_bytes(P.k, s.a, s.p, bi, s.a > 1 ? kActGlobal : kActLeaf) > lds_max) fits = false;
+        for (const Chain &ch : P.chains)
+            if (chain_lds_bytes(P.k, ch.wmax, bi) > lds_max) fits = false;
         if (fits) break;
     }
     return bi;
@@ -182,13 +186,21 @@ bool build_plan(int t, int root, const std::vector<int> &child_ptr,
     for (int u = 0; u < t; ++u) if (seen[u] != 1) { err = "plan is not a rooted spanning tree"; return false; }
 
     Arena arena;
-    auto new_buf = [&](int size) {
-        Buf b{size, table_bytes(n, k, size, batch), 0};
-        b.offset = arena.alloc(b.bytes);
+    // stored: a table in the arena; else a chain's intermediate (LDS only)
+    auto new_buf = [&](int size, bool stored) {
+        Buf b{size, table_bytes(n, k, size, batch), 0, stored};
+        if (stored) b.offset = arena.alloc(b.bytes);
         P.bufs.push_back(b);
         return (int)P.bufs.size() - 1;
     };
-    auto drop = [&](int id) { if (id >= 0) arena.release(P.bufs[id].offset, P.bufs[id].bytes); };
+    auto drop = [&](int id) {
+        if (id >= 0 && P.bufs[id].stored) arena.release(P.bufs[id].offset, P.bufs[id].bytes);
+    };
+    // Runs of single-vertex attaches to the same vertex are fused into one
+    // chain kernel when its two widest rows fit the LDS limit at any width.
+    int widest = 0;
+    for (int s = 0; s < k; ++s) widest = std::max<int>(widest, (int)binom(k - 1, s));
+    const bool chains = o.chain && chain_lds_bytes(k, widest, 1) <= o.lds_max;
 
     // post-order walk: the subtree of u is built by attaching its children in order
     std::function<int(int)> walk = [&](int u) -> int {
@@ -203,7 +215,8 @@ bool build_plan(int t, int root, const std::vector<int> &child_ptr,
             s.mode = s.p == 1 ? kStepHist : kStepGather;
             s.amode = kActLeaf;
             s.lds_bytes = 0;
-            s.buf_s = new_buf(s.h);
+            s.fuse_next = chains && s.p == 1 && e + 1 < child_ptr[u + 1] && P.subtree[child_idx[e + 1]] == 1;
+            s.buf_s = new_buf(s.h, !s.fuse_next);
             s.last = false;
             drop(s.buf_a);
             drop(s.buf_p);
@@ -217,6 +230,14 @@ bool build_plan(int t, int root, const std::vector<int> &child_ptr,
     if (!P.steps.empty()) P.steps.back().last = true;
     (void)top;
     P.arena_bytes = arena.end;
+    for (int i = 0; i < (int)P.steps.size(); ++i) {
+        if (!P.steps[i].fuse_next || (i > 0 && P.steps[i - 1].fuse_next)) continue;
+        Chain ch{i, i, 0};
+        while (P.steps[ch.last].fuse_next) ++ch.last;
+        if (P.steps[i].a > 1) ch.wmax = (int)binom(k - 1, P.steps[i].a - 1);
+        for (int j = i; j <= ch.last; ++j) ch.wmax = std::max<int>(ch.wmax, (int)binom(k - 1, P.steps[j].h - 1));
+        P.chains.push_back(ch);
+    }
 
     // Interleave and per-step LDS use.  A row kernel needs at least the
     // neighbour-sum row of one colouring and the index tables; when even that

@@ -94,12 +94,12 @@ struct PassBuffers {
 };
 
 struct GraphExecKey {
-    int graph_id, tmpl_id, k, batch, interleave, lds_max, wave_row_max, seg;
+    int graph_id, tmpl_id, k, batch, interleave, lds_max, wave_row_max, seg, chain;
     uint64_t mod, bufgen;
     bool operator<(const GraphExecKey &o) const {
-        return std::tie(graph_id, tmpl_id, k, batch, interleave, lds_max, wave_row_max, seg, mod, bufgen) <
+        return std::tie(graph_id, tmpl_id, k, batch, interleave, lds_max, wave_row_max, seg, chain, mod, bufgen) <
                std::tie(o.graph_id, o.tmpl_id, o.k, o.batch, o.interleave, o.lds_max, o.wave_row_max, o.seg,
-                        o.mod, o.bufgen);
+                        o.chain, o.mod, o.bufgen);
     }
 };
 
@@ -128,7 +128,7 @@ struct sc_ctx {
     std::map<sc::TuneKey, sc::Tuned> tuned;
     // options
     int64_t max_batch = SC_MAX_BATCH, use_graph = 0, segment = 0;
-    int64_t interleave = 0, lds_max = 0, wave_row_max = -1, reorder = 1;
+    int64_t interleave = 0, lds_max = 0, wave_row_max = -1, reorder = 1, chain = 1;
     // tracing
     bool prof = false;
     struct Rec {

@@ -163,6 +163,7 @@ ExecOpts exec_opts(const sc_ctx *c, int gid, int tid, int k, int batch) {
     o.interleave = (int)c->interleave;
     if (c->lds_max > 0) o.lds_max = (int)c->lds_max;
     if (c->wave_row_max >= 0) o.wave_row_max = (int)c->wave_row_max;
+    o.chain = (int)c->chain;
     auto it = c->tuned.find(TuneKey{gid, tid, k, batch});
     if (it != c->tuned.end()) {
         if (it->second.interleave > 0) o.interleave = it->second.interleave;
@@ -480,6 +481,9 @@ int sc_set_option(sc_ctx *c, int32_t opt, int64_t v) {
         if (v < 0 || v > 2) return fail(c, SC_EINVAL, "SC_OPT_REORDER must be 0, 1 or 2");
         c->reorder = v;
         return SC_OK;
+    case SC_OPT_CHAIN:
+        if (v < 0 || v > 1) return fail(c, SC_EINVAL, "SC_OPT_CHAIN must be 0 or 1");
+        c->chain = v; return SC_OK;
     default: return fail(c, SC_EINVAL, "unknown option %d", opt);
     }
 }
@@ -495,6 +499,7 @@ int sc_get_option(sc_ctx *c, int32_t opt, int64_t *v) {
     case SC_OPT_LDS_MAX: *v = c->lds_max > 0 ? c->lds_max : ExecOpts().lds_max; return SC_OK;
     case SC_OPT_WAVE_ROW_MAX: *v = c->wave_row_max >= 0 ? c->wave_row_max : ExecOpts().wave_row_max; return SC_OK;
     case SC_OPT_REORDER: *v = c->reorder; return SC_OK;
+    case SC_OPT_CHAIN: *v = c->chain; return SC_OK;
     default: return fail(c, SC_EINVAL, "unknown option %d", opt);
     }
 }
@@ -570,6 +575,41 @@ int sc_profile_read(sc_ctx *c, sc_kernel_stat_t *out, int32_t cap, int32_t *n_ou
     }
     *n_out = (int32_t)agg.size();
     for (int32_t i = 0; i < cap && i < (int32_t)agg.size(); ++i) out[i] = agg[i];
+    return SC_OK;
+}
+
+int sc_valu_probe(sc_ctx *c, int32_t form, void *stream, double *mul_adds_per_s) {
+    if (!c) return SC_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    if (!mul_adds_per_s || form < 0 || form > 2) return fail(c, SC_EINVAL, "bad form or NULL output");
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, SC_EDEVICE, "hipSetDevice failed");
+    hipStream_t st = stream ? (hipStream_t)stream : c->stream;
+    DevMem out;
+    int rc = dev_alloc(c, out, (size_t)kern::valu_probe_threads() * sizeof(uint64_t), st);
+    if (rc) return rc;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    double madds = 0;
+    float ms = 0.f;
+    auto run = [&]() -> int {
+        HIPCHK(c, hipEventCreate(&e0));
+        HIPCHK(c, hipEventCreate(&e1));
+        auto *o = (unsigned long long *)out.p;
+        HIPCHK(c, kern::launch_valu_probe(form, 1, 256, o, &madds, st));          // warm
+        HIPCHK(c, hipEventRecord(e0, st));
+        HIPCHK(c, kern::launch_valu_probe(form, 2, 16384, o, &madds, st));
+        HIPCHK(c, hipEventRecord(e1, st));
+        HIPCHK(c, hipEventSynchronize(e1));
+        HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+        return SC_OK;
+    };
+    rc = run();
+    (void)hipStreamSynchronize(st);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    dev_free(c, out);
+    if (rc) return rc;
+    if (ms <= 0.f) return fail(c, SC_EDEVICE, "probe time not measured");
+    *mul_adds_per_s = madds / (ms * 1e-3);
     return SC_OK;
 }
 

@@ -32,6 +32,7 @@ struct ExecOpts {
     int interleave = 0;        // cap on colourings interleaved per plane (0: no cap)
     int lds_max = 64 * 1024;   // LDS bytes a row kernel may use
     int wave_row_max = 8192;   // per-row LDS bytes up to which a wavefront builds a row alone
+    int chain = 1;             // runs of single-vertex attaches fused into one kernel
 };
 
 // One DP step: attach the subtree of `child` (passive, size p) to what `node`
@@ -46,12 +47,23 @@ struct Step {
     int lds_bytes;     // dynamic LDS of its row kernel
     int buf_a, buf_p, buf_s;
     bool last;
+    // The next step attaches a single vertex to this step's output, and both
+    // run in one chain kernel: this output lives only in that kernel's LDS.
+    bool fuse_next;
 };
 
 struct Buf {
     int size;          // sub-template size (binom(k-1,size-1) entries per row and colouring)
     uint64_t bytes;    // n * binom(k-1,size-1) * batch * 8, rounded to 256
     uint64_t offset;   // byte offset inside the run arena
+    bool stored;       // false: a chain's intermediate, never placed in the arena
+};
+
+// A run of steps [first, last] executed by one kernel: every step after the
+// first attaches a single vertex to the previous step's output.
+struct Chain {
+    int first, last;
+    int wmax;          // widest row (entries per colouring) the chain holds in LDS
 };
 
 struct Plan {
@@ -61,6 +73,7 @@ struct Plan {
     std::vector<int> child_ptr, child_idx, subtree;
     std::vector<Step> steps;
     std::vector<Buf> bufs;
+    std::vector<Chain> chains;
     uint64_t arena_bytes = 0;
     double spmm_updates = 0, ema_updates = 0, lemma1_ops = 0, exec_updates = 0;
     double compulsory_bytes = 0, cost = 0;
@@ -69,6 +82,8 @@ struct Plan {
 
 // Dynamic LDS bytes of a step's row kernel with `bi` interleaved colourings.
 int step_lds_bytes(int k, int a, int p, int bi, int amode);
+// Dynamic LDS bytes of a chain kernel whose widest row has `wmax` entries.
+int chain_lds_bytes(int k, int wmax, int bi);
 
 // Validates an edge list as a tree on t vertices; returns "" or a message.
 std::string check_tree(int t, const int32_t *edges);

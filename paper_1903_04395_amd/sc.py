@@ -15,7 +15,7 @@ import numpy as np
 __all__ = [
     "SC_OK", "SC_EINVAL", "SC_ENOMEM", "SC_EDEVICE", "SC_ENOTFOUND", "SC_EBUSY", "SC_ESTATE",
     "SC_OPT_MAX_BATCH", "SC_OPT_GRAPH", "SC_OPT_SEGMENT", "SC_OPT_REORDER", "SC_OPT_INTERLEAVE",
-    "SC_OPT_LDS_MAX", "SC_OPT_WAVE_ROW_MAX", "OPTION_DEFAULTS", "ScError", "PlanInfo", "KernelStat", "Launch",
+    "SC_OPT_LDS_MAX", "SC_OPT_WAVE_ROW_MAX", "SC_OPT_CHAIN", "OPTION_DEFAULTS", "ScError", "PlanInfo", "KernelStat", "Launch",
     "Job", "Tune", "ServeCfg", "Query", "Result", "ServeStats", "lib", "lib_path", "sc_version",
     "sc_plan_template",
     "sc_colorset_rank", "sc_color_of", "Context",
@@ -25,7 +25,7 @@ __all__ = [
 
 SC_OK, SC_EINVAL, SC_ENOMEM, SC_EDEVICE, SC_ENOTFOUND, SC_EBUSY, SC_ESTATE = 0, -1, -2, -3, -4, -5, -6
 SC_OPT_MAX_BATCH, SC_OPT_GRAPH, SC_OPT_SEGMENT, SC_OPT_REORDER = 1, 3, 5, 8
-SC_OPT_INTERLEAVE, SC_OPT_LDS_MAX, SC_OPT_WAVE_ROW_MAX = 9, 10, 11
+SC_OPT_INTERLEAVE, SC_OPT_LDS_MAX, SC_OPT_WAVE_ROW_MAX, SC_OPT_CHAIN = 9, 10, 11, 12
 SC_MAX_T = 16
 SC_STATIC_SCRATCH_BYTES = 64 << 20     # the allocation-free entry point's device array
 
@@ -103,7 +103,7 @@ class Launch(ctypes.Structure):
 
 
 OPTION_DEFAULTS = {SC_OPT_MAX_BATCH: 64, SC_OPT_GRAPH: 0, SC_OPT_SEGMENT: 0, SC_OPT_REORDER: 1,
-                   SC_OPT_INTERLEAVE: 0, SC_OPT_LDS_MAX: 0, SC_OPT_WAVE_ROW_MAX: -1}
+                   SC_OPT_INTERLEAVE: 0, SC_OPT_LDS_MAX: 0, SC_OPT_WAVE_ROW_MAX: -1, SC_OPT_CHAIN: 1}
 
 
 class Job(ctypes.Structure):
@@ -223,6 +223,7 @@ def lib():
             "sc_profile": (ctypes.c_int, [_vp, ctypes.c_int32]),
             "sc_profile_read": (ctypes.c_int, [_vp, ctypes.POINTER(KernelStat), ctypes.c_int32,
                                                _i32p]),
+            "sc_valu_probe": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, _dblp]),
             "sc_profile_launches": (ctypes.c_int, [_vp, ctypes.POINTER(Launch), ctypes.c_int32, _i32p]),
         }
         for name, (res, args) in sig.items():
@@ -403,6 +404,14 @@ class Context:
                                        "alg_bytes": arr[i].alg_bytes, "layout_bytes": arr[i].layout_bytes,
                                        "updates": arr[i].updates}
                 for i in range(min(n.value, cap))}
+
+    def valu_probe(self, form=0, stream=None):
+        """Exact 64-bit multiply-adds per second of the device's vector ALU
+        (form 0: 128-bit product, 1: three 32-bit multiplies, 2: 32-bit second
+        operand)."""
+        out = ctypes.c_double()
+        self._check(self._L.sc_valu_probe(self._h, int(form), self._stream(stream), ctypes.byref(out)))
+        return out.value
 
     def profile_launches(self):
         """Every recorded launch in order, as dicts (kernel, family, step, h, a, p,

@@ -31,9 +31,11 @@ OUT = os.path.join(HERE, "full_size.json")
 ENTRIES = {
     "er2000_p5_k5": (("erdos_renyi", (2000, 10000), {"seed": 1}), ("path", 5), 0, 5, 2024, list(range(64))),
     "rmat20_tree10_k10": (("rmat", (20, 16), {"seed": 0}), ("prufer", 10, 0), 0, 10, 1, list(range(8))),
-    "chunglu4m_tree12_k12": (("chung_lu", (4194304, 30, 2.1), {"seed": 3}), ("prufer", 12, 3), 0, 12, 7, [0, 15]),
+    "chunglu4m_tree12_k12": (("chung_lu", (4194304, 30, 2.1), {"seed": 3}), ("prufer", 12, 3), 0, 12, 7,
+                             list(range(16))),
+    # every colouring of the star is also checked against its closed form
     "chunglu4m_star12_k12": (("chung_lu", (4194304, 30, 2.1), {"seed": 3}), ("star", 12), 0, 12, 7, [0, 15]),
-    "rmat19_tree15_k15": (("rmat", (19, 16), {"seed": 4}), ("prufer", 15, 4), 0, 15, 9, [0]),
+    "rmat19_tree15_k15": (("rmat", (19, 16), {"seed": 4}), ("prufer", 15, 4), 0, 15, 9, list(range(4))),
 }
 
 

@@ -203,3 +203,36 @@ def test_bench_traffic_follows_the_kernel_sources(tmp_path, monkeypatch):
     assert bench.traffic_per_step() == 123.0
     monkeypatch.setattr(bench, "source_hash", lambda: "0" * 16)
     assert bench.traffic_per_step() is None
+
+
+def test_bench_step_table_groups_launches_by_template_and_step():
+    """bench.py's per-step table: a trace of two passes of one template and
+    one of another is split into passes at the colour kernel, each pass
+    assigned its template in call order, and times summed per step."""
+    import bench
+    def pass_(steps, ms):
+        out = [{"family": "zero", "step": -1, "h": 0, "a": 0, "p": 0, "colorings": 8, "ms": 0.01,
+                "alg_bytes": 0.0, "layout_bytes": 0.0, "updates": 0.0},
+               {"family": "color", "step": -1, "h": 0, "a": 0, "p": 0, "colorings": 8, "ms": 0.02,
+                "alg_bytes": 0.0, "layout_bytes": 0.0, "updates": 0.0}]
+        for i, (h, a, p) in enumerate(steps):
+            if p > 1:
+                out.append({"family": "split", "step": i, "h": h, "a": a, "p": p, "colorings": 8, "ms": ms / 2,
+                            "alg_bytes": 0.0, "layout_bytes": 1e9, "updates": 0.0})
+            out.append({"family": "row_gather" if p > 1 else "row_hist", "step": i, "h": h, "a": a, "p": p,
+                        "colorings": 8, "ms": ms, "alg_bytes": 8e9, "layout_bytes": 2e9, "updates": 1e9})
+        return out
+    t1 = [(2, 1, 1), (3, 1, 2)]
+    t2 = [(2, 1, 1), (3, 2, 1)]
+    trace = pass_(t1, 10.0) + pass_(t1, 10.0) + pass_(t2, 4.0)
+    tab = bench.step_table(trace, ["a", "a", "b"], rows=10**7, valu={0: 1e12, 1: 2e12, 2: 3e12})
+    got = {(e["template"], e["step"]): e for e in tab}
+    assert set(got) == {("a", 0), ("a", 1), ("b", 0), ("b", 1)}
+    # 16 colourings per step of the benchmark: the two 8-colouring passes of
+    # template a make one step, the one pass of b half a step
+    assert got[("a", 1)]["ms"] == pytest.approx(30.0)
+    assert got[("a", 1)]["alg_GB"] == pytest.approx(16.0)
+    assert got[("b", 0)]["ms"] == pytest.approx(8.0)
+    assert got[("b", 1)]["G_mul_adds"] == pytest.approx(10**7 * math.comb(11, 2) * 2 * 16 / 1e9, abs=0.01)
+    assert got[("b", 1)]["valu_frac"] == pytest.approx(17.6e9 / 3e12 / 8e-3, abs=2e-3)
+    assert got[("a", 0)]["valu_frac"] is None and got[("b", 1)]["valu_frac"] > 0

@@ -118,6 +118,47 @@ def star_closed_form(g, col, k):
     return math.factorial(k - 1) * sum(math.prod(r) for r in rows.tolist())
 
 
+def star_closed_form_residue(g, col, k):
+    """The star closed form mod 2^64 (uint64 products and sums wrap), and its
+    value in floating point (log2), for one colouring."""
+    src = np.repeat(np.arange(g.n, dtype=np.int64), np.diff(g.row_ptr))
+    cnt = np.bincount(src * k + col[g.col_idx].astype(np.int64), minlength=g.n * k).reshape(g.n, k)
+    del src
+    cnt[np.arange(g.n), col] = 1
+    rows = cnt[cnt.min(axis=1) > 0]
+    with np.errstate(over="ignore"):
+        s = int(np.prod(rows.astype(np.uint64), axis=1).sum(dtype=np.uint64))
+    logs = np.log2(rows.astype(np.float64)).sum(axis=1)
+    top = logs.max()
+    log2_value = math.log2(math.factorial(k - 1)) + top + math.log2(np.exp2(logs - top).sum())
+    return (math.factorial(k - 1) * s) % 2**64, log2_value
+
+
+def test_full_size_star_every_colouring_against_closed_form(ctx):
+    """Chung-Lu n=4,194,304, the 12-star, k = 12, all 16 colourings as the
+    library folds them into passes: each residue and flag against the star
+    closed form (every count there is past 2^64, so every flag is set)."""
+    import oracle as O
+    data = load()
+    name = "chunglu4m_star12_k12"
+    if name not in data:
+        pytest.skip("no golden entry for the Chung-Lu workload")
+    e = data[name]
+    print(f"[case] {name} every colouring: generating and loading the graph", flush=True)
+    gid = graph_for(ctx, e["graph"])
+    g = host_graph(e["graph"])
+    tid = ctx.load_template_plan(e["t"], e["root"], e["children"])
+    k = e["k"]
+    ctx.set_colors(k, e["seed"])
+    R = RUN_COLOURINGS[name]
+    counts, ovf, _, _ = ctx.run(gid, tid, 0, R)
+    for r in range(R):
+        res, lg = star_closed_form_residue(g, O.colors(e["seed"], r, g.n, k), k)
+        print(f"[case] {name} colouring {r}: 2^{lg:.1f}", flush=True)
+        assert lg > 64.5
+        assert int(counts[r]) == res and int(ovf[r]) == 1, r
+
+
 def test_full_size_exact_star_against_closed_form(ctx):
     """Chung-Lu n=4,194,304, the 12-star, k = 12: sc_run_exact's counts (past
     2^64) against the star closed form evaluated exactly on the host."""

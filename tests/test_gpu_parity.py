@@ -147,6 +147,64 @@ def test_row_per_workgroup_or_per_wavefront_agree(ctx, wave_rows, scale, inter):
              opts={sc.SC_OPT_WAVE_ROW_MAX: wave_rows, sc.SC_OPT_INTERLEAVE: inter})
 
 
+# ------------------------------------------------------------------ chains of single-vertex attaches
+
+def spider(legs):
+    """Centre 0 with one path (leg) of each given length."""
+    edges, nxt = [], 1
+    for L in legs:
+        prev = 0
+        for _ in range(L):
+            edges.append((prev, nxt))
+            prev, nxt = nxt, nxt + 1
+    return nxt, edges
+
+
+CHAIN_CASES = [
+    # (name, t, edges, root, k, explicit plan): runs of leaf children fused into one kernel
+    ("star8", 8, I.star(8), 0, 8, None),
+    ("star11_k12", 11, I.star(11), 0, 12, None),
+    # the leg first, then four leaves: a chain whose first active table is
+    # the gather step's output (a0 = 4)
+    ("spider_leg_then_leaves", *spider([3, 1, 1, 1, 1]), 0, 9, (0, [[1, 4, 5, 6, 7], [2], [3], [], [], [], [], []])),
+    ("spider_leaves_then_leg", *spider([1, 1, 1, 2]), 0, 7, None),
+    ("tree12_seed3", 12, I.prufer_tree(12, 3), -1, 12, None),
+]
+
+
+@pytest.mark.parametrize("name,t,edges,root,k,plan", CHAIN_CASES, ids=[c[0] for c in CHAIN_CASES])
+@pytest.mark.parametrize("chain", [1, 0])
+def test_chains_fused_or_per_step_match_oracle(ctx, name, t, edges, root, k, plan, chain):
+    """Runs of single-vertex attaches as one chain kernel (intermediate tables
+    in LDS) or one kernel per step: both equal the oracle, on a power-law
+    graph with rows above the segment size (their colour counts come from the
+    split pre-pass), with 1, 2 and 8 interleaved colourings."""
+    g = I.chung_lu(3000, 20, 2.1, seed=5)
+    for inter in (1, 2, 8):
+        run_both(ctx, g, t, edges, k, 31, 5, 8, root=root, plan=plan,
+                 opts={sc.SC_OPT_CHAIN: chain, sc.SC_OPT_INTERLEAVE: inter, sc.SC_OPT_SEGMENT: 100})
+
+
+def test_chain_overflow_flags_and_residues(ctx):
+    """A star whose count passes 2^64 on K_{1,d} plus a hub graph: the chain
+    kernel's flags and residues equal the oracle's and the per-step path's;
+    its residue passes (mod p) equal the oracle's modular DP."""
+    d = 300
+    g = I.csr_from_edges(d + 1, np.zeros(d, np.int64), np.arange(1, d + 1))
+    c1 = run_both(ctx, g, 12, I.star(12), 12, 3, 0, 8, root=0, opts={sc.SC_OPT_CHAIN: 1})
+    c0 = run_both(ctx, g, 12, I.star(12), 12, 3, 0, 8, root=0, opts={sc.SC_OPT_CHAIN: 0})
+    assert c1[1].all() and np.array_equal(c1[0], c0[0])
+    gid = ctx.load_graph(g)
+    tid = ctx.load_template(12, I.star(12), 0)
+    ctx.set_colors(12, 3)
+    info = ctx.plan_info(gid, tid, 8)
+    for p in O.PRIMES:
+        got = ctx.run_mod(gid, tid, 0, 8, p)
+        want = O.count_mod(g, 12, (info.root, info.children()), 12, 3, 0, 8, p)
+        assert np.array_equal(got, want), p
+    ctx.unload_graph(gid)
+
+
 # ------------------------------------------------------------------ overflow and edge cases
 
 def test_overflow_flags_match(ctx):

@@ -76,11 +76,11 @@ def test_static_run_flags_overflow_like_sc_run(ctx):
 def test_static_run_rejects_runs_beyond_its_array(ctx):
     g = I.rmat(16, 16, seed=6)
     gid = ctx.load_graph(g)
-    tid = ctx.load_template(12, I.star(12), 0)
+    tid = ctx.load_template(12, I.path(12))
     ctx.set_colors(12, 1)
     info = ctx.plan_info(gid, tid, 1)
     assert info.arena_bytes > sc.SC_STATIC_SCRATCH_BYTES
-    say("static run beyond the array: RMAT-16, 12-star, k=12")
+    say("static run beyond the array: RMAT-16, 12-vertex path, k=12")
     before = hook_allocations()
     with pytest.raises(sc.ScError) as e:
         ctx.run_static(gid, tid, 0, 1)
