@@ -51,12 +51,16 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip sc_autotune of both templates before the timed region")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the side measurements (RMAT-20 workload, plain vs batched, exact counts)")
     ap.add_argument("--opt", action="append", default=[], help="libsc option NUM=VALUE (ablation)")
     ap.add_argument("--breakdown", action="store_true", help="also print the per-family table")
     ap.add_argument("--configs", action="store_true",
                     help="timings of the other configurations (ER 2000 / Chung-Lu 4M k=12 / RMAT-19 k=15)")
+    ap.add_argument("--only", default=None, help="with --configs: run only the named configuration")
+    ap.add_argument("--no-tune", action="store_true", help="with --configs: skip the autotuner")
     ap.add_argument("--gather-probe", action="store_true",
                     help="only time whole-row gathers of the widest step's rows in RMAT-20 neighbour order")
     ap.add_argument("--copy-probe", action="store_true",
@@ -132,7 +136,6 @@ def serve_bench(nq, qps=200.0, streams=4):
     import numpy as np
     from paper_1903_04395_amd import inputs as I
     from paper_1903_04395_amd import sc
-    rng = np.random.default_rng(2019)
     ctx = sc.Context(0)
     gids = []
     for scale in (18, 20, 22):
@@ -142,13 +145,7 @@ def serve_bench(nq, qps=200.0, streams=4):
         print(f"[bench] serve graph scale {scale}: n={g.n} nnz={g.nnz} ({time.time() - tg:.0f}s)",
               file=sys.stderr, flush=True)
         del g
-    qs = []
-    t_arr = 0.0
-    for i in range(nq):
-        t_arr += rng.exponential(1 / qps)
-        t = int(rng.integers(3, 13))
-        qs.append(dict(at=t_arr, graph=int(rng.integers(0, 3)), t=t, edges=I.prufer_tree(t, 10_000 + i),
-                       n=int(rng.integers(1, 33)), seed=int(rng.integers(0, 1 << 40))))
+    qs = I.serving_queries(nq, qps, seed=2019)
     tids = [ctx.load_template(q["t"], q["edges"]) for q in qs]
     ctx.serve_start(mem_budget_bytes=200 * 10**9, max_inflight=streams, max_batch=64)
     pending = {}
@@ -225,7 +222,7 @@ def gather_probe():
                                        "read_GBps": round(gathered / (ms / 1e3) / 1e9, 1)}}), flush=True)
 
 
-def configs_bench():
+def configs_bench(only=None, tune_ok=True):
     """Per-configuration timings after a warm-up pass (allocation excluded):
     ER 2000 / P5 / k=5 (one colouring per call: launch latency); Chung-Lu
     n=4,194,304 (mean degree 30, exponent 2.1) / 12-vertex tree and 12-star /
@@ -251,9 +248,17 @@ def configs_bench():
             ctx.run(gid, tid, R * (i + 1), R)
         dt = (time.perf_counter() - t0) / reps
         ctx.profile(False)
-        return dt, ctx.profile_read()
+        steps = {}
+        for r in ctx.profile_launches():
+            if r["step"] >= 0:
+                key = f"{r['step']}:{r['family']}:({r['h']},{r['a']},{r['p']})"
+                steps[key] = steps.get(key, 0.0) + r["ms"] / reps
+        return dt, ctx.profile_read(), {k: round(v, 2) for k, v in steps.items()}
 
     for gname, gen, tmpls, k, R, reps, tune in cases:
+        if only and gname != only:
+            continue
+        tune = tune and tune_ok
         tg = time.time()
         g = gen()
         gid = ctx.load_graph(g)
@@ -262,19 +267,20 @@ def configs_bench():
             tid = ctx.load_template(t, edges, root)
             ctx.set_colors(k, 7)
             info0 = ctx.plan_info(gid, tid, R)
-            dt0, fams = timed_calls(gid, tid, R, reps)
+            dt0, fams, steps = timed_calls(gid, tid, R, reps)
             tuned, dt, info = None, dt0, info0
             if tune:
                 tuned = ctx.autotune(gid, tid, R)
                 info = ctx.plan_info(gid, tid, R)
-                dt, fams = timed_calls(gid, tid, R, reps)
+                dt, fams, steps = timed_calls(gid, tid, R, reps)
             key = f"{gname}/{tname}"
             out[key] = {"colorings": R, "batch": info.batch, "interleave": info.interleave,
                         "passes": -(-R // info.batch), "tables_GB_per_pass": round(info.arena_bytes / 1e9, 1),
                         "s_per_call": round(dt, 4), "colorings_per_s": round(R / dt, 2),
                         "default_s_per_call": round(dt0, 4), "default_interleave": info0.interleave,
                         "autotuned": tuned,
-                        "families_ms_per_call": {f: round(v["total_ms"] / reps, 2) for f, v in fams.items()}}
+                        "families_ms_per_call": {f: round(v["total_ms"] / reps, 2) for f, v in fams.items()},
+                        "steps_ms_per_call": steps}
             print(f"[bench] configs {key}: {out[key]}", file=sys.stderr, flush=True)
         ctx.unload_graph(gid)
         del g
@@ -596,7 +602,7 @@ def main():
         elif args.ablation:
             ablation_bench()
         else:
-            configs_bench()
+            configs_bench(args.only, not args.no_tune)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); splitting the colourings "
@@ -621,10 +627,14 @@ def main():
         ctx.set_option(int(key), int(val))
     gid = ctx.load_graph(g)
     ctx.set_colors(K, SEED)
-    tmpls, infos, plans = {}, {}, {}
+    tmpls, infos, plans, tuned = {}, {}, {}, {}
     upd = 0.0
     for name, t, edges, root in templates():
         tid = ctx.load_template(t, edges, root)
+        if not args.no_autotune:                     # untimed: the autotuner's real passes
+            tt = time.time()
+            tuned[name] = ctx.autotune(gid, tid, R_STEP)
+            print(f"[bench] {name}: autotuned {tuned[name]} in {time.time() - tt:.0f}s", file=sys.stderr, flush=True)
         info = ctx.plan_info(gid, tid, R_STEP)
         tmpls[name], infos[name], plans[name] = tid, info, info.steps()
         upd += (info.spmm_updates + info.ema_updates) * R_STEP
@@ -700,7 +710,8 @@ def main():
                    "templates": {nm: {"template": "12-vertex Pruefer tree (seed 3)" if nm == "tree12" else "12-star",
                                       "root": infos[nm].root, "steps": infos[nm].steps(),
                                       "batch": infos[nm].batch, "interleave": infos[nm].interleave,
-                                      "tables_GB_per_pass": round(infos[nm].arena_bytes / 1e9, 1)}
+                                      "tables_GB_per_pass": round(infos[nm].arena_bytes / 1e9, 1),
+                                      "autotuned": tuned.get(nm)}
                                  for nm in tmpls}},
         "roofline": roofline,
         "valu_mul_adds_per_s": {["128-bit", "3-multiply", "32-bit operand"][f]: v for f, v in valu.items()},

@@ -218,8 +218,9 @@ int sc_run(sc_ctx *ctx, int32_t graph_id, int32_t tmpl_id, uint64_t first_colori
  * process (the array keeps the last call's contents; everything a run reads
  * is written by that run first).  Synchronous.
  * Errors: as sc_run; SC_ENOMEM when even one colouring's buffers exceed
- * SC_STATIC_SCRATCH_BYTES; SC_ESTATE when the graph's heavy-row bins are
- * stale (SC_OPT_SEGMENT changed since the graph was last run or loaded). */
+ * SC_STATIC_SCRATCH_BYTES; SC_ESTATE when the graph has no heavy-row bins for
+ * the run's segment size (SC_OPT_SEGMENT or a tuned segment size not yet
+ * used by sc_run on this graph: building the bins would allocate). */
 #define SC_STATIC_SCRATCH_BYTES 67108864ull   /* 64 MiB */
 int sc_run_static(sc_ctx *ctx, int32_t graph_id, int32_t tmpl_id, uint64_t first_coloring,
                   int32_t n_colorings, void *stream, uint64_t *counts, uint8_t *overflow,
@@ -332,12 +333,15 @@ int sc_run_batch(sc_ctx *ctx, sc_job_t *jobs, int32_t n_jobs, void *stream);
 
 /* Autotuner: times real passes of (graph, template) at the batch `n_colorings`
  * plans to, over the interleave caps {1, 2, 4, ..., batch} (at most four of
- * them, the largest ones) and the row-kernel LDS limits {32, 64, 96, 128} KB, and
- * keeps the fastest for that (graph, template, k, batch).  The choice never
- * changes a result. */
+ * them, the largest ones) times the row-kernel LDS limits {32, 64, 96, 128} KB;
+ * then, around the fastest, the neighbours per split-row work item {256, 512,
+ * 1024, 2048}; then the per-row LDS up to which a wavefront builds a row alone
+ * {0, 8192, 16384} bytes; and keeps the fastest for that (graph, template, k,
+ * batch).  The choice never changes a result. */
 typedef struct {
     int32_t interleave, lds_max, batch, trials;
     double ms;                      /* time of one pass with the chosen knobs */
+    int32_t seg, wave_row_max;      /* the chosen segment size and row threshold */
 } sc_tune_t;
 int sc_autotune(sc_ctx *ctx, int32_t graph_id, int32_t tmpl_id, int32_t n_colorings, sc_tune_t *out);
 /* Tuning cache as text lines keyed by graph shape (n, nnz, max degree),
@@ -355,6 +359,8 @@ int sc_tune_load(sc_ctx *ctx, const char *path, int32_t *n_applied);
  * so a query that arrives while others run starts as soon as a stream and
  * memory free up, and passes of different queries overlap on the device.
  * Results do not depend on how a query was split or what ran beside it.
+ * sc_serve_start first releases the count tables the synchronous calls keep
+ * (a later sc_run allocates them again), so that the budget is the loop's.
  * sc_submit / sc_poll / sc_serve_stats may be called from any thread;
  * sc_serve_stop waits for every submitted query (poll results first: stop
  * discards them).  While the loop runs, options other than SC_OPT_GRAPH

@@ -109,6 +109,24 @@ int step_args(sc_ctx *c, const Plan &P, const Step &s, uint64_t mod, kern::StepS
     return SC_OK;
 }
 
+// Shape and split tables of one chain (tables uploaded on first use, or the
+// staged copies).
+int chain_args(sc_ctx *c, const Plan &P, const Chain &ch, uint64_t mod, kern::ChainShape &cs,
+               const StagedTables *staged) {
+    const int k = P.k;
+    const Step &s0 = P.steps[ch.first];
+    cs.k = k; cs.a0 = s0.a; cs.steps = ch.last - ch.first + 1;
+    cs.B = P.batch; cs.Bi = P.interleave; cs.wmax = ch.wmax; cs.mod = mod;
+    for (int i = 0; i < cs.steps; ++i) {
+        const Step &s = P.steps[ch.first + i];
+        kern::StepShape sh;
+        kern::StepTables tb;
+        if (int rc = step_args(c, P, s, mod, sh, tb, staged)) return rc;
+        cs.Wa[i] = sh.Wa; cs.Wh[i] = sh.Wh; cs.nsplit[i] = sh.nsplit; cs.split[i] = tb.split;
+    }
+    return SC_OK;
+}
+
 }  // namespace
 
 size_t npre_bytes(const Graph &g, const Plan &P) {
@@ -128,17 +146,17 @@ int prepare_pass(sc_ctx *c, const PassSpec &s, PassBuffers &b, hipStream_t st) {
     Graph &g = *s.g;
     const Plan &P = *s.P;
     int rc;
-    if ((rc = rebin(c, g, default_segment(c)))) return rc;
+    if ((rc = rebin(c, g, plan_segment(c, P)))) return rc;
     if ((rc = ensure_gen(c, b.arena, P.arena_bytes, st, b))) return rc;
     if ((rc = ensure_gen(c, b.colbuf, (size_t)g.n_rows * P.batch, st, b))) return rc;
     if ((rc = ensure_gen(c, b.xbuf, (SC_MAX_BATCH + 1) * sizeof(uint64_t), st, b))) return rc;
     if ((rc = ensure_gen(c, b.desc, 2 * sizeof(uint64_t), st, b))) return rc;
     const size_t np = npre_bytes(g, P);
     if (np && (rc = ensure_gen(c, b.npre, np, st, b))) return rc;
-    for (const Step &st_ : P.steps) {
+    for (int si = 0; si < (int)P.steps.size(); ++si) {
         kern::StepShape sh;
         kern::StepTables tb;
-        if ((rc = step_args(c, P, st_, s.mod, sh, tb))) return rc;
+        if ((rc = step_args(c, P, P.steps[si], s.mod, sh, tb))) return rc;
     }
     return SC_OK;
 }
@@ -160,15 +178,10 @@ int enqueue_chain(sc_ctx *c, const PassSpec &sp, const Chain &ch, const kern::Gr
     kern::StepTables tb;
     if ((rc = step_args(c, P, s0, sp.mod, sh, tb, staged))) return rc;
     kern::ChainShape cs;
-    cs.k = k; cs.a0 = s0.a; cs.steps = ch.last - ch.first + 1;
-    cs.B = B; cs.Bi = P.interleave; cs.wmax = ch.wmax; cs.mod = sp.mod;
+    if ((rc = chain_args(c, P, ch, sp.mod, cs, staged))) return rc;
     LaunchInfo li{"chain", ch.first, sl.h, s0.a, 1, B};
     for (int i = 0; i < cs.steps; ++i) {
         const Step &s = P.steps[ch.first + i];
-        kern::StepShape shi;
-        kern::StepTables tbi;
-        if ((rc = step_args(c, P, s, sp.mod, shi, tbi, staged))) return rc;
-        cs.Wa[i] = shi.Wa; cs.Wh[i] = shi.Wh; cs.nsplit[i] = shi.nsplit; cs.split[i] = tbi.split;
         li.updates += (nnz * (double)k + nall * (double)binom(k, s.h) * (s.a > 1 ? (double)binom(s.h, s.a) : 1.0)) * dB;
     }
     // compulsory bytes of the fused chain: the adjacency and colours once, the
@@ -499,42 +512,70 @@ int sc_autotune(sc_ctx *c, int32_t gid, int32_t tid, int32_t n_colorings, sc_tun
     const int B = P.batch;
     const TuneKey key{gid, tid, c->k, B};
     c->tuned.erase(key);
-    // interleave caps: the four largest powers of two dividing the batch
-    std::vector<int> inter;
-    for (int bi = 64; bi >= 1 && inter.size() < 4; bi /= 2)
-        if (B % bi == 0) inter.push_back(bi);
-    static const int ldss[] = {32 * 1024, 64 * 1024, 96 * 1024, 128 * 1024};
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));
     Tuned best;
     best.ms = 1e300;
     int trials = 0;
+    // one pass of the planned batch with the candidate knobs, after a warm-up pass
+    auto trial = [&](const Tuned &cand) -> int {
+        c->tuned[key] = cand;
+        std::vector<PassJob> passes;
+        int r;
+        if ((r = plan_job(c, 0, gid, tid, c->k, c->seed, 0, B, passes))) return r;
+        auto sink = [&](const PassJob &, const uint64_t *) {};
+        if ((r = run_passes(c, passes, c->stream, sink))) return r;
+        HIPCHK(c, hipEventRecord(e0, c->stream));
+        if ((r = run_passes(c, passes, c->stream, sink))) return r;
+        HIPCHK(c, hipEventRecord(e1, c->stream));
+        HIPCHK(c, hipEventSynchronize(e1));
+        float ms = 0;
+        HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+        ++trials;
+        if (ms < best.ms) { best = cand; best.ms = ms; }
+        return SC_OK;
+    };
+    // 1. interleave caps (the four largest powers of two dividing the batch)
+    //    and row-kernel LDS limits, at the default segment and row threshold
+    std::vector<int> inter;
+    for (int bi = 64; bi >= 1 && inter.size() < 4; bi /= 2)
+        if (B % bi == 0) inter.push_back(bi);
+    static const int ldss[] = {32 * 1024, 64 * 1024, 96 * 1024, 128 * 1024};
     for (int bi : inter)
         for (int lm : ldss) {
+            if (rc) break;
             Tuned cand;
             cand.interleave = bi;
             cand.lds_max = lm;
-            c->tuned[key] = cand;
-            std::vector<PassJob> passes;
-            if ((rc = plan_job(c, 0, gid, tid, c->k, c->seed, 0, B, passes))) break;
-            auto sink = [&](const PassJob &, const uint64_t *) {};
-            if ((rc = run_passes(c, passes, c->stream, sink))) break;          // warm
-            HIPCHK(c, hipEventRecord(e0, c->stream));
-            if ((rc = run_passes(c, passes, c->stream, sink))) break;
-            HIPCHK(c, hipEventRecord(e1, c->stream));
-            HIPCHK(c, hipEventSynchronize(e1));
-            float ms = 0;
-            HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
-            ++trials;
-            if (ms < best.ms) { best = cand; best.ms = ms; }
+            rc = trial(cand);
         }
+    // 2. neighbours per split-row work item, then 3. the per-row LDS up to
+    //    which a wavefront builds a row alone, each around the best so far
+    static const int segs[] = {256, 1024, 2048};
+    const Tuned base1 = best;
+    for (int sg : segs) {
+        if (rc) break;
+        Tuned cand = base1;
+        cand.seg = sg;
+        rc = trial(cand);
+    }
+    static const int waves[] = {0, 16384};
+    const Tuned base2 = best;
+    for (int wr : waves) {
+        if (rc) break;
+        Tuned cand = base2;
+        cand.wave_row_max = wr;
+        rc = trial(cand);
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc) { c->tuned.erase(key); return rc; }
     c->tuned[key] = best;
     out->interleave = best.interleave;
     out->lds_max = best.lds_max;
+    out->seg = best.seg > 0 ? best.seg : default_segment(c);
+    out->wave_row_max = best.wave_row_max >= 0 ? best.wave_row_max : ExecOpts().wave_row_max;
     out->batch = B;
     out->ms = best.ms;
     out->trials = trials;
@@ -553,9 +594,10 @@ int sc_tune_save(sc_ctx *c, const char *path) {
         if (gi == c->graphs.end() || ti == c->tmpls.end()) continue;
         const Graph &g = *gi->second;
         const Template &T = *ti->second;
-        fprintf(f, "%lld %lld %lld %d %d %d %d %d %.6f", (long long)g.n, (long long)g.nnz,
+        fprintf(f, "%lld %lld %lld %d %d %d %d %d %d %d %.6f", (long long)g.n, (long long)g.nnz,
                 (long long)g.max_deg, std::get<2>(kv.first), std::get<3>(kv.first),
-                kv.second.interleave, kv.second.lds_max, T.t, kv.second.ms);
+                kv.second.interleave, kv.second.lds_max, kv.second.seg, kv.second.wave_row_max, T.t,
+                kv.second.ms);
         for (int32_t e : T.edges) fprintf(f, " %d", e);
         fprintf(f, "\n");
     }
@@ -571,9 +613,10 @@ int sc_tune_load(sc_ctx *c, const char *path, int32_t *n_applied) {
     if (!f) return fail(c, SC_ENOTFOUND, "cannot read %s", path);
     int applied = 0;
     long long n, nnz, maxd;
-    int k, B, inter, lmax, t;
+    int k, B, inter, lmax, seg, wrow, t;
     double ms;
-    while (fscanf(f, "%lld %lld %lld %d %d %d %d %d %lf", &n, &nnz, &maxd, &k, &B, &inter, &lmax, &t, &ms) == 9) {
+    while (fscanf(f, "%lld %lld %lld %d %d %d %d %d %d %d %lf", &n, &nnz, &maxd, &k, &B, &inter, &lmax, &seg, &wrow,
+                  &t, &ms) == 11) {
         if (t < 1 || t > SC_MAX_T) break;
         std::vector<int32_t> e(2 * (t - 1));
         bool ok = true;
@@ -586,6 +629,8 @@ int sc_tune_load(sc_ctx *c, const char *path, int32_t *n_applied) {
                 Tuned tu;
                 tu.interleave = inter;
                 tu.lds_max = lmax;
+                tu.seg = seg > 64 ? seg : 0;
+                tu.wave_row_max = wrow >= 0 && wrow <= 40960 ? wrow : -1;
                 tu.ms = ms;
                 c->tuned[TuneKey{gk.first, tk.first, k, B}] = tu;
                 ++applied;

@@ -85,14 +85,15 @@ struct ChainShape {
     int B = 1, Bi = 1;
     int wmax = 0;                      // widest row held in LDS (entries per colouring)
     // per step: active and output row entries, split pairs per output entry
-    // (h - 1), and (a >= 2) the (k-1, h-1, a-1) split table
+    // (a = h - 1), and (a >= 2) its (k-1, h-1, a-1) split table
     int Wa[kMaxChainSteps] = {}, Wh[kMaxChainSteps] = {}, nsplit[kMaxChainSteps] = {};
     const uint32_t *split[kMaxChainSteps] = {};
     uint64_t mod = 0;
 };
-// Dynamic LDS bytes of a chain kernel (neighbour colour counts and two rows of
-// `wmax` entries per interleaved colouring).
-int chain_lds_bytes(int k1, int wmax, int bi);
+// Dynamic LDS bytes of a chain kernel: per team the neighbour colour counts
+// and two rows of `wmax` entries per interleaved colouring, then `tab_entries`
+// uint16 index-table entries shared by the workgroup.
+int chain_lds_bytes(int k1, int wmax, int bi, int tab_entries, int teams = 1);
 // Runs the chain over every row: A is the first step's active table (NULL for
 // a0 = 1), S the last step's output; rows above the segment size take their
 // colour counts from Npre, written by launch_dp_split for the first step.

@@ -242,14 +242,17 @@ __device__ __forceinline__ void scatter_wide(const Team &tm, const DpArgs &a, in
     const uint32_t vbit = 1u << cv;
     const int Lq = a.Wq * a.Bi;
     uint32_t carry = 0;
-    for (int64_t eb = e0 + wave; eb < e1; eb += (int64_t)waves * NB) {
-        for (int base = 0; base < (BIG ? Lq : 1); base += kWave * CH) {
-            uint32_t msk[CH];
-            if (BIG) lane_masks<CH>(a, unr, base, msk);
-            else {
+    // rows wider than CH chunks are walked a group of CH chunks at a time,
+    // every neighbour's group before the next group, so a lane's set masks
+    // are read once per group and row
+    for (int base = 0; base < (BIG ? Lq : 1); base += kWave * CH) {
+        uint32_t msk[CH];
+        if (BIG) lane_masks<CH>(a, unr, base, msk);
+        else {
 #pragma unroll
-                for (int i = 0; i < CH; ++i) msk[i] = rmsk[i];
-            }
+            for (int i = 0; i < CH; ++i) msk[i] = rmsk[i];
+        }
+        for (int64_t eb = e0 + wave; eb < e1; eb += (int64_t)waves * NB) {
             int cu[NB];
             uint64_t x[NB][CH];
 #pragma unroll
@@ -677,7 +680,7 @@ __global__ __launch_bounds__(TPB) void dp_split_kernel(DpArgs a) {
 // ------------------------------------------------------------------ chains of single-vertex attaches
 
 struct ChainStepArgs {
-    const uint32_t *split;
+    const uint32_t *split;        // a >= 2: the (k-1, h-1, a-1) split table
     int Wh, nsplit, eg, lg_eg;
 };
 
@@ -690,16 +693,18 @@ struct ChainArgs {
 };
 
 // One chain step's output row: for every output set D and colouring, the sum
-// over the nsplit pairs (Ia, {x}) of D of cur[Ia] * N'[x], N' the row's
-// neighbour colour counts (below 2^32: the two-multiply product); lanes meet
-// as in emit_row.  `out` is the next LDS row, or the step's table in global
-// memory for the chain's last step.
+// over the nsplit pairs (Ia, {x}) of D (the split table, read through the
+// caches) of cur[Ia] * N'[x], N' the row's neighbour colour counts (below
+// 2^32: the two-multiply product); four pairs per lane are issued together,
+// and a group of eg lanes per entry meets as in emit_row.  `out` is the next
+// LDS row, or the step's table in global memory for the chain's last step.
 template <bool MOD>
 __device__ __forceinline__ void chain_emit(const Team &tm, const DpArgs &a, const ChainStepArgs &cs, int pl,
                                            const uint64_t *cur, const uint64_t *Nl, uint64_t *out, uint64_t &m) {
     const int Ls = cs.Wh * a.Bi;
     const int g = tm.tid & (cs.eg - 1);
     const int per = tm.size >> cs.lg_eg;
+    const int step = cs.eg;
     for (int q0 = 0; q0 < Ls; q0 += per) {          // uniform over the team
         const int q = q0 + (tm.tid >> cs.lg_eg);
         const int D = q >> a.sh, ri = q & (a.Bi - 1);
@@ -709,7 +714,25 @@ __device__ __forceinline__ void chain_emit(const Team &tm, const DpArgs &a, cons
         uint64_t wtop = 0;
         if (q < Ls) {
             const uint32_t *sp = cs.split + (int64_t)D * cs.nsplit;
-            for (int j = g; j < cs.nsplit; j += cs.eg) {
+            int j = g;
+            for (; j + 3 * step < cs.nsplit; j += 4 * step) {
+                uint32_t pr[4];
+                uint64_t x[4];
+                uint32_t y[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) pr[i] = sp[j + i * step];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    x[i] = cur[((pr[i] & 0xffffu) << a.sh) + ri];
+                    y[i] = (uint32_t)Nl[((pr[i] >> 16) << a.sh) + ri];
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    if constexpr (MOD) wide_add_product_n32(wlo, wtop, x[i], y[i]);
+                    else acc = mad_ovf_n32(acc, x[i], y[i], ovf);
+                }
+            }
+            for (; j < cs.nsplit; j += step) {
                 const uint32_t pr = sp[j];
                 const uint64_t xa = cur[((pr & 0xffffu) << a.sh) + ri];
                 const uint32_t yn = (uint32_t)Nl[((pr >> 16) << a.sh) + ri];
@@ -1114,8 +1137,8 @@ int dp_lds_bytes(const StepShape &s, int amode, int n_rank, int teams) {
     return bytes > (1 << 30) ? (1 << 30) : (int)bytes;
 }
 
-int chain_lds_bytes(int k1, int wmax, int bi) {
-    int64_t bytes = 8LL * bi * (k1 + 2LL * wmax);
+int chain_lds_bytes(int k1, int wmax, int bi, int tab_entries, int teams) {
+    int64_t bytes = 8LL * bi * (k1 + 2LL * wmax) * teams + 2LL * tab_entries;
     bytes = (bytes + 15) & ~15LL;
     return bytes > (1 << 30) ? (1 << 30) : (int)bytes;
 }
@@ -1154,10 +1177,10 @@ hipError_t launch_dp_chain(const GraphBins &g, const ChainShape &cs, const uint8
             (i == 0 && a > 1 && cs.Wa[0] > cs.wmax))
             return hipErrorInvalidValue;
     }
-    const int region = chain_lds_bytes(k1, cs.wmax, cs.Bi);
+    const int region = chain_lds_bytes(k1, cs.wmax, cs.Bi, 0);
     const bool wave = region <= wave_row_max && g.n * (cs.B / cs.Bi) >= kWaveRowsMin;
     const int teams = wave ? kWaves : 1;
-    const int lds = region * teams;
+    const int lds = chain_lds_bytes(k1, cs.wmax, cs.Bi, 0, teams);
     if (lds > kLdsPerCU) return hipErrorInvalidValue;
     const int tpb = !wave && lds > kWideLds ? kBlockWide : kBlock;
     DpArgs &a = c.d;

@@ -94,7 +94,27 @@ int step_lds_bytes(int k, int a, int p, int bi, int amode) {
     return kern::dp_lds_bytes(sh, amode, kern::rank_entries(k - 1));
 }
 
-int chain_lds_bytes(int k, int wmax, int bi) { return kern::chain_lds_bytes(k - 1, wmax, bi); }
+void lemma1_counts(Plan &P, int64_t n) {
+    const int k = P.k;
+    const double nnz = (double)P.nnz;
+    P.lemma1_ops = P.spmm_updates = P.ema_updates = 0;
+    for (const Step &s : P.steps) {
+        const double Wp = (double)binom(k, s.p), Wh = (double)binom(k, s.h);
+        P.lemma1_ops += nnz * Wp + (double)n * Wh * (double)binom(s.h, s.p);
+        P.spmm_updates += nnz * Wp;
+        P.ema_updates += s.a > 1 ? (double)n * Wh * (double)binom(s.h, s.a) : (double)n * Wh;
+    }
+}
+
+int chain_lds_bytes(int k, int wmax, int bi, int tab_entries) {
+    return kern::chain_lds_bytes(k - 1, wmax, bi, tab_entries);
+}
+
+void chain_extent(int k, int a0, int steps, int &wmax, int &tab_entries) {
+    wmax = a0 > 1 ? (int)binom(k - 1, a0 - 1) : 0;
+    for (int i = 0; i < steps; ++i) wmax = std::max<int>(wmax, (int)binom(k - 1, a0 + i));   // step (a+1, a, 1)
+    tab_entries = 0;            // the split tables are read through the caches
+}
 
 namespace {
 
@@ -153,7 +173,7 @@ int pick_interleave(const Plan &P, int cap, int lds_max) {
         for (const Step &s : P.steps)
             if (step_lds_bytes(P.k, s.a, s.p, bi, s.a > 1 ? kActGlobal : kActLeaf) > lds_max) fits = false;
         for (const Chain &ch : P.chains)
-            if (chain_lds_bytes(P.k, ch.wmax, bi) > lds_max) fits = false;
+            if (chain_lds_bytes(P.k, ch.wmax, bi, ch.tab_entries) > lds_max) fits = false;
         if (fits) break;
     }
     return bi;
@@ -196,15 +216,32 @@ bool build_plan(int t, int root, const std::vector<int> &child_ptr,
     auto drop = [&](int id) {
         if (id >= 0 && P.bufs[id].stored) arena.release(P.bufs[id].offset, P.bufs[id].bytes);
     };
-    // Runs of single-vertex attaches to the same vertex are fused into one
-    // chain kernel when its two widest rows fit the LDS limit at any width.
-    int widest = 0;
-    for (int s = 0; s < k; ++s) widest = std::max<int>(widest, (int)binom(k - 1, s));
-    const bool chains = o.chain && chain_lds_bytes(k, widest, 1) <= o.lds_max;
+    // A run of two or more single-vertex children attached to the same vertex
+    // one after another becomes one chain kernel when its two widest rows and
+    // its index tables fit the LDS limit with one colouring per plane.
+    auto chain_fuse = [&](int u) {
+        const int c0 = child_ptr[u], c1 = child_ptr[u + 1];
+        std::vector<char> fuse(c1 - c0, 0);
+        if (!o.chain) return fuse;
+        int size = 1;
+        for (int e = c0; e < c1;) {
+            if (P.subtree[child_idx[e]] != 1) { size += P.subtree[child_idx[e]]; ++e; continue; }
+            int r = e;
+            while (r < c1 && P.subtree[child_idx[r]] == 1) ++r;
+            int wmax = 0, tab = 0;
+            chain_extent(k, size, r - e, wmax, tab);
+            if (r - e >= 2 && chain_lds_bytes(k, wmax, 1, tab) <= o.lds_max)
+                for (int j = e; j + 1 < r; ++j) fuse[j - c0] = 1;
+            size += r - e;
+            e = r;
+        }
+        return fuse;
+    };
 
     // post-order walk: the subtree of u is built by attaching its children in order
     std::function<int(int)> walk = [&](int u) -> int {
         int cur = -1, size = 1;
+        const std::vector<char> fuse = chain_fuse(u);
         for (int e = child_ptr[u]; e < child_ptr[u + 1]; ++e) {
             int w = child_idx[e];
             int pb = walk(w);
@@ -215,7 +252,7 @@ bool build_plan(int t, int root, const std::vector<int> &child_ptr,
             s.mode = s.p == 1 ? kStepHist : kStepGather;
             s.amode = kActLeaf;
             s.lds_bytes = 0;
-            s.fuse_next = chains && s.p == 1 && e + 1 < child_ptr[u + 1] && P.subtree[child_idx[e + 1]] == 1;
+            s.fuse_next = fuse[e - child_ptr[u]] != 0;
             s.buf_s = new_buf(s.h, !s.fuse_next);
             s.last = false;
             drop(s.buf_a);
@@ -232,10 +269,9 @@ bool build_plan(int t, int root, const std::vector<int> &child_ptr,
     P.arena_bytes = arena.end;
     for (int i = 0; i < (int)P.steps.size(); ++i) {
         if (!P.steps[i].fuse_next || (i > 0 && P.steps[i - 1].fuse_next)) continue;
-        Chain ch{i, i, 0};
+        Chain ch{i, i, 0, 0};
         while (P.steps[ch.last].fuse_next) ++ch.last;
-        if (P.steps[i].a > 1) ch.wmax = (int)binom(k - 1, P.steps[i].a - 1);
-        for (int j = i; j <= ch.last; ++j) ch.wmax = std::max<int>(ch.wmax, (int)binom(k - 1, P.steps[j].h - 1));
+        chain_extent(k, P.steps[i].a, ch.last - i + 1, ch.wmax, ch.tab_entries);
         P.chains.push_back(ch);
     }
 
@@ -246,12 +282,16 @@ bool build_plan(int t, int root, const std::vector<int> &child_ptr,
     for (Step &s : P.steps) {
         const int base = step_lds_bytes(k, s.a, s.p, P.interleave, s.a > 1 ? kActGlobal : kActLeaf);
         if (base > 160 * 1024) { err = "a step's neighbour-sum row does not fit in LDS"; return false; }
-        // The active row is staged in LDS when it fits the limit; wider rows
-        // are read from global memory, where the row stays in the caches.
+        // The active row is staged in LDS when it fits the limit and its
+        // entries are read more than once: an active set C1 pairs with
+        // binom(k - a, p) output sets (one when the step's output is the whole
+        // colour set, where staging only costs occupancy).  Other rows are
+        // read from global memory, where the row stays in the caches.
         s.amode = kActLeaf;
         if (s.a > 1) {
             const int staged = step_lds_bytes(k, s.a, s.p, P.interleave, kActLds);
-            s.amode = staged <= std::max(o.lds_max, base) ? kActLds : kActGlobal;
+            const bool reused = binom(k - s.a, s.p) > 1;
+            s.amode = reused && staged <= std::max(o.lds_max, base) ? kActLds : kActGlobal;
         }
         s.lds_bytes = step_lds_bytes(k, s.a, s.p, P.interleave, s.amode);
     }
@@ -259,11 +299,8 @@ bool build_plan(int t, int root, const std::vector<int> &child_ptr,
     // Per colouring: Lemma 1 counts of the paper's layout (the benchmark's
     // update counts), the updates executed in the rooted-colour layout, and a
     // byte model of that layout.
+    lemma1_counts(P, n);
     for (const Step &s : P.steps) {
-        const double Wp = (double)binom(k, s.p), Wh = (double)binom(k, s.h);
-        P.lemma1_ops += (double)nnz * Wp + (double)n * Wh * (double)binom(s.h, s.p);
-        P.spmm_updates += (double)nnz * Wp;
-        P.ema_updates += s.a > 1 ? (double)n * Wh * (double)binom(s.h, s.a) : (double)n * Wh;
         const double Rq = (double)binom(k - 1, s.p - 1), Rn = (double)binom(k - 1, s.p);
         const double Ra = (double)binom(k - 1, s.a - 1), Rh = (double)binom(k - 1, s.h - 1);
         const double madds = s.a > 1 ? (double)n * Rh * (double)binom(s.h - 1, s.a - 1) : (double)n * Rn;

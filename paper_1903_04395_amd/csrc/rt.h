@@ -42,6 +42,14 @@ struct Graph {
     DevMem split_rows, split_items, slot;
     int64_t n_split = 0, n_split_items = 0;
     double split_nnz = 0;
+    // the same for segment sizes used before (kept until unload, so passes
+    // and captured graphs that read them stay valid)
+    struct SavedBins {
+        DevMem split_rows, split_items, slot;
+        int64_t n_split = 0, n_split_items = 0;
+        double split_nnz = 0;
+    };
+    std::map<int, SavedBins> saved_bins;
     int busy = 0;                // passes of the serving loop in flight on this graph
 };
 
@@ -63,6 +71,8 @@ struct TableKey {
 struct Tuned {
     int interleave = 0;
     int lds_max = 0;
+    int seg = 0;
+    int wave_row_max = -1;
     double ms = 0;
 };
 using TuneKey = std::tuple<int, int, int, int>;   // graph id, template id, k, batch
@@ -166,7 +176,12 @@ int upload(sc_ctx *c, DevMem &m, const void *host, size_t bytes);
 int host_staging(sc_ctx *c, size_t words);
 
 int default_segment(const sc_ctx *c);
-int rebin(sc_ctx *c, Graph &g, int seg);
+// The segment size a plan runs with (its tuned one, else the context's).
+int plan_segment(const sc_ctx *c, const Plan &P);
+// Makes `seg` the graph's current binning: switches to saved bins without
+// allocating when they exist (allocate = false: fails with SC_ESTATE
+// otherwise), else builds and uploads them.
+int rebin(sc_ctx *c, Graph &g, int seg, bool allocate = true);
 kern::GraphBins bins_of(const Graph &g);
 // Device copies of the host index tables, cached per context.
 int get_split(sc_ctx *c, int k, int h, int a, const uint32_t **out);

@@ -74,13 +74,33 @@ int host_staging(sc_ctx *c, size_t words) {
 
 int default_segment(const sc_ctx *c) { return c->segment > 0 ? (int)c->segment : 512; }
 
+int plan_segment(const sc_ctx *c, const Plan &P) { return P.opts.seg > 0 ? P.opts.seg : default_segment(c); }
+
 // Rows with more than `seg` neighbours ("split rows"): their (row, segment)
 // items and the compact slot of every split row for precomputed neighbour sums.
-int rebin(sc_ctx *c, Graph &g, int seg) {
+// Bins of earlier segment sizes are kept, so switching back costs nothing.
+int rebin(sc_ctx *c, Graph &g, int seg, bool allocate) {
     if (g.seg == seg && g.slot.p) return SC_OK;
-    if (g.busy) return fail(c, SC_ESTATE, "segment size cannot change while the serving loop uses the graph");
-    HIPCHK(c, hipDeviceSynchronize());
-    dev_free(c, g.split_rows); dev_free(c, g.split_items); dev_free(c, g.slot);
+    auto it = g.saved_bins.find(seg);
+    if (it == g.saved_bins.end() && !allocate)
+        return fail(c, SC_ESTATE, "graph has no heavy-row bins for segment size %d", seg);
+    if (g.busy && it == g.saved_bins.end())
+        return fail(c, SC_ESTATE, "segment size cannot change while the serving loop uses the graph");
+    if (g.slot.p) {
+        Graph::SavedBins &sv = g.saved_bins[g.seg];
+        sv.split_rows = g.split_rows; sv.split_items = g.split_items; sv.slot = g.slot;
+        sv.n_split = g.n_split; sv.n_split_items = g.n_split_items; sv.split_nnz = g.split_nnz;
+        g.split_rows = g.split_items = g.slot = DevMem{};
+    }
+    it = g.saved_bins.find(seg);
+    if (it != g.saved_bins.end()) {
+        const Graph::SavedBins &sv = it->second;
+        g.split_rows = sv.split_rows; g.split_items = sv.split_items; g.slot = sv.slot;
+        g.n_split = sv.n_split; g.n_split_items = sv.n_split_items; g.split_nnz = sv.split_nnz;
+        g.saved_bins.erase(it);
+        g.seg = seg;
+        return SC_OK;
+    }
     std::vector<int32_t> split_rows, slot(std::max<int64_t>(g.n_rows, 1), -1);
     std::vector<int2> items;
     g.split_nnz = 0;
@@ -99,8 +119,6 @@ int rebin(sc_ctx *c, Graph &g, int seg) {
     if ((rc = upload(c, g.split_items, items.data(), items.size() * sizeof(int2)))) return rc;
     if ((rc = upload(c, g.slot, slot.data(), slot.size() * sizeof(int32_t)))) return rc;
     g.seg = seg;
-    for (auto &kv : c->graph_cache) (void)hipGraphExecDestroy(kv.second);
-    c->graph_cache.clear();
     return SC_OK;
 }
 
@@ -168,6 +186,8 @@ ExecOpts exec_opts(const sc_ctx *c, int gid, int tid, int k, int batch) {
     if (it != c->tuned.end()) {
         if (it->second.interleave > 0) o.interleave = it->second.interleave;
         if (it->second.lds_max > 0) o.lds_max = it->second.lds_max;
+        if (it->second.seg > 0) o.seg = it->second.seg;
+        if (it->second.wave_row_max >= 0) o.wave_row_max = it->second.wave_row_max;
     }
     return o;
 }
@@ -182,6 +202,8 @@ int make_plan(sc_ctx *c, const Graph &g, const Template &T, const ExecOpts &o, i
     else
         ok = choose_plan(T.t, T.edges.data(), T.root, k, rows, g.nnz, batch, o, P, err);
     if (!ok) return fail(c, SC_EINVAL, "planning failed: %s", err.c_str());
+    // tables hold the non-isolated rows; the paper's counts run over every vertex
+    lemma1_counts(P, g.n);
     return SC_OK;
 }
 
@@ -237,6 +259,10 @@ double aut_of(int t, const std::vector<int32_t> &edges) {
 void free_graph(sc_ctx *c, Graph &g) {
     dev_free(c, g.rp); dev_free(c, g.ci); dev_free(c, g.split_rows); dev_free(c, g.split_items);
     dev_free(c, g.slot); dev_free(c, g.perm);
+    for (auto &kv : g.saved_bins) {
+        dev_free(c, kv.second.split_rows); dev_free(c, kv.second.split_items); dev_free(c, kv.second.slot);
+    }
+    g.saved_bins.clear();
 }
 
 bool serving(const sc_ctx *c) { return c->serve != nullptr; }

@@ -33,6 +33,7 @@ struct ExecOpts {
     int lds_max = 64 * 1024;   // LDS bytes a row kernel may use
     int wave_row_max = 8192;   // per-row LDS bytes up to which a wavefront builds a row alone
     int chain = 1;             // runs of single-vertex attaches fused into one kernel
+    int seg = 0;               // neighbours per work item of split rows (0: the context's segment size)
 };
 
 // One DP step: attach the subtree of `child` (passive, size p) to what `node`
@@ -64,6 +65,7 @@ struct Buf {
 struct Chain {
     int first, last;
     int wmax;          // widest row (entries per colouring) the chain holds in LDS
+    int tab_entries;   // uint16 index-table entries it stages in LDS
 };
 
 struct Plan {
@@ -82,8 +84,16 @@ struct Plan {
 
 // Dynamic LDS bytes of a step's row kernel with `bi` interleaved colourings.
 int step_lds_bytes(int k, int a, int p, int bi, int amode);
-// Dynamic LDS bytes of a chain kernel whose widest row has `wmax` entries.
-int chain_lds_bytes(int k, int wmax, int bi);
+// The paper's per-colouring counts (Lemma 1) of plan P on a graph of n
+// vertices and P.nnz nonzeros: spmm_updates, ema_updates, lemma1_ops.
+void lemma1_counts(Plan &P, int64_t n);
+
+// Dynamic LDS bytes of a chain kernel whose widest row has `wmax` entries and
+// whose index tables hold `tab_entries` uint16 entries.
+int chain_lds_bytes(int k, int wmax, int bi, int tab_entries);
+// Widest row and index-table entries of a chain of `steps` single-vertex
+// attaches starting from an active child of size a0, over k colours.
+void chain_extent(int k, int a0, int steps, int &wmax, int &tab_entries);
 
 // Validates an edge list as a tree on t vertices; returns "" or a message.
 std::string check_tree(int t, const int32_t *edges);

@@ -289,6 +289,11 @@ int sc_serve_start(sc_ctx *c, const sc_serve_cfg_t *cfg) {
         return fail(c, SC_EINVAL, "max_inflight must be in [1, %d]", kMaxInflight);
     if (cfg->max_batch < 1 || cfg->max_batch > SC_MAX_BATCH) return fail(c, SC_EINVAL, "max_batch must be in [1, %d]", SC_MAX_BATCH);
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, SC_EDEVICE, "hipSetDevice failed");
+    // the count tables of the synchronous calls would hold device memory
+    // beside the serving budget: give them back (a later sc_run regrows them)
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    dev_free(c, c->main.arena); dev_free(c, c->main.colbuf); dev_free(c, c->main.npre);
+    c->main.gen = 0;
     auto S = std::make_unique<ServeState>();
     S->cfg = *cfg;
     if (!S->cfg.mem_budget_bytes) S->cfg.mem_budget_bytes = c->budget;

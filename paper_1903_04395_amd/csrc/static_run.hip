@@ -61,6 +61,20 @@ void layout_pass(const sc::Graph &g, const sc::Plan &P, unsigned char *base, Sta
     size_t off = 0;
     L.desc = off;  off = align_up(off + 2 * sizeof(uint64_t));
     L.xbuf = off;  off = align_up(off + (SC_MAX_BATCH + 1) * sizeof(uint64_t));
+    auto stage_unrank = [&](int sz) {
+        const TableKey ukey{k - 1, sz, 0};
+        if (!L.staged.unrank.count(ukey)) {
+            L.staged.unrank[ukey] = (const uint16_t *)(base + off);
+            add_table(L, off, sc::unrank_table(k - 1, sz));
+        }
+    };
+    auto stage_rank = [&]() {
+        const TableKey rkey{k - 1, 0, 0};
+        if (!L.staged.rank.count(rkey)) {
+            L.staged.rank[rkey] = (const uint16_t *)(base + off);
+            add_table(L, off, sc::rank_table(k - 1));
+        }
+    };
     for (const sc::Step &s : P.steps) {
         if (s.a > 1) {
             const TableKey key{k - 1, s.h - 1, s.a - 1};
@@ -70,15 +84,8 @@ void layout_pass(const sc::Graph &g, const sc::Plan &P, unsigned char *base, Sta
             }
         }
         if (s.p > 1) {
-            const TableKey ukey{k - 1, s.p - 1, 0}, rkey{k - 1, 0, 0};
-            if (!L.staged.unrank.count(ukey)) {
-                L.staged.unrank[ukey] = (const uint16_t *)(base + off);
-                add_table(L, off, sc::unrank_table(k - 1, s.p - 1));
-            }
-            if (!L.staged.rank.count(rkey)) {
-                L.staged.rank[rkey] = (const uint16_t *)(base + off);
-                add_table(L, off, sc::rank_table(k - 1));
-            }
+            stage_unrank(s.p - 1);
+            stage_rank();
         }
     }
     L.col = off;   off = align_up(off + (size_t)g.n_rows * P.batch);
@@ -129,9 +136,6 @@ extern "C" int sc_run_static(sc_ctx *c, int32_t gid, int32_t tid, uint64_t first
     if (!base) return fail(c, SC_EDEVICE, "the static scratch of device %d is not set up", c->device);
     Graph &g = *c->graphs[gid];
     const Template &T = *c->tmpls[tid];
-    if (g.seg != default_segment(c) || !g.slot.p)
-        return fail(c, SC_ESTATE, "graph %d is binned for segment %d, the option asks for %d; "
-                    "the allocation-free run cannot rebin it", gid, g.seg, default_segment(c));
     hipStream_t st = stream ? (hipStream_t)stream : c->stream;
     const int k = c->k;
 
@@ -162,6 +166,12 @@ extern "C" int sc_run_static(sc_ctx *c, int32_t gid, int32_t tid, uint64_t first
         if (!fits)
             return fail(c, SC_ENOMEM, "one colouring needs %zu bytes of device buffers; the static scratch holds %llu",
                         ps.L.total, (unsigned long long)SC_STATIC_SCRATCH_BYTES);
+        // the heavy-row bins of the plan's segment size must exist already
+        // (switching to them allocates nothing; building them would)
+        const int seg = plan_segment(c, ps.P);
+        if (seg != g.seg && !g.saved_bins.count(seg))
+            return fail(c, SC_ESTATE, "graph %d has no heavy-row bins for segment size %d (the allocation-free "
+                        "run cannot build them; run sc_run once with this segment size)", gid, seg);
         ps.first = first + (uint64_t)off;
         ps.offset = off;
         off += ps.P.batch;
@@ -191,6 +201,7 @@ extern "C" int sc_run_static(sc_ctx *c, int32_t gid, int32_t tid, uint64_t first
         for (const auto &t : ps.L.tabs)
             if (!t.bytes.empty())
                 SC_STATIC_CHK(hipMemcpyAsync(base + t.off, t.bytes.data(), t.bytes.size(), hipMemcpyHostToDevice, st));
+        if (int rc = rebin(c, g, plan_segment(c, P), false)) return failed(rc);
         ps.desc[0] = c->seed;
         ps.desc[1] = ps.first;
         SC_STATIC_CHK(hipMemcpyAsync(base + ps.L.desc, ps.desc, sizeof ps.desc, hipMemcpyHostToDevice, st));

@@ -22,6 +22,8 @@ Generators (all seeded through ``numpy.random.Generator(PCG64(seed))``):
   stands in for the paper's power-law social graphs (Table 3).
 * ``prufer_tree(t, seed)``, ``star(t)``, ``path(t)`` -- template trees as edge
   lists over vertices 0..t-1.
+* ``serving_queries(nq, qps, seed)`` -- a Poisson stream of counting queries
+  over three resident graphs.
 """
 from __future__ import annotations
 
@@ -30,7 +32,7 @@ import numpy as np
 __all__ = [
     "CSR", "csr_from_edges", "erdos_renyi", "rmat", "chung_lu",
     "prufer_tree", "prufer_decode", "star", "path", "random_small_graph",
-    "degree_stats",
+    "degree_stats", "serving_queries",
 ]
 
 
@@ -213,3 +215,17 @@ def degree_stats(g: CSR) -> dict:
         "max_deg": int(d.max()) if d.size else 0,
         "p99_deg": float(np.percentile(d, 99)) if d.size else 0.0,
     }
+
+
+def serving_queries(nq: int, qps: float = 200.0, seed: int = 2019):
+    """A seeded Poisson query stream over three resident graphs: arrival time
+    (seconds, exponential gaps at `qps`), graph index 0..2, a Pruefer tree of
+    3..12 vertices (its own seed), k = t, 1..32 colourings, colouring seed."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out, at = [], 0.0
+    for i in range(nq):
+        at += rng.exponential(1.0 / qps)
+        t = int(rng.integers(3, 13))
+        out.append({"at": at, "graph": int(rng.integers(0, 3)), "t": t, "edges": prufer_tree(t, 10_000 + i),
+                    "n": int(rng.integers(1, 33)), "seed": int(rng.integers(0, 1 << 40))})
+    return out

@@ -117,7 +117,8 @@ class Job(ctypes.Structure):
 
 class Tune(ctypes.Structure):
     _fields_ = [("interleave", ctypes.c_int32), ("lds_max", ctypes.c_int32),
-                ("batch", ctypes.c_int32), ("trials", ctypes.c_int32), ("ms", ctypes.c_double)]
+                ("batch", ctypes.c_int32), ("trials", ctypes.c_int32), ("ms", ctypes.c_double),
+                ("seg", ctypes.c_int32), ("wave_row_max", ctypes.c_int32)]
 
 
 class Estimate(ctypes.Structure):
@@ -458,8 +459,8 @@ class Context:
     def autotune(self, gid, tid, n_colorings):
         t = Tune()
         self._check(self._L.sc_autotune(self._h, gid, tid, n_colorings, ctypes.byref(t)))
-        return {"interleave": t.interleave, "lds_max": t.lds_max, "batch": t.batch,
-                "trials": t.trials, "ms": t.ms}
+        return {"interleave": t.interleave, "lds_max": t.lds_max, "seg": t.seg, "wave_row_max": t.wave_row_max,
+                "batch": t.batch, "trials": t.trials, "ms": t.ms}
 
     def tune_save(self, path):
         self._check(self._L.sc_tune_save(self._h, str(path).encode()))

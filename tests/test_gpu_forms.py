@@ -108,8 +108,9 @@ def test_autotune_keeps_results_and_round_trips(ctx, tmp_path):
     before = ctx.run(gid, tid, 0, 8)[:2]
     tune = ctx.autotune(gid, tid, 8)
     say("tuned", tune)
-    assert tune["batch"] == 8 and tune["trials"] == 16
+    assert tune["batch"] == 8 and tune["trials"] == 16 + 3 + 2
     assert tune["interleave"] in (1, 2, 4, 8) and tune["lds_max"] in (32768, 65536, 98304, 131072)
+    assert tune["seg"] in (256, 512, 1024, 2048) and tune["wave_row_max"] in (0, 8192, 16384)
     after = ctx.run(gid, tid, 0, 8)[:2]
     assert np.array_equal(before[0], after[0]) and np.array_equal(before[1], after[1])
     path = tmp_path / "tune.txt"
