@@ -66,11 +66,12 @@ __global__ __launch_bounds__(kThreads) void fascia_step_kernel(AblArgs a) {
     for (int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x; q < total; q += (int64_t)gridDim.x * kThreads) {
         const int64_t v = q / a.Wh;
         const int Is = (int)(q - v * a.Wh);
-        const uint32_t *sp = a.split + (int64_t)Is * a.nsplit;
+        const uint32_t *sp = a.split + Is;                 // pair j at sp[j * Wh]
         uint64_t acc = 0;
         uint32_t ovf = 0;
         for (int j = 0; j < a.nsplit; ++j) {
-            const int Ia = (int)(sp[j] & 0xffffu), Ip = (int)(sp[j] >> 16);
+            const uint32_t pr = sp[(int64_t)j * a.Wh];
+            const int Ia = (int)(pr & 0xffffu), Ip = (int)(pr >> 16);
             const uint64_t x = a.A ? a.A[v * a.Wa + Ia] : leaf_entry(a.col, v, Ia);
             uint32_t novf = 0;
             const uint64_t y = neighbour_sum(a, v, Ip, novf);      // again for every split
@@ -106,11 +107,12 @@ __global__ __launch_bounds__(kThreads) void pfascia_ema_kernel(AblArgs a) {
     for (int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x; q < total; q += (int64_t)gridDim.x * kThreads) {
         const int64_t v = q / a.Wh;
         const int Is = (int)(q - v * a.Wh);
-        const uint32_t *sp = a.split + (int64_t)Is * a.nsplit;
+        const uint32_t *sp = a.split + Is;                 // pair j at sp[j * Wh]
         uint64_t acc = 0;
         uint32_t ovf = 0;
         for (int j = 0; j < a.nsplit; ++j) {
-            const int Ia = (int)(sp[j] & 0xffffu), Ip = (int)(sp[j] >> 16);
+            const uint32_t pr = sp[(int64_t)j * a.Wh];
+            const int Ia = (int)(pr & 0xffffu), Ip = (int)(pr >> 16);
             const uint64_t x = a.A ? a.A[v * a.Wa + Ia] : leaf_entry(a.col, v, Ia);
             acc = mad_ovf(acc, x, a.N[v * a.Wp + Ip], ovf);
         }

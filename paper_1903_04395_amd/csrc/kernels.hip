@@ -516,13 +516,13 @@ __device__ __forceinline__ void emit_row(const Team &tm, const DpArgs &a, int64_
         unsigned __int128 wlo = 0;                  // MOD: the lane's exact sum of products,
         uint64_t wtop = 0;                          // reduced once below
         if (q < Ls) {
-            const uint32_t *sp = split + (int64_t)D * a.nsplit;
+            const uint32_t *sp = split + D;              // pair j at sp[j * Wh]
             int j = g;
             for (; j + 3 * step < a.nsplit; j += 4 * step) {
                 uint32_t pr[4];
                 uint64_t x[4], y[4];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) pr[i] = sp[j + i * step];
+                for (int i = 0; i < 4; ++i) pr[i] = sp[(int64_t)(j + i * step) * a.Wh];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     x[i] = Ar[((pr[i] & 0xffffu) << a.sh) + ri];
@@ -546,7 +546,7 @@ __device__ __forceinline__ void emit_row(const Team &tm, const DpArgs &a, int64_
                 }
             }
             for (; j < a.nsplit; j += step) {
-                const uint32_t pr = sp[j];
+                const uint32_t pr = sp[(int64_t)j * a.Wh];
                 const uint64_t xa = Ar[((pr & 0xffffu) << a.sh) + ri], yn = Nl[((pr >> 16) << a.sh) + ri];
                 if constexpr (MOD && N32) wide_add_product_n32(wlo, wtop, xa, (uint32_t)yn);
                 else if constexpr (MOD) wide_add_product(wlo, wtop, xa, yn);
@@ -713,14 +713,14 @@ __device__ __forceinline__ void chain_emit(const Team &tm, const DpArgs &a, cons
         unsigned __int128 wlo = 0;
         uint64_t wtop = 0;
         if (q < Ls) {
-            const uint32_t *sp = cs.split + (int64_t)D * cs.nsplit;
+            const uint32_t *sp = cs.split + D;           // pair j at sp[j * Wh]
             int j = g;
             for (; j + 3 * step < cs.nsplit; j += 4 * step) {
                 uint32_t pr[4];
                 uint64_t x[4];
                 uint32_t y[4];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) pr[i] = sp[j + i * step];
+                for (int i = 0; i < 4; ++i) pr[i] = sp[(int64_t)(j + i * step) * cs.Wh];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     x[i] = cur[((pr[i] & 0xffffu) << a.sh) + ri];
@@ -733,7 +733,7 @@ __device__ __forceinline__ void chain_emit(const Team &tm, const DpArgs &a, cons
                 }
             }
             for (; j < cs.nsplit; j += step) {
-                const uint32_t pr = sp[j];
+                const uint32_t pr = sp[(int64_t)j * cs.Wh];
                 const uint64_t xa = cur[((pr & 0xffffu) << a.sh) + ri];
                 const uint32_t yn = (uint32_t)Nl[((pr >> 16) << a.sh) + ri];
                 if constexpr (MOD) wide_add_product_n32(wlo, wtop, xa, yn);

@@ -399,7 +399,8 @@ double tree_automorphisms(int t, const std::vector<std::pair<int,int>> &edges) {
 
 std::vector<uint32_t> split_table(int k, int h, int a) {
     const int per = (int)binom(h, a);
-    std::vector<uint32_t> out(binom(k, h) * (uint64_t)per);
+    const uint64_t sets = binom(k, h);
+    std::vector<uint32_t> out(sets * (uint64_t)per);
     for (uint32_t ms = 0; ms < (1u << k); ++ms) {
         if (__builtin_popcount(ms) != h) continue;
         int64_t is = colorset_rank(ms);
@@ -408,7 +409,7 @@ std::vector<uint32_t> split_table(int k, int h, int a) {
         for (uint32_t ma = ms;; ma = (ma - 1) & ms) {
             if (__builtin_popcount(ma) == a) {
                 uint32_t ia = (uint32_t)colorset_rank(ma), ip = (uint32_t)colorset_rank(ms ^ ma);
-                out[is * per + q++] = ia | (ip << 16);
+                out[(uint64_t)q++ * sets + is] = ia | (ip << 16);
             }
             if (!ma) break;
         }

@@ -118,8 +118,10 @@ bool choose_plan(int t, const int32_t *edges, int root, int k, int64_t n, int64_
 double tree_automorphisms(int t, const std::vector<std::pair<int,int>> &edges);
 
 // Split table over k colours: for every colour set I_s of size h (in index
-// order), binom(h,a) packed pairs (I_a | I_p << 16).  A rooted-colour step
-// (h, a, p) uses the table of (k-1, h-1, a-1).
+// order), binom(h,a) packed pairs (I_a | I_p << 16), pair-major: pair j of
+// set I_s at [j * binom(k,h) + I_s], so threads taking consecutive sets read
+// consecutive words.  A rooted-colour step (h, a, p) uses the table of
+// (k-1, h-1, a-1).
 std::vector<uint32_t> split_table(int k, int h, int a);
 // Masks of the s-subsets of k1 colours in Eq. 1 order.
 std::vector<uint16_t> unrank_table(int k1, int s);
