@@ -292,7 +292,9 @@ def exact_bench():
     """Exact wide counts beside the uint64 pass, per call after a warm-up:
     RMAT scale 20 / 10-vertex tree / k=10 / 8 colourings, and Chung-Lu
     n=4,194,304 / 12-star / k=12 / 16 colourings.  Every colouring of these
-    workloads overflows 2^64, so sc_run_exact adds three residue passes."""
+    workloads overflows 2^64: for the tree sc_run_exact adds residue passes,
+    the star (one chain from its centre) takes one multi-limb pass; the star's
+    residue route (chains off) is timed beside it."""
     from paper_1903_04395_amd import inputs as I
     from paper_1903_04395_amd import sc
     ctx = sc.Context(0)
@@ -320,6 +322,15 @@ def exact_bench():
                      "hom_bound_log2": round(math.log2(hom2), 1) if hom2 > 0 else None,
                      "max_count_log2": round(math.log2(max(counts)), 1) if max(counts) > 0 else None,
                      "est_maps": maps, "est_copies": copies}
+        if name.startswith("chunglu"):
+            ctx.set_option(sc.SC_OPT_CHAIN, 0)
+            ctx.run_exact(gid, tid, 0, R)
+            t5 = time.perf_counter()
+            c_res, e_res, _, _, _ = ctx.run_exact(gid, tid, R, R)
+            t6 = time.perf_counter()
+            ctx.set_option(sc.SC_OPT_CHAIN, sc.OPTION_DEFAULTS[sc.SC_OPT_CHAIN])
+            assert list(c_res) == list(counts) and e_res.all()
+            out[name]["s_exact_residue_route"] = round(t6 - t5, 4)
         print(f"[bench] exact {name}: {out[name]}", file=sys.stderr, flush=True)
         ctx.unload_graph(gid)
         del g
@@ -328,7 +339,7 @@ def exact_bench():
 
 
 def ablation_bench():
-    """The paper's pruning ablation (Sec. 6.3), on MI355X: per colouring, the
+    """The paper's pruning ablation (Sec. 7.1), on MI355X: per colouring, the
     FASCIA baseline (Algorithm 1: every split re-sums the passive column over
     the neighbours), PFASCIA (pruned: neighbour sums once), and the library's
     path (one colouring per pass, and 8 folded into a pass), on RMAT scale 16
@@ -517,8 +528,8 @@ def golden_check(counts):
 
 def extras(ctx, gid3, star_tid):
     """Side measurements for the same line, after the timed region: exact
-    counts (sc_run_exact, residue passes and CRT) of 16 colourings of the
-    Chung-Lu 12-star beside its uint64 pass; then, on RMAT scale 20 / 10-vertex
+    counts (sc_run_exact: one multi-limb pass, the star being one chain from its
+    centre) of 16 colourings of the Chung-Lu 12-star beside its uint64 pass; then, on RMAT scale 20 / 10-vertex
     Pruefer tree (seed 0) / k = 10, the uint64 pass of 8 colourings, exact
     counts of 8 colourings, and the plain per-colouring launch loop (one
     colouring per sc_run) against the batched form (8 colourings folded into a

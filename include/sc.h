@@ -235,11 +235,18 @@ int sc_run_static(sc_ctx *ctx, int32_t graph_id, int32_t tmpl_id, uint64_t first
  * the graph bounds every colouring's colourful count; the first one, two or
  * three primes run, as that bound (with a 2^-10 margin) lies below 2^124,
  * 2^185 or 2^247, and the result is certified exact when it does.
+ * A template that is one chain of single-vertex attaches from a single vertex
+ * (the star rooted at its centre; SC_OPT_CHAIN on) skips the residue passes
+ * when its bound reaches 2^64: one pass keeps every table entry as 2, 3 or 4
+ * little-endian 64-bit limbs, the fewest whose range holds the bound with the
+ * same margin, and the counts are exact without any modular step (a bound at
+ * or past 2^256 takes the residue passes).  The homomorphism count is then
+ * always computed.
  * Synchronous.  Host outputs: counts[n_colorings][4] (the count as four uint64
  * limbs, least significant first), exact[n_colorings] (1: the count is exact;
  * 0: only its residue mod 2^64 p1 p2 p3 is), hom_bound (may be NULL: the
- * homomorphism count, computed when a colouring overflowed or when asked for,
- * else NaN), est_maps / est_copies (may be NULL; from the exact counts, NaN if
+ * homomorphism count, computed when a colouring overflowed, when asked for
+ * or for a single-chain template, else NaN), est_maps / est_copies (may be NULL; from the exact counts, NaN if
  * any is not exact).
  * Errors: as sc_run. */
 int sc_run_exact(sc_ctx *ctx, int32_t graph_id, int32_t tmpl_id, uint64_t first_coloring,

@@ -1,12 +1,12 @@
 // Plain kernels of the two CPU designs the paper improves on, kept as
-// baselines for its pruning ablation (Sec. 3.2, Sec. 4.1, Sec. 6.3): one
+// baselines for its pruning ablation (Sec. 3.1, Sec. 4.1, Sec. 7.1): one
 // colouring at a time, tables in the paper's layout (row v of sub-template
 // size s holds all binom(k, s) colour sets, column = Eq. 1 rank), one thread
 // per table entry.
 //
 //  * FASCIA (Algorithm 1): for every row, output set and split, the passive
 //    child's column is summed over the row's neighbours again -- the redundant
-//    neighbour traversal of Sec. 3.2.
+//    neighbour traversal of Sec. 3.1.
 //  * PFASCIA (pruned, Sec. 4.1): the neighbour sum of every passive column is
 //    taken once per row, then the split multiply-add reads it.
 //

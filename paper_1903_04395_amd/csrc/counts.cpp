@@ -128,7 +128,9 @@ long double limbs_value(const uint64_t *l) {
            std::ldexp((long double)l[3], 192);
 }
 
-// Exact counts of colourings first..first+n-1 as four limbs each: the uint64
+// Exact counts of colourings first..first+n-1 as four limbs each.  A
+// single-chain template whose homomorphism bound passes 2^64 takes one
+// multi-limb pass.  Otherwise the uint64
 // pass, then residue passes for the colourings that overflowed, combined by
 // CRT and certified by the homomorphism count (computed when a colouring
 // overflowed or `want_hom`, into *H if that is still NaN).
@@ -140,6 +142,34 @@ int exact_counts(sc_ctx *c, int gid, int tid, uint64_t first, int ncol, hipStrea
     {
         std::vector<PassJob> passes;
         if ((rc = plan_job(c, 0, gid, tid, c->k, c->seed, first, ncol, passes))) return rc;
+        // a template that is one chain from a single vertex (a star rooted at
+        // its centre) whose counts may pass 2^64 runs once with as many
+        // 64-bit limbs as the homomorphism bound asks for
+        bool chains = !passes.empty();
+        for (const PassJob &p : passes) chains &= single_chain(p.P);
+        if (chains && std::isnan(*H) && (rc = hom_count(c, gid, tid, st, H))) return rc;
+        int limbs = 0;
+        if (chains && !(*H * kHomSlack < 0x1p64))
+            for (int l = 2; l <= 4 && !limbs; ++l)
+                if (*H * kHomSlack < std::ldexp(1.0, 64 * l)) limbs = l;
+        // the two widest rows of one colouring must fit the LDS limit
+        for (const PassJob &p : passes)
+            if (limbs && kern::chain_wide_lds_bytes(p.k - 1, p.P.chains[0].wmax, 1, limbs) > p.P.opts.lds_max)
+                limbs = 0;
+        if (limbs) {
+            std::vector<uint8_t> bad((size_t)ncol);
+            rc = run_wide_passes(c, passes, limbs, st, [&](const PassJob &p, const uint64_t *x, uint64_t flags) {
+                for (int i = 0; i < p.P.batch; ++i) {
+                    uint64_t *out = counts + 4 * (size_t)(p.offset + i);
+                    const uint64_t *xi = x + (size_t)i * (limbs + 1);
+                    for (int l = 0; l < 4; ++l) out[l] = l < limbs ? xi[l] : 0;
+                    bad[p.offset + i] = ((flags >> i) & 1) || xi[limbs] != 0;
+                }
+            });
+            if (rc) return rc;
+            for (int r = 0; r < ncol; ++r) exact[r] = bad[r] ? 0 : 1;
+            return SC_OK;
+        }
         rc = run_passes(c, passes, st, [&](const PassJob &p, const uint64_t *res) {
             unpack_pass(res, p.P.batch, c64.data() + p.offset, ovf.data() + p.offset);
         });

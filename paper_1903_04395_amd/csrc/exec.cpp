@@ -377,6 +377,71 @@ int run_passes(sc_ctx *c, std::vector<PassJob> &passes, hipStream_t st,
     return SC_OK;
 }
 
+bool single_chain(const Plan &P) {
+    return P.steps.size() >= 2 && P.chains.size() == 1 && P.chains[0].first == 0 &&
+           P.chains[0].last == (int)P.steps.size() - 1 && P.steps[0].a == 1;
+}
+
+int run_wide_passes(sc_ctx *c, std::vector<PassJob> &passes, int limbs, hipStream_t st,
+                    const std::function<void(const PassJob &, const uint64_t *, uint64_t)> &done) {
+    int rc;
+    const size_t words = (size_t)SC_MAX_BATCH * (limbs + 1) + 1;          // sums, then the flag word
+    if ((rc = host_staging(c, std::max<size_t>(1, passes.size()) * (words + 2)))) return rc;
+    PassBuffers &b = c->main;
+    for (size_t i = 0; i < passes.size(); ++i) {
+        PassJob &pj = passes[i];
+        Graph &g = *c->graphs[pj.gid];
+        // the interleave whose two widest rows of `limbs` limbs fit the LDS limit
+        const int k1 = pj.k - 1;
+        const int wmax = pj.P.chains.empty() ? 0 : pj.P.chains[0].wmax;
+        int bi = pj.P.interleave;
+        while (bi > 1 && kern::chain_wide_lds_bytes(k1, wmax, bi, limbs) > pj.P.opts.lds_max) bi /= 2;
+        if (bi != pj.P.interleave) {
+            ExecOpts o = pj.P.opts;
+            o.interleave = bi;
+            Plan P2;
+            if ((rc = make_plan(c, g, *c->tmpls[pj.tid], o, pj.k, pj.P.batch, P2))) return rc;
+            pj.P = std::move(P2);
+        }
+        const Plan &P = pj.P;
+        if (!single_chain(P)) return fail(c, SC_EINVAL, "the exact multi-limb pass needs a single-chain plan");
+        PassSpec sp;
+        sp.g = &g; sp.P = &P; sp.k = pj.k; sp.seed = pj.seed; sp.first = pj.first;
+        if ((rc = prepare_pass(c, sp, b, st))) return rc;
+        const uint64_t W = binom(pj.k - 1, P.steps.back().h - 1);
+        if ((rc = ensure(c, c->wide_tab, (size_t)g.n_rows * W * P.batch * limbs * 8, st))) return rc;
+        if ((rc = ensure(c, c->wide_x, words * 8, st))) return rc;
+        auto *X = (unsigned long long *)c->wide_x.p;
+        auto *flags = X + (size_t)SC_MAX_BATCH * (limbs + 1);
+        uint64_t *stage = c->host_out + i * (words + 2);
+        stage[0] = pj.seed;
+        stage[1] = pj.first;
+        HIPCHK(c, hipMemcpyAsync(b.desc.p, stage, 2 * sizeof(uint64_t), hipMemcpyHostToDevice, st));
+        HIPCHK(c, kern::launch_zero_u64((uint64_t *)X, (int64_t)words, st));
+        auto *col = (uint8_t *)b.colbuf.p;
+        HIPCHK(c, kern::launch_color((const uint64_t *)b.desc.p, g.n_rows, P.batch, pj.k, (const int32_t *)g.perm.p,
+                                     col, st));
+        const kern::GraphBins bins = bins_of(g);
+        kern::ChainShape cs;
+        if ((rc = chain_args(c, P, P.chains[0], 0, cs, nullptr))) return rc;
+        kern::StepShape sh;
+        kern::StepTables tb;
+        if ((rc = step_args(c, P, P.steps[0], 0, sh, tb))) return rc;
+        if (g.n_split) HIPCHK(c, kern::launch_dp_split(bins, sh, tb, col, nullptr, (uint64_t *)b.npre.p, flags, st));
+        auto *S = (uint64_t *)c->wide_tab.p;
+        HIPCHK(c, kern::launch_dp_chain_wide(bins, cs, limbs, col, (const uint64_t *)b.npre.p, S, flags,
+                                             P.opts.wave_row_max, st));
+        HIPCHK(c, kern::launch_reduce_wide(g.n_rows, S, (int)W, P.batch, P.interleave, limbs, X, st));
+        HIPCHK(c, hipMemcpyAsync(stage + 2, X, words * 8, hipMemcpyDeviceToHost, st));
+    }
+    HIPCHK(c, hipStreamSynchronize(st));
+    for (size_t i = 0; i < passes.size(); ++i) {
+        const uint64_t *stage = c->host_out + i * (words + 2) + 2;
+        done(passes[i], stage, stage[(size_t)SC_MAX_BATCH * (limbs + 1)]);
+    }
+    return SC_OK;
+}
+
 int check_coloring_range(sc_ctx *c, uint64_t first, int64_t n) {
     if (n < 0 || first > SC_MAX_COLORING || (uint64_t)n > SC_MAX_COLORING - first)
         return fail(c, SC_EINVAL, "colourings %llu..%llu+%lld reach past 2^24, where the colouring rule repeats",

@@ -101,6 +101,19 @@ hipError_t launch_dp_chain(const GraphBins &g, const ChainShape &c, const uint8_
                            const uint64_t *Npre, uint64_t *S, unsigned long long *flags, int wave_row_max,
                            hipStream_t st);
 
+// Exact counts of a template that is one chain from a single vertex (the
+// star rooted at its centre; a0 = 1), every entry kept as `limbs` (2..4)
+// little-endian 64-bit limbs: the chain's last output to S (entry (v, j, r)
+// limb l at (((plane*n + v)*W + j)*Bi + ri)*limbs + l); a carry out of the top
+// limb sets the colouring's flag.  launch_reduce_wide adds colouring r's n*W
+// entries into X[r][0..limbs] (limbs + 1 words, which must start at zero).
+int chain_wide_lds_bytes(int k1, int wmax, int bi, int limbs, int teams = 1);
+hipError_t launch_dp_chain_wide(const GraphBins &g, const ChainShape &c, int limbs, const uint8_t *col,
+                                const uint64_t *Npre, uint64_t *S, unsigned long long *flags, int wave_row_max,
+                                hipStream_t st);
+hipError_t launch_reduce_wide(int64_t n, const uint64_t *S, int W, int B, int Bi, int limbs,
+                              unsigned long long *X, hipStream_t st);
+
 // col[v*B + r] = colour of vertex v in colouring first+r (SplitMix64 rule),
 // drawn from the original id perm[v] when the graph was relabelled (perm != NULL);
 // desc[0] = seed and desc[1] = first live in device memory.

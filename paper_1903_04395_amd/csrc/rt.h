@@ -132,6 +132,7 @@ struct sc_ctx {
     int next_graph = 1, next_tmpl = 1;
     std::map<sc::TableKey, sc::DevMem> split_tabs, unrank_tabs, rank_tabs;
     sc::PassBuffers main;                 // buffers of the synchronous calls
+    sc::DevMem wide_tab, wide_x;          // exact multi-limb chain passes: output table, sums
     uint64_t *host_out = nullptr;         // pinned staging for results and descriptors
     size_t host_out_words = 0;
     std::map<sc::GraphExecKey, hipGraphExec_t> graph_cache;
@@ -233,6 +234,15 @@ struct PassJob {
 // SC_MAX_BATCH + 1 result words) for each.
 int run_passes(sc_ctx *c, std::vector<PassJob> &passes, hipStream_t st,
                const std::function<void(const PassJob &, const uint64_t *)> &done);
+// Whether plan P is one chain from a single vertex covering every step (a
+// star rooted at its centre), which the exact multi-limb kernels run.
+bool single_chain(const Plan &P);
+// Exact multi-limb counts (limbs 2..4) of the colourings of passes with a
+// single-chain plan: each count's limbs (limbs + 1 words per colouring, the
+// last the carry beyond) and a per-colouring flag set when a carry left the
+// top limb; waits for `st`.
+int run_wide_passes(sc_ctx *c, std::vector<PassJob> &passes, int limbs, hipStream_t st,
+                    const std::function<void(const PassJob &, const uint64_t *, uint64_t)> &done);
 // SC_EINVAL unless colourings first..first+n-1 all lie below SC_MAX_COLORING.
 int check_coloring_range(sc_ctx *c, uint64_t first, int64_t n);
 // Splits n colourings of one job into passes of the planned batch.

@@ -310,6 +310,7 @@ int sc_destroy(sc_ctx *c) {
     for (auto &kv : c->rank_tabs) dev_free(c, kv.second);
     PassBuffers &b = c->main;
     dev_free(c, b.arena); dev_free(c, b.colbuf); dev_free(c, b.xbuf); dev_free(c, b.npre); dev_free(c, b.desc);
+    dev_free(c, c->wide_tab); dev_free(c, c->wide_x);
     if (c->host_out) (void)hipHostFree(c->host_out);
     for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
     (void)hipStreamDestroy(c->stream);

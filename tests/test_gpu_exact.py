@@ -233,3 +233,70 @@ def test_exact_counts_replayed_from_captured_graphs(ctx):
         ctx.set_option(sc.SC_OPT_GRAPH, sc.OPTION_DEFAULTS[sc.SC_OPT_GRAPH])
     assert max(eager[0]) >= 2**64
     ctx.unload_graph(gid)
+
+
+def star_closed_form(g, col, k):
+    """Colourful maps of the k-vertex star (k colours) into g for one colouring:
+    (k-1)! * the sum over centres v of the product, over the k-1 colours other
+    than col(v), of the number of v's neighbours with that colour (exact)."""
+    src = np.repeat(np.arange(g.n, dtype=np.int64), np.diff(g.row_ptr))
+    cnt = np.bincount(src * k + col[g.col_idx].astype(np.int64), minlength=g.n * k).reshape(g.n, k)
+    cnt[np.arange(g.n), col] = 1
+    rows = cnt[cnt.min(axis=1) > 0]
+    return math.factorial(k - 1) * sum(math.prod(r) for r in rows.tolist())
+
+
+# (name, n, hub degree, limbs the homomorphism bound asks for, interleave option, colourings)
+WIDE_STAR_CASES = [
+    ("two_limbs", 1500, 900, 2, 0, 5),
+    ("three_limbs", 6000, 4000, 3, 0, 9),
+    ("three_limbs_bi2", 6000, 4000, 3, 2, 4),
+    ("four_limbs", 200000, 190000, 4, 0, 3),
+]
+
+
+@pytest.mark.parametrize("case", WIDE_STAR_CASES, ids=[c[0] for c in WIDE_STAR_CASES])
+def test_exact_star_multi_limb_against_closed_form(ctx, case):
+    """The 12-star rooted at its centre takes one pass whose entries carry as
+    many 64-bit limbs as the homomorphism bound asks for: its counts against
+    the star closed form, and (where three primes certify them) against the
+    residue passes with chains switched off."""
+    name, n, hub_deg, limbs, bi, R = case
+    k, t, seed, first = 12, 12, 31, 1
+    g = hubby_graph(17, n=n, m=2 * n, hubs=2, hub_deg=hub_deg)
+    if bi:
+        ctx.set_option(sc.SC_OPT_INTERLEAVE, bi)
+    try:
+        gid, tid, info = setup(ctx, g, t, I.star(t), k, seed, R, 0)
+        say(f"wide star {name}: n={g.n} nnz={g.nnz} R={R} batch={info.batch}")
+        counts, exact, hom, _, _ = ctx.run_exact(gid, tid, first, R)
+        assert exact.all()
+        want = [star_closed_form(g, O.colors(seed, first + r, g.n, k), k) for r in range(R)]
+        assert counts == want
+        assert 2 ** (64 * (limbs - 1)) <= hom * (1 + 2**-10) < 2 ** (64 * limbs)
+        assert max(want) <= hom
+        if hom * (1 + 2**-10) < 2**247:
+            ctx.set_option(sc.SC_OPT_CHAIN, 0)
+            try:
+                c2, e2, _, _, _ = ctx.run_exact(gid, tid, first, R)
+            finally:
+                ctx.set_option(sc.SC_OPT_CHAIN, sc.OPTION_DEFAULTS[sc.SC_OPT_CHAIN])
+            assert e2.all() and c2 == want
+        ctx.unload_graph(gid)
+    finally:
+        if bi:
+            ctx.set_option(sc.SC_OPT_INTERLEAVE, sc.OPTION_DEFAULTS[sc.SC_OPT_INTERLEAVE])
+
+
+def test_exact_star_smaller_k_and_t(ctx):
+    """A 9-star with k = 11 colours (k > t): the last step keeps binom(10, 8)
+    entries per row, each of two limbs."""
+    g = hubby_graph(23, n=3000, m=6000, hubs=3, hub_deg=2500)
+    k, t, seed, R = 11, 9, 5, 6
+    gid, tid, info = setup(ctx, g, t, I.star(t), k, seed, R, 0)
+    say(f"wide star k>t: n={g.n} nnz={g.nnz} R={R} batch={info.batch}")
+    counts, exact, hom, _, _ = ctx.run_exact(gid, tid, 0, R)
+    want = O.count_exact(g, t, (info.root, info.children()), k, seed, 0, R)
+    assert exact.all() and counts == want
+    assert max(want) >= 2**64
+    ctx.unload_graph(gid)
