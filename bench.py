@@ -53,6 +53,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip sc_autotune of both templates before the timed region")
+    ap.add_argument("--tune-save", default=None, help="write the autotuner's picks to this file (sc_tune_save)")
+    ap.add_argument("--tune-load", default=None,
+                    help="load tuning from this file (sc_tune_load) instead of running the autotuner")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the side measurements (RMAT-20 workload, plain vs batched, exact counts)")
     ap.add_argument("--opt", action="append", default=[], help="libsc option NUM=VALUE (ablation)")
@@ -641,13 +644,19 @@ def main():
     tmpls, infos, plans, tuned = {}, {}, {}, {}
     upd = 0.0
     for name, t, edges, root in templates():
-        tid = ctx.load_template(t, edges, root)
-        if not args.no_autotune:                     # untimed: the autotuner's real passes
+        tmpls[name] = ctx.load_template(t, edges, root)
+    if args.tune_load:
+        print(f"[bench] loaded {ctx.tune_load(args.tune_load)} tuning entries", file=sys.stderr, flush=True)
+    for name, tid in tmpls.items():
+        if not args.no_autotune and not args.tune_load:   # untimed: the autotuner's real passes
             tt = time.time()
             tuned[name] = ctx.autotune(gid, tid, R_STEP)
             print(f"[bench] {name}: autotuned {tuned[name]} in {time.time() - tt:.0f}s", file=sys.stderr, flush=True)
         info = ctx.plan_info(gid, tid, R_STEP)
-        tmpls[name], infos[name], plans[name] = tid, info, info.steps()
+        infos[name], plans[name] = info, info.steps()
+    if args.tune_save:
+        ctx.tune_save(args.tune_save)
+    for name, info in infos.items():
         upd += (info.spmm_updates + info.ema_updates) * R_STEP
         print(f"[bench] {name}: root={info.root} steps={info.steps()} batch={info.batch} "
               f"interleave={info.interleave} arena={info.arena_bytes / 1e9:.1f} GB", file=sys.stderr, flush=True)

@@ -75,32 +75,48 @@ int run_mod(sc_ctx *c, int gid, int tid, uint64_t first, int n, uint64_t mod, hi
 
 // Homomorphisms of the template into the graph, in double, by the plan's
 // steps on one value per vertex (an upper bound on the colourful maps of any
-// colouring).
-int hom_count(sc_ctx *c, int gid, int tid, hipStream_t st, double *out) {
+// colouring).  step_max (optional): per step of the plan, its (h, a, p) and
+// the largest value at any vertex (a bound on every entry of that step's
+// table in any colouring).
+struct StepBound {
+    int h, a, p;
+    double max;
+};
+int hom_count(sc_ctx *c, int gid, int tid, hipStream_t st, double *out, std::vector<StepBound> *step_max = nullptr) {
     Plan P;
     int rc = pick_batch(c, gid, tid, c->k, 1, 0, P);
     if (rc) return rc;
     Graph &g = *c->graphs[gid];
+    if (step_max) step_max->clear();
     if (P.steps.empty()) { *out = (double)g.n; return SC_OK; }
     if (g.n_rows == 0) { *out = 0; return SC_OK; }
     if ((rc = rebin(c, g, default_segment(c)))) return rc;
     const int64_t n = g.n_rows;
+    const size_t ns = P.steps.size(), head = 1 + ns;       // the sum, then the step maxima
     DevMem tmp;
-    if ((rc = dev_alloc(c, tmp, (P.bufs.size() * (size_t)n + 1) * sizeof(double), st))) return rc;
+    if ((rc = dev_alloc(c, tmp, (P.bufs.size() * (size_t)n + head) * sizeof(double), st))) return rc;
     double *base = (double *)tmp.p;
-    auto hb = [&](int id) { return id < 0 ? (double *)nullptr : base + 1 + (size_t)id * n; };
+    auto hb = [&](int id) { return id < 0 ? (double *)nullptr : base + head + (size_t)id * n; };
     const kern::GraphBins bins = bins_of(g);
-    hipError_t e = kern::launch_zero_u64((uint64_t *)base, 1, st);
+    hipError_t e = kern::launch_zero_u64((uint64_t *)base, (int64_t)head, st);
     const Step *last = nullptr;
-    for (const Step &s : P.steps) {
-        if (e != hipSuccess) break;
-        e = kern::launch_hom_step(bins, hb(s.buf_a), hb(s.buf_p), hb(s.buf_s), st);
+    for (size_t i = 0; i < ns; ++i) {
+        const Step &s = P.steps[i];
+        if (e == hipSuccess) e = kern::launch_hom_step(bins, hb(s.buf_a), hb(s.buf_p), hb(s.buf_s), st);
+        if (e == hipSuccess && step_max) e = kern::launch_hom_max(n, hb(s.buf_s), base + 1 + i, st);
         last = &s;
     }
+    std::vector<double> host(head);
     if (e == hipSuccess) e = kern::launch_hom_sum(n, hb(last->buf_s), base, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(out, base, sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(host.data(), base, head * sizeof(double), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     dev_free(c, tmp);
+    if (e == hipSuccess) {
+        *out = host[0];
+        if (step_max)
+            for (size_t i = 0; i < ns; ++i)
+                step_max->push_back({P.steps[i].h, P.steps[i].a, P.steps[i].p, host[1 + i]});
+    }
     if (e != hipSuccess) return fail(c, SC_EDEVICE, "homomorphism count failed: %s", hipGetErrorString(e));
     return SC_OK;
 }
@@ -121,6 +137,44 @@ int primes_for(double H) {
     return 3;
 }
 
+
+// Limbs of 64 bits that hold every value up to the bound x (with the
+// homomorphism count's margin); 5 if four do not.
+int limbs_for(double x) {
+    int l = 1;
+    while (l <= 4 && !(x * kHomSlack < std::ldexp(1.0, 64 * l))) ++l;
+    return l;
+}
+
+// Per step of a single-chain plan, the limbs its entries keep in the exact
+// multi-limb pass: step i's bound (the largest homomorphism count of its
+// sub-template at any vertex), never fewer than the step before, the colour
+// counts of step 0 in one, and the last step at least what the total bound H
+// asks for, so that the root sums fit.  Empty when that pass does not apply:
+// H below 2^64 (the uint64 pass is exact), a bound past four limbs, rows too
+// wide for the LDS limit, or bounds that do not match the plan's steps.
+std::vector<int> chain_limbs(double H, const std::vector<StepBound> &bounds, const std::vector<PassJob> &passes) {
+    const int total = limbs_for(H);
+    if (total < 2 || total > 4 || passes.empty()) return {};
+    const Plan &P = passes[0].P;
+    if (bounds.size() != P.steps.size()) return {};
+    std::vector<int> limbs(P.steps.size());
+    for (size_t i = 0; i < limbs.size(); ++i) {
+        const Step &s = P.steps[i];
+        if (bounds[i].h != s.h || bounds[i].a != s.a || bounds[i].p != s.p) return {};
+        limbs[i] = i == 0 ? 1 : std::max(limbs[i - 1], limbs_for(bounds[i].max));
+        if (limbs[i] > 4) return {};
+    }
+    limbs.back() = std::max(limbs.back(), total);
+    for (const PassJob &p : passes) {
+        if (p.P.steps.size() != limbs.size()) return {};
+        int wrow = 0;                       // the widest intermediate row, in words per colouring
+        for (size_t i = 1; i + 1 < limbs.size(); ++i)
+            wrow = std::max(wrow, (int)binom(p.k - 1, p.P.steps[i].h - 1) * limbs[i]);
+        if (kern::chain_wide_lds_bytes(p.k - 1, wrow, 1) > p.P.opts.lds_max) return {};
+    }
+    return limbs;
+}
 
 // Count of four little-endian limbs as a long double.
 long double limbs_value(const uint64_t *l) {
@@ -147,23 +201,18 @@ int exact_counts(sc_ctx *c, int gid, int tid, uint64_t first, int ncol, hipStrea
         // 64-bit limbs as the homomorphism bound asks for
         bool chains = !passes.empty();
         for (const PassJob &p : passes) chains &= single_chain(p.P);
-        if (chains && std::isnan(*H) && (rc = hom_count(c, gid, tid, st, H))) return rc;
-        int limbs = 0;
-        if (chains && !(*H * kHomSlack < 0x1p64))
-            for (int l = 2; l <= 4 && !limbs; ++l)
-                if (*H * kHomSlack < std::ldexp(1.0, 64 * l)) limbs = l;
-        // the two widest rows of one colouring must fit the LDS limit
-        for (const PassJob &p : passes)
-            if (limbs && kern::chain_wide_lds_bytes(p.k - 1, p.P.chains[0].wmax, 1, limbs) > p.P.opts.lds_max)
-                limbs = 0;
-        if (limbs) {
+        std::vector<StepBound> bounds;
+        if (chains && (rc = hom_count(c, gid, tid, st, H, &bounds))) return rc;
+        const std::vector<int> limbs = chains ? chain_limbs(*H, bounds, passes) : std::vector<int>();
+        if (!limbs.empty()) {
+            const int L = limbs.back();
             std::vector<uint8_t> bad((size_t)ncol);
             rc = run_wide_passes(c, passes, limbs, st, [&](const PassJob &p, const uint64_t *x, uint64_t flags) {
                 for (int i = 0; i < p.P.batch; ++i) {
                     uint64_t *out = counts + 4 * (size_t)(p.offset + i);
-                    const uint64_t *xi = x + (size_t)i * (limbs + 1);
-                    for (int l = 0; l < 4; ++l) out[l] = l < limbs ? xi[l] : 0;
-                    bad[p.offset + i] = ((flags >> i) & 1) || xi[limbs] != 0;
+                    const uint64_t *xi = x + (size_t)i * (L + 1);
+                    for (int l = 0; l < 4; ++l) out[l] = l < L ? xi[l] : 0;
+                    bad[p.offset + i] = ((flags >> i) & 1) || xi[L] != 0;
                 }
             });
             if (rc) return rc;

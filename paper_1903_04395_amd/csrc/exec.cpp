@@ -382,20 +382,26 @@ bool single_chain(const Plan &P) {
            P.chains[0].last == (int)P.steps.size() - 1 && P.steps[0].a == 1;
 }
 
-int run_wide_passes(sc_ctx *c, std::vector<PassJob> &passes, int limbs, hipStream_t st,
+int run_wide_passes(sc_ctx *c, std::vector<PassJob> &passes, const std::vector<int> &limbs, hipStream_t st,
                     const std::function<void(const PassJob &, const uint64_t *, uint64_t)> &done) {
     int rc;
-    const size_t words = (size_t)SC_MAX_BATCH * (limbs + 1) + 1;          // sums, then the flag word
+    if (limbs.empty()) return fail(c, SC_EINVAL, "no limbs for the exact multi-limb pass");
+    const int L = limbs.back();
+    const size_t words = (size_t)SC_MAX_BATCH * (L + 1) + 1;          // sums, then the flag word
     if ((rc = host_staging(c, std::max<size_t>(1, passes.size()) * (words + 2)))) return rc;
     PassBuffers &b = c->main;
     for (size_t i = 0; i < passes.size(); ++i) {
         PassJob &pj = passes[i];
         Graph &g = *c->graphs[pj.gid];
-        // the interleave whose two widest rows of `limbs` limbs fit the LDS limit
+        if (pj.P.steps.size() != limbs.size())
+            return fail(c, SC_EINVAL, "limbs given for %zu steps, the plan has %zu", limbs.size(), pj.P.steps.size());
+        // the interleave whose two widest intermediate rows fit the LDS limit
         const int k1 = pj.k - 1;
-        const int wmax = pj.P.chains.empty() ? 0 : pj.P.chains[0].wmax;
+        int wrow = 0;
+        for (size_t j = 1; j + 1 < limbs.size(); ++j)
+            wrow = std::max(wrow, (int)binom(k1, pj.P.steps[j].h - 1) * limbs[j]);
         int bi = pj.P.interleave;
-        while (bi > 1 && kern::chain_wide_lds_bytes(k1, wmax, bi, limbs) > pj.P.opts.lds_max) bi /= 2;
+        while (bi > 1 && kern::chain_wide_lds_bytes(k1, wrow, bi) > pj.P.opts.lds_max) bi /= 2;
         if (bi != pj.P.interleave) {
             ExecOpts o = pj.P.opts;
             o.interleave = bi;
@@ -409,10 +415,10 @@ int run_wide_passes(sc_ctx *c, std::vector<PassJob> &passes, int limbs, hipStrea
         sp.g = &g; sp.P = &P; sp.k = pj.k; sp.seed = pj.seed; sp.first = pj.first;
         if ((rc = prepare_pass(c, sp, b, st))) return rc;
         const uint64_t W = binom(pj.k - 1, P.steps.back().h - 1);
-        if ((rc = ensure(c, c->wide_tab, (size_t)g.n_rows * W * P.batch * limbs * 8, st))) return rc;
+        if ((rc = ensure(c, c->wide_tab, (size_t)g.n_rows * W * P.batch * L * 8, st))) return rc;
         if ((rc = ensure(c, c->wide_x, words * 8, st))) return rc;
         auto *X = (unsigned long long *)c->wide_x.p;
-        auto *flags = X + (size_t)SC_MAX_BATCH * (limbs + 1);
+        auto *flags = X + (size_t)SC_MAX_BATCH * (L + 1);
         uint64_t *stage = c->host_out + i * (words + 2);
         stage[0] = pj.seed;
         stage[1] = pj.first;
@@ -429,15 +435,15 @@ int run_wide_passes(sc_ctx *c, std::vector<PassJob> &passes, int limbs, hipStrea
         if ((rc = step_args(c, P, P.steps[0], 0, sh, tb))) return rc;
         if (g.n_split) HIPCHK(c, kern::launch_dp_split(bins, sh, tb, col, nullptr, (uint64_t *)b.npre.p, flags, st));
         auto *S = (uint64_t *)c->wide_tab.p;
-        HIPCHK(c, kern::launch_dp_chain_wide(bins, cs, limbs, col, (const uint64_t *)b.npre.p, S, flags,
+        HIPCHK(c, kern::launch_dp_chain_wide(bins, cs, limbs.data(), col, (const uint64_t *)b.npre.p, S, flags,
                                              P.opts.wave_row_max, st));
-        HIPCHK(c, kern::launch_reduce_wide(g.n_rows, S, (int)W, P.batch, P.interleave, limbs, X, st));
+        HIPCHK(c, kern::launch_reduce_wide(g.n_rows, S, (int)W, P.batch, P.interleave, L, X, st));
         HIPCHK(c, hipMemcpyAsync(stage + 2, X, words * 8, hipMemcpyDeviceToHost, st));
     }
     HIPCHK(c, hipStreamSynchronize(st));
     for (size_t i = 0; i < passes.size(); ++i) {
         const uint64_t *stage = c->host_out + i * (words + 2) + 2;
-        done(passes[i], stage, stage[(size_t)SC_MAX_BATCH * (limbs + 1)]);
+        done(passes[i], stage, stage[(size_t)SC_MAX_BATCH * (L + 1)]);
     }
     return SC_OK;
 }

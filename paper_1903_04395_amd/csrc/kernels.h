@@ -102,13 +102,18 @@ hipError_t launch_dp_chain(const GraphBins &g, const ChainShape &c, const uint8_
                            hipStream_t st);
 
 // Exact counts of a template that is one chain from a single vertex (the
-// star rooted at its centre; a0 = 1), every entry kept as `limbs` (2..4)
-// little-endian 64-bit limbs: the chain's last output to S (entry (v, j, r)
-// limb l at (((plane*n + v)*W + j)*Bi + ri)*limbs + l); a carry out of the top
-// limb sets the colouring's flag.  launch_reduce_wide adds colouring r's n*W
-// entries into X[r][0..limbs] (limbs + 1 words, which must start at zero).
-int chain_wide_lds_bytes(int k1, int wmax, int bi, int limbs, int teams = 1);
-hipError_t launch_dp_chain_wide(const GraphBins &g, const ChainShape &c, int limbs, const uint8_t *col,
+// star rooted at its centre; a0 = 1), step i's entries kept as limbs[i]
+// (1..4, limbs[0] = 1, non-decreasing) little-endian 64-bit limbs: the
+// chain's last output to S (entry (v, j, r) limb l at
+// (((plane*n + v)*W + j)*Bi + ri)*L + l, L the last step's limbs); a carry out
+// of a step's top limb sets the colouring's flag.  chain_wide_row_words is
+// the widest intermediate row (entries times limbs) per colouring, which
+// chain_wide_lds_bytes takes.  launch_reduce_wide adds colouring r's n*W
+// entries of `limbs` limbs into X[r][0..limbs] (limbs + 1 words, which must
+// start at zero).
+int chain_wide_row_words(const ChainShape &cs, const int *limbs);
+int chain_wide_lds_bytes(int k1, int row_words, int bi, int teams = 1);
+hipError_t launch_dp_chain_wide(const GraphBins &g, const ChainShape &c, const int *limbs, const uint8_t *col,
                                 const uint64_t *Npre, uint64_t *S, unsigned long long *flags, int wave_row_max,
                                 hipStream_t st);
 hipError_t launch_reduce_wide(int64_t n, const uint64_t *S, int W, int B, int Bi, int limbs,
@@ -150,6 +155,8 @@ bool mod_supported(uint64_t p);
 // ones).  launch_hom_sum adds the sum of S[0..n) into *out.
 hipError_t launch_hom_step(const GraphBins &g, const double *A, const double *P, double *S, hipStream_t st);
 hipError_t launch_hom_sum(int64_t n, const double *S, double *out, hipStream_t st);
+// *out = max(*out, the largest of S[0..n)) (S >= 0; *out must start at a value >= 0).
+hipError_t launch_hom_max(int64_t n, const double *S, double *out, hipStream_t st);
 
 hipError_t launch_zero_u64(uint64_t *p, int64_t count, hipStream_t st);
 

@@ -682,6 +682,7 @@ __global__ __launch_bounds__(TPB) void dp_split_kernel(DpArgs a) {
 struct ChainStepArgs {
     const uint32_t *split;        // a >= 2: the (k-1, h-1, a-1) split table
     int Wh, nsplit, eg, lg_eg;
+    int lin, lout;                // exact multi-limb chain: limbs of the step's input and output rows
 };
 
 struct ChainArgs {
@@ -809,36 +810,41 @@ __global__ __launch_bounds__(TPB) void dp_chain_kernel(ChainArgs c) {
     flush_flags(m, a.flags);
 }
 
-// ------------------------------------------------------------------ exact multi-limb chains
+// Exact counts of a template that is one chain from a single vertex (a star
+// rooted at its centre): every entry is kept as little-endian 64-bit limbs,
+// so no count is reduced modulo anything.  A step's entries count colourful
+// maps of a sub-star rooted at the row's vertex, so the largest homomorphism
+// count of that sub-star at any vertex bounds them; each step keeps the
+// fewest limbs (1..4) that hold its bound, so early steps stay one word
+// wide.  A carry out of a step's top limb (impossible under the bounds) sets
+// the colouring's flag.
 
-// Exact counts of a template that is a single chain from one vertex (a star
-// rooted at its centre): every entry is kept as L little-endian 64-bit limbs,
-// so no count is reduced modulo anything.  The homomorphism count bounds every
-// entry (each entry counts colourful maps of a sub-star into the graph), and
-// L is chosen so that it stays below 2^(64 L); a carry out of the top limb
-// (impossible under that bound) sets the colouring's flag.
-
-// acc += x * y for an L-limb x and a 32-bit y; returns the carry out of the
-// top limb.
-template <int L>
-__device__ __forceinline__ uint64_t wide_mad_n32(uint64_t (&acc)[L], const uint64_t *x, uint32_t y) {
+// acc (LO limbs) += x (LI <= LO limbs) * y for a 32-bit y; returns the carry
+// out of the top limb.
+template <int LI, int LO>
+__device__ __forceinline__ uint64_t wide_mad_n32(uint64_t (&acc)[LO], const uint64_t *x, uint32_t y) {
     uint64_t carry = 0;
 #pragma unroll
-    for (int l = 0; l < L; ++l) {
+    for (int l = 0; l < LI; ++l) {
         const unsigned __int128 pr = (unsigned __int128)x[l] * y + carry;   // < 2^96 + 2^64
         const uint64_t lo = (uint64_t)pr;
         carry = (uint64_t)(pr >> 64);
         acc[l] += lo;
         carry += acc[l] < lo;
     }
+#pragma unroll
+    for (int l = LI; l < LO; ++l) {
+        acc[l] += carry;
+        carry = acc[l] < carry;
+    }
     return carry;
 }
 
-// One step of the exact chain: out[q] (L limbs) = the sum over the members x
-// of output set D of cur[D - {x}] * N'[x], with the pairs from the pair-major
-// split table; a group of eg lanes per entry meets through shuffles, limb by
-// limb with carries.
-template <int L>
+// One step of the exact chain: out[q] (LO limbs) = the sum over the members x
+// of output set D of cur[D - {x}] (LI limbs) * N'[x], with the pairs from the
+// pair-major split table; a group of eg lanes per entry meets through
+// shuffles, limb by limb with carries.
+template <int LI, int LO>
 __device__ __forceinline__ void chain_emit_wide(const Team &tm, const DpArgs &a, const ChainStepArgs &cs, int pl,
                                                 const uint64_t *cur, const uint64_t *Nl, uint64_t *out,
                                                 uint64_t &m) {
@@ -848,23 +854,23 @@ __device__ __forceinline__ void chain_emit_wide(const Team &tm, const DpArgs &a,
     for (int q0 = 0; q0 < Ls; q0 += per) {          // uniform over the team
         const int q = q0 + (tm.tid >> cs.lg_eg);
         const int D = q >> a.sh, ri = q & (a.Bi - 1);
-        uint64_t acc[L];
+        uint64_t acc[LO];
 #pragma unroll
-        for (int l = 0; l < L; ++l) acc[l] = 0;
+        for (int l = 0; l < LO; ++l) acc[l] = 0;
         uint64_t top = 0;
         if (q < Ls) {
             const uint32_t *sp = cs.split + D;
             for (int j = g; j < cs.nsplit; j += cs.eg) {
                 const uint32_t pr = sp[(int64_t)j * cs.Wh];
-                const uint64_t *xa = cur + (int64_t)(((pr & 0xffffu) << a.sh) + ri) * L;
+                const uint64_t *xa = cur + (int64_t)(((pr & 0xffffu) << a.sh) + ri) * LI;
                 const uint32_t yn = (uint32_t)Nl[((pr >> 16) << a.sh) + ri];
-                top |= wide_mad_n32<L>(acc, xa, yn);
+                top |= wide_mad_n32<LI, LO>(acc, xa, yn);
             }
         }
         for (int o = 1; o < cs.eg; o <<= 1) {
             uint64_t c = 0;
 #pragma unroll
-            for (int l = 0; l < L; ++l) {
+            for (int l = 0; l < LO; ++l) {
                 const uint64_t y = shfl_xor_u64(acc[l], o);
                 const uint64_t t = acc[l] + y;
                 const uint64_t c1 = t < y;
@@ -875,21 +881,30 @@ __device__ __forceinline__ void chain_emit_wide(const Team &tm, const DpArgs &a,
         }
         if (q < Ls && g == 0) {
 #pragma unroll
-            for (int l = 0; l < L; ++l) out[(int64_t)q * L + l] = acc[l];
+            for (int l = 0; l < LO; ++l) out[(int64_t)q * LO + l] = acc[l];
             if (top) m |= 1ull << (pl * a.Bi + ri);
         }
     }
 }
 
-// The exact chain kernel: as dp_chain_kernel for a0 = 1, the rows holding L
-// limbs per entry.  LDS per team: N' (k1 * Bi), then two rows of wmax * Bi * L.
-template <int L, bool WAVE, int TPB>
+template <int LI, int LO>
+__device__ __forceinline__ void chain_emit_wide_if(const Team &tm, const DpArgs &a, const ChainStepArgs &cs,
+                                                   int pl, const uint64_t *cur, const uint64_t *Nl, uint64_t *out,
+                                                   uint64_t &m) {
+    if (cs.lin == LI && cs.lout == LO) chain_emit_wide<LI, LO>(tm, a, cs, pl, cur, Nl, out, m);
+}
+
+// The exact chain kernel: as dp_chain_kernel for a0 = 1, step i's rows
+// holding st[i].lout limbs per entry (st[0]: the colour counts N', one limb).
+// LDS per team: N' (k1 * Bi), then two rows of wmax * Bi words (wmax: the
+// widest intermediate row in entries times limbs).
+template <bool WAVE, int TPB>
 __global__ __launch_bounds__(TPB) void dp_chain_wide_kernel(ChainArgs c) {
     constexpr int kTeams = WAVE ? TPB / kWave : 1;
     extern __shared__ uint64_t lds[];
     const DpArgs &a = c.d;
     const Team tm = WAVE ? wave_team() : block_team<TPB>();
-    const int Ln = c.k1 * a.Bi, Lw = c.wmax * a.Bi * L;
+    const int Ln = c.k1 * a.Bi, Lw = c.wmax * a.Bi;
     uint64_t *Nl = lds + (WAVE ? (int)(threadIdx.x >> 6) * (Ln + 2 * Lw) : 0);
     uint64_t *rows[2] = {Nl + Ln, Nl + Ln + Lw};
     const int64_t total = a.n * a.planes;
@@ -908,20 +923,24 @@ __global__ __launch_bounds__(TPB) void dp_chain_wide_kernel(ChainArgs c) {
         team_sync<WAVE>();
         if (sv < 0) count_colours(tm, a, v, pl, a.rp[v], a.rp[v + 1], Nl);
         team_sync<WAVE>();
-        // the first step's output is N' itself, widened to L limbs
-        for (int q = tm.tid; q < Ln; q += tm.size) {
-            rows[0][(int64_t)q * L] = Nl[q];
-#pragma unroll
-            for (int l = 1; l < L; ++l) rows[0][(int64_t)q * L + l] = 0;
-        }
-        team_sync<WAVE>();
-        const uint64_t *cur = rows[0];
-        int next = 1;
+        // the first step's output is N' itself (one limb)
+        const uint64_t *cur = Nl;
+        int next = 0;
         for (int i = 1; i < c.steps; ++i) {
             const ChainStepArgs &cs = c.st[i];
-            uint64_t *out = i == c.steps - 1 ? c.S + ((int64_t)pl * a.n + v) * (int64_t)(cs.Wh * a.Bi) * L
-                                             : rows[next];
-            chain_emit_wide<L>(tm, a, cs, pl, cur, Nl, out, m);
+            uint64_t *out = i == c.steps - 1
+                                ? c.S + ((int64_t)pl * a.n + v) * (int64_t)(cs.Wh * a.Bi) * cs.lout
+                                : rows[next];
+            chain_emit_wide_if<1, 1>(tm, a, cs, pl, cur, Nl, out, m);
+            chain_emit_wide_if<1, 2>(tm, a, cs, pl, cur, Nl, out, m);
+            chain_emit_wide_if<1, 3>(tm, a, cs, pl, cur, Nl, out, m);
+            chain_emit_wide_if<1, 4>(tm, a, cs, pl, cur, Nl, out, m);
+            chain_emit_wide_if<2, 2>(tm, a, cs, pl, cur, Nl, out, m);
+            chain_emit_wide_if<2, 3>(tm, a, cs, pl, cur, Nl, out, m);
+            chain_emit_wide_if<2, 4>(tm, a, cs, pl, cur, Nl, out, m);
+            chain_emit_wide_if<3, 3>(tm, a, cs, pl, cur, Nl, out, m);
+            chain_emit_wide_if<3, 4>(tm, a, cs, pl, cur, Nl, out, m);
+            chain_emit_wide_if<4, 4>(tm, a, cs, pl, cur, Nl, out, m);
             team_sync<WAVE>();
             cur = out;
             next ^= 1;
@@ -1085,6 +1104,23 @@ __global__ __launch_bounds__(kBlock) void hom_sum_kernel(int64_t n, const double
         __syncthreads();
     }
     if (threadIdx.x == 0) atomicAdd(out, part[0]);
+}
+
+// The largest of S[0..n) into *out; non-negative doubles order as their bit
+// patterns, so the blocks meet in an unsigned 64-bit atomic max.
+__global__ __launch_bounds__(kBlock) void hom_max_kernel(int64_t n, const double *__restrict__ S,
+                                                        unsigned long long *__restrict__ out) {
+    __shared__ double part[kBlock];
+    double acc = 0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        acc = fmax(acc, S[i]);
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) part[threadIdx.x] = fmax(part[threadIdx.x], part[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax(out, (unsigned long long)__double_as_longlong(part[0]));
 }
 
 // ------------------------------------------------------------------ vector-ALU roof
@@ -1396,54 +1432,54 @@ hipError_t launch_dp_chain(const GraphBins &g, const ChainShape &cs, const uint8
     return cs.mod ? chain_launch<false, true, kBlock>(c, lds, st) : chain_launch<false, false, kBlock>(c, lds, st);
 }
 
-int chain_wide_lds_bytes(int k1, int wmax, int bi, int limbs, int teams) {
-    int64_t bytes = 8LL * bi * (k1 + 2LL * wmax * limbs) * teams;
+int chain_wide_row_words(const ChainShape &cs, const int *limbs) {
+    int w = 0;
+    for (int i = 1; i + 1 < cs.steps; ++i) w = std::max(w, cs.Wh[i] * limbs[i]);
+    return w;
+}
+
+int chain_wide_lds_bytes(int k1, int row_words, int bi, int teams) {
+    int64_t bytes = 8LL * bi * (k1 + 2LL * row_words) * teams;
     bytes = (bytes + 15) & ~15LL;
     return bytes > (1 << 30) ? (1 << 30) : (int)bytes;
 }
 
 namespace {
 
-template <int L, bool WAVE, int TPB>
+template <bool WAVE, int TPB>
 hipError_t chain_wide_launch(const ChainArgs &c, int lds, hipStream_t st) {
-    hipError_t e = allow_lds(dp_chain_wide_kernel<L, WAVE, TPB>, lds);
+    hipError_t e = allow_lds(dp_chain_wide_kernel<WAVE, TPB>, lds);
     if (e != hipSuccess) return e;
     const int64_t teams = WAVE ? TPB / kWave : 1;
     const int64_t blocks =
         std::min<int64_t>((c.d.n * c.d.planes + teams - 1) / teams, 2 * resident_blocks(lds, TPB));
-    name_kernel("dp_chain_wide_kernel<%d, %s, %d>", L, tf(WAVE), TPB);
-    dp_chain_wide_kernel<L, WAVE, TPB><<<dim3((unsigned)blocks), dim3(TPB), lds, st>>>(c);
+    name_kernel("dp_chain_wide_kernel<%s, %d>", tf(WAVE), TPB);
+    dp_chain_wide_kernel<WAVE, TPB><<<dim3((unsigned)blocks), dim3(TPB), lds, st>>>(c);
     return hipGetLastError();
-}
-
-template <int L>
-hipError_t chain_wide_dispatch(const ChainArgs &c, bool wave, int tpb, int lds, hipStream_t st) {
-    if (wave) return chain_wide_launch<L, true, kBlock>(c, lds, st);
-    if (tpb == kBlockWide) return chain_wide_launch<L, false, kBlockWide>(c, lds, st);
-    return chain_wide_launch<L, false, kBlock>(c, lds, st);
 }
 
 }  // namespace
 
-hipError_t launch_dp_chain_wide(const GraphBins &g, const ChainShape &cs, int limbs, const uint8_t *col,
+hipError_t launch_dp_chain_wide(const GraphBins &g, const ChainShape &cs, const int *limbs, const uint8_t *col,
                                 const uint64_t *Npre, uint64_t *S, unsigned long long *flags, int wave_row_max,
                                 hipStream_t st) {
     t_last_kernel[0] = 0;
     if (g.n <= 0) return hipSuccess;
     const int k1 = cs.k - 1;
-    if (limbs < 2 || limbs > 4 || cs.a0 != 1 || cs.steps < 2 || cs.steps > kMaxChainSteps ||
-        cs.steps + 1 > cs.k || cs.k > 16 || cs.Bi < 1 || cs.Bi > kWave || (cs.Bi & (cs.Bi - 1)) ||
-        cs.B % cs.Bi || !S || !col || (g.n_split && !Npre) || cs.mod)
+    if (!limbs || cs.a0 != 1 || cs.steps < 2 || cs.steps > kMaxChainSteps || cs.steps + 1 > cs.k || cs.k > 16 ||
+        cs.Bi < 1 || cs.Bi > kWave || (cs.Bi & (cs.Bi - 1)) || cs.B % cs.Bi || !S || !col ||
+        (g.n_split && !Npre) || cs.mod)
         return hipErrorInvalidValue;
-    ChainArgs c{};
+    if (limbs[0] != 1) return hipErrorInvalidValue;           // the colour counts N'
     for (int i = 1; i < cs.steps; ++i)
-        if (!cs.split[i] || cs.Wh[i] < 1 || cs.Wh[i] > cs.wmax || cs.nsplit[i] != 1 + i)
+        if (!cs.split[i] || cs.Wh[i] < 1 || cs.nsplit[i] != 1 + i || limbs[i] < limbs[i - 1] || limbs[i] > 4)
             return hipErrorInvalidValue;
-    if (cs.wmax < k1) return hipErrorInvalidValue;           // the widened first output row
-    const int region = chain_wide_lds_bytes(k1, cs.wmax, cs.Bi, limbs, 1);
+    ChainArgs c{};
+    const int wrow = chain_wide_row_words(cs, limbs);
+    const int region = chain_wide_lds_bytes(k1, wrow, cs.Bi, 1);
     const bool wave = region <= wave_row_max && g.n * (cs.B / cs.Bi) >= kWaveRowsMin;
     const int teams = wave ? kWaves : 1;
-    const int lds = chain_wide_lds_bytes(k1, cs.wmax, cs.Bi, limbs, teams);
+    const int lds = chain_wide_lds_bytes(k1, wrow, cs.Bi, teams);
     if (lds > kLdsPerCU) return hipErrorInvalidValue;
     const int tpb = !wave && lds > kWideLds ? kBlockWide : kBlock;
     DpArgs &a = c.d;
@@ -1453,12 +1489,13 @@ hipError_t launch_dp_chain_wide(const GraphBins &g, const ChainShape &cs, int li
     a.Npre = const_cast<uint64_t *>(Npre);
     a.slot = g.n_split ? g.slot : nullptr; a.n_split = g.n_split;
     a.flags = flags;
-    c.steps = cs.steps; c.a0 = 1; c.wmax = cs.wmax; c.k1 = k1; c.Wa0 = 1;
+    c.steps = cs.steps; c.a0 = 1; c.wmax = wrow; c.k1 = k1; c.Wa0 = 1;
     c.S = S;
     const int threads = tpb / teams;
     for (int i = 0; i < cs.steps; ++i) {
         ChainStepArgs &x = c.st[i];
         x.split = cs.split[i]; x.Wh = cs.Wh[i]; x.nsplit = cs.nsplit[i];
+        x.lin = i ? limbs[i - 1] : 1; x.lout = limbs[i];
         x.eg = 1; x.lg_eg = 0;
         const int Ls = cs.Wh[i] * cs.Bi;
         int64_t best = -1;
@@ -1469,22 +1506,21 @@ hipError_t launch_dp_chain_wide(const GraphBins &g, const ChainShape &cs, int li
             if (best < 0 || chain < best) { best = chain; x.eg = G; x.lg_eg = lg; }
         }
     }
-    switch (limbs) {
-    case 2: return chain_wide_dispatch<2>(c, wave, tpb, lds, st);
-    case 3: return chain_wide_dispatch<3>(c, wave, tpb, lds, st);
-    default: return chain_wide_dispatch<4>(c, wave, tpb, lds, st);
-    }
+    if (wave) return chain_wide_launch<true, kBlock>(c, lds, st);
+    if (tpb == kBlockWide) return chain_wide_launch<false, kBlockWide>(c, lds, st);
+    return chain_wide_launch<false, kBlock>(c, lds, st);
 }
 
 hipError_t launch_reduce_wide(int64_t n, const uint64_t *S, int W, int B, int Bi, int limbs,
                               unsigned long long *X, hipStream_t st) {
     t_last_kernel[0] = 0;
     if (n <= 0 || B <= 0) return hipSuccess;
-    if (Bi < 1 || B % Bi || limbs < 2 || limbs > 4) return hipErrorInvalidValue;
+    if (Bi < 1 || B % Bi || limbs < 1 || limbs > 4) return hipErrorInvalidValue;
     const int64_t total = n * W;
     const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((total + kBlock - 1) / kBlock, 1024));
     name_kernel("reduce_wide_kernel<%d>", limbs);
-    if (limbs == 2) reduce_wide_kernel<2><<<dim3(blocks, (unsigned)B), dim3(kBlock), 0, st>>>(n, S, W, Bi, X);
+    if (limbs == 1) reduce_wide_kernel<1><<<dim3(blocks, (unsigned)B), dim3(kBlock), 0, st>>>(n, S, W, Bi, X);
+    else if (limbs == 2) reduce_wide_kernel<2><<<dim3(blocks, (unsigned)B), dim3(kBlock), 0, st>>>(n, S, W, Bi, X);
     else if (limbs == 3) reduce_wide_kernel<3><<<dim3(blocks, (unsigned)B), dim3(kBlock), 0, st>>>(n, S, W, Bi, X);
     else reduce_wide_kernel<4><<<dim3(blocks, (unsigned)B), dim3(kBlock), 0, st>>>(n, S, W, Bi, X);
     return hipGetLastError();
@@ -1602,6 +1638,13 @@ hipError_t launch_hom_sum(int64_t n, const double *S, double *out, hipStream_t s
     if (n <= 0) return hipSuccess;
     const int64_t blocks = std::min<int64_t>((n + kBlock - 1) / kBlock, 1024);
     hom_sum_kernel<<<dim3((unsigned)blocks), dim3(kBlock), 0, st>>>(n, S, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_hom_max(int64_t n, const double *S, double *out, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((n + kBlock - 1) / kBlock, 1024);
+    hom_max_kernel<<<dim3((unsigned)blocks), dim3(kBlock), 0, st>>>(n, S, (unsigned long long *)out);
     return hipGetLastError();
 }
 

@@ -237,11 +237,12 @@ int run_passes(sc_ctx *c, std::vector<PassJob> &passes, hipStream_t st,
 // Whether plan P is one chain from a single vertex covering every step (a
 // star rooted at its centre), which the exact multi-limb kernels run.
 bool single_chain(const Plan &P);
-// Exact multi-limb counts (limbs 2..4) of the colourings of passes with a
-// single-chain plan: each count's limbs (limbs + 1 words per colouring, the
-// last the carry beyond) and a per-colouring flag set when a carry left the
-// top limb; waits for `st`.
-int run_wide_passes(sc_ctx *c, std::vector<PassJob> &passes, int limbs, hipStream_t st,
+// Exact multi-limb counts of the colourings of passes with a single-chain
+// plan, step i's entries kept as limbs[i] 64-bit limbs (launch_dp_chain_wide):
+// each count's L = limbs.back() limbs (L + 1 words per colouring, the last
+// the carry beyond) and a per-colouring flag mask, set where a carry left a
+// step's top limb; waits for `st`.
+int run_wide_passes(sc_ctx *c, std::vector<PassJob> &passes, const std::vector<int> &limbs, hipStream_t st,
                     const std::function<void(const PassJob &, const uint64_t *, uint64_t)> &done);
 // SC_EINVAL unless colourings first..first+n-1 all lie below SC_MAX_COLORING.
 int check_coloring_range(sc_ctx *c, uint64_t first, int64_t n);
