@@ -95,7 +95,8 @@ def forms_bench():
     """Colourings/s of the plain per-colouring launch loop (one colouring per
     sc_run call, no folding) against the batched form (colourings folded into
     the columns, each pass replayed from a captured hipGraph, one host wait per
-    call), on the same colourings; results must agree."""
+    call; then the whole call replayed from one graph), on the same colourings;
+    results must agree."""
     import numpy as np
     from paper_1903_04395_amd import inputs as I
     from paper_1903_04395_amd import sc
@@ -114,16 +115,22 @@ def forms_bench():
         ctx.set_option(sc.SC_OPT_GRAPH, 0)
         ctx.run(gid, tid, 0, 1)
         dt_p, plain = timed(lambda: [ctx.run(gid, tid, r, 1)[0][0] for r in range(R)])
-        # batched: B colourings per pass, hipGraph replay
+        # batched: B colourings per pass, hipGraph replay per pass, then one
+        # graph for the whole call
         ctx.set_option(sc.SC_OPT_MAX_BATCH, B)
         ctx.set_option(sc.SC_OPT_GRAPH, 1)
         ctx.run(gid, tid, 0, R)
         dt_b, (cb, _, _, _) = timed(lambda: ctx.run(gid, tid, 0, R))
+        ctx.set_option(sc.SC_OPT_GRAPH, 2)
+        ctx.run(gid, tid, 0, R)
+        dt_g, (cg, _, _, _) = timed(lambda: ctx.run(gid, tid, 0, R))
         ctx.set_option(sc.SC_OPT_GRAPH, 0)
         ctx.set_option(sc.SC_OPT_MAX_BATCH, 64)
         assert np.array_equal(np.asarray(plain, np.uint64), cb), name
+        assert np.array_equal(cg, cb), name
         out[name] = {"colorings": R, "batch": B, "plain_colorings_per_s": round(R / dt_p, 1),
-                     "batched_colorings_per_s": round(R / dt_b, 1), "ratio": round(dt_p / dt_b, 2)}
+                     "batched_colorings_per_s": round(R / dt_b, 1), "ratio": round(dt_p / dt_b, 2),
+                     "one_graph_colorings_per_s": round(R / dt_g, 1)}
         print(f"[bench] forms {name}: {out[name]}", file=sys.stderr, flush=True)
         ctx.unload_graph(gid)
     ctx.close()
@@ -229,7 +236,8 @@ def configs_bench(only=None, tune_ok=True):
     """Per-configuration timings after a warm-up pass (allocation excluded):
     ER 2000 / P5 / k=5 (one colouring per call: launch latency); Chung-Lu
     n=4,194,304 (mean degree 30, exponent 2.1) / 12-vertex tree and 12-star /
-    k=12 / 16 colourings; RMAT scale 19 / 15-vertex tree / k=15 / 4 colourings.
+    k=12 / 16 colourings; RMAT scale 19 / 15-vertex tree / k=15 / 4 colourings;
+    RMAT scale 20 / 10-vertex tree / k=10 / 8 colourings (5 timed calls).
     The multi-colouring cases are timed with the planner's default knobs, then
     again after the autotuner picks the interleave and LDS limit."""
     from paper_1903_04395_amd import inputs as I
@@ -241,7 +249,9 @@ def configs_bench(only=None, tune_ok=True):
              ("chunglu4m-k12", lambda: I.chung_lu(4194304, 30, 2.1, seed=3),
               [("tree12", 12, I.prufer_tree(12, 3), -1), ("star12", 12, I.star(12), 0)], 12, 16, 1, True),
              ("rmat19-tree15-k15", lambda: I.rmat(19, 16, seed=4), [("tree15", 15, I.prufer_tree(15, 4), -1)],
-              15, 4, 1, True)]
+              15, 4, 1, True),
+             ("rmat20-tree10-k10", lambda: I.rmat(20, 16, seed=0), [("tree10", 10, I.prufer_tree(10, 0), -1)],
+              10, 8, 5, True)]
 
     def timed_calls(gid, tid, R, reps):
         ctx.run(gid, tid, 0, R)                           # warm (allocation, tables)
