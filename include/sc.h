@@ -321,8 +321,8 @@ int sc_hom_count(sc_ctx *ctx, int32_t graph_id, int32_t tmpl_id, void *stream, d
 /* Batched form: many jobs -- each a (graph, template, k, seed, colouring range)
  * -- planned together and run back to back on one stream with a single host
  * wait at the end (colourings folded into the table columns, up to the
- * planned batch per pass; with SC_OPT_GRAPH each pass replays a captured
- * hipGraph).  Jobs may mix templates of different sizes and different k.
+ * planned batch per pass; with SC_OPT_GRAPH = 1 each pass replays a captured
+ * hipGraph, with SC_OPT_GRAPH = 2 the whole call does).  Jobs may mix templates of different sizes and different k.
  * Host outputs per job: counts[n_colorings], overflow[n_colorings],
  * est_maps / est_copies (NaN if any colouring overflowed), status.
  * Returns SC_OK, or the first job's error (that job's status is set, the
@@ -413,7 +413,13 @@ int sc_serve_stop(sc_ctx *ctx);
  * Errors: SC_EINVAL (unknown option or value out of range). */
 enum {
     SC_OPT_MAX_BATCH = 1,     /* cap on colourings per pass (1..SC_MAX_BATCH)   */
-    SC_OPT_GRAPH = 3,         /* 1: replay each pass from a captured hipGraph   */
+    SC_OPT_GRAPH = 3,         /* 1: replay each pass from a captured hipGraph;
+                                 2: capture every pass of an sc_run /
+                                 sc_run_batch call (templates, sizes and k
+                                 mixed) into one hipGraph, replayed with one
+                                 launch whenever a call of the same shape
+                                 (passes, plans, knobs) comes again; serving
+                                 treats 2 as 1                                 */
     SC_OPT_SEGMENT = 5,       /* neighbours per work item of heavy rows, > 64
                                  (0 = default, 512)                            */
     SC_OPT_REORDER = 8,       /* graphs loaded afterwards are kept relabelled:

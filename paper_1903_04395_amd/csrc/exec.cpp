@@ -342,6 +342,86 @@ using namespace sc;
 namespace sc {
 
 constexpr size_t kStageWords = 2 + SC_MAX_BATCH + 1;   // descriptor + results of one pass
+constexpr size_t kResWords = SC_MAX_BATCH + 1;         // results of one pass
+constexpr size_t kMaxCallGraphs = 64;                  // whole-call graphs kept at once
+
+void drop_call_graphs(sc_ctx *c) {
+    for (auto &kv : c->call_graphs) (void)hipGraphExecDestroy(kv.second);
+    c->call_graphs.clear();
+}
+
+namespace {
+
+// SC_OPT_GRAPH = 2: every pass of the call in one captured graph, replayed
+// with one launch.  The passes run back to back on the shared buffers (sized
+// for the largest pass beforehand); pass i reads its seed and first colouring
+// from call_desc[2i..] and leaves its sums and flags in call_x[i][..].  Every
+// pass is prepared first (bins, index tables), so nothing allocates while the
+// stream is captured.
+int run_passes_one_graph(sc_ctx *c, std::vector<PassJob> &passes, hipStream_t st,
+                         const std::function<void(const PassJob &, const uint64_t *)> &done) {
+    int rc;
+    PassBuffers &b = c->main;
+    const size_t np = passes.size();
+    std::vector<PassSpec> specs(np);
+    std::vector<GraphExecKey> key(np);
+    for (size_t i = 0; i < np; ++i) {
+        PassJob &p = passes[i];
+        PassSpec &s = specs[i];
+        s.g = c->graphs[p.gid].get();
+        s.P = &p.P;
+        s.k = p.k; s.seed = p.seed; s.first = p.first; s.mod = p.mod;
+        if ((rc = prepare_pass(c, s, b, st))) return rc;
+    }
+    if (c->call_desc.bytes < np * 2 * sizeof(uint64_t) || c->call_x.bytes < np * kResWords * sizeof(uint64_t))
+        ++c->call_gen;
+    if ((rc = ensure(c, c->call_desc, np * 2 * sizeof(uint64_t), st))) return rc;
+    if ((rc = ensure(c, c->call_x, np * kResWords * sizeof(uint64_t), st))) return rc;
+    for (size_t i = 0; i < np; ++i) {
+        const Plan &P = passes[i].P;
+        key[i] = GraphExecKey{passes[i].gid, passes[i].tid, P.k, P.batch, P.interleave, P.opts.lds_max,
+                              P.opts.wave_row_max, plan_segment(c, P), P.opts.chain, passes[i].mod, b.gen};
+    }
+    auto ck = std::make_pair(key, c->call_gen);
+    auto it = c->call_graphs.find(ck);
+    if (it == c->call_graphs.end()) {
+        if (c->call_graphs.size() >= kMaxCallGraphs) {
+            HIPCHK(c, hipStreamSynchronize(st));
+            drop_call_graphs(c);
+        }
+        hipGraph_t graph = nullptr;
+        HIPCHK(c, hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
+        for (size_t i = 0; i < np && !rc; ++i) {
+            // the pass's bins exist (prepare_pass built them): this only swaps them in
+            if ((rc = rebin(c, *specs[i].g, plan_segment(c, passes[i].P), false))) break;
+            PassBuffers v = b;
+            v.desc.p = (uint64_t *)c->call_desc.p + 2 * i;
+            v.xbuf.p = (uint64_t *)c->call_x.p + kResWords * i;
+            rc = enqueue_pass(c, specs[i], v, st, false);
+        }
+        hipError_t e = hipStreamEndCapture(st, &graph);
+        if (rc) { if (graph) (void)hipGraphDestroy(graph); return rc; }
+        if (e != hipSuccess) return fail(c, SC_EDEVICE, "hipStreamEndCapture failed: %s", hipGetErrorString(e));
+        hipGraphExec_t exec = nullptr;
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return fail(c, SC_EDEVICE, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
+        it = c->call_graphs.emplace(ck, exec).first;
+    }
+    uint64_t *desc = c->host_out, *res = c->host_out + 2 * np;
+    for (size_t i = 0; i < np; ++i) {
+        desc[2 * i] = passes[i].seed;
+        desc[2 * i + 1] = passes[i].first;
+    }
+    HIPCHK(c, hipMemcpyAsync(c->call_desc.p, desc, np * 2 * sizeof(uint64_t), hipMemcpyHostToDevice, st));
+    HIPCHK(c, hipGraphLaunch(it->second, st));
+    HIPCHK(c, hipMemcpyAsync(res, c->call_x.p, np * kResWords * sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    for (size_t i = 0; i < np; ++i) done(passes[i], res + kResWords * i);
+    return SC_OK;
+}
+
+}  // namespace
 
 // Plans every pass of the jobs, runs them back to back on `st` and waits once.
 int run_passes(sc_ctx *c, std::vector<PassJob> &passes, hipStream_t st,
@@ -350,16 +430,20 @@ int run_passes(sc_ctx *c, std::vector<PassJob> &passes, hipStream_t st,
     if ((rc = host_staging(c, std::max<size_t>(1, passes.size()) * kStageWords))) return rc;
     // size the buffers for the largest pass first, so no buffer moves mid-chain
     size_t arena = 0, colb = 0, npre = 0;
+    bool trivial = false;
     for (auto &p : passes) {
         const Graph &g = *c->graphs[p.gid];
         arena = std::max<size_t>(arena, p.P.arena_bytes);
         colb = std::max<size_t>(colb, (size_t)g.n_rows * p.P.batch);
         npre = std::max<size_t>(npre, npre_bytes(g, p.P));
+        trivial |= p.P.steps.empty() || g.n_rows == 0;
     }
     PassBuffers &b = c->main;
     if ((rc = ensure_gen(c, b.arena, arena, st, b))) return rc;
     if ((rc = ensure_gen(c, b.colbuf, colb, st, b))) return rc;
     if (npre && (rc = ensure_gen(c, b.npre, npre, st, b))) return rc;
+    if (c->use_graph == 2 && !c->prof && !trivial && !passes.empty())
+        return run_passes_one_graph(c, passes, st, done);
     for (size_t i = 0; i < passes.size(); ++i) {
         auto &p = passes[i];
         PassSpec s;

@@ -136,6 +136,12 @@ struct sc_ctx {
     uint64_t *host_out = nullptr;         // pinned staging for results and descriptors
     size_t host_out_words = 0;
     std::map<sc::GraphExecKey, hipGraphExec_t> graph_cache;
+    // SC_OPT_GRAPH = 2: one captured graph per call shape (every pass of an
+    // sc_run / sc_run_batch call), reading per-pass descriptors from call_desc
+    // and writing per-pass sums to call_x; call_gen changes when those move
+    std::map<std::pair<std::vector<sc::GraphExecKey>, uint64_t>, hipGraphExec_t> call_graphs;
+    sc::DevMem call_desc, call_x;
+    uint64_t call_gen = 0;
     std::map<sc::TuneKey, sc::Tuned> tuned;
     // options
     int64_t max_batch = SC_MAX_BATCH, use_graph = 0, segment = 0;
@@ -253,5 +259,8 @@ int plan_job(sc_ctx *c, int job, int gid, int tid, int k, uint64_t seed, uint64_
 int check_run_args(sc_ctx *c, int gid, int tid, int ncol);
 
 void serve_shutdown(sc_ctx *c);
+// Destroys the whole-call graphs (SC_OPT_GRAPH = 2); the device must be idle
+// or the graphs' last launches finished.
+void drop_call_graphs(sc_ctx *c);
 
 }  // namespace sc

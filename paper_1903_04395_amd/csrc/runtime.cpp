@@ -304,6 +304,8 @@ int sc_destroy(sc_ctx *c) {
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
     for (auto &kv : c->graph_cache) (void)hipGraphExecDestroy(kv.second);
+    drop_call_graphs(c);
+    dev_free(c, c->call_desc); dev_free(c, c->call_x);
     for (auto &kv : c->graphs) free_graph(c, *kv.second);
     for (auto &kv : c->split_tabs) dev_free(c, kv.second);
     for (auto &kv : c->unrank_tabs) dev_free(c, kv.second);
@@ -423,6 +425,7 @@ int sc_unload_graph(sc_ctx *c, int32_t id) {
         if (g->first.graph_id == id) { (void)hipGraphExecDestroy(g->second); g = c->graph_cache.erase(g); }
         else ++g;
     }
+    drop_call_graphs(c);
     free_graph(c, *it->second);
     c->graphs.erase(it);
     return SC_OK;
@@ -490,7 +493,9 @@ int sc_set_option(sc_ctx *c, int32_t opt, int64_t v) {
     case SC_OPT_MAX_BATCH:
         if (v < 1 || v > SC_MAX_BATCH) return fail(c, SC_EINVAL, "max batch must be in [1, %d]", SC_MAX_BATCH);
         c->max_batch = v; return SC_OK;
-    case SC_OPT_GRAPH: c->use_graph = v != 0; return SC_OK;
+    case SC_OPT_GRAPH:
+        if (v < 0 || v > 2) return fail(c, SC_EINVAL, "graph option must be 0, 1 or 2");
+        c->use_graph = v; return SC_OK;
     case SC_OPT_SEGMENT:
         if (v < 0 || v > (1 << 24)) return fail(c, SC_EINVAL, "segment must be in [0, 2^24]");
         if (v > 0 && v <= 64) return fail(c, SC_EINVAL, "segment must exceed 64");

@@ -100,6 +100,68 @@ def test_graph_replay_matches_eager(ctx):
     ctx.unload_graph(gid)
 
 
+def test_whole_call_graph_matches_eager_and_oracle(ctx):
+    """SC_OPT_GRAPH = 2: every pass of a call -- jobs on two graphs, templates
+    of 3 to 10 vertices, k from 3 to 10, several passes per job -- is captured
+    into one hipGraph and replayed with one launch.  The replays run with
+    eager calls and synchronisations between them; each is checked against
+    the eager results, which are checked against the oracle."""
+    g1 = I.rmat(12, 16, seed=33)
+    g2 = I.erdos_renyi(3000, 12000, 34)
+    gids = [ctx.load_graph(g1), ctx.load_graph(g2)]
+    tids = [ctx.load_template(t, e) for t, e, _ in TEMPLATES]
+    jobs = []
+    for i, ((t, e, k), tid) in enumerate(zip(TEMPLATES, tids)):
+        for gi in range(2):
+            jobs.append({"graph_id": gids[gi], "tmpl_id": tid, "k": k, "seed": 500 + 7 * i + gi,
+                         "first": 2 * i, "n": 6 + 3 * i})
+    ctx.set_option(sc.SC_OPT_MAX_BATCH, 4)                       # several passes per job
+    try:
+        eager = ctx.run_batch(jobs)
+        for j, (cnt, ovf, _, _, st) in zip(jobs, eager):
+            assert st == 0
+            i = tids.index(j["tmpl_id"])
+            t, _, k = TEMPLATES[i]
+            g = g1 if j["graph_id"] == gids[0] else g2
+            oc, of = oracle_for(ctx, g, j["graph_id"], j["tmpl_id"], t, k, j["seed"], j["first"], j["n"])
+            assert np.array_equal(cnt, oc) and np.array_equal(ovf, of)
+        ctx.set_option(sc.SC_OPT_GRAPH, 2)
+        for rep in range(3):
+            say("whole-call replay", rep)
+            out = ctx.run_batch(jobs)
+            for (cnt, ovf, em, ec, st), (ecnt, eovf, eem, eec, _) in zip(out, eager):
+                assert st == 0 and np.array_equal(cnt, ecnt) and np.array_equal(ovf, eovf)
+                assert (math.isnan(em) and math.isnan(eem)) or em == eem
+            ctx.set_option(sc.SC_OPT_GRAPH, 0)                   # eager work between replays
+            ctx.set_colors(TEMPLATES[1][2], 9)
+            c2, f2, _, _ = ctx.run(gids[0], tids[1], 40 + rep, 3)
+            ctx.set_option(sc.SC_OPT_GRAPH, 2)
+            oc, of = oracle_for(ctx, g1, gids[0], tids[1], TEMPLATES[1][0], TEMPLATES[1][2], 9, 40 + rep, 3)
+            assert np.array_equal(c2, oc) and np.array_equal(f2, of)
+        # other seeds and colouring ranges replay the same graph (same call shape)
+        moved = [dict(j, seed=j["seed"] + 1000, first=j["first"] + 17) for j in jobs]
+        out = ctx.run_batch(moved)
+        ctx.set_option(sc.SC_OPT_GRAPH, 0)
+        ref = ctx.run_batch(moved)
+        for (cnt, ovf, _, _, st), (rcnt, rovf, _, _, _) in zip(out, ref):
+            assert st == 0 and np.array_equal(cnt, rcnt) and np.array_equal(ovf, rovf)
+        # a single sc_run of several passes through the whole-call graph
+        ctx.set_option(sc.SC_OPT_GRAPH, 2)
+        ctx.set_colors(9, 3)
+        t9 = ctx.load_template(9, I.prufer_tree(9, 35))
+        for rep in range(2):
+            c, f, _, _ = ctx.run(gids[0], t9, 5, 11)
+            ctx.set_option(sc.SC_OPT_GRAPH, 0)
+            ce, fe, _, _ = ctx.run(gids[0], t9, 5, 11)
+            ctx.set_option(sc.SC_OPT_GRAPH, 2)
+            assert np.array_equal(c, ce) and np.array_equal(f, fe)
+    finally:
+        ctx.set_option(sc.SC_OPT_GRAPH, 0)
+        ctx.set_option(sc.SC_OPT_MAX_BATCH, 64)
+    for gid in gids:
+        ctx.unload_graph(gid)
+
+
 def test_autotune_keeps_results_and_round_trips(ctx, tmp_path):
     g = I.rmat(13, 16, seed=33)
     gid = ctx.load_graph(g)
