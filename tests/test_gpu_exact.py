@@ -213,14 +213,16 @@ def test_degenerate_templates_and_graphs(ctx):
     ctx.unload_graph(gid0)
 
 
-def test_exact_counts_replayed_from_captured_graphs(ctx):
+@pytest.mark.parametrize("mode", [1, 2])
+def test_exact_counts_replayed_from_captured_graphs(ctx, mode):
     """With SC_OPT_GRAPH the uint64 and residue passes replay captured hipGraphs
-    (one per modulus); every replay, with eager work in between, matches the
-    eager result."""
+    (mode 1: one per pass shape and modulus; mode 2: one per call, its residue
+    passes for every modulus in one graph); every replay, with eager work in
+    between, matches the eager result."""
     g = hubby_graph(9)
     gid, tid, info = setup(ctx, g, 12, SPIDER, 12, 21, 4)
     eager = [ctx.run_exact(gid, tid, first, 4)[0] for first in (0, 4, 8)]
-    ctx.set_option(sc.SC_OPT_GRAPH, 1)
+    ctx.set_option(sc.SC_OPT_GRAPH, mode)
     try:
         for rep in range(2):
             for i, first in enumerate((0, 4, 8)):
@@ -228,7 +230,7 @@ def test_exact_counts_replayed_from_captured_graphs(ctx):
                 assert got == eager[i], (rep, first)
                 ctx.set_option(sc.SC_OPT_GRAPH, 0)           # eager work between replays
                 ctx.run(gid, tid, 100, 2)
-                ctx.set_option(sc.SC_OPT_GRAPH, 1)
+                ctx.set_option(sc.SC_OPT_GRAPH, mode)
     finally:
         ctx.set_option(sc.SC_OPT_GRAPH, sc.OPTION_DEFAULTS[sc.SC_OPT_GRAPH])
     assert max(eager[0]) >= 2**64

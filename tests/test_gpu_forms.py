@@ -160,6 +160,9 @@ def test_whole_call_graph_matches_eager_and_oracle(ctx):
         ctx.set_option(sc.SC_OPT_MAX_BATCH, 64)
     for gid in gids:
         ctx.unload_graph(gid)
+    for bad in (-1, 3):
+        with pytest.raises(sc.ScError):
+            ctx.set_option(sc.SC_OPT_GRAPH, bad)
 
 
 def test_autotune_keeps_results_and_round_trips(ctx, tmp_path):
