@@ -237,11 +237,13 @@ int sc_run_static(sc_ctx *ctx, int32_t graph_id, int32_t tmpl_id, uint64_t first
  * 2^185 or 2^247, and the result is certified exact when it does.
  * A template that is one chain of single-vertex attaches from a single vertex
  * (the star rooted at its centre; SC_OPT_CHAIN on) skips the residue passes
- * when its bound reaches 2^64: one pass keeps every table entry as 2, 3 or 4
- * little-endian 64-bit limbs, the fewest whose range holds the bound with the
- * same margin, and the counts are exact without any modular step (a bound at
- * or past 2^256 takes the residue passes).  The homomorphism count is then
- * always computed.
+ * when its bound reaches 2^64: one pass keeps each step's table entries as
+ * 1 to 4 little-endian 64-bit limbs, the fewest that hold that step's bound
+ * (the largest homomorphism count of its sub-star at any vertex, with the
+ * same margin; the last step at least what the total bound needs), and the
+ * counts are exact without any modular step (a bound at or past 2^256, or
+ * rows too wide for the LDS limit, take the residue passes).  The
+ * homomorphism count is then always computed.
  * Synchronous.  Host outputs: counts[n_colorings][4] (the count as four uint64
  * limbs, least significant first), exact[n_colorings] (1: the count is exact;
  * 0: only its residue mod 2^64 p1 p2 p3 is), hom_bound (may be NULL: the
