@@ -38,12 +38,6 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 
-# HIP kernel behind each libsc kernel family
-KERNEL_OF = {
-    "row_gather": "dp_row_kernel<false, *>", "row_hist": "dp_row_kernel<true, *>",
-    "split": "dp_split_kernel<*>", "reduce": "reduce_kernel", "color": "color_kernel",
-}
-
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -710,7 +704,8 @@ def main():
     roofline = {
         "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
         "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic_per_step(),
-        "kernel": "DP step = dp_split_kernel (rows above the segment size) + dp_row_kernel",
+        "kernel": "DP step = dp_split_kernel (rows above the segment size) + dp_row_kernel (dp_root_kernel for "
+                  "the root step (k, 1, k-1))",
         "bytes": "paper layout: binom(k, s) colour sets per row, every vertex; fused steps",
         "avg_step_ms": round(dp_ms / dp_launches, 4),
         "alg_bytes_per_step": dp_alg / dp_launches,

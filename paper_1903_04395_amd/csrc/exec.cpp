@@ -262,10 +262,11 @@ int enqueue_pass(sc_ctx *c, const PassSpec &sp, PassBuffers &pb, hipStream_t st,
                    (s.a > 1 ? 8.0 * nall * dB * Wa : nall * dB) + 8.0 * nall * dB * Wh;
         // the same in the rooted-colour layout over the table rows, plus the
         // split rows' sums written and read back
+        const bool pre = g.n_split && !kern::root_step(sh);      // the root step sums every row itself
         li.layout_bytes = 4.0 * nnz + 8.0 * (dn + 1) + dn * dB +
                           8.0 * dn * dB * ((s.p > 1 ? sh.Wq : 0) + (s.a > 1 ? sh.Wa : 0) + sh.Wh) +
-                          8.0 * (double)g.n_split * sh.Wn * dB;
-        if (g.n_split) {
+                          (pre ? 8.0 * (double)g.n_split * sh.Wn * dB : 0.0);
+        if (pre) {
             // the heavy rows' share of the step's neighbour sums; its bytes
             // and updates are counted with the row kernel, which completes them
             LaunchInfo ls{"split", si, s.h, s.a, s.p, B};

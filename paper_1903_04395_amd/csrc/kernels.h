@@ -125,6 +125,11 @@ hipError_t launch_reduce_wide(int64_t n, const uint64_t *S, int W, int B, int Bi
 hipError_t launch_color(const uint64_t *desc, int64_t n, int B, int k, const int32_t *perm,
                         uint8_t *col, hipStream_t st);
 
+// Whether s is the root step (k, 1, k-1) of a template on all k colours: its
+// neighbour sum is one entry, which the row kernel sums for every row (split
+// rows included), so the step has no pre-pass.
+bool root_step(const StepShape &s);
+
 // Neighbour sums of the split rows into Npre[planes][n_split][Wn * Bi]
 // (zeroed here first), from the passive table P (p >= 2) or the colours (p = 1).
 hipError_t launch_dp_split(const GraphBins &g, const StepShape &s, const StepTables &t,
@@ -135,7 +140,9 @@ hipError_t launch_dp_split(const GraphBins &g, const StepShape &s, const StepTab
 // without col_r(v)) is built in LDS -- scattered from the neighbours' passive
 // rows (p >= 2), counted from their colours (p = 1), or copied from Npre for
 // split rows -- and S[v] = sum over splits of A[v][Ia] * N'[v][Ip] is written
-// (S[v] = N'[v] when a = 1).
+// (S[v] = N'[v] when a = 1).  The root step (k, 1, k-1) of a template on all
+// k colours, whose neighbour sum is a single entry, reads one word of each
+// neighbour's row instead (dp_root_kernel).
 hipError_t launch_dp_row(const GraphBins &g, const StepShape &s, const StepTables &t,
                          const uint8_t *col, const uint64_t *P, const uint64_t *A,
                          const uint64_t *Npre, uint64_t *S, unsigned long long *flags,

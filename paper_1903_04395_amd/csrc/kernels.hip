@@ -630,6 +630,70 @@ __global__ __launch_bounds__(TPB) void dp_row_kernel(DpArgs a) {
     flush_flags(m, a.flags);
 }
 
+// The root step of a template on all k colours, (k, 1, k-1): the single-vertex
+// root joins a passive child that holds every other colour, so the output row
+// is one set (all k colours) and the neighbour sum one entry (the k-1 colours
+// other than col(v)).  Of a neighbour u's row only the entry that leaves out
+// col(v) adds to it: in u's space (the colours other than col(u), renumbered
+// 0..k-2) the (k-2)-subset that misses col(v)'s index x, whose Eq. 1 rank is
+// k-2-x; a neighbour with col(u) = col(v) adds nothing.  So a visit reads one
+// word per colouring, not the whole row.  One wavefront per (plane, row):
+// groups of Bi lanes take the row's neighbours in turn, lane ri of a group
+// serving colouring pl*Bi + ri, and the groups meet through shuffles (carry
+// flags, or modular adds).  Visits are cheap enough that rows above the
+// segment size are summed here too: the step has no split pre-pass.
+
+template <bool MOD>
+__global__ __launch_bounds__(kBlock) void dp_root_kernel(DpArgs a) {
+    constexpr int kTeams = kBlock / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int ri = lane & (a.Bi - 1);
+    const int grp = lane >> a.sh, groups = kWave >> a.sh;
+    const int k2 = a.Wq - 1;                     // k - 2: a row of P holds k - 1 entries
+    const int64_t total = a.n * a.planes;
+    uint64_t m = 0;
+    for (int64_t it = (int64_t)blockIdx.x * kTeams + (int)(threadIdx.x >> 6); it < total;
+         it += (int64_t)gridDim.x * kTeams) {
+        const int pl = (int)(it / a.n);
+        const int64_t v = it - (int64_t)pl * a.n;
+        const int r = pl * a.Bi + ri;
+        uint64_t acc = 0;
+        uint32_t carry = 0;
+        const int cv = a.col[v * a.B + r];
+        const int64_t e1 = a.rp[v + 1];
+        for (int64_t e = a.rp[v] + grp; e < e1; e += groups) {
+            const int u = a.ci[e];
+            const int cu = a.col[(int64_t)u * a.B + r];
+            if (cu == cv) continue;
+            const int x = cv - (cv > cu);
+            const uint64_t y = a.P[(((int64_t)pl * a.n + u) * a.Wq + (k2 - x)) * a.Bi + ri];
+            if constexpr (MOD) {
+                acc = mod_add(acc, y, a.md);
+            } else {
+                const uint64_t t = acc + y;
+                carry |= (uint32_t)(t < y);
+                acc = t;
+            }
+        }
+        for (int o = a.Bi; o < kWave; o <<= 1) {
+            const uint64_t y = shfl_xor_u64(acc, o);
+            if constexpr (MOD) {
+                acc = mod_add(acc, y, a.md);
+            } else {
+                carry |= (uint32_t)__shfl_xor((int)carry, o, kWave);
+                const uint64_t t = acc + y;
+                carry |= (uint32_t)(t < y);
+                acc = t;
+            }
+        }
+        if (grp == 0) {
+            a.S[((int64_t)pl * a.n + v) * a.Bi + ri] = acc;
+            if (carry) m |= 1ull << r;
+        }
+    }
+    flush_flags(m, a.flags);
+}
+
 // Split rows: one workgroup per (plane, row, segment of `seg` neighbours)
 // item; the segment's sum is built in LDS as in the row kernel and added into
 // Npre with global atomics (carry from the returned old value).
@@ -1546,11 +1610,15 @@ hipError_t launch_color(const uint64_t *desc, int64_t n, int B, int k, const int
     return hipGetLastError();
 }
 
+bool root_step(const StepShape &s) {
+    return s.a == 1 && s.p >= 2 && s.p == s.k - 1 && s.Wq == s.k - 1 && s.Wn == 1 && s.Wh == 1;
+}
+
 hipError_t launch_dp_split(const GraphBins &g, const StepShape &s, const StepTables &t,
                            const uint8_t *col, const uint64_t *P, uint64_t *Npre,
                            unsigned long long *flags, hipStream_t st) {
     t_last_kernel[0] = 0;
-    if (g.n_split == 0 || g.n_split_items == 0) return hipSuccess;
+    if (g.n_split == 0 || g.n_split_items == 0 || root_step(s)) return hipSuccess;   // the root kernel sums every row
     if (!shape_ok(s) || (s.p >= 2 && (!P || !t.unrank || !t.rank))) return hipErrorInvalidValue;
     hipError_t e = launch_zero_u64(Npre, g.n_split * (int64_t)s.Wn * s.B, st);
     if (e != hipSuccess) return e;
@@ -1570,6 +1638,15 @@ hipError_t launch_dp_row(const GraphBins &g, const StepShape &s, const StepTable
     if (!shape_ok(s) || !S || (s.p >= 2 && (!P || !t.unrank || !t.rank)) ||
         (s.amode != kActiveLeaf && (!A || !t.split)) || (g.n_split && !Npre))
         return hipErrorInvalidValue;
+    if (root_step(s)) {
+        // the root step of a template on all k colours reads one word per visit
+        DpArgs a = make_args(g, s, t, col, P, nullptr, Npre, S, flags, kWaves);
+        const int64_t blocks = std::min<int64_t>((a.n * a.planes + kWaves - 1) / kWaves, 2 * resident_blocks(0));
+        name_kernel("dp_root_kernel<%s>", tf(s.mod != 0));
+        if (s.mod) dp_root_kernel<true><<<dim3((unsigned)blocks), dim3(kBlock), 0, st>>>(a);
+        else dp_root_kernel<false><<<dim3((unsigned)blocks), dim3(kBlock), 0, st>>>(a);
+        return hipGetLastError();
+    }
     // steps whose per-row LDS is small run one row per wavefront, when there
     // are enough rows to keep every wavefront slot of the chip busy (on a
     // small graph a row's latency matters more than the rows in flight)
