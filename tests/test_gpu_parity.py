@@ -205,6 +205,52 @@ def test_chain_overflow_flags_and_residues(ctx):
     ctx.unload_graph(gid)
 
 
+@pytest.mark.parametrize("tmpl,seg,inter", [("path", 0, 0), ("path", 128, 1), ("star_leaf", 128, 8),
+                                            ("star_leaf", 0, 2)])
+def test_root_step_kernel_matches_oracle(ctx, tmpl, seg, inter):
+    """A template on all k colours whose root has one leaf child ends in the
+    step (k, 1, k-1), which reads one word of each neighbour's row and sums
+    rows of every degree itself: counts and flags (hub rows past the segment
+    size, counts past 2^64) and residues against the oracle, and the traced
+    kernel is the root-step kernel."""
+    rng = np.random.default_rng(5)
+    base = I.erdos_renyi(1200, 5000, 5)
+    e = base.edges()
+    src, dst = [e[:, 0]], [e[:, 1]]
+    for h in range(4):
+        nb = rng.choice(np.arange(4, 1200), size=900, replace=False)
+        src.append(np.full(900, h))
+        dst.append(nb)
+    g = I.csr_from_edges(1200, np.concatenate(src), np.concatenate(dst))
+    t = k = 9
+    # rooted at an endpoint or at a leaf of the star: the last step is (9, 1, 8)
+    edges, root = (I.path(t), 0) if tmpl == "path" else (I.star(t), 1)
+    opts = {sc.SC_OPT_SEGMENT: seg, sc.SC_OPT_INTERLEAVE: inter}
+    counts, ovf, _, _, info = run_both(ctx, g, t, edges, k, 23, 2, 8, root=root, opts=opts)
+    assert tuple(info.steps()[-1]) == (k, 1, k - 1)
+    if tmpl == "star_leaf":
+        assert ovf.any()                        # the hubs push the star's counts past 2^64
+    for o, v in opts.items():
+        ctx.set_option(o, v)
+    try:
+        gid = ctx.load_graph(g)
+        tid = ctx.load_template(t, edges, root)
+        ctx.set_colors(k, 23)
+        ctx.profile(True)
+        ctx.run(gid, tid, 2, 8)
+        ctx.profile(False)
+        last = [r for r in ctx.profile_launches() if r["family"] == "row_gather" and r["h"] == k]
+        assert last and all(r["kernel"].startswith("dp_root_kernel") for r in last)
+        for p in O.PRIMES[:2]:
+            got = ctx.run_mod(gid, tid, 2, 8, p)
+            want = O.count_mod(g, t, (info.root, info.children()), k, 23, 2, 8, p)
+            assert np.array_equal(got, want), p
+        ctx.unload_graph(gid)
+    finally:
+        for o in opts:
+            ctx.set_option(o, sc.OPTION_DEFAULTS[o])
+
+
 # ------------------------------------------------------------------ overflow and edge cases
 
 def test_overflow_flags_match(ctx):
