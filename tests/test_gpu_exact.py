@@ -302,3 +302,25 @@ def test_exact_star_smaller_k_and_t(ctx):
     assert exact.all() and counts == want
     assert max(want) >= 2**64
     ctx.unload_graph(gid)
+
+
+@pytest.mark.parametrize("max_batch,interleave", [(4, 0), (4, 1), (2, 2)])
+def test_exact_star_multi_limb_several_passes(ctx, max_batch, interleave):
+    """The multi-limb star pass folded into several passes (the last one
+    partial) and at small interleaves: counts against the closed form."""
+    k, t, seed, first, R = 12, 12, 41, 3, 9
+    g = hubby_graph(19, n=6000, m=12000, hubs=2, hub_deg=4000)
+    ctx.set_option(sc.SC_OPT_MAX_BATCH, max_batch)
+    ctx.set_option(sc.SC_OPT_INTERLEAVE, interleave)
+    try:
+        gid, tid, info = setup(ctx, g, t, I.star(t), k, seed, R, 0)
+        say(f"wide star passes: n={g.n} batch={info.batch} interleave={info.interleave} R={R}")
+        assert info.batch <= max_batch
+        counts, exact, hom, _, _ = ctx.run_exact(gid, tid, first, R)
+        want = [star_closed_form(g, O.colors(seed, first + r, g.n, k), k) for r in range(R)]
+        assert exact.all() and counts == want
+        assert max(want) >= 2**64 and hom * (1 + 2**-10) >= 2**128      # three limbs at the root
+        ctx.unload_graph(gid)
+    finally:
+        ctx.set_option(sc.SC_OPT_MAX_BATCH, sc.OPTION_DEFAULTS[sc.SC_OPT_MAX_BATCH])
+        ctx.set_option(sc.SC_OPT_INTERLEAVE, sc.OPTION_DEFAULTS[sc.SC_OPT_INTERLEAVE])
