@@ -59,7 +59,8 @@ def parse():
     ap.add_argument("--only", default=None, help="with --configs: run only the named configuration")
     ap.add_argument("--no-tune", action="store_true", help="with --configs: skip the autotuner")
     ap.add_argument("--gather-probe", action="store_true",
-                    help="only time whole-row gathers of the widest step's rows in RMAT-20 neighbour order")
+                    help="only time whole-row gathers in RMAT-20 and Chung-Lu neighbour order, and streaming "
+                         "copy and read rates")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB three times (calibrates rocprofv3 FETCH_SIZE/WRITE_SIZE)")
     ap.add_argument("--forms", action="store_true",
@@ -188,42 +189,69 @@ def serve_bench(nq, qps=200.0, streams=4):
 
 
 def gather_probe():
-    """Ceiling of the DP's dominant access: whole passive rows of the widest
-    step (126 sets x 8 colourings = 1008 uint64, 8064 bytes) gathered in the
-    neighbour order of RMAT scale 20, from a table of one row per non-isolated
-    vertex (rows relabelled by descending degree, as the library keeps them).
-    torch.index_select into a reused 32768-row buffer; GB/s counts the
+    """Ceiling of the DP's dominant access: whole passive rows gathered in a
+    graph's neighbour order, from a table of one row per non-isolated vertex
+    (rows relabelled by descending degree, as the library keeps them):
+    RMAT scale 20 with rows of 126 sets x 8 colourings (1008 uint64, the
+    widest step of the 10-vertex tree), and Chung-Lu n=4,194,304 with rows of
+    462 sets x 2 colourings (924 uint64, the step (11,5,6) of the 12-vertex
+    tree).  torch.index_select into a reused 32768-row buffer; GB/s counts the
     gathered (read) bytes only, so it is a lower bound of the read ceiling."""
     import numpy as np
     import torch
     from paper_1903_04395_amd import inputs as I
-    g = I.rmat(20, 16, seed=0)
-    deg = g.degrees()
-    order = np.argsort(-deg, kind="stable")
-    rows = int((deg > 0).sum())
-    new_id = np.empty(g.n, np.int64)
-    new_id[order] = np.arange(g.n)
-    idx = torch.from_numpy(new_id[g.col_idx.astype(np.int64)]).cuda()
-    W = 1008
-    table = torch.ones((rows, W), dtype=torch.int64, device="cuda")
-    chunk = 32768
-    buf = torch.empty((chunk, W), dtype=torch.int64, device="cuda")
-    def run():
-        for c0 in range(0, idx.numel(), chunk):
-            sel = idx[c0:c0 + chunk]
-            torch.index_select(table, 0, sel, out=buf[:sel.numel()])
-    run()
+    out = {}
+    for name, gen, W in (("rmat20", lambda: I.rmat(20, 16, seed=0), 1008),
+                         ("chunglu4m", lambda: I.chung_lu(4194304, 30, 2.1, seed=3), 924)):
+        g = gen()
+        deg = g.degrees()
+        order = np.argsort(-deg, kind="stable")
+        rows = int((deg > 0).sum())
+        new_id = np.empty(g.n, np.int64)
+        new_id[order] = np.arange(g.n)
+        idx = torch.from_numpy(new_id[g.col_idx.astype(np.int64)]).cuda()
+        del g
+        table = torch.ones((rows, W), dtype=torch.int64, device="cuda")
+        chunk = 32768
+        buf = torch.empty((chunk, W), dtype=torch.int64, device="cuda")
+
+        def run():
+            for c0 in range(0, idx.numel(), chunk):
+                sel = idx[c0:c0 + chunk]
+                torch.index_select(table, 0, sel, out=buf[:sel.numel()])
+        run()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        run()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        gathered = idx.numel() * W * 8
+        out[name] = {"rows": rows, "row_bytes": W * 8, "gathers": int(idx.numel()), "ms": round(ms, 2),
+                     "read_GBps": round(gathered / (ms / 1e3) / 1e9, 1)}
+        print(f"[bench] gather probe {name}: {out[name]}", file=sys.stderr, flush=True)
+        del table, buf, idx
+        torch.cuda.empty_cache()
+    # streaming references: a 4 GiB device copy (read + write) and a 16 GiB sum (read)
+    a = torch.ones(1 << 29, dtype=torch.int64, device="cuda")
+    b = torch.empty_like(a)
+    big = torch.ones(1 << 31, dtype=torch.int64, device="cuda")
+    for _ in range(2):
+        b.copy_(a)
+        big.sum()
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    run()
-    e1.record()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    e[0].record()
+    b.copy_(a)
+    e[1].record()
+    big.sum()
+    e[2].record()
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
-    gathered = idx.numel() * W * 8
-    print(json.dumps({"gather_probe": {"rows": rows, "row_bytes": W * 8, "gathers": int(idx.numel()),
-                                       "ms": round(ms, 2),
-                                       "read_GBps": round(gathered / (ms / 1e3) / 1e9, 1)}}), flush=True)
+    out["stream"] = {"copy_GBps": round(2 * a.numel() * 8 / (e[0].elapsed_time(e[1]) / 1e3) / 1e9, 1),
+                     "read_GBps": round(big.numel() * 8 / (e[1].elapsed_time(e[2]) / 1e3) / 1e9, 1)}
+    print(f"[bench] stream: {out['stream']}", file=sys.stderr, flush=True)
+    print(json.dumps({"gather_probe": out}), flush=True)
 
 
 def configs_bench(only=None, tune_ok=True):
