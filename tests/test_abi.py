@@ -74,6 +74,18 @@ def test_colorset_rank_matches_oracle(k):
         assert sc.sc_colorset_rank(m) == O.rank(m)
 
 
+@pytest.mark.parametrize("k", [3, 5, 9, 12, 16])
+def test_root_step_entry_rank(k):
+    """The root step (k, 1, k-1) reads, of a neighbour's row, the set of the
+    k-2 renumbered colours that misses index x; its Eq. 1 rank is k-2-x (the
+    oracle's rank, and the library's, of that mask)."""
+    full = (1 << (k - 1)) - 1
+    for x in range(k - 1):
+        m = full & ~(1 << x)
+        assert O.rank(m) == k - 2 - x
+        assert sc.sc_colorset_rank(m) == k - 2 - x
+
+
 def test_color_rule_matches_oracle():
     for seed in (0, 1, 2**63 + 5):
         for r in (0, 1, 77):
